@@ -1,0 +1,174 @@
+"""Benchmark of the AT finite-difference step on one MI355X.
+
+Workload: 3-D advection-diffusion on a periodic 256^3 grid split into 8x8x8
+PEs of 32^3, fourth-order AT scheme (T = 3 levels), L = 4 uniform delays per
+PE face and step, AB2, 500 steps, u0 = four plane waves with random phases.
+A "step" is one AT time step of the whole grid (delay draw, AT halo
+combination, interior sweep, right-hand side, AB2 update, halo publish).
+
+Prints one JSON line: grid-point updates/s of the FP32-bulk AT run (FP64 AT
+combination), its HBM roofline fraction, the FP64 and synchronous-scheme arms
+with their errors against the exact solution, and the FP64 CPU oracle timed on
+a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD published figure
+
+p = argparse.ArgumentParser()
+p.add_argument("--gpus", type=int, default=1)
+p.add_argument("--steps", type=int, default=500)
+p.add_argument("--warmup", type=int, default=20)
+p.add_argument("--graph", type=int, default=50, help="steps per captured HIP graph (0: plain launches)")
+p.add_argument("--n", type=int, default=256)
+p.add_argument("--b", type=int, default=32)
+p.add_argument("--no-cpu-baseline", action="store_true")
+p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to time")
+p.add_argument("--cpu-steps", type=int, default=4)
+args = p.parse_args()
+
+if args.gpus != 1:
+    print(json.dumps({"error": "this benchmark runs on one GPU only: the simulated PEs all live "
+                      "on one device; run with --gpus 1"}))
+    sys.exit(2)
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+import workloads as W  # noqa: E402
+from paper_1702_00496_amd import Solver  # noqa: E402
+
+cfg = W.config_3d_advdiff(n=args.n, b=args.b)
+N = cfg["n"][0]
+npts = N ** 3
+u0_host = torch.from_numpy(W.eval_modes(cfg["modes"], cfg["n"], 3))
+dev = torch.device("cuda:0")
+u0 = u0_host.to(dev)
+
+
+def make(precision, mode):
+    return Solver(ndim=3, n=cfg["n"], pe=cfg["pe"], dt=cfg["dt"], order=4, equation="advdiff",
+                  c=cfg["c"], alpha=cfg["alpha"], integrator="ab2", precision=precision,
+                  L=cfg["L"], T=cfg["T"], mode=mode, seed=cfg["seed"])
+
+
+def bytes_per_update(precision, mode):
+    """Algorithmic HBM bytes per grid-point update of the AB2 AT step.
+
+    Bulk: u^n read, u^{n+1} written, f^{n-1} read, f^n written (4 values).
+    Faces: h = 2 * dim * s / b halo values per point and level; a face with
+    delay k reads T levels when k > 0 and one level when k = 0 (zero weights
+    are skipped), so E[levels] = p0 + (1 - p0) T with p0 = 1/L; the new edge
+    values are published once (h values written)."""
+    w = 8 if precision == "f64" else 4
+    if mode == "sync":
+        return 4 * w
+    h = 2 * 3 * 2 / args.b
+    p0 = 1.0 / cfg["L"]
+    levels = p0 + (1 - p0) * cfg["T"]
+    return (4 + h * (levels + 1)) * w
+
+
+def time_arm(precision, mode):
+    s = make(precision, mode)
+    if args.graph:
+        s.set_graph(args.graph)
+    s.set_state(u0)
+    s.step(args.warmup)
+    s.set_state(u0)                     # the timed run is steps 0..K-1 of the workload
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nrm = s.norms(modes=cfg["modes"])
+    ups = npts * args.steps / (ms / 1e3)
+    bpu = bytes_per_update(precision, mode)
+    gbs = ups * bpu / 1e9
+    return dict(precision=precision, mode=mode, ms=ms, ms_per_step=ms / args.steps,
+                updates_per_s=ups, bytes_per_update=bpu, achieved_gbs=gbs,
+                frac=gbs / HBM_PEAK_GBS, l2_error=nrm["l2"], linf_error=nrm["linf"])
+
+
+def copy_bandwidth():
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbs
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host cores: the first cpu_steps steps of the same
+    workload (a bounded sample of the run)."""
+    from oracle.solver import DelayModel, Oracle, Problem
+    torch.set_num_threads(os.cpu_count() or 1)
+    prob = Problem(ndim=3, n=cfg["n"], pe=cfg["pe"], dt=cfg["dt"], order=4, equation="advdiff",
+                   c=cfg["c"], alpha=cfg["alpha"], integrator="ab2")
+    o = Oracle(prob, DelayModel(L=cfg["L"], T=cfg["T"], mode="rng", seed=cfg["seed"]), u0_host)
+    t0 = time.perf_counter()
+    o.run(args.cpu_steps)
+    dt_ = time.perf_counter() - t0
+    return dict(value=npts * args.cpu_steps / dt_, unit="grid-pt updates/s",
+                cores=torch.get_num_threads(), kind="oracle",
+                sample=f"first {args.cpu_steps} of {cfg['steps']} steps of the {N}^3 workload, FP64, "
+                       f"{dt_:.1f} s")
+
+
+arms = {}
+for arm in args.arms.split(","):
+    precision = "f64" if "64" in arm else "f32"
+    mode = "sync" if arm.startswith("sync") else "rng"
+    arms[arm] = time_arm(precision, mode)
+    print(f"[bench] {arm}: {arms[arm]['ms_per_step']:.4f} ms/step "
+          f"{arms[arm]['updates_per_s']:.3e} upd/s {arms[arm]['achieved_gbs']:.0f} GB/s "
+          f"l2={arms[arm]['l2_error']:.3e}", file=sys.stderr, flush=True)
+
+head = arms.get("f32") or next(iter(arms.values()))
+copy_gbs = copy_bandwidth()
+out = {
+    "metric": "AT stencil grid-pt updates/s, % HBM roofline, vs standard at matched error",
+    "value": head["updates_per_s"],
+    "unit": "grid-pt updates/s",
+    "n_gpus": 1,
+    "steps": args.steps,
+    "warmup": args.warmup,
+    "ms_per_step": head["ms_per_step"],
+    "higher_is_better": True,
+    "scaling": "weak",
+    "vs_baseline": None,
+    "dtype": "f32" if head["precision"] == "f32" else "f64",
+    "data": "synthetic",
+    "config": {"workload": f"3-D advection-diffusion {N}^3, {cfg['pe'][0]}^3 PEs of {args.b}^3, "
+                           f"4th-order AT (T=3), L={cfg['L']} uniform delays, AB2, {cfg['steps']} steps",
+               "grid": N, "pe_edge": args.b, "order": 4, "L": cfg["L"], "integrator": "ab2",
+               "dt": cfg["dt"], "graph_chunk": args.graph},
+    "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": head["frac"], "traffic": None,
+                 "kernel": "at_step_kernel<float,3,2>", "bytes_per_update": head["bytes_per_update"],
+                 "measured_copy_gbs": copy_gbs},
+    "arms": arms,
+}
+if not args.no_cpu_baseline:
+    out["cpu_baseline"] = cpu_baseline()
+print(json.dumps(out))

@@ -1,0 +1,186 @@
+/*
+ * atfd.h - C ABI of libatfd, asynchrony-tolerant (AT) finite differences on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: K. Aditya & D. A. Donzis, "High-order asynchrony-tolerant finite
+ * difference schemes for partial differential equations", arXiv 1702.00496.
+ *
+ * A periodic 1-, 2- or 3-D box is split into simulated processing elements
+ * (PEs). Every PE face receives its neighbour's edge values through a ring of
+ * past time levels and sees them with a random delay k in [0, L-1] (Sec. 2),
+ * drawn per step and per face from a counter-based generator (Sec. 5.1).
+ * Points whose stencil crosses a face combine T successive delayed levels with
+ * weights c_m(k) so that the delay error cancels to the scheme's order
+ * (Sec. 3.3 Example 3 eq. cd4-at; Tables atschemes-left/right); all other
+ * points take the standard central difference (Sec. 2 eq. general_deriv).
+ * The right-hand side is advection-diffusion or viscous Burgers (Sec. 5 eq.
+ * general) and is advanced with Euler, AB2, AB3 (Sec. 4.1 eqs. time_disc,
+ * time_ab2) or Heun RK2.
+ *
+ * Conventions for every call:
+ *  - Device pointers ("_dev") point to HIP device memory owned by the caller.
+ *    The library never allocates or frees device memory: all its state lives
+ *    in a caller-provided workspace whose size the *_workspace_size calls
+ *    report. Host pointers are read during the call only.
+ *  - Fields are dense C-order arrays [nz][ny][nx] (x fastest) of the bulk
+ *    precision: double for AT_F64, float for AT_F32_F64B. Grid nodes are
+ *    x_i = i * length / n (per axis).
+ *  - Work is queued on the HIP stream given at creation; calls that return
+ *    numbers to the host synchronise that stream.
+ *  - Errors are reported only through the status code; at_last_error()
+ *    returns a text for the most recent failure of a context (or, with NULL,
+ *    of the calling thread). Nothing throws across this interface.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef ATFD_H
+#define ATFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AT_OK = 0,
+  AT_EINVAL = 1,     /* invalid argument or unsupported combination            */
+  AT_ENOMEM = 2,     /* workspace too small                                    */
+  AT_EHIP = 3,       /* a HIP runtime call failed                              */
+  AT_EUNSTABLE = 4,  /* a norm evaluation met a non-finite value (blow-up)     */
+  AT_ESTATE = 5      /* call out of order (e.g. at_step before at_set_state)   */
+} at_status;
+
+/* Model equation (Sec. 5 eq. general). */
+enum { AT_ADVDIFF = 0,   /* u_t + c . grad u = alpha lap u                     */
+       AT_BURGERS = 1 }; /* u_t + u (sum_d u_{x_d}) = alpha lap u (scalar)     */
+
+/* Time integrator (Sec. 4.1). AB2 starts with one Euler step, AB3 with Euler
+ * then AB2. RK2 is Heun's method; its predictor u* is a field of its own
+ * with its own ring of past levels, so its stage derivative is also AT. */
+enum { AT_EULER = 0, AT_AB2 = 1, AT_AB3 = 2, AT_RK2 = 3 };
+
+/* Arithmetic. AT_F32_F64B: fields, history and rings stored in float, the
+ * bulk stencil in float, the AT combination of delayed levels and all error
+ * norms in double. */
+enum { AT_F64 = 0, AT_F32_F64B = 1 };
+
+/* Delay model. RNG: one draw per step, PE and face from the counter-based
+ * generator below. ZERO: every delay is 0 (the scheme then equals the
+ * synchronous one). HOST: delays from a caller table. SYNC: the synchronous
+ * reference scheme that reads neighbours' current values directly (no ring
+ * traffic; the comparison arm "standard scheme"). */
+enum { AT_DELAY_RNG = 0, AT_DELAY_ZERO = 1, AT_DELAY_HOST = 2, AT_SYNC = 3 };
+
+typedef struct at_problem {
+  int32_t ndim;        /* 1, 2 or 3                                              */
+  int32_t pe[3];       /* PEs per axis (x, y, z); unused axes 1                  */
+  int64_t n[3];        /* points per axis; n[d] % pe[d] == 0; unused axes 1      */
+  double length;       /* periodic box edge (same on every axis), e.g. 2*pi     */
+  double c[3];         /* advection velocity (AT_ADVDIFF)                        */
+  double alpha;        /* diffusivity (AT_ADVDIFF) or viscosity (AT_BURGERS)     */
+  double dt;           /* time step                                              */
+  int32_t equation;    /* AT_ADVDIFF | AT_BURGERS                                */
+  int32_t order;       /* spatial order a: 2, 4 or 6; half-width s = a/2         */
+  int32_t integrator;  /* AT_EULER | AT_AB2 | AT_AB3 | AT_RK2                    */
+  int32_t precision;   /* AT_F64 | AT_F32_F64B                                   */
+} at_problem;
+
+/*
+ * Delay generator (the paper leaves it unspecified, Sec. 5.1): with
+ *   G = 0x9E3779B97F4A7C15 and mix() the SplitMix64 finaliser
+ *   (Steele, Lea & Flood, OOPSLA 2014),
+ *   face = p * 2 * ndim + 2 * axis + side   (p = px + PX*(py + PY*pz),
+ *                                            side 0 = low neighbour),
+ *   u53  = mix(seed + ((n << 32 | face) + 1) * G) >> 11,
+ *   k~   = first j with u53 < THR[j],  THR[j] = floor(2^53 * W_j / W_{L-1})
+ *          with W_j the running sum of the integer bin weights,
+ *   k    = min(k~, max(0, n - T + 1))   (no level before t = 0 is touched).
+ * Every buffer point of one face uses the same k (uniform-delay class).
+ */
+typedef struct at_delay {
+  int32_t L;                 /* maximum delay levels, k in [0, L-1]; 1..8       */
+  int32_t T;                 /* time levels in the AT combination; 0 = order/2+1;
+                                1 = standard scheme fed with delayed halos     */
+  int32_t mode;              /* AT_DELAY_RNG | AT_DELAY_ZERO | AT_DELAY_HOST | AT_SYNC */
+  int32_t reserved;
+  uint64_t seed;             /* generator key                                   */
+  const uint32_t* weights;   /* host, L integer bin weights (p_j ~ weights[j]);
+                                NULL = uniform                                  */
+  const int8_t* host_delays; /* host, AT_DELAY_HOST: [host_nsteps][P][ndim][2],
+                                each in [0, L-1]; copied at creation            */
+  int64_t host_nsteps;
+} at_delay;
+
+typedef struct at_ctx at_ctx;
+typedef struct at_ens at_ens;
+
+/* Library version string. */
+const char* at_version(void);
+
+/* Bytes of device workspace at_create needs for this problem (256-B aligned
+ * sub-buffers: two field buffers, the integrator history, the face rings of
+ * L+T slots, delay tables, counters and reduction scratch). */
+at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_t* bytes);
+
+/* Create a context on `ws_dev` (>= at_workspace_size bytes, 256-B aligned)
+ * queuing work on `hip_stream` (a hipStream_t; NULL = default stream).
+ * Validates: ndim 1..3; divisibility; PE edge >= 2s on used axes; order in
+ * {2,4,6}; 1 <= L <= 8; 1 <= T <= 4; host delays < L. */
+at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev,
+                    size_t ws_bytes, void* hip_stream, at_ctx** out);
+
+/* Set u^0 (bulk precision, device) and reset the step counter to 0. Every
+ * ring slot is filled with the edge strips of u^0. */
+at_status at_set_state(at_ctx* ctx, const void* u0_dev);
+
+/* Advance nsteps time steps (queued, asynchronous). */
+at_status at_step(at_ctx* ctx, int64_t nsteps);
+
+/* Capture chunks of `chunk` steps into a HIP graph and replay it inside
+ * at_step (0 disables). All per-step quantities are read from a device
+ * counter, so one graph serves every chunk. */
+at_status at_set_graph(at_ctx* ctx, int32_t chunk);
+
+/* Copy the current field u^n (bulk precision) to `u_dev`. */
+at_status at_get_state(at_ctx* ctx, void* u_dev);
+
+/* Current step number n (host-side mirror; no synchronisation). */
+at_status at_get_step(const at_ctx* ctx, int64_t* n);
+
+/* Delays k (after the start-up clamp) of steps n0 .. n0+count-1, computed on
+ * the device with the same routine the step kernel uses:
+ * host_out[count][P][ndim][2] (int8). Synchronises the stream. */
+at_status at_get_delays(at_ctx* ctx, int64_t n0, int64_t count, int8_t* host_out);
+
+/* Error norms of the current field (Sec. 4 averages; Sec. 5.1 error E = u -
+ * u_a), accumulated in double with a fixed reduction order. Reference: the
+ * decaying advected Fourier series of Sec. 5.1 eq. ana_sol with nmodes > 0
+ * (kappa host [nmodes][3], amp, phase host [nmodes]; evaluated at t = n dt as
+ * sum A exp(-alpha |kappa|^2 t) sin(kappa . (x - c t) + phase)), or, with
+ * nmodes == 0, the double field `ref_dev` [nz][ny][nx].
+ * out (host, 9 doubles): mean|E|, rms E, max|E| over all points; mean|E|,
+ * rms E over I_B (points within s of a PE face); mean|E|, rms E over I_I;
+ * |I_B|; |I_I|. Returns AT_EUNSTABLE if any value is not finite.
+ * Synchronises the stream. At most 16 modes. */
+at_status at_norms(at_ctx* ctx, int32_t nmodes, const int32_t* kappa, const double* amp,
+                   const double* phase, const double* ref_dev, double* out);
+
+/* Checkpoint: bytes needed, save to / restore from `ckpt_dev`. The state is
+ * the field, the integrator history, every ring slot and the step counter; a
+ * restored run continues bit for bit. */
+at_status at_checkpoint_size(const at_ctx* ctx, size_t* bytes);
+at_status at_save(at_ctx* ctx, void* ckpt_dev);
+at_status at_load(at_ctx* ctx, const void* ckpt_dev);
+
+/* Release the context (device memory stays with the caller). */
+at_status at_destroy(at_ctx* ctx);
+
+/* Text of the last failure of `ctx`, or of the calling thread for NULL. */
+const char* at_last_error(const at_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATFD_H */

@@ -1,0 +1,157 @@
+"""Asynchrony-tolerant finite differences on MI355X: thin Python binding.
+
+The numerical work is done by the HIP library ``libatfd.so`` through the C
+ABI of ``include/atfd.h``. PyTorch only provides device memory (the caller-
+owned workspace) and the current HIP stream. Nothing here computes any part
+of the method.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ATError, AtDelay, AtProblem, check
+
+__all__ = ["Solver", "ATError", "lib"]
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _as_ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One AT simulation context (``at_create`` .. ``at_destroy``)."""
+
+    def __init__(self, ndim, n, pe, dt, order=2, equation="advdiff", c=(0.0, 0.0, 0.0), alpha=0.0,
+                 integrator="euler", precision="f64", length=2.0 * math.pi, L=1, T=0, mode="rng",
+                 seed=0, weights=None, host_delays=None, device="cuda"):
+        L_ = _lib.load()
+        n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+        pe = tuple(int(v) for v in pe) + (1,) * (3 - len(pe))
+        c = tuple(float(v) for v in c) + (0.0,) * (3 - len(c))
+        self.ndim, self.n, self.pe = ndim, n, pe
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.shape = (n[2], n[1], n[0])
+        self.device = torch.device(device)
+        prob = AtProblem()
+        prob.ndim = ndim
+        for a in range(3):
+            prob.pe[a] = pe[a]
+            prob.n[a] = n[a]
+            prob.c[a] = c[a]
+        prob.length = length
+        prob.alpha = alpha
+        prob.dt = dt
+        prob.equation = _lib.EQUATIONS[equation]
+        prob.order = order
+        prob.integrator = _lib.INTEGRATORS[integrator]
+        prob.precision = _lib.PRECISIONS[precision]
+        dl = AtDelay()
+        dl.L = L
+        dl.T = T
+        dl.mode = _lib.MODES[mode]
+        dl.seed = seed
+        self._keep = []
+        if weights is not None:
+            w = (ctypes.c_uint32 * len(weights))(*[int(v) for v in weights])
+            self._keep.append(w)
+            dl.weights = ctypes.cast(w, ctypes.POINTER(ctypes.c_uint32))
+        if host_delays is not None:
+            hd = np.ascontiguousarray(host_delays, dtype=np.int8)
+            self._keep.append(hd)
+            dl.host_delays = hd.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+            dl.host_nsteps = hd.shape[0]
+        self._prob, self._delay = prob, dl
+        nbytes = ctypes.c_size_t(0)
+        check(L_.at_workspace_size(ctypes.byref(prob), ctypes.byref(dl), ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        check(L_.at_create(ctypes.byref(prob), ctypes.byref(dl), _as_ptr(self.workspace),
+                           nbytes.value, _stream_ptr(), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._lib = L_
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.at_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state
+    def set_state(self, u0):
+        u0 = u0.to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(u0.shape) != self.shape:
+            raise ValueError(f"u0 shape {tuple(u0.shape)} != {self.shape}")
+        self._u0_keep = u0
+        check(self._lib.at_set_state(self._ctx, _as_ptr(u0)), self._ctx)
+
+    def step(self, nsteps=1):
+        check(self._lib.at_step(self._ctx, int(nsteps)), self._ctx)
+
+    def set_graph(self, chunk):
+        check(self._lib.at_set_graph(self._ctx, int(chunk)), self._ctx)
+
+    def state(self):
+        out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        check(self._lib.at_get_state(self._ctx, _as_ptr(out)), self._ctx)
+        return out
+
+    @property
+    def n_step(self):
+        v = ctypes.c_int64(0)
+        check(self._lib.at_get_step(self._ctx, ctypes.byref(v)), self._ctx)
+        return v.value
+
+    def delays(self, n0, count):
+        npe = self.pe[0] * self.pe[1] * self.pe[2]
+        out = np.zeros((count, npe, self.ndim, 2), dtype=np.int8)
+        check(self._lib.at_get_delays(self._ctx, int(n0), int(count),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), self._ctx)
+        return out
+
+    def norms(self, modes=None, ref=None):
+        """Error norms vs Fourier modes [(kappa3, amp, phase)] or a float64 reference field."""
+        out = (ctypes.c_double * 9)()
+        if modes:
+            nm = len(modes)
+            kap = (ctypes.c_int32 * (3 * nm))(*[int(k) for m in modes for k in (tuple(m[0]) + (0, 0, 0))[:3]])
+            amp = (ctypes.c_double * nm)(*[float(m[1]) for m in modes])
+            ph = (ctypes.c_double * nm)(*[float(m[2]) for m in modes])
+            st = self._lib.at_norms(self._ctx, nm, kap, amp, ph, None, out)
+        else:
+            ref = ref.to(device=self.device, dtype=torch.float64).contiguous()
+            st = self._lib.at_norms(self._ctx, 0, None, None, None, _as_ptr(ref), out)
+        check(st, self._ctx)
+        keys = ["l1", "l2", "linf", "l1_b", "l2_b", "l1_i", "l2_i", "n_b", "n_i"]
+        return dict(zip(keys, list(out)))
+
+    # -- checkpoints
+    def checkpoint_size(self):
+        v = ctypes.c_size_t(0)
+        check(self._lib.at_checkpoint_size(self._ctx, ctypes.byref(v)), self._ctx)
+        return v.value
+
+    def save(self, buf=None):
+        if buf is None:
+            buf = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device=self.device)
+        check(self._lib.at_save(self._ctx, _as_ptr(buf)), self._ctx)
+        return buf
+
+    def load(self, buf):
+        check(self._lib.at_load(self._ctx, _as_ptr(buf)), self._ctx)

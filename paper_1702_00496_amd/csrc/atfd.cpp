@@ -1,0 +1,553 @@
+// libatfd host side: argument validation, workspace layout, launch sequencing
+// and HIP graph capture behind the C ABI of include/atfd.h.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "atfd_internal.hpp"
+
+using namespace atfd;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kNormBlocks = 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Integer-only cumulative thresholds floor(2^53 * W_j / W_total).
+bool make_thresholds(int L, const uint32_t* weights, uint64_t* thr) {
+  unsigned __int128 total = 0;
+  for (int j = 0; j < L; ++j) total += weights ? weights[j] : 1u;
+  if (total == 0) return false;
+  unsigned __int128 cum = 0;
+  for (int j = 0; j < L; ++j) {
+    cum += weights ? weights[j] : 1u;
+    thr[j] = static_cast<uint64_t>((cum << 53) / total);
+  }
+  return true;
+}
+
+// Central-difference taps of Sec. 2 eq. general_deriv (the synchronous parts
+// of Tables atschemes-left/right and the textbook sixth-order first
+// derivative), indexed o = -s..s.
+bool cd_taps(int d, int order, double* t) {
+  static const double d1_2[] = {-0.5, 0.0, 0.5};
+  static const double d1_4[] = {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12};
+  static const double d1_6[] = {-1.0 / 60, 9.0 / 60, -45.0 / 60, 0.0, 45.0 / 60, -9.0 / 60, 1.0 / 60};
+  static const double d2_2[] = {1.0, -2.0, 1.0};
+  static const double d2_4[] = {-1.0 / 12, 16.0 / 12, -30.0 / 12, 16.0 / 12, -1.0 / 12};
+  static const double d2_6[] = {2.0 / 180, -27.0 / 180, 270.0 / 180, -490.0 / 180, 270.0 / 180, -27.0 / 180, 2.0 / 180};
+  const double* src = nullptr;
+  if (d == 1) src = order == 2 ? d1_2 : order == 4 ? d1_4 : order == 6 ? d1_6 : nullptr;
+  if (d == 2) src = order == 2 ? d2_2 : order == 4 ? d2_4 : order == 6 ? d2_6 : nullptr;
+  if (!src) return false;
+  for (int i = 0; i <= order; ++i) t[i] = src[i];
+  return true;
+}
+
+struct Layout {
+  size_t field_bytes = 0, ring_bytes = 0, host_tab_bytes = 0;
+  size_t off_u[2] = {0, 0}, off_f[2] = {0, 0}, off_ustar = 0, off_ring = 0, off_sring = 0;
+  size_t off_counter = 0, off_partial = 0, off_result = 0, off_delays = 0, off_host = 0;
+  size_t total = 0;
+  int nslots = 0;
+  int64_t pe_block = 0;
+  int64_t face_off[6] = {0, 0, 0, 0, 0, 0};
+  int nfbuf = 0;
+  bool star = false;
+};
+
+constexpr int64_t kDelayScratch = 1 << 16;   // bytes for at_get_delays chunks
+
+struct Geometry {
+  int ndim, s, T;
+  int64_t n[3];
+  int pe[3], b[3];
+  int64_t npts;
+  int npe;
+  bool f64;
+};
+
+}  // namespace
+
+struct at_ctx {
+  at_problem prob;
+  at_delay delay;
+  Geometry g;
+  Layout lay;
+  StepParams sp;
+  unsigned char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  bool state_set = false;
+  std::string err;
+  // graph replay
+  int graph_chunk = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+at_status fail(at_ctx* ctx, at_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_thread_error = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(ctx, AT_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+at_status validate(const at_problem* p, const at_delay* d, Geometry* g) {
+  if (!p || !d) return fail(nullptr, AT_EINVAL, "null problem or delay");
+  if (p->ndim < 1 || p->ndim > 3) return fail(nullptr, AT_EINVAL, "ndim must be 1..3");
+  if (p->order != 2 && p->order != 4 && p->order != 6)
+    return fail(nullptr, AT_EINVAL, "order must be 2, 4 or 6");
+  if (p->equation != AT_ADVDIFF && p->equation != AT_BURGERS)
+    return fail(nullptr, AT_EINVAL, "unknown equation");
+  if (p->integrator < AT_EULER || p->integrator > AT_RK2)
+    return fail(nullptr, AT_EINVAL, "unknown integrator");
+  if (p->precision != AT_F64 && p->precision != AT_F32_F64B)
+    return fail(nullptr, AT_EINVAL, "unknown precision");
+  if (!(p->dt > 0) || !(p->length > 0)) return fail(nullptr, AT_EINVAL, "dt and length must be > 0");
+  if (d->mode < AT_DELAY_RNG || d->mode > AT_SYNC) return fail(nullptr, AT_EINVAL, "unknown delay mode");
+  g->ndim = p->ndim;
+  g->s = p->order / 2;
+  g->T = d->T == 0 ? p->order / 2 + 1 : d->T;
+  g->f64 = p->precision == AT_F64;
+  if (d->mode != AT_SYNC) {
+    if (d->L < 1 || d->L > kMaxL) return fail(nullptr, AT_EINVAL, "L must be 1..%d", kMaxL);
+    if (g->T < 1 || g->T > kMaxT) return fail(nullptr, AT_EINVAL, "T must be 1..%d", kMaxT);
+  }
+  g->npts = 1;
+  g->npe = 1;
+  for (int a = 0; a < 3; ++a) {
+    g->n[a] = p->n[a];
+    g->pe[a] = p->pe[a];
+    if (a >= p->ndim) {
+      if (p->n[a] != 1 || p->pe[a] != 1)
+        return fail(nullptr, AT_EINVAL, "unused axis %d must have n = 1 and pe = 1", a);
+    }
+    if (p->n[a] < 1 || p->pe[a] < 1 || p->n[a] % p->pe[a])
+      return fail(nullptr, AT_EINVAL, "axis %d: n must be a positive multiple of pe", a);
+    if (p->n[a] > (int64_t(1) << 30)) return fail(nullptr, AT_EINVAL, "axis %d too long", a);
+    g->b[a] = static_cast<int>(p->n[a] / p->pe[a]);
+    if (a < p->ndim && g->b[a] < 2 * g->s)
+      return fail(nullptr, AT_EINVAL, "axis %d: PE edge %d < 2s = %d", a, g->b[a], 2 * g->s);
+    g->npts *= p->n[a];
+    g->npe *= p->pe[a];
+  }
+  if (static_cast<int64_t>(g->b[0]) * g->b[1] > 64 * 64)
+    return fail(nullptr, AT_EINVAL, "PE x*y extent above 4096 points");
+  if (d->mode == AT_DELAY_HOST) {
+    if (!d->host_delays || d->host_nsteps < 1)
+      return fail(nullptr, AT_EINVAL, "AT_DELAY_HOST needs a delay table");
+    const int64_t cnt = d->host_nsteps * g->npe * 2 * g->ndim;
+    for (int64_t i = 0; i < cnt; ++i)
+      if (d->host_delays[i] < 0 || d->host_delays[i] >= d->L)
+        return fail(nullptr, AT_EINVAL, "host delay %d at entry %lld outside [0, L-1]",
+                    int(d->host_delays[i]), (long long)i);
+  }
+  if (d->weights) {
+    for (int j = 0; j < d->L; ++j) (void)d->weights[j];
+  }
+  return AT_OK;
+}
+
+Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
+  Layout l;
+  const size_t w = g.f64 ? 8 : 4;
+  l.field_bytes = static_cast<size_t>(g.npts) * w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  l.off_u[0] = take(l.field_bytes);
+  l.off_u[1] = take(l.field_bytes);
+  l.nfbuf = p->integrator == AT_AB2 ? 1 : p->integrator == AT_AB3 ? 2 : 0;
+  for (int i = 0; i < l.nfbuf; ++i) l.off_f[i] = take(l.field_bytes);
+  l.star = p->integrator == AT_RK2;
+  if (l.star) l.off_ustar = take(l.field_bytes);
+  // face strips of one PE: faces 2a, 2a+1 hold s * (product of the other edges)
+  const int s = g.s;
+  int64_t fo = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t area = 1;
+    for (int c = 0; c < 3; ++c)
+      if (c != a) area *= g.b[c];
+    const int64_t sz = a < g.ndim ? s * area : 0;
+    l.face_off[2 * a] = fo;
+    fo += sz;
+    l.face_off[2 * a + 1] = fo;
+    fo += sz;
+  }
+  l.pe_block = fo;
+  if (d->mode != AT_SYNC) {
+    l.nslots = d->L + g.T;
+    l.ring_bytes = static_cast<size_t>(l.nslots) * g.npe * l.pe_block * w;
+    l.off_ring = take(l.ring_bytes);
+    if (l.star) l.off_sring = take(l.ring_bytes);
+  }
+  l.off_counter = take(2 * sizeof(int64_t));
+  l.off_partial = take(static_cast<size_t>(kNormBlocks) * 8 * sizeof(double));
+  l.off_result = take(16 * sizeof(double));
+  l.off_delays = take(kDelayScratch);
+  if (d->mode == AT_DELAY_HOST) {
+    l.host_tab_bytes = static_cast<size_t>(d->host_nsteps) * g.npe * 2 * g.ndim;
+    l.off_host = take(l.host_tab_bytes);
+  }
+  l.total = off;
+  return l;
+}
+
+void fill_params(at_ctx* c) {
+  StepParams& p = c->sp;
+  std::memset(&p, 0, sizeof(p));
+  const Geometry& g = c->g;
+  p.nx = int(g.n[0]); p.ny = int(g.n[1]); p.nz = int(g.n[2]);
+  p.bx = g.b[0]; p.by = g.b[1]; p.bz = g.b[2];
+  p.px = g.pe[0]; p.py = g.pe[1]; p.pz = g.pe[2];
+  p.ndim = g.ndim;
+  p.npe = g.npe;
+  for (int a = 0; a < 3; ++a) {
+    double t1[2 * kMaxS + 1] = {0}, t2[2 * kMaxS + 1] = {0};
+    cd_taps(1, c->prob.order, t1);
+    cd_taps(2, c->prob.order, t2);
+    const double dx = c->prob.length / double(g.n[a]);
+    for (int o = 0; o <= 2 * g.s; ++o) {
+      p.c1[a][o] = t1[o] / dx;
+      p.c2[a][o] = t2[o] / (dx * dx);
+    }
+    p.vel[a] = a < g.ndim ? c->prob.c[a] : 0.0;
+  }
+  p.alpha = c->prob.alpha;
+  p.dt = c->prob.dt;
+  p.equation = c->prob.equation;
+  p.integrator = c->prob.integrator;
+  p.stage = kStageSingle;
+  p.mode = c->delay.mode;
+  p.L = c->delay.mode == AT_SYNC ? 1 : c->delay.L;
+  p.T = g.T;
+  p.key = c->delay.seed;
+  make_thresholds(p.L, c->delay.weights, p.thr);
+  unsigned char* ws = c->ws;
+  const Layout& l = c->lay;
+  p.host_delays = c->delay.mode == AT_DELAY_HOST ? reinterpret_cast<const int8_t*>(ws + l.off_host) : nullptr;
+  p.ubuf[0] = ws + l.off_u[0];
+  p.ubuf[1] = ws + l.off_u[1];
+  p.fbuf[0] = l.nfbuf > 0 ? ws + l.off_f[0] : nullptr;
+  p.fbuf[1] = l.nfbuf > 1 ? ws + l.off_f[1] : nullptr;
+  p.ustar = l.star ? ws + l.off_ustar : nullptr;
+  p.ring = l.nslots ? ws + l.off_ring : nullptr;
+  p.sring = (l.nslots && l.star) ? ws + l.off_sring : nullptr;
+  p.nslots = l.nslots;
+  p.pe_block = l.pe_block;
+  for (int f = 0; f < 6; ++f) p.face_off[f] = l.face_off[f];
+  p.counter = reinterpret_cast<int64_t*>(ws + l.off_counter);
+  p.advance = 1;
+}
+
+// Queue the kernels of one time step on `st`.
+at_status enqueue_step(at_ctx* c, hipStream_t st) {
+  StepParams p = c->sp;
+  if (c->prob.integrator == AT_RK2) {
+    p.stage = kStageRk1;
+    p.advance = 0;
+    HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
+    p.stage = kStageRk2;
+    p.advance = 1;
+    HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
+  } else {
+    HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
+  }
+  return AT_OK;
+}
+
+void drop_graph(at_ctx* c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* at_version(void) { return "atfd 0.1 (gfx950)"; }
+
+at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_t* bytes) {
+  Geometry g;
+  at_status st = validate(prob, delay, &g);
+  if (st != AT_OK) return st;
+  if (!bytes) return fail(nullptr, AT_EINVAL, "null bytes");
+  *bytes = make_layout(prob, delay, g).total;
+  return AT_OK;
+}
+
+at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev, size_t ws_bytes,
+                    void* hip_stream, at_ctx** out) {
+  if (!out) return fail(nullptr, AT_EINVAL, "null out");
+  *out = nullptr;
+  Geometry g;
+  at_status st = validate(prob, delay, &g);
+  if (st != AT_OK) return st;
+  Layout l = make_layout(prob, delay, g);
+  if (!ws_dev) return fail(nullptr, AT_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign)
+    return fail(nullptr, AT_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  if (ws_bytes < l.total)
+    return fail(nullptr, AT_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, l.total);
+  at_ctx* c = new (std::nothrow) at_ctx();
+  if (!c) return fail(nullptr, AT_ENOMEM, "host allocation failed");
+  c->prob = *prob;
+  c->delay = *delay;
+  c->delay.weights = nullptr;
+  c->delay.host_delays = nullptr;
+  c->g = g;
+  c->lay = l;
+  c->ws = static_cast<unsigned char*>(ws_dev);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  // thresholds are derived from the caller's weights now; keep a private copy
+  {
+    at_delay tmp = *delay;
+    c->delay = tmp;
+    fill_params(c);          // uses delay.weights for the thresholds
+    c->delay.weights = nullptr;
+    c->delay.host_delays = nullptr;
+  }
+  const size_t lds = step_lds_bytes(c->sp, g.f64, g.s);
+  if (lds > kLdsLimit) {
+    delete c;
+    return fail(nullptr, AT_EINVAL, "PE tile needs %zu B of LDS (> %zu)", lds, kLdsLimit);
+  }
+  if (delay->mode == AT_DELAY_HOST) {
+    hipError_t e = hipMemcpyAsync(c->ws + l.off_host, delay->host_delays, l.host_tab_bytes,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, AT_EHIP, "copy of host delays: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = launch_set_counter(c->sp.counter, 0, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, AT_EHIP, "counter init: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return AT_OK;
+}
+
+at_status at_set_state(at_ctx* c, const void* u0_dev) {
+  if (!c || !u0_dev) return fail(c, AT_EINVAL, "null argument");
+  HIP_TRY(c, hipMemcpyAsync(c->sp.ubuf[0], u0_dev, c->lay.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, launch_set_counter(c->sp.counter, 0, c->stream));
+  if (c->delay.mode != AT_SYNC) HIP_TRY(c, launch_publish_all(c->sp, c->g.f64, c->g.s, c->stream));
+  c->n = 0;
+  c->state_set = true;
+  return AT_OK;
+}
+
+at_status at_set_graph(at_ctx* c, int32_t chunk) {
+  if (!c || chunk < 0) return fail(c, AT_EINVAL, "bad graph chunk");
+  if (chunk != c->graph_chunk) drop_graph(c);
+  c->graph_chunk = chunk;
+  return AT_OK;
+}
+
+at_status at_step(at_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, AT_EINVAL, "bad arguments");
+  if (!c->state_set) return fail(c, AT_ESTATE, "at_step before at_set_state");
+  if (c->delay.mode == AT_DELAY_HOST && c->n + nsteps > c->delay.host_nsteps)
+    return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
+  int64_t done = 0;
+  if (c->graph_chunk > 0 && nsteps >= c->graph_chunk) {
+    if (!c->graph_exec) {
+      if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      at_status st = AT_OK;
+      for (int i = 0; i < c->graph_chunk && st == AT_OK; ++i) st = enqueue_step(c, c->cap_stream);
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+      if (st != AT_OK) {
+        if (gr) hipGraphDestroy(gr);
+        return st;
+      }
+      if (e != hipSuccess) return fail(c, AT_EHIP, "graph capture: %s", hipGetErrorString(e));
+      c->graph = gr;
+      HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    }
+    while (nsteps - done >= c->graph_chunk) {
+      HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+      done += c->graph_chunk;
+    }
+  }
+  for (; done < nsteps; ++done) {
+    at_status st = enqueue_step(c, c->stream);
+    if (st != AT_OK) return st;
+  }
+  c->n += nsteps;
+  return AT_OK;
+}
+
+at_status at_get_state(at_ctx* c, void* u_dev) {
+  if (!c || !u_dev) return fail(c, AT_EINVAL, "null argument");
+  if (!c->state_set) return fail(c, AT_ESTATE, "no state");
+  HIP_TRY(c, hipMemcpyAsync(u_dev, c->sp.ubuf[c->n & 1], c->lay.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  return AT_OK;
+}
+
+at_status at_get_step(const at_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(nullptr, AT_EINVAL, "null argument");
+  *n = c->n;
+  return AT_OK;
+}
+
+at_status at_get_delays(at_ctx* c, int64_t n0, int64_t count, int8_t* host_out) {
+  if (!c || !host_out || n0 < 0 || count < 0) return fail(c, AT_EINVAL, "bad arguments");
+  if (c->delay.mode == AT_DELAY_HOST && n0 + count > c->delay.host_nsteps)
+    return fail(c, AT_EINVAL, "beyond the host delay table");
+  const int64_t per = static_cast<int64_t>(c->g.npe) * 2 * c->g.ndim;
+  if (per > kDelayScratch) return fail(c, AT_EINVAL, "too many faces for one step of scratch");
+  const int64_t chunk = kDelayScratch / per;
+  int8_t* scratch = reinterpret_cast<int8_t*>(c->ws + c->lay.off_delays);
+  for (int64_t s = 0; s < count; s += chunk) {
+    const int64_t m = count - s < chunk ? count - s : chunk;
+    HIP_TRY(c, launch_delays(c->sp, n0 + s, m, scratch, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(host_out + s * per, scratch, m * per, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return AT_OK;
+}
+
+at_status at_norms(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double* amp,
+                   const double* phase, const double* ref_dev, double* out) {
+  if (!c || !out) return fail(c, AT_EINVAL, "null argument");
+  if (!c->state_set) return fail(c, AT_ESTATE, "no state");
+  if (nmodes < 0 || nmodes > kMaxModes) return fail(c, AT_EINVAL, "nmodes must be 0..%d", kMaxModes);
+  if (nmodes == 0 && !ref_dev) return fail(c, AT_EINVAL, "need modes or a reference field");
+  if (nmodes > 0 && (!kappa || !amp || !phase)) return fail(c, AT_EINVAL, "null mode arrays");
+  NormParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = int(c->g.n[0]); p.ny = int(c->g.n[1]); p.nz = int(c->g.n[2]);
+  p.bx = c->g.b[0]; p.by = c->g.b[1]; p.bz = c->g.b[2];
+  p.ndim = c->g.ndim;
+  p.s = c->g.s;
+  p.length = c->prob.length;
+  p.alpha = c->prob.alpha;
+  p.dt = c->prob.dt;
+  for (int a = 0; a < 3; ++a) p.vel[a] = a < c->g.ndim ? c->prob.c[a] : 0.0;
+  p.nmodes = nmodes;
+  for (int m = 0; m < nmodes; ++m) {
+    for (int a = 0; a < 3; ++a) p.kap[m][a] = kappa[3 * m + a];
+    p.amp[m] = amp[m];
+    p.phase[m] = phase[m];
+  }
+  p.u = c->sp.ubuf[c->n & 1];
+  p.ref = ref_dev;
+  p.partial = reinterpret_cast<double*>(c->ws + c->lay.off_partial);
+  p.counter = c->sp.counter;
+  double* res = reinterpret_cast<double*>(c->ws + c->lay.off_result);
+  int blocks = static_cast<int>((c->g.npts + 255) / 256);
+  if (blocks > kNormBlocks) blocks = kNormBlocks;
+  HIP_TRY(c, launch_norms(p, c->g.f64, blocks, res, c->stream));
+  double host[10];
+  HIP_TRY(c, hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < 9; ++j) out[j] = host[j];
+  if (host[9] > 0 || !std::isfinite(host[1]))
+    return fail(c, AT_EUNSTABLE, "%.0f non-finite values in the field at step %lld", host[9],
+                (long long)c->n);
+  return AT_OK;
+}
+
+at_status at_checkpoint_size(const at_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(nullptr, AT_EINVAL, "null argument");
+  const Layout& l = c->lay;
+  *bytes = align_up(l.field_bytes) * (1 + l.nfbuf + (l.star ? 1 : 0)) +
+           align_up(l.ring_bytes) * (l.star ? 2 : 1) + kAlign;
+  return AT_OK;
+}
+
+namespace {
+at_status ckpt_copy(at_ctx* c, unsigned char* dst_base, const unsigned char* src_base, bool save) {
+  const Layout& l = c->lay;
+  size_t off = 0;
+  auto cp = [&](size_t ws_off, size_t bytes) -> hipError_t {
+    unsigned char* wsp = c->ws + ws_off;
+    hipError_t e = save ? hipMemcpyAsync(dst_base + off, wsp, bytes, hipMemcpyDeviceToDevice, c->stream)
+                        : hipMemcpyAsync(wsp, src_base + off, bytes, hipMemcpyDeviceToDevice, c->stream);
+    off += align_up(bytes);
+    return e;
+  };
+  // the current solution is stored as slot 0 of the checkpoint
+  HIP_TRY(c, cp(l.off_u[c->n & 1], l.field_bytes));
+  for (int i = 0; i < l.nfbuf; ++i) HIP_TRY(c, cp(l.off_f[i], l.field_bytes));
+  if (l.star) HIP_TRY(c, cp(l.off_ustar, l.field_bytes));
+  if (l.ring_bytes) HIP_TRY(c, cp(l.off_ring, l.ring_bytes));
+  if (l.ring_bytes && l.star) HIP_TRY(c, cp(l.off_sring, l.ring_bytes));
+  HIP_TRY(c, cp(l.off_counter, 2 * sizeof(int64_t)));
+  return AT_OK;
+}
+}  // namespace
+
+at_status at_save(at_ctx* c, void* ckpt_dev) {
+  if (!c || !ckpt_dev) return fail(c, AT_EINVAL, "null argument");
+  if (!c->state_set) return fail(c, AT_ESTATE, "no state");
+  return ckpt_copy(c, static_cast<unsigned char*>(ckpt_dev), nullptr, true);
+}
+
+at_status at_load(at_ctx* c, const void* ckpt_dev) {
+  if (!c || !ckpt_dev) return fail(c, AT_EINVAL, "null argument");
+  // the step number travels in the checkpoint's counter; read it back
+  const Layout& l = c->lay;
+  size_t coff = align_up(l.field_bytes) * (1 + l.nfbuf + (l.star ? 1 : 0)) +
+                align_up(l.ring_bytes) * (l.star ? 2 : 1);
+  int64_t cnt[2];
+  HIP_TRY(c, hipMemcpyAsync(cnt, static_cast<const unsigned char*>(ckpt_dev) + coff, sizeof(cnt),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (cnt[0] < 0) return fail(c, AT_EINVAL, "corrupt checkpoint");
+  c->n = cnt[0];
+  // the saved solution goes to the buffer of its level's parity
+  at_status st = ckpt_copy(c, nullptr, static_cast<const unsigned char*>(ckpt_dev), false);
+  c->state_set = st == AT_OK;
+  return st;
+}
+
+at_status at_destroy(at_ctx* c) {
+  if (!c) return AT_OK;
+  drop_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  delete c;
+  return AT_OK;
+}
+
+const char* at_last_error(const at_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_thread_error.c_str();
+}
+
+}  // extern "C"

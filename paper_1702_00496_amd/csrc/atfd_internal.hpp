@@ -1,0 +1,128 @@
+// Internal declarations of libatfd: device helpers shared by the kernels and
+// the parameter blocks the host passes to them. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/atfd.h"
+
+namespace atfd {
+
+constexpr int kMaxL = 8;
+constexpr int kMaxT = 4;
+constexpr int kMaxS = 3;
+constexpr int kMaxModes = 16;
+constexpr int kThreads = 256;          // workgroup size of the sweep kernels
+constexpr size_t kLdsLimit = 160 * 1024;
+
+// ---------------------------------------------------------------- generator
+// SplitMix64 output finaliser (Steele, Lea & Flood, OOPSLA 2014) used as a
+// counter hash; golden-ratio increment.
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+// Raw delay of (step n, face id) before the start-up clamp: the top 53 bits
+// of the hash are binned by the cumulative thresholds thr[0..L-1]
+// (thr[L-1] = 2^53), as in the bin matching of Sec. 5.1.
+__host__ __device__ inline int raw_delay(uint64_t key, int64_t n, uint32_t face,
+                                         const uint64_t* thr, int L) {
+  const uint64_t ctr = ((static_cast<uint64_t>(n) << 32) | face) + 1ull;
+  const uint64_t u53 = mix64(key + ctr * kGolden) >> 11;
+  int k = 0;
+  while (k < L - 1 && u53 >= thr[k]) ++k;
+  return k;
+}
+
+// No level before t = 0 exists: the delay is clamped so that the oldest level
+// of the T-level combination, n - k - (T - 1), is not negative.
+__host__ __device__ inline int clamp_startup(int k, int64_t n, int T) {
+  const int64_t cap = n - T + 1 > 0 ? n - T + 1 : 0;
+  return k < cap ? k : static_cast<int>(cap);
+}
+
+// Weights over delayed levels n-k-m, m = 0..T-1, of the time-expanded AT
+// schemes (Sec. 3.3 Example 3, eq. cd4-at; Tables atschemes-left/right): the
+// values that extrapolate T successive past levels back to level n, i.e. the
+// Lagrange basis on nodes k, k+1, .., k+T-1 evaluated at 0:
+//   w_m(k) = prod_{i != m} (k + i) / (i - m).
+// For k = 0 this is (1, 0, .., 0): the scheme is the standard CD.
+__host__ __device__ inline void level_weights(int k, int T, double* w) {
+  for (int m = 0; m < T; ++m) {
+    double num = 1.0, den = 1.0;
+    for (int i = 0; i < T; ++i) {
+      if (i == m) continue;
+      num *= static_cast<double>(k + i);
+      den *= static_cast<double>(i - m);
+    }
+    w[m] = num / den;
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+enum Stage : int { kStageSingle = 0, kStageRk1 = 1, kStageRk2 = 2 };
+
+// Everything one sweep needs. Passed by value.
+struct StepParams {
+  // geometry
+  int nx, ny, nz;              // global points
+  int bx, by, bz;              // PE edge
+  int px, py, pz;              // PEs per axis
+  int ndim;
+  int npe;
+  // scheme
+  double c1[3][2 * kMaxS + 1]; // first-derivative taps / dx (per axis)
+  double c2[3][2 * kMaxS + 1]; // second-derivative taps / dx^2
+  double vel[3];
+  double alpha, dt;
+  int equation, integrator, stage;
+  // delays
+  int mode, L, T;
+  uint64_t key;
+  uint64_t thr[kMaxL];
+  const int8_t* host_delays;   // [host_nsteps][npe][ndim][2]
+  // state (element type = bulk precision)
+  void* ubuf[2];               // ping-pong solution, u^n in ubuf[n & 1]
+  void* fbuf[2];               // f history (AB2: fbuf[0]; AB3: f^n -> fbuf[n & 1])
+  void* ustar;                 // RK2 predictor
+  void* ring;                  // u levels: [nslots][npe][pe_block]
+  void* sring;                 // RK2 predictor levels
+  int nslots;
+  int64_t pe_block;            // elements of all face strips of one PE
+  int64_t face_off[6];         // strip offset of face 2*axis+side within a PE block
+  int64_t* counter;            // [0] = step n, [1] = finished workgroups
+  int advance;                 // this launch ends the step: bump the counter
+};
+
+struct NormParams {
+  int nx, ny, nz, bx, by, bz, ndim, s;
+  double length, alpha, dt;
+  double vel[3];
+  int nmodes;
+  int kap[kMaxModes][3];
+  double amp[kMaxModes], phase[kMaxModes];
+  const void* u;
+  const double* ref;
+  double* partial;             // [nblocks][8]
+  int64_t* counter;            // step n (time t = n dt)
+};
+
+// Launchers (step.hip / norms.hip). Return the HIP error of the launch.
+hipError_t launch_step(const StepParams& p, bool f64, int s, hipStream_t st);
+hipError_t launch_publish_all(const StepParams& p, bool f64, int s, hipStream_t st);
+hipError_t launch_set_counter(int64_t* counter, int64_t n, hipStream_t st);
+hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t* out,
+                         hipStream_t st);
+hipError_t launch_norms(const NormParams& p, bool f64, int nblocks, double* result,
+                        hipStream_t st);
+size_t step_lds_bytes(const StepParams& p, bool f64, int s);
+
+}  // namespace atfd

@@ -1,0 +1,466 @@
+// AT finite-difference sweep for gfx950.
+//
+// One workgroup owns one PE (a bx*by*bz brick) and streams its z-planes
+// through a ring of LDS planes. Each LDS plane holds the PE's bx*by points
+// plus an s-wide frame of x/y halo values; the z neighbours are the planes
+// above and below in the LDS ring. Halo values across a PE face are the AT
+// combination of T delayed levels of the neighbour's edge strip (computed in
+// double, Sec. 3.3 eq. cd4-at), so every point then applies the standard
+// central difference (Sec. 2 eq. general_deriv) to LDS data: interior points
+// (set I_I) see only level-n values, buffer-adjacent points (set I_B) see the
+// extrapolated halo exactly as in Tables atschemes-left/right.
+//
+// After the right-hand side (Sec. 5 eq. general) and the time update (Sec. 4.1
+// eqs. time_disc, time_ab2; Heun), the new values of the s-deep edge layers
+// are published into the neighbour-visible ring slot of the new level.
+//
+// Memory traffic per point and step: u^n read once, u^{n+1} written once,
+// f^{n-1} read and f^n written (AB2), plus the face strips (1/b of the points
+// per face and level).
+
+#include "atfd_internal.hpp"
+
+namespace atfd {
+namespace {
+
+// LDS plane slot of z-plane zz (zz >= -S). 3-D sweeps keep 2S+2 planes: the
+// 2S+1 planes of the current stencil plus the one being filled, so a single
+// barrier per plane separates reads from overwrites.
+template <int DIM, int S>
+__device__ inline int slot_of(int zz) {
+  return DIM == 3 ? (zz + S) % (2 * S + 2) : 0;
+}
+
+template <typename Real, int DIM, int S>
+struct Sweep {
+  static constexpr int NSL = DIM == 3 ? 2 * S + 2 : 1;
+
+  const StepParams& p;
+  Real* lds;
+  int pid, qx, qy, qz, x0, y0, z0;
+  int px_stride, plane;     // LDS row stride and plane size
+  int64_t n;
+  const Real* centre;       // field whose level-n values feed the stencil
+  const Real* ring_rd;      // ring the halos come from
+  // per-face delay data (AT) in LDS
+  const double* w;          // [6][kMaxT]
+  const int* lev_slot;      // [6][kMaxT] ring slot of level n-k-m, -1 if weight 0
+  const int* nbr;           // [6] neighbour PE of face
+
+  __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
+                   const int* ls_, const int* nb_)
+      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_) {
+    pid = blockIdx.x;
+    qx = pid % p.px;
+    qy = (pid / p.px) % p.py;
+    qz = pid / (p.px * p.py);
+    x0 = qx * p.bx;
+    y0 = qy * p.by;
+    z0 = qz * p.bz;
+    px_stride = p.bx + 2 * S;
+    plane = (DIM >= 2 ? p.by + 2 * S : 1) * px_stride;
+    const bool rk2 = p.stage == kStageRk2;
+    centre = static_cast<const Real*>(rk2 ? p.ustar : p.ubuf[n & 1]);
+    ring_rd = static_cast<const Real*>(rk2 ? p.sring : p.ring);
+  }
+
+  __device__ int64_t gidx(int x, int y, int z) const {
+    return (static_cast<int64_t>(z) * p.ny + y) * p.nx + x;
+  }
+
+  // Offset of element q of face `face` of PE `pe` in ring slot `slot`.
+  __device__ int64_t ring_off(int slot, int pe, int face, int64_t q) const {
+    return (static_cast<int64_t>(slot) * p.npe + pe) * p.pe_block + p.face_off[face] + q;
+  }
+
+  // Halo value across face f = 2*axis + side, element q of the producer strip.
+  // AT: sum over the T delayed levels, in double. SYNC: the neighbour's
+  // level-n value at global position (gx, gy, gz).
+  __device__ Real halo(int f, int64_t q, int gx, int gy, int gz) const {
+    if (p.mode == AT_SYNC) return centre[gidx(gx, gy, gz)];
+    const int pf = f ^ 1;   // producer face: the opposite side
+    const int nb = nbr[f];
+    double acc = 0.0;
+    for (int m = 0; m < p.T; ++m) {
+      const int sl = lev_slot[f * kMaxT + m];
+      if (sl < 0) continue;   // zero weight (k = 0): exact synchronous value
+      acc += w[f * kMaxT + m] * static_cast<double>(ring_rd[ring_off(sl, nb, pf, q)]);
+    }
+    return static_cast<Real>(acc);
+  }
+
+  __device__ void load_plane(int zz) {
+    Real* P = lds + slot_of<DIM, S>(zz) * plane;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int bx = p.bx, by = p.by, bz = p.bz;
+    if (zz >= 0 && zz < bz) {
+      const int gz = z0 + zz;
+      for (int i = tid; i < bx * by; i += nt) {
+        const int x = i % bx, y = i / bx;
+        P[(DIM >= 2 ? y + S : 0) * px_stride + x + S] = centre[gidx(x0 + x, y0 + y, gz)];
+      }
+      // x halos: [side][y][d], producer strip [z][y][d]
+      for (int h = tid; h < 2 * S * by; h += nt) {
+        const int side = h / (S * by), r = h % (S * by), y = r / S, d = r % S;
+        const int xl = side ? bx + d : d - S;
+        const int gx = (x0 + xl + p.nx) % p.nx;
+        const int64_t q = (static_cast<int64_t>(zz) * by + y) * S + d;
+        P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, q, gx, y0 + y, gz);
+      }
+      if (DIM >= 2) {
+        // y halos: producer strip [z][d][x]
+        for (int h = tid; h < 2 * S * bx; h += nt) {
+          const int side = h / (S * bx), r = h % (S * bx), d = r / bx, x = r % bx;
+          const int yl = side ? by + d : d - S;
+          const int gy = (y0 + yl + p.ny) % p.ny;
+          const int64_t q = (static_cast<int64_t>(zz) * S + d) * bx + x;
+          P[(yl + S) * px_stride + x + S] = halo(2 + side, q, x0 + x, gy, gz);
+        }
+      }
+    } else {
+      // z halo plane: producer strip [d][y][x]
+      const int side = zz < 0 ? 0 : 1;
+      const int d = side ? zz - bz : zz + S;
+      const int gz = (z0 + zz + p.nz) % p.nz;
+      for (int i = tid; i < bx * by; i += nt) {
+        const int x = i % bx, y = i / bx;
+        const int64_t q = (static_cast<int64_t>(d) * by + y) * bx + x;
+        P[(y + S) * px_stride + x + S] = halo(4 + side, q, x0 + x, y0 + y, gz);
+      }
+    }
+  }
+
+  __device__ void compute_plane(int z) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int bx = p.bx, by = p.by, bz = p.bz;
+    const Real* C = lds + slot_of<DIM, S>(z) * plane;
+    Real c1[3][2 * S + 1], c2[3][2 * S + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o <= 2 * S; ++o) {
+        c1[a][o] = static_cast<Real>(p.c1[a][o]);
+        c2[a][o] = static_cast<Real>(p.c2[a][o]);
+      }
+    const Real dt = static_cast<Real>(p.dt), alpha = static_cast<Real>(p.alpha);
+    const Real vx = static_cast<Real>(p.vel[0]), vy = static_cast<Real>(p.vel[1]),
+               vz = static_cast<Real>(p.vel[2]);
+    const int gz = z0 + z;
+    for (int i = tid; i < bx * by; i += nt) {
+      const int x = i % bx, y = i / bx;
+      const int ly = DIM >= 2 ? y + S : 0;
+      const int c_at = ly * px_stride + x + S;
+      const Real u0 = C[c_at];
+      Real g1 = 0, g2 = 0;
+      {
+        Real d1 = 0, d2 = 0;
+#pragma unroll
+        for (int o = -S; o <= S; ++o) {
+          const Real v = C[c_at + o];
+          d1 += c1[0][o + S] * v;
+          d2 += c2[0][o + S] * v;
+        }
+        g1 = p.equation == AT_ADVDIFF ? vx * d1 : d1;
+        g2 = d2;
+      }
+      if (DIM >= 2) {
+        Real d1 = 0, d2 = 0;
+#pragma unroll
+        for (int o = -S; o <= S; ++o) {
+          const Real v = C[c_at + o * px_stride];
+          d1 += c1[1][o + S] * v;
+          d2 += c2[1][o + S] * v;
+        }
+        g1 += p.equation == AT_ADVDIFF ? vy * d1 : d1;
+        g2 += d2;
+      }
+      if (DIM == 3) {
+        Real d1 = 0, d2 = 0;
+#pragma unroll
+        for (int o = -S; o <= S; ++o) {
+          const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at];
+          d1 += c1[2][o + S] * v;
+          d2 += c2[2][o + S] * v;
+        }
+        g1 += p.equation == AT_ADVDIFF ? vz * d1 : d1;
+        g2 += d2;
+      }
+      const Real f = p.equation == AT_ADVDIFF ? alpha * g2 - g1 : alpha * g2 - u0 * g1;
+      const int64_t g = gidx(x0 + x, y0 + y, gz);
+      Real un;
+      if (p.stage == kStageRk1) {
+        un = u0 + dt * f;
+        static_cast<Real*>(p.ustar)[g] = un;
+      } else if (p.stage == kStageRk2) {
+        const Real uold = static_cast<const Real*>(p.ubuf[n & 1])[g];
+        un = Real(0.5) * (uold + u0) + (Real(0.5) * dt) * f;
+        static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
+      } else {
+        if (p.integrator == AT_EULER || n == 0) {
+          un = u0 + dt * f;
+          if (p.integrator == AT_AB2) static_cast<Real*>(p.fbuf[0])[g] = f;
+          if (p.integrator == AT_AB3) static_cast<Real*>(p.fbuf[0])[g] = f;
+        } else if (p.integrator == AT_AB2 || n == 1) {
+          // AB3 at n = 1 takes an AB2 step; f^{n-1} is in fbuf[0] either way
+          Real* fb = static_cast<Real*>(p.fbuf[0]);
+          const Real fo = fb[g];
+          un = u0 + dt * (Real(1.5) * f - Real(0.5) * fo);
+          if (p.integrator == AT_AB2) {
+            fb[g] = f;
+          } else {
+            static_cast<Real*>(p.fbuf[1])[g] = f;   // f^1 -> fbuf[1]
+          }
+        } else {
+          // AB3, n >= 2: f^{n-1} in fbuf[(n-1)&1], f^{n-2} in fbuf[n&1]
+          Real* fm1 = static_cast<Real*>(p.fbuf[(n - 1) & 1]);
+          Real* fm2 = static_cast<Real*>(p.fbuf[n & 1]);
+          const Real a1 = fm1[g], a2 = fm2[g];
+          un = u0 + dt * ((Real(23) * f - Real(16) * a1 + Real(5) * a2) / Real(12));
+          fm2[g] = f;
+        }
+        static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
+      }
+      if (p.mode != AT_SYNC) publish(x, y, z, un);
+    }
+  }
+
+  // Write a new edge value into the ring slot of its level: u^{n+1} after a
+  // full step, u*^n after the first RK2 stage.
+  __device__ void publish(int x, int y, int z, Real v) const {
+    const bool rk1 = p.stage == kStageRk1;
+    Real* R = static_cast<Real*>(rk1 ? p.sring : p.ring);
+    const int slot = static_cast<int>((rk1 ? n : n + 1) % p.nslots);
+    const int bx = p.bx, by = p.by, bz = p.bz;
+    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * by + y) * S + x)] = v;
+    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * by + y) * S + x - (bx - S))] = v;
+    if (DIM >= 2) {
+      if (y < S) R[ring_off(slot, pid, 2, (static_cast<int64_t>(z) * S + y) * bx + x)] = v;
+      if (y >= by - S) R[ring_off(slot, pid, 3, (static_cast<int64_t>(z) * S + y - (by - S)) * bx + x)] = v;
+    }
+    if (DIM == 3) {
+      if (z < S) R[ring_off(slot, pid, 4, (static_cast<int64_t>(z) * by + y) * bx + x)] = v;
+      if (z >= bz - S) R[ring_off(slot, pid, 5, (static_cast<int64_t>(z - (bz - S)) * by + y) * bx + x)] = v;
+    }
+  }
+};
+
+// Neighbour PE across face f = 2*axis + side (periodic).
+__device__ inline int neighbour(const StepParams& p, int pid, int f) {
+  int q[3] = {pid % p.px, (pid / p.px) % p.py, pid / (p.px * p.py)};
+  const int ext[3] = {p.px, p.py, p.pz};
+  const int a = f >> 1;
+  q[a] = (q[a] + ((f & 1) ? 1 : ext[a] - 1)) % ext[a];
+  return q[0] + p.px * (q[1] + p.py * q[2]);
+}
+
+// Delay of face f at step n (after the clamp), from the generator, zero or the
+// host table.
+__device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n) {
+  int k = 0;
+  if (p.mode == AT_DELAY_RNG) {
+    k = raw_delay(p.key, n, static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L);
+  } else if (p.mode == AT_DELAY_HOST) {
+    k = p.host_delays[(n * p.npe + pid) * (2 * p.ndim) + f];
+  }
+  return clamp_startup(k, n, p.T);
+}
+
+template <typename Real, int DIM, int S>
+__global__ __launch_bounds__(kThreads) void at_step_kernel(StepParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Real* lds = reinterpret_cast<Real*>(smem_raw);
+  __shared__ double s_w[6 * kMaxT];
+  __shared__ int s_slot[6 * kMaxT];
+  __shared__ int s_nbr[6];
+
+  const int64_t n = p.counter[0];
+  const int pid = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < 2 * DIM) {
+    const int f = tid;
+    s_nbr[f] = neighbour(p, pid, f);
+    if (p.mode != AT_SYNC) {
+      const int k = face_delay(p, pid, f, n);
+      double w[kMaxT];
+      level_weights(k, p.T, w);
+      for (int m = 0; m < kMaxT; ++m) {
+        const bool live = m < p.T && w[m] != 0.0;
+        s_w[f * kMaxT + m] = live ? w[m] : 0.0;
+        s_slot[f * kMaxT + m] = live ? static_cast<int>((n - k - m) % p.nslots) : -1;
+      }
+    }
+  }
+  __syncthreads();
+
+  Sweep<Real, DIM, S> sw(p, lds, n, s_w, s_slot, s_nbr);
+  if (DIM == 3) {
+    for (int zz = -S; zz < S; ++zz) sw.load_plane(zz);
+    for (int z = 0; z < p.bz; ++z) {
+      sw.load_plane(z + S);
+      __syncthreads();
+      sw.compute_plane(z);
+    }
+  } else {
+    sw.load_plane(0);
+    __syncthreads();
+    sw.compute_plane(0);
+  }
+
+  if (p.advance) {
+    // The last workgroup to finish advances the step counter. Every other
+    // workgroup has read n before its own increment below.
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const unsigned long long prev =
+          atomicAdd(reinterpret_cast<unsigned long long*>(&p.counter[1]), 1ull);
+      if (prev == static_cast<unsigned long long>(gridDim.x) - 1ull) {
+        p.counter[1] = 0;
+        p.counter[0] = n + 1;
+        __threadfence();
+      }
+    }
+  }
+}
+
+// Fill every ring slot (and the predictor ring) with the edge strips of the
+// current field u^0.
+template <typename Real, int DIM, int S>
+__global__ __launch_bounds__(kThreads) void publish_all_kernel(StepParams p) {
+  const int pid = blockIdx.x;
+  const int qx = pid % p.px, qy = (pid / p.px) % p.py, qz = pid / (p.px * p.py);
+  const int x0 = qx * p.bx, y0 = qy * p.by, z0 = qz * p.bz;
+  const Real* u = static_cast<const Real*>(p.ubuf[0]);
+  Real* R = static_cast<Real*>(p.ring);
+  Real* SR = static_cast<Real*>(p.sring);
+  const int64_t npts = static_cast<int64_t>(p.bx) * p.by * p.bz;
+  for (int64_t i = threadIdx.x; i < npts; i += blockDim.x) {
+    const int x = static_cast<int>(i % p.bx);
+    const int y = static_cast<int>((i / p.bx) % p.by);
+    const int z = static_cast<int>(i / (static_cast<int64_t>(p.bx) * p.by));
+    int face[6];
+    int64_t q[6];
+    int nf = 0;
+    if (x < S) { face[nf] = 0; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x; }
+    if (x >= p.bx - S) { face[nf] = 1; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x - (p.bx - S); }
+    if (DIM >= 2 && y < S) { face[nf] = 2; q[nf++] = (static_cast<int64_t>(z) * S + y) * p.bx + x; }
+    if (DIM >= 2 && y >= p.by - S) { face[nf] = 3; q[nf++] = (static_cast<int64_t>(z) * S + y - (p.by - S)) * p.bx + x; }
+    if (DIM == 3 && z < S) { face[nf] = 4; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * p.bx + x; }
+    if (DIM == 3 && z >= p.bz - S) { face[nf] = 5; q[nf++] = (static_cast<int64_t>(z - (p.bz - S)) * p.by + y) * p.bx + x; }
+    if (!nf) continue;
+    const Real v = u[(static_cast<int64_t>(z0 + z) * p.ny + y0 + y) * p.nx + x0 + x];
+    for (int j = 0; j < nf; ++j)
+      for (int sl = 0; sl < p.nslots; ++sl) {
+        const int64_t off = (static_cast<int64_t>(sl) * p.npe + pid) * p.pe_block + p.face_off[face[j]] + q[j];
+        R[off] = v;
+        if (SR) SR[off] = v;
+      }
+  }
+}
+
+__global__ void set_counter_kernel(int64_t* counter, int64_t n) {
+  if (threadIdx.x == 0) {
+    counter[0] = n;
+    counter[1] = 0;
+  }
+}
+
+// Delay table [count][npe][2*ndim] of steps n0.. with the sweep's routine.
+__global__ void delays_kernel(StepParams p, int64_t n0, int64_t count, int8_t* out) {
+  const int64_t per = static_cast<int64_t>(p.npe) * 2 * p.ndim;
+  const int64_t total = count * per;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t n = n0 + i / per;
+    const int r = static_cast<int>(i % per);
+    const int pid = r / (2 * p.ndim), f = r % (2 * p.ndim);
+    out[i] = p.mode == AT_SYNC ? 0 : static_cast<int8_t>(face_delay(p, pid, f, n));
+  }
+}
+
+template <typename Real, int DIM, int S>
+size_t lds_bytes_t(const StepParams& p) {
+  const int nsl = DIM == 3 ? 2 * S + 2 : 1;
+  const size_t plane = static_cast<size_t>(DIM >= 2 ? p.by + 2 * S : 1) * (p.bx + 2 * S);
+  return nsl * plane * sizeof(Real);
+}
+
+template <typename Real, int DIM, int S>
+hipError_t launch_t(const StepParams& p, hipStream_t st) {
+  const size_t lds = lds_bytes_t<Real, DIM, S>(p);
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S>), dim3(p.npe), dim3(kThreads), lds, st, p);
+  return hipGetLastError();
+}
+
+template <typename Real, int DIM, int S>
+hipError_t launch_pub_t(const StepParams& p, hipStream_t st) {
+  hipLaunchKernelGGL((publish_all_kernel<Real, DIM, S>), dim3(p.npe), dim3(kThreads), 0, st, p);
+  return hipGetLastError();
+}
+
+template <typename Real, int DIM>
+hipError_t dispatch_s(const StepParams& p, int s, hipStream_t st, bool pub) {
+  switch (s) {
+    case 1: return pub ? launch_pub_t<Real, DIM, 1>(p, st) : launch_t<Real, DIM, 1>(p, st);
+    case 2: return pub ? launch_pub_t<Real, DIM, 2>(p, st) : launch_t<Real, DIM, 2>(p, st);
+    case 3: return pub ? launch_pub_t<Real, DIM, 3>(p, st) : launch_t<Real, DIM, 3>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t dispatch_dim(const StepParams& p, int s, hipStream_t st, bool pub) {
+  switch (p.ndim) {
+    case 1: return dispatch_s<Real, 1>(p, s, st, pub);
+    case 2: return dispatch_s<Real, 2>(p, s, st, pub);
+    case 3: return dispatch_s<Real, 3>(p, s, st, pub);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+size_t lds_dim(const StepParams& p, int s) {
+  switch (p.ndim * 4 + s) {
+    case 5: return lds_bytes_t<Real, 1, 1>(p);
+    case 6: return lds_bytes_t<Real, 1, 2>(p);
+    case 7: return lds_bytes_t<Real, 1, 3>(p);
+    case 9: return lds_bytes_t<Real, 2, 1>(p);
+    case 10: return lds_bytes_t<Real, 2, 2>(p);
+    case 11: return lds_bytes_t<Real, 2, 3>(p);
+    case 13: return lds_bytes_t<Real, 3, 1>(p);
+    case 14: return lds_bytes_t<Real, 3, 2>(p);
+    case 15: return lds_bytes_t<Real, 3, 3>(p);
+  }
+  return ~size_t(0);
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepParams& p, bool f64, int s, hipStream_t st) {
+  return f64 ? dispatch_dim<double>(p, s, st, false) : dispatch_dim<float>(p, s, st, false);
+}
+
+hipError_t launch_publish_all(const StepParams& p, bool f64, int s, hipStream_t st) {
+  return f64 ? dispatch_dim<double>(p, s, st, true) : dispatch_dim<float>(p, s, st, true);
+}
+
+size_t step_lds_bytes(const StepParams& p, bool f64, int s) {
+  return f64 ? lds_dim<double>(p, s) : lds_dim<float>(p, s);
+}
+
+hipError_t launch_set_counter(int64_t* counter, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, st, counter, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t* out,
+                         hipStream_t st) {
+  const int64_t total = count * p.npe * 2 * p.ndim;
+  int blocks = static_cast<int>((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(delays_kernel, dim3(blocks), dim3(256), 0, st, p, n0, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace atfd

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/atfd.h declares, and validates arguments without a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "atfd.h")
+LIB = os.path.join(ROOT, "paper_1702_00496_amd", "libatfd.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(at_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libatfd.so is not built (python -m paper_1702_00496_amd.build)")
+    from paper_1702_00496_amd import _lib as L
+    return L, L.load()
+
+
+def test_every_declared_function_is_exported():
+    _, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    L, _ = _lib()
+    assert set(declared_functions()) <= set(L.SIGNATURES), set(declared_functions()) - set(L.SIGNATURES)
+
+
+def _prob(L, **kw):
+    p = L.AtProblem()
+    p.ndim = kw.get("ndim", 3)
+    for a in range(3):
+        p.n[a] = kw.get("n", (64, 64, 64))[a]
+        p.pe[a] = kw.get("pe", (2, 2, 2))[a]
+    p.length = 2 * math.pi
+    p.alpha = 0.1
+    p.dt = 1e-4
+    p.order = kw.get("order", 4)
+    p.integrator = L.INTEGRATORS[kw.get("integrator", "ab2")]
+    p.precision = L.PRECISIONS[kw.get("precision", "f64")]
+    return p
+
+
+def _delay(mod, **kw):
+    d = mod.AtDelay()
+    d.L = kw.get("L", 4)
+    d.T = kw.get("T", 0)
+    d.mode = mod.MODES[kw.get("mode", "rng")]
+    return d
+
+
+def _size(L, lib, p, d):
+    v = ctypes.c_size_t(0)
+    st = lib.at_workspace_size(ctypes.byref(p), ctypes.byref(d), ctypes.byref(v))
+    return st, v.value
+
+
+def test_workspace_size_accounts_for_fields_and_rings():
+    L, lib = _lib()
+    p, d = _prob(L), _delay(L)
+    st, nb = _size(L, lib, p, d)
+    assert st == L.AT_OK
+    npts = 64 ** 3
+    # two solution buffers + one AB2 history at 8 bytes, plus L+T ring slots of
+    # 6 faces * s * 32^2 per PE for 8 PEs
+    ring = (4 + 3) * 8 * 6 * 2 * 32 * 32 * 8
+    assert nb >= 3 * npts * 8 + ring
+    assert nb < 3 * npts * 8 + ring + 4 * 2 ** 20
+    d.mode = L.MODES["sync"]
+    st, nb2 = _size(L, lib, p, d)
+    assert st == L.AT_OK and nb2 < nb - ring + 2 ** 20
+
+
+@pytest.mark.parametrize("kw,dkw", [
+    (dict(n=(64, 64, 60), pe=(2, 2, 8)), {}),           # 60 % 8 != 0
+    (dict(n=(64, 64, 64), pe=(2, 2, 32)), {}),          # PE edge 2 < 2s
+    (dict(order=3), {}),
+    (dict(ndim=4), {}),
+    (dict(ndim=1, n=(64, 2, 1), pe=(2, 1, 1)), {}),     # unused axis with n > 1
+    ({}, dict(L=9)),
+    ({}, dict(L=0)),
+    ({}, dict(T=5)),
+    (dict(n=(256, 256, 8), pe=(2, 2, 1)), {}),          # PE x*y extent too large
+])
+def test_invalid_arguments_are_rejected(kw, dkw):
+    L, lib = _lib()
+    st, _ = _size(L, lib, _prob(L, **kw), _delay(L, **dkw))
+    assert st == L.AT_EINVAL
+    assert lib.at_last_error(None)
+
+
+def test_host_delay_table_is_validated():
+    L, lib = _lib()
+    import numpy as np
+    p = _prob(L, ndim=1, n=(64, 1, 1), pe=(4, 1, 1), order=2)
+    d = _delay(L, mode="host")
+    d.L = 3
+    tab = np.zeros((5, 4, 1, 2), dtype=np.int8)
+    tab[2, 1, 0, 1] = 3          # >= L
+    d.host_delays = tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+    d.host_nsteps = 5
+    st, _ = _size(L, lib, p, d)
+    assert st == L.AT_EINVAL
+    tab[2, 1, 0, 1] = 2
+    st, _ = _size(L, lib, p, d)
+    assert st == L.AT_OK
