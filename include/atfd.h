@@ -142,6 +142,21 @@ at_status at_step(at_ctx* ctx, int64_t nsteps);
  * counter, so one graph serves every chunk. */
 at_status at_set_graph(at_ctx* ctx, int32_t chunk);
 
+/* Tuning of the sweep schedule. `depth` = z-planes of reads kept in flight
+ * per thread by the 3-D kernel for 32 x 32 PE cross-sections (1, 2 or 4;
+ * 0 = the library default). Every depth computes bit-identical results; only
+ * speed differs. Other shapes ignore it. */
+at_status at_set_tuning(at_ctx* ctx, int32_t depth);
+at_status at_get_tuning(const at_ctx* ctx, int32_t* depth);
+
+/* Autotune: time `nsteps` steps for every candidate schedule, keep the
+ * fastest and return it in *best_depth (ms per step of each candidate in
+ * ms_out[3] for depths 1, 2, 4; may be NULL). The field and all history are
+ * saved to `scratch_dev` (>= at_checkpoint_size bytes) first and restored
+ * afterwards, so the simulation is unchanged. Synchronises the stream. */
+at_status at_autotune(at_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t nsteps,
+                      int32_t* best_depth, double* ms_out);
+
 /* Copy the current field u^n (bulk precision) to `u_dev`. */
 at_status at_get_state(at_ctx* ctx, void* u_dev);
 

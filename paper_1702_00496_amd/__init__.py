@@ -107,6 +107,24 @@ class Solver:
     def set_graph(self, chunk):
         check(self._lib.at_set_graph(self._ctx, int(chunk)), self._ctx)
 
+    def set_tuning(self, depth):
+        check(self._lib.at_set_tuning(self._ctx, int(depth)), self._ctx)
+
+    def tuning(self):
+        v = ctypes.c_int32(0)
+        check(self._lib.at_get_tuning(self._ctx, ctypes.byref(v)), self._ctx)
+        return v.value
+
+    def autotune(self, nsteps=10):
+        """Time every schedule candidate on the current state (restored
+        afterwards) and keep the fastest. Returns (depth, {depth: ms/step})."""
+        scratch = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device=self.device)
+        best = ctypes.c_int32(0)
+        ms = (ctypes.c_double * 3)()
+        check(self._lib.at_autotune(self._ctx, _as_ptr(scratch), scratch.numel(), int(nsteps),
+                                    ctypes.byref(best), ms), self._ctx)
+        return best.value, {d: ms[i] for i, d in enumerate((1, 2, 4)) if ms[i] >= 0}
+
     def state(self):
         out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
         check(self._lib.at_get_state(self._ctx, _as_ptr(out)), self._ctx)

@@ -78,6 +78,9 @@ SIGNATURES = {
     "at_set_state": (I32, [P, P]),
     "at_step": (I32, [P, I64]),
     "at_set_graph": (I32, [P, I32]),
+    "at_set_tuning": (I32, [P, I32]),
+    "at_get_tuning": (I32, [P, ctypes.POINTER(I32)]),
+    "at_autotune": (I32, [P, P, SZ, I32, ctypes.POINTER(I32), DP]),
     "at_get_state": (I32, [P, P]),
     "at_get_step": (I32, [P, ctypes.POINTER(I64)]),
     "at_get_delays": (I32, [P, I64, I64, ctypes.POINTER(ctypes.c_int8)]),

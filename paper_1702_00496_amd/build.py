@@ -1,8 +1,12 @@
 """Compile libatfd.so (HIP, gfx950) in-tree with hipcc.
 
-Run as ``python -m paper_1702_00496_amd.build``; ``__graft_entry__.build()``
-calls :func:`build`.
+Every source is compiled to an object in parallel, then linked into
+``paper_1702_00496_amd/libatfd.so``. Run as
+``python -m paper_1702_00496_amd.build``; ``__graft_entry__.build()`` calls
+:func:`build`.
 """
+import concurrent.futures as cf
+import glob
 import os
 import shutil
 import subprocess
@@ -10,11 +14,12 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libatfd.so")
-SOURCES = ["atfd.cpp", "step.hip", "norms.hip", "ensemble.hip", "adjoint.hip"]
+INCLUDE = os.path.join(HERE, "..", "include")
 
-HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared",
+COMMON = [
+    "-O3", "-std=c++17", "-fPIC",
     "--offload-arch=gfx950",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -29,16 +34,41 @@ def hipcc():
     return path
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [hipcc()] + COMMON + ["-I", INCLUDE, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return obj, res
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    objs = []
+    errors = []
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for obj, res in ex.map(lambda s: _compile(s, verbose), srcs):
+            objs.append(obj)
+            if res.returncode != 0:
+                errors.append(res.stdout + res.stderr)
+    if errors:
+        sys.stderr.write("\n".join(errors))
+        raise RuntimeError("hipcc failed compiling libatfd sources")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libatfd.so")
+        raise RuntimeError("hipcc failed linking libatfd.so")
     os.replace(tmp, LIB)
     return LIB
 

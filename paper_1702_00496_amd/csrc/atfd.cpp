@@ -230,17 +230,24 @@ void fill_params(at_ctx* c) {
   p.px = g.pe[0]; p.py = g.pe[1]; p.pz = g.pe[2];
   p.ndim = g.ndim;
   p.npe = g.npe;
+  p.s = g.s;
   for (int a = 0; a < 3; ++a) {
     double t1[2 * kMaxS + 1] = {0}, t2[2 * kMaxS + 1] = {0};
     cd_taps(1, c->prob.order, t1);
     cd_taps(2, c->prob.order, t2);
     const double dx = c->prob.length / double(g.n[a]);
+    p.vel[a] = a < g.ndim ? c->prob.c[a] : 0.0;
     for (int o = 0; o <= 2 * g.s; ++o) {
       p.c1[a][o] = t1[o] / dx;
       p.c2[a][o] = t2[o] / (dx * dx);
+      p.d2a[a][o] = c->prob.alpha * p.c2[a][o];
+      p.kad[a][o] = p.d2a[a][o] - p.vel[a] * p.c1[a][o];
+      p.c1f[a][o] = static_cast<float>(p.c1[a][o]);
+      p.d2af[a][o] = static_cast<float>(p.d2a[a][o]);
+      p.kadf[a][o] = static_cast<float>(p.kad[a][o]);
     }
-    p.vel[a] = a < g.ndim ? c->prob.c[a] : 0.0;
   }
+  p.depth = fast3d_default_depth(g.f64);
   p.alpha = c->prob.alpha;
   p.dt = c->prob.dt;
   p.equation = c->prob.equation;
@@ -409,6 +416,75 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
     if (st != AT_OK) return st;
   }
   c->n += nsteps;
+  return AT_OK;
+}
+
+at_status at_set_tuning(at_ctx* c, int32_t depth) {
+  if (!c) return fail(nullptr, AT_EINVAL, "null context");
+  if (depth == 0) depth = fast3d_default_depth(c->g.f64);
+  if (depth != 1 && depth != 2 && depth != 4) return fail(c, AT_EINVAL, "depth must be 1, 2 or 4");
+  if (depth != c->sp.depth) drop_graph(c);
+  c->sp.depth = depth;
+  return AT_OK;
+}
+
+at_status at_get_tuning(const at_ctx* c, int32_t* depth) {
+  if (!c || !depth) return fail(nullptr, AT_EINVAL, "null argument");
+  *depth = c->sp.depth;
+  return AT_OK;
+}
+
+at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_t nsteps,
+                      int32_t* best_depth, double* ms_out) {
+  if (!c || !scratch_dev || nsteps < 1) return fail(c, AT_EINVAL, "bad arguments");
+  if (!c->state_set) return fail(c, AT_ESTATE, "autotune before at_set_state");
+  size_t need = 0;
+  at_checkpoint_size(c, &need);
+  if (scratch_bytes < need) return fail(c, AT_ENOMEM, "scratch %zu < %zu bytes", scratch_bytes, need);
+  if (c->delay.mode == AT_DELAY_HOST && c->n + nsteps > c->delay.host_nsteps)
+    return fail(c, AT_EINVAL, "host delay table too short for autotuning");
+  at_status st = at_save(c, scratch_dev);
+  if (st != AT_OK) return st;
+  const int cand[3] = {1, 2, 4};
+  const int keep = c->sp.depth, keep_chunk = c->graph_chunk;
+  double best_ms = 1e300;
+  int best = keep;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  c->graph_chunk = 0;
+  for (int i = 0; i < 3; ++i) {
+    double ms = -1.0;
+    StepParams trial = c->sp;
+    trial.depth = cand[i];
+    if (fast3d_applies(trial, c->g.f64)) {
+      c->sp.depth = cand[i];
+      st = at_load(c, scratch_dev);
+      if (st == AT_OK) st = enqueue_step(c, c->stream);          // warm-up
+      if (st == AT_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = AT_EHIP;
+      for (int k = 0; k < nsteps && st == AT_OK; ++k) st = enqueue_step(c, c->stream);
+      if (st == AT_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = AT_EHIP;
+      if (st == AT_OK && hipEventSynchronize(e1) != hipSuccess) st = AT_EHIP;
+      float t = 0.f;
+      if (st == AT_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / nsteps;
+      if (st != AT_OK) break;
+      if (ms >= 0 && ms < best_ms) {
+        best_ms = ms;
+        best = cand[i];
+      }
+    }
+    if (ms_out) ms_out[i] = ms;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->graph_chunk = keep_chunk;
+  c->sp.depth = keep;
+  at_status st2 = at_load(c, scratch_dev);
+  if (st != AT_OK) return st;
+  if (st2 != AT_OK) return st2;
+  if (best != keep) drop_graph(c);
+  c->sp.depth = best;
+  if (best_depth) *best_depth = best;
   return AT_OK;
 }
 

@@ -78,9 +78,15 @@ struct StepParams {
   int px, py, pz;              // PEs per axis
   int ndim;
   int npe;
+  int s;                       // stencil half-width (order / 2)
   // scheme
   double c1[3][2 * kMaxS + 1]; // first-derivative taps / dx (per axis)
   double c2[3][2 * kMaxS + 1]; // second-derivative taps / dx^2
+  // folded taps for the 32 x 32 path: kad = alpha c2 - vel c1 (advection-
+  // diffusion, one coefficient per tap), d2a = alpha c2 (Burgers), in double
+  // and float
+  double kad[3][2 * kMaxS + 1], d2a[3][2 * kMaxS + 1];
+  float kadf[3][2 * kMaxS + 1], d2af[3][2 * kMaxS + 1], c1f[3][2 * kMaxS + 1];
   double vel[3];
   double alpha, dt;
   int equation, integrator, stage;
@@ -100,6 +106,7 @@ struct StepParams {
   int64_t face_off[6];         // strip offset of face 2*axis+side within a PE block
   int64_t* counter;            // [0] = step n, [1] = finished workgroups
   int advance;                 // this launch ends the step: bump the counter
+  int depth;                   // 3-D 32x32 path: planes of reads in flight (1, 2, 4); 0 = generic kernel
 };
 
 struct NormParams {
@@ -124,5 +131,9 @@ hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t*
 hipError_t launch_norms(const NormParams& p, bool f64, int nblocks, double* result,
                         hipStream_t st);
 size_t step_lds_bytes(const StepParams& p, bool f64, int s);
+// 3-D sweep for 32 x 32 PE cross-sections (step3d_fast.hip)
+bool fast3d_applies(const StepParams& p, bool f64);
+int fast3d_default_depth(bool f64);
+hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st);
 
 }  // namespace atfd

@@ -99,12 +99,12 @@ struct Sweep {
         const int x = i % bx, y = i / bx;
         P[(DIM >= 2 ? y + S : 0) * px_stride + x + S] = centre[gidx(x0 + x, y0 + y, gz)];
       }
-      // x halos: [side][y][d], producer strip [z][y][d]
+      // x halos: [side][d][y], producer strip [z][d][y]
       for (int h = tid; h < 2 * S * by; h += nt) {
-        const int side = h / (S * by), r = h % (S * by), y = r / S, d = r % S;
+        const int side = h / (S * by), r = h % (S * by), d = r / by, y = r % by;
         const int xl = side ? bx + d : d - S;
         const int gx = (x0 + xl + p.nx) % p.nx;
-        const int64_t q = (static_cast<int64_t>(zz) * by + y) * S + d;
+        const int64_t q = (static_cast<int64_t>(zz) * S + d) * by + y;
         P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, q, gx, y0 + y, gz);
       }
       if (DIM >= 2) {
@@ -151,12 +151,15 @@ struct Sweep {
       const int ly = DIM >= 2 ? y + S : 0;
       const int c_at = ly * px_stride + x + S;
       const Real u0 = C[c_at];
+      // difference form: the taps of each derivative sum to zero, so each
+      // neighbour enters as (v - u0), which keeps float rounding small
       Real g1 = 0, g2 = 0;
       {
         Real d1 = 0, d2 = 0;
 #pragma unroll
         for (int o = -S; o <= S; ++o) {
-          const Real v = C[c_at + o];
+          if (o == 0) continue;
+          const Real v = C[c_at + o] - u0;
           d1 += c1[0][o + S] * v;
           d2 += c2[0][o + S] * v;
         }
@@ -167,7 +170,8 @@ struct Sweep {
         Real d1 = 0, d2 = 0;
 #pragma unroll
         for (int o = -S; o <= S; ++o) {
-          const Real v = C[c_at + o * px_stride];
+          if (o == 0) continue;
+          const Real v = C[c_at + o * px_stride] - u0;
           d1 += c1[1][o + S] * v;
           d2 += c2[1][o + S] * v;
         }
@@ -178,7 +182,8 @@ struct Sweep {
         Real d1 = 0, d2 = 0;
 #pragma unroll
         for (int o = -S; o <= S; ++o) {
-          const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at];
+          if (o == 0) continue;
+          const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at] - u0;
           d1 += c1[2][o + S] * v;
           d2 += c2[2][o + S] * v;
         }
@@ -231,8 +236,8 @@ struct Sweep {
     Real* R = static_cast<Real*>(rk1 ? p.sring : p.ring);
     const int slot = static_cast<int>((rk1 ? n : n + 1) % p.nslots);
     const int bx = p.bx, by = p.by, bz = p.bz;
-    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * by + y) * S + x)] = v;
-    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * by + y) * S + x - (bx - S))] = v;
+    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * S + x) * by + y)] = v;
+    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * S + x - (bx - S)) * by + y)] = v;
     if (DIM >= 2) {
       if (y < S) R[ring_off(slot, pid, 2, (static_cast<int64_t>(z) * S + y) * bx + x)] = v;
       if (y >= by - S) R[ring_off(slot, pid, 3, (static_cast<int64_t>(z) * S + y - (by - S)) * bx + x)] = v;
@@ -341,8 +346,8 @@ __global__ __launch_bounds__(kThreads) void publish_all_kernel(StepParams p) {
     int face[6];
     int64_t q[6];
     int nf = 0;
-    if (x < S) { face[nf] = 0; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x; }
-    if (x >= p.bx - S) { face[nf] = 1; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x - (p.bx - S); }
+    if (x < S) { face[nf] = 0; q[nf++] = (static_cast<int64_t>(z) * S + x) * p.by + y; }
+    if (x >= p.bx - S) { face[nf] = 1; q[nf++] = (static_cast<int64_t>(z) * S + x - (p.bx - S)) * p.by + y; }
     if (DIM >= 2 && y < S) { face[nf] = 2; q[nf++] = (static_cast<int64_t>(z) * S + y) * p.bx + x; }
     if (DIM >= 2 && y >= p.by - S) { face[nf] = 3; q[nf++] = (static_cast<int64_t>(z) * S + y - (p.by - S)) * p.bx + x; }
     if (DIM == 3 && z < S) { face[nf] = 4; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * p.bx + x; }
@@ -437,6 +442,8 @@ size_t lds_dim(const StepParams& p, int s) {
 }  // namespace
 
 hipError_t launch_step(const StepParams& p, bool f64, int s, hipStream_t st) {
+  const int64_t field_bytes = static_cast<int64_t>(p.nx) * p.ny * p.nz * (f64 ? 8 : 4);
+  if (fast3d_applies(p, f64) && field_bytes < (int64_t(1) << 32)) return launch_step_fast3d(p, f64, s, st);
   return f64 ? dispatch_dim<double>(p, s, st, false) : dispatch_dim<float>(p, s, st, false);
 }
 

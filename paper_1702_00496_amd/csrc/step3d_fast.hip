@@ -1,0 +1,36 @@
+// Dispatcher of the 3-D sweep for 32 x 32 PE cross-sections; the kernel is
+// in step3d_fast.hpp.
+
+#include "step3d_fast.hpp"
+
+namespace atfd {
+
+int fast3d_default_depth(bool f64) { return f64 ? 2 : 4; }
+
+bool fast3d_applies(const StepParams& p, bool f64) {
+  (void)f64;
+  // time-expanded AT (T = s + 1) or the synchronous arm; other T take the
+  // generic kernel
+  const bool levels_ok = p.mode == AT_SYNC || p.T == p.s + 1;
+  return p.ndim == 3 && p.bx == fast3d::kB && p.by == fast3d::kB && levels_ok &&
+         (p.depth == 1 || p.depth == 2 || p.depth == 4) && p.bz % p.depth == 0;
+}
+
+hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st) {
+  if (f64) {
+    switch (s) {
+      case 1: return launch_fast3d_f64_s1(p, st);
+      case 2: return launch_fast3d_f64_s2(p, st);
+      case 3: return launch_fast3d_f64_s3(p, st);
+    }
+  } else {
+    switch (s) {
+      case 1: return launch_fast3d_f32_s1(p, st);
+      case 2: return launch_fast3d_f32_s2(p, st);
+      case 3: return launch_fast3d_f32_s3(p, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace atfd

@@ -1,0 +1,477 @@
+// 3-D AT sweep specialised for 32 x 32 PE cross-sections (gfx950): kernel
+// template, instantiated per precision and half-width in fast3d_*.hip.
+//
+// Same scheme as the generic sweep in step.hip, organised for HBM bandwidth:
+//  - 256 threads (4 waves) per workgroup, one PE per workgroup; each thread
+//    owns a quad of 4 consecutive x points of one row and streams the PE's
+//    z-planes, so every bulk global access is a 16-byte vector access;
+//  - the z neighbours of a quad live in a register queue of 2s+1 quads; x/y
+//    neighbours come from a double-buffered LDS plane (row stride 40 with the
+//    x halo at columns 4-s..3 and 36..35+s, so quads stay 16-byte aligned),
+//    one barrier per plane;
+//  - reads of u^n, of the integrator history and of the halo values (the AT
+//    combination of T delayed ring levels, in double) are issued D planes
+//    ahead in a rotating set of registers: the slot consumed for plane z is
+//    refilled with plane z + D, so no register copies stall the pipeline;
+//  - the integrator stage and the equation are template parameters and the
+//    stencil taps arrive pre-folded with velocity and diffusivity; every
+//    neighbour enters as (v - u0), which keeps float rounding relative to the
+//    O(dx) differences instead of the O(1/dx^2) taps.
+// Halo items are quads (x faces are stored [z][d][y], y faces [z][d][x]); the
+// ring slot and weight of every live delayed level of a face sit in LDS, and
+// a level with zero weight re-reads level n-k with weight 0.
+
+#pragma once
+
+#include "atfd_internal.hpp"
+
+namespace atfd {
+namespace fast3d {
+
+constexpr int kB = 32;           // PE edge in x and y for this path
+constexpr int kQ = kB / 4;       // quads per row
+constexpr int kQThreads = kB * kQ;
+constexpr int kRS = 40;          // LDS row stride (elements)
+constexpr int kHO = 4;           // LDS column of x = 0
+
+enum Kind : int { kEuler = 0, kAb2 = 1, kAb3 = 2, kRk1 = 3, kRk2 = 4 };
+
+template <typename Real>
+struct Q4 {
+  Real v[4];
+};
+
+__device__ inline Q4<float> ldq(const float* p) {
+  const float4 t = *reinterpret_cast<const float4*>(p);
+  return Q4<float>{{t.x, t.y, t.z, t.w}};
+}
+__device__ inline Q4<double> ldq(const double* p) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  return Q4<double>{{a.x, a.y, b.x, b.y}};
+}
+__device__ inline void stq(float* p, const Q4<float>& q) {
+  *reinterpret_cast<float4*>(p) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+}
+__device__ inline void stq(double* p, const Q4<double>& q) {
+  *reinterpret_cast<double2*>(p) = make_double2(q.v[0], q.v[1]);
+  *reinterpret_cast<double2*>(p + 2) = make_double2(q.v[2], q.v[3]);
+}
+template <typename Real>
+__device__ inline Q4<Real> zero4() {
+  return Q4<Real>{{Real(0), Real(0), Real(0), Real(0)}};
+}
+
+__device__ inline int neighbour_pe(const StepParams& p, int pid, int f) {
+  int q[3] = {pid % p.px, (pid / p.px) % p.py, pid / (p.px * p.py)};
+  const int ext[3] = {p.px, p.py, p.pz};
+  const int a = f >> 1;
+  q[a] = (q[a] + ((f & 1) ? 1 : ext[a] - 1)) % ext[a];
+  return q[0] + p.px * (q[1] + p.py * q[2]);
+}
+
+__device__ inline int face_delay_fast(const StepParams& p, int pid, int f, int64_t n) {
+  int k = 0;
+  if (p.mode == AT_DELAY_RNG) {
+    k = raw_delay(p.key, n, static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L);
+  } else if (p.mode == AT_DELAY_HOST) {
+    k = p.host_delays[(n * p.npe + pid) * (2 * p.ndim) + f];
+  }
+  return clamp_startup(k, n, p.T);
+}
+
+template <typename Real>
+struct Taps;
+template <>
+struct Taps<double> {
+  __device__ static double kad(const StepParams& p, int a, int o) { return p.kad[a][o]; }
+  __device__ static double d2a(const StepParams& p, int a, int o) { return p.d2a[a][o]; }
+  __device__ static double d1(const StepParams& p, int a, int o) { return p.c1[a][o]; }
+};
+template <>
+struct Taps<float> {
+  __device__ static float kad(const StepParams& p, int a, int o) { return p.kadf[a][o]; }
+  __device__ static float d2a(const StepParams& p, int a, int o) { return p.d2af[a][o]; }
+  __device__ static float d1(const StepParams& p, int a, int o) { return p.c1f[a][o]; }
+};
+
+template <typename Real, int S, int D, int KIND, int EQ, int TT>
+__global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p) {
+  static_assert(S <= kHO, "the x halo must fit left of column kHO");
+  static_assert(TT >= 1 && TT <= kMaxT, "levels per halo value");
+  constexpr int ROWS = kB + 2 * S;
+  constexpr int NX = 2 * S * kB;          // x-halo scalar items
+  constexpr int NY = 2 * S * kQ;          // y-halo quad items
+  constexpr bool kHist = KIND == kAb2 || KIND == kAb3 || KIND == kRk2;
+  constexpr bool kSync = TT == 1;         // synchronous arm: neighbours' u^n directly
+  __shared__ __align__(16) Real buf[2][ROWS * kRS];
+  __shared__ __align__(16) Real zhi_lds[S * kB * kB];   // planes bz .. bz+S-1
+  __shared__ double s_w[6 * kMaxT];
+  __shared__ int s_slot[6 * kMaxT];
+  __shared__ int s_nbr[6];
+
+  const int tid = threadIdx.x;
+  const int qi = tid & (kQ - 1), y = tid >> 3;
+  const int x = 4 * qi;
+  const int64_t n = p.counter[0];
+  const int pid = blockIdx.x;
+  const int pex = pid % p.px, pey = (pid / p.px) % p.py, pez = pid / (p.px * p.py);
+  const int x0 = pex * kB, y0 = pey * kB, z0 = pez * p.bz;
+  const int bz = p.bz;
+
+  if (tid < 6) {
+    const int f = tid;
+    s_nbr[f] = neighbour_pe(p, pid, f);
+    if (!kSync) {
+      const int k = face_delay_fast(p, pid, f, n);
+      double w[kMaxT];
+      level_weights(k, TT, w);
+      // a level whose weight is zero re-reads level n-k (same lines, cache
+      // hits) and is multiplied by an exact zero, so every read is issued
+      // without a branch
+      const int s0 = static_cast<int>((n - k) % p.nslots);
+      for (int m = 0; m < kMaxT; ++m) {
+        const bool live = m < TT && w[m] != 0.0;
+        s_w[f * kMaxT + m] = live ? w[m] : 0.0;
+        s_slot[f * kMaxT + m] = live ? static_cast<int>((n - k - m) % p.nslots) : s0;
+      }
+    }
+  }
+  __syncthreads();
+
+  const Real* centre = static_cast<const Real*>(KIND == kRk2 ? p.ustar : p.ubuf[n & 1]);
+  const Real* ring = static_cast<const Real*>(KIND == kRk2 ? p.sring : p.ring);
+  // field offsets fit 32 bits (the host checks the field size)
+  const uint32_t zstride = static_cast<uint32_t>(p.nx) * p.ny;
+  const uint32_t col = (static_cast<uint32_t>(z0) * p.ny + (y0 + y)) * p.nx + (x0 + x);
+  const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
+
+  // A halo source: one pointer per level (TT of them) to the element of plane
+  // 0, a per-plane stride and the level weights. AT: the neighbour's strip in
+  // the ring slots of the delayed levels; SYNC: the neighbour's u^n.
+  struct Src {
+    const Real* lvl[TT];
+    double w[TT];
+    int64_t stride;
+  };
+  auto make_src = [&](int f, int64_t q0, int64_t qstride, int64_t sync_g) -> Src {
+    Src r;
+    if (kSync) {
+      r.lvl[0] = centre + sync_g;
+      r.w[0] = 1.0;
+      r.stride = zstride;
+      return r;
+    }
+    const Real* strip = ring + static_cast<int64_t>(s_nbr[f]) * p.pe_block + p.face_off[f ^ 1] + q0;
+#pragma unroll
+    for (int m = 0; m < TT; ++m) {
+      r.lvl[m] = strip + s_slot[f * kMaxT + m] * slot_stride;
+      r.w[m] = s_w[f * kMaxT + m];
+    }
+    r.stride = qstride;
+    return r;
+  };
+  // combine raw level values (already loaded) in double
+  auto combine4 = [&](const Src& h, const Q4<Real>* raw) -> Q4<Real> {
+    if (kSync) return raw[0];
+    Q4<Real> r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < TT; ++m) acc += h.w[m] * static_cast<double>(raw[m].v[j]);
+      r.v[j] = static_cast<Real>(acc);
+    }
+    return r;
+  };
+
+  // Halo items, all quads so that every thread issues the same reads:
+  // x items (side, depth d, rows yq..yq+3; producer strip [z][d][y]) and y
+  // items (side, depth d, columns xq..xq+3; strip [z][d][x]). Each wave owns a
+  // contiguous quarter of the items in its low lanes; other lanes alias item 0
+  // (their reads hit the same lines and are discarded).
+  constexpr int NHX = 2 * S * kQ;
+  constexpr int NH = 2 * NHX;
+  constexpr int NHW = NH / 4;
+  const int lane = tid & 63;
+  const bool is_h = lane < NHW;
+  const int hid = is_h ? (tid >> 6) * NHW + lane : 0;
+  Src hs;
+  int hpos, lstride, estride;       // LDS position / stride of the 4 values, element stride (SYNC)
+  if (hid < NHX) {
+    const int side = hid / (S * kQ), r = hid % (S * kQ), d = r / kQ, yq = 4 * (r % kQ);
+    const int xl = side ? kB + d : d - S;
+    const int gx = (x0 + xl + p.nx) % p.nx;
+    hpos = (yq + S) * kRS + kHO + xl;
+    lstride = kRS;
+    estride = p.nx;
+    hs = make_src(side, static_cast<int64_t>(d) * kB + yq, static_cast<int64_t>(S) * kB,
+                  (static_cast<int64_t>(z0) * p.ny + y0 + yq) * p.nx + gx);
+  } else {
+    const int h = hid - NHX;
+    const int side = h / (S * kQ), r = h % (S * kQ), d = r / kQ, xq = 4 * (r % kQ);
+    const int yl = side ? kB + d : d - S;
+    const int gy = (y0 + yl + p.ny) % p.ny;
+    hpos = (yl + S) * kRS + kHO + xq;
+    lstride = 1;
+    estride = 1;
+    hs = make_src(2 + side, static_cast<int64_t>(d) * kB + xq, static_cast<int64_t>(S) * kB,
+                  (static_cast<int64_t>(z0) * p.ny + gy) * p.nx + x0 + xq);
+  }
+  // raw read of level m of this thread's halo item at plane zz
+  auto halo_raw = [&](int zz, int m) -> Q4<Real> {
+    if (!kSync) return ldq(hs.lvl[m] + zz * hs.stride);
+    const Real* b = hs.lvl[0] + zz * hs.stride;
+    return Q4<Real>{{b[0], b[estride], b[2 * estride], b[3 * estride]}};
+  };
+
+  // The 2S planes beyond the PE's z faces (strip [d][y][x]) are loaded and
+  // combined once, before the sweep; the upper ones wait in LDS (they are
+  // picked by a run-time plane index).
+  Q4<Real> zlo[S];
+  {
+    const int gzl = (z0 - S + p.nz) % p.nz, gzh = (z0 + bz) % p.nz;
+    const int64_t q0 = static_cast<int64_t>(y) * kB + x;
+    const Src lo = make_src(4, q0, static_cast<int64_t>(kB) * kB,
+                            (static_cast<int64_t>(gzl) * p.ny + y0 + y) * p.nx + x0 + x);
+    const Src hi = make_src(5, q0, static_cast<int64_t>(kB) * kB,
+                            (static_cast<int64_t>(gzh) * p.ny + y0 + y) * p.nx + x0 + x);
+#pragma unroll
+    for (int d = 0; d < S; ++d) {
+      Q4<Real> rl[TT], rh[TT];
+#pragma unroll
+      for (int m = 0; m < TT; ++m) {
+        rl[m] = ldq(lo.lvl[m] + d * lo.stride);
+        rh[m] = ldq(hi.lvl[m] + d * hi.stride);
+      }
+      zlo[d] = combine4(lo, rl);
+      stq(zhi_lds + (d * kB + y) * kB + x, combine4(hi, rh));
+    }
+  }
+  // u quad of plane zz in [0, bz + S): interior planes from u^n, the last S
+  // from LDS (each thread reads back what it wrote)
+  auto plane_quad = [&](int zz) -> Q4<Real> {
+    if (zz < bz) return ldq(centre + (col + zz * zstride));
+    return ldq(zhi_lds + ((zz - bz) * kB + y) * kB + x);
+  };
+
+  // integrator history: f^{n-1} (AB2, AB3), u^n (second RK2 stage). AB3 keeps
+  // f^{n-1} in fbuf[(n-1)&1] and f^{n-2} in fbuf[n&1]; f^n overwrites f^{n-2}.
+  // The reads are issued unconditionally (a value the formula does not use at
+  // start-up is never touched).
+  Real* fb0 = static_cast<Real*>(p.fbuf[0]);
+  Real* fm1 = KIND == kAb3 ? static_cast<Real*>(p.fbuf[(n + 1) & 1]) : nullptr;
+  Real* fm2 = KIND == kAb3 ? static_cast<Real*>(p.fbuf[n & 1]) : nullptr;
+  const Real* hist = KIND == kAb2 ? fb0 : KIND == kAb3 ? fm1
+                   : KIND == kRk2 ? static_cast<const Real*>(p.ubuf[n & 1]) : nullptr;
+  // where f^n goes
+  Real* fout = KIND == kAb2 ? fb0
+             : KIND == kAb3 ? (n == 0 ? fb0 : n == 1 ? static_cast<Real*>(p.fbuf[1]) : fm2) : nullptr;
+  auto hist1 = [&](int z) -> Q4<Real> {
+    return kHist ? ldq(hist + (col + z * zstride)) : zero4<Real>();
+  };
+  auto hist2 = [&](int z) -> Q4<Real> {
+    return KIND == kAb3 ? ldq(fm2 + (col + z * zstride)) : zero4<Real>();
+  };
+
+  const Real dt = static_cast<Real>(p.dt);
+  Real* unext = static_cast<Real*>(KIND == kRk1 ? p.ustar : p.ubuf[(n + 1) & 1]);
+  Real* pub = static_cast<Real*>(KIND == kRk1 ? p.sring : p.ring);
+  const int pslot = static_cast<int>((KIND == kRk1 ? n : n + 1) % (p.nslots > 0 ? p.nslots : 1));
+  Real* pstrip = kSync ? nullptr : pub + (static_cast<int64_t>(pslot) * p.npe + pid) * p.pe_block;
+
+  // z queue (planes z-S .. z+S) and the rotating prefetch slots
+  Q4<Real> qz[2 * S + 1];
+#pragma unroll
+  for (int i = 0; i < S; ++i) qz[i] = zlo[i];
+#pragma unroll
+  for (int i = 0; i < S; ++i) qz[S + i] = plane_quad(i);
+  Q4<Real> A[D], F1[D], F2[D], HR[D][TT];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    A[j] = plane_quad(j + S);
+    F1[j] = hist1(j);
+    F2[j] = hist2(j);
+#pragma unroll
+    for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(j, m);
+  }
+
+  const int c_at = (y + S) * kRS + kHO + x;     // LDS index of this quad's first point
+  for (int zb = 0; zb < bz; zb += D) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int z = zb + j;
+      qz[2 * S] = A[j];
+      const Q4<Real> fo1 = F1[j], fo2 = F2[j];
+      Real* Lp = buf[z & 1];
+      stq(Lp + c_at, qz[S]);
+      if (is_h) {
+        const Q4<Real> hv = combine4(hs, HR[j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Lp[hpos + i * lstride] = hv.v[i];
+      }
+      // refill the slot with what iteration z + D consumes
+      if (z + D < bz) {
+        A[j] = plane_quad(z + D + S);
+        F1[j] = hist1(z + D);
+        F2[j] = hist2(z + D);
+#pragma unroll
+        for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(z + D, m);
+      }
+      __syncthreads();
+      // x row segment [x - S, x + 3 + S] and the y neighbour quads
+      Real row[4 + 2 * S];
+#pragma unroll
+      for (int i = 0; i < 4 + 2 * S; ++i) row[i] = Lp[c_at - S + i];
+      Q4<Real> ym[S], yp[S];
+#pragma unroll
+      for (int o = 1; o <= S; ++o) {
+        ym[o - 1] = ldq(Lp + c_at - o * kRS);
+        yp[o - 1] = ldq(Lp + c_at + o * kRS);
+      }
+      Q4<Real> un, fq;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const Real u0 = qz[S].v[e];
+        Real fval;
+        if (EQ == AT_ADVDIFF) {
+          Real acc = 0;
+#pragma unroll
+          for (int o = 1; o <= S; ++o) {
+            acc += Taps<Real>::kad(p, 0, S - o) * (row[S + e - o] - u0);
+            acc += Taps<Real>::kad(p, 0, S + o) * (row[S + e + o] - u0);
+            acc += Taps<Real>::kad(p, 1, S - o) * (ym[o - 1].v[e] - u0);
+            acc += Taps<Real>::kad(p, 1, S + o) * (yp[o - 1].v[e] - u0);
+            acc += Taps<Real>::kad(p, 2, S - o) * (qz[S - o].v[e] - u0);
+            acc += Taps<Real>::kad(p, 2, S + o) * (qz[S + o].v[e] - u0);
+          }
+          fval = acc;
+        } else {
+          Real lap = 0, grad = 0;
+#pragma unroll
+          for (int o = 1; o <= S; ++o) {
+            const Real xm = row[S + e - o] - u0, xp = row[S + e + o] - u0;
+            const Real ymv = ym[o - 1].v[e] - u0, ypv = yp[o - 1].v[e] - u0;
+            const Real zm = qz[S - o].v[e] - u0, zp = qz[S + o].v[e] - u0;
+            lap += Taps<Real>::d2a(p, 0, S - o) * xm + Taps<Real>::d2a(p, 0, S + o) * xp;
+            lap += Taps<Real>::d2a(p, 1, S - o) * ymv + Taps<Real>::d2a(p, 1, S + o) * ypv;
+            lap += Taps<Real>::d2a(p, 2, S - o) * zm + Taps<Real>::d2a(p, 2, S + o) * zp;
+            grad += Taps<Real>::d1(p, 0, S - o) * xm + Taps<Real>::d1(p, 0, S + o) * xp;
+            grad += Taps<Real>::d1(p, 1, S - o) * ymv + Taps<Real>::d1(p, 1, S + o) * ypv;
+            grad += Taps<Real>::d1(p, 2, S - o) * zm + Taps<Real>::d1(p, 2, S + o) * zp;
+          }
+          fval = lap - u0 * grad;
+        }
+        fq.v[e] = fval;
+        Real r;
+        if (KIND == kRk1 || KIND == kEuler) {
+          r = u0 + dt * fval;
+        } else if (KIND == kRk2) {
+          r = Real(0.5) * (fo1.v[e] + u0) + (Real(0.5) * dt) * fval;
+        } else if (KIND == kAb2) {
+          r = n == 0 ? u0 + dt * fval : u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e]);
+        } else {   // AB3: Euler, then AB2, then AB3
+          r = n == 0 ? u0 + dt * fval
+            : n == 1 ? u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e])
+                     : u0 + dt * ((Real(23) * fval - Real(16) * fo1.v[e] + Real(5) * fo2.v[e]) / Real(12));
+        }
+        un.v[e] = r;
+      }
+      const uint32_t g = col + z * zstride;
+      stq(unext + g, un);
+      if (KIND == kAb2 || KIND == kAb3) stq(fout + g, fq);
+      if (!kSync) {
+        // publish the new edge values into the ring slot of their level
+        // x faces: strip [z][d][y]
+        if (qi == 0) {
+#pragma unroll
+          for (int e = 0; e < S; ++e)
+            pstrip[p.face_off[0] + (static_cast<int64_t>(z) * S + e) * kB + y] = un.v[e];
+        }
+        if (qi == kQ - 1) {
+#pragma unroll
+          for (int e = 4 - S; e < 4; ++e)
+            pstrip[p.face_off[1] + (static_cast<int64_t>(z) * S + e - (4 - S)) * kB + y] = un.v[e];
+        }
+        if (y < S) stq(pstrip + p.face_off[2] + (static_cast<int64_t>(z) * S + y) * kB + x, un);
+        if (y >= kB - S) stq(pstrip + p.face_off[3] + (static_cast<int64_t>(z) * S + y - (kB - S)) * kB + x, un);
+        if (z < S) stq(pstrip + p.face_off[4] + (static_cast<int64_t>(z) * kB + y) * kB + x, un);
+        if (z >= bz - S) stq(pstrip + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * kB + y) * kB + x, un);
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];
+    }
+  }
+
+  if (KIND != kRk1) {
+    // The last workgroup to finish advances the step counter; every other
+    // workgroup read n before its own increment.
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const unsigned long long prev =
+          atomicAdd(reinterpret_cast<unsigned long long*>(&p.counter[1]), 1ull);
+      if (prev == static_cast<unsigned long long>(gridDim.x) - 1ull) {
+        p.counter[1] = 0;
+        p.counter[0] = n + 1;
+        __threadfence();
+      }
+    }
+  }
+}
+
+template <typename Real, int S, int D, int KIND, int TT>
+hipError_t launch_eq(const StepParams& p, hipStream_t st) {
+  if (p.equation == AT_ADVDIFF)
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, D, KIND, AT_ADVDIFF, TT>), dim3(p.npe),
+                       dim3(kQThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, D, KIND, AT_BURGERS, TT>), dim3(p.npe),
+                       dim3(kQThreads), 0, st, p);
+  return hipGetLastError();
+}
+
+// The synchronous arm reads one value per halo point; the AT schemes read the
+// T = s + 1 delayed levels of the time-expanded family.
+template <typename Real, int S, int D, int KIND>
+hipError_t launch_kind(const StepParams& p, hipStream_t st) {
+  if (p.mode == AT_SYNC) return launch_eq<Real, S, D, KIND, 1>(p, st);
+  return launch_eq<Real, S, D, KIND, S + 1>(p, st);
+}
+
+template <typename Real, int S, int D>
+hipError_t launch_fast_d(const StepParams& p, hipStream_t st) {
+  if (p.stage == kStageRk1) return launch_kind<Real, S, D, kRk1>(p, st);
+  if (p.stage == kStageRk2) return launch_kind<Real, S, D, kRk2>(p, st);
+  switch (p.integrator) {
+    case AT_EULER: return launch_kind<Real, S, D, kEuler>(p, st);
+    case AT_AB2: return launch_kind<Real, S, D, kAb2>(p, st);
+    case AT_AB3: return launch_kind<Real, S, D, kAb3>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Planes of reads kept in flight per thread: the tunable of this path. All
+// depths compute bit-identical results; they trade registers for bytes in
+// flight.
+template <typename Real, int S>
+hipError_t launch_fast_t(const StepParams& p, hipStream_t st) {
+  switch (p.depth) {
+    case 1: return launch_fast_d<Real, S, 1>(p, st);
+    case 2: return launch_fast_d<Real, S, 2>(p, st);
+    case 4: return launch_fast_d<Real, S, 4>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fast3d
+
+// one instantiation per translation unit (fast3d_*.hip), built in parallel
+hipError_t launch_fast3d_f32_s1(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_f32_s2(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_f32_s3(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_f64_s1(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_f64_s2(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_f64_s3(const StepParams& p, hipStream_t st);
+
+}  // namespace atfd

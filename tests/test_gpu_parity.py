@@ -41,6 +41,12 @@ CASES = {
     "2d_o2_euler": dict(ndim=2, n=(48, 32), pe=(3, 2), order=2, integrator="euler", c=(1.0, 1.0), L=2, steps=40, ra=0.05),
     "3d_o4_ab2_ragged": dict(ndim=3, n=(40, 36, 30), pe=(4, 3, 3), order=4, integrator="ab2", c=(1.0, 1.0, 1.0), L=4, steps=24, ra=0.02),
     "3d_o6_rk2_burgers": dict(ndim=3, n=(36, 36, 36), pe=(3, 3, 3), order=6, integrator="rk2", equation="burgers", alpha=0.05, L=4, steps=16, ra=0.004),
+    # 32 x 32 cross-sections take the 1024-thread 3-D path
+    "3d_fast_o6_rk2_burgers": dict(ndim=3, n=(64, 64, 64), pe=(2, 2, 2), order=6, integrator="rk2", equation="burgers", alpha=0.05, L=4, steps=10, ra=0.004),
+    "3d_fast_o2_euler": dict(ndim=3, n=(64, 32, 64), pe=(2, 1, 2), order=2, integrator="euler", c=(1.0, 0.5, -0.5), L=3, steps=14, ra=0.05),
+    "3d_fast_o4_ab3_px1": dict(ndim=3, n=(32, 64, 32), pe=(1, 2, 1), order=4, integrator="ab3", c=(1.0, 1.0, 1.0), L=4, steps=14, ra=0.01),
+    "3d_fast_o4_ab2_bz16": dict(ndim=3, n=(64, 64, 48), pe=(2, 2, 3), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), L=4, steps=12, ra=0.02),
+    "3d_fast_o4_ab2_sync": dict(ndim=3, n=(64, 64, 32), pe=(2, 2, 1), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), mode="sync", steps=12, ra=0.02),
     "3d_o2_euler_sync": dict(ndim=3, n=(32, 32, 32), pe=(2, 2, 2), order=2, integrator="euler", c=(1.0, 0.5, 0.25), mode="sync", steps=20, ra=0.05),
 }
 
@@ -86,7 +92,8 @@ def test_delays_bit_exact(name):
         assert np.array_equal(got[n], want.reshape(got[n].shape)), n
 
 
-@pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers"])
+@pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
+                                  "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
@@ -152,7 +159,7 @@ def test_checkpoint_resume_bitwise():
     assert torch.equal(b.state(), ref)
 
 
-@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3"])
+@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3", "3d_fast_o6_rk2_burgers"])
 def test_graph_replay_equals_plain_launches(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
@@ -218,3 +225,27 @@ def test_full_size_3d_workload_full_run_properties():
     e_at, e_sy = res["at64"][1]["l2"], res["sync64"][1]["l2"]
     assert abs(e_at - e_sy) <= 0.05 * e_sy
     assert rel_l2(res["at32"][0], res["at64"][0]) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_schedule_depths_bit_identical_and_autotune_restores_state(precision):
+    case = _case("3d_fast_o4_ab2_bz16")
+    u0 = torch.from_numpy(initial_field(case))
+    outs = []
+    for depth in (1, 2, 4):
+        s = solver_for(case, precision)
+        s.set_tuning(depth)
+        assert s.tuning() == depth
+        s.set_state(u0)
+        s.step(9)
+        outs.append(s.state())
+    assert all(torch.equal(outs[0], o) for o in outs[1:])
+    s = solver_for(case, precision)
+    s.set_state(u0)
+    s.step(4)
+    before = s.state()
+    best, ms = s.autotune(nsteps=3)
+    assert best in (1, 2, 4) and set(ms) == {1, 2, 4}
+    assert torch.equal(s.state(), before) and s.n_step == 4
+    s.step(5)
+    assert torch.equal(s.state(), outs[0])
