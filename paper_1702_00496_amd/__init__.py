@@ -14,7 +14,10 @@ import torch
 from . import _lib
 from ._lib import ATError, AtDelay, AtProblem, check
 
-__all__ = ["Solver", "ATError", "lib"]
+__all__ = ["Solver", "ATError", "lib", "VARIANTS"]
+
+# schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
+VARIANTS = (1, 2, 4, 9, 10, 12)
 
 
 def lib():
@@ -120,10 +123,10 @@ class Solver:
         afterwards) and keep the fastest. Returns (depth, {depth: ms/step})."""
         scratch = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device=self.device)
         best = ctypes.c_int32(0)
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * 6)()
         check(self._lib.at_autotune(self._ctx, _as_ptr(scratch), scratch.numel(), int(nsteps),
                                     ctypes.byref(best), ms), self._ctx)
-        return best.value, {d: ms[i] for i, d in enumerate((1, 2, 4)) if ms[i] >= 0}
+        return best.value, {d: ms[i] for i, d in enumerate(VARIANTS) if ms[i] >= 0}
 
     def state(self):
         out = torch.empty(self.shape, dtype=self.dtype, device=self.device)

@@ -422,7 +422,7 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
 at_status at_set_tuning(at_ctx* c, int32_t depth) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
   if (depth == 0) depth = fast3d_default_depth(c->g.f64);
-  if (depth != 1 && depth != 2 && depth != 4) return fail(c, AT_EINVAL, "depth must be 1, 2 or 4");
+  if (!fast3d_valid_variant(depth)) return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10 or 12");
   if (depth != c->sp.depth) drop_graph(c);
   c->sp.depth = depth;
   return AT_OK;
@@ -445,7 +445,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
     return fail(c, AT_EINVAL, "host delay table too short for autotuning");
   at_status st = at_save(c, scratch_dev);
   if (st != AT_OK) return st;
-  const int cand[3] = {1, 2, 4};
+  const int cand[6] = {1, 2, 4, 9, 10, 12};
   const int keep = c->sp.depth, keep_chunk = c->graph_chunk;
   double best_ms = 1e300;
   int best = keep;
@@ -453,7 +453,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
   c->graph_chunk = 0;
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 6; ++i) {
     double ms = -1.0;
     StepParams trial = c->sp;
     trial.depth = cand[i];

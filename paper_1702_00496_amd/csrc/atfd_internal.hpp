@@ -106,7 +106,8 @@ struct StepParams {
   int64_t face_off[6];         // strip offset of face 2*axis+side within a PE block
   int64_t* counter;            // [0] = step n, [1] = finished workgroups
   int advance;                 // this launch ends the step: bump the counter
-  int depth;                   // 3-D 32x32 path: planes of reads in flight (1, 2, 4); 0 = generic kernel
+  int depth;                   // 3-D 32x32 path schedule: planes in flight D (1, 2, 4) with 4
+                               // points per thread, or 8 + D with 2 points per thread
 };
 
 struct NormParams {
@@ -134,6 +135,7 @@ size_t step_lds_bytes(const StepParams& p, bool f64, int s);
 // 3-D sweep for 32 x 32 PE cross-sections (step3d_fast.hip)
 bool fast3d_applies(const StepParams& p, bool f64);
 int fast3d_default_depth(bool f64);
+bool fast3d_valid_variant(int v);
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st);
 
 }  // namespace atfd

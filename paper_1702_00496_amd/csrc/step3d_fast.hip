@@ -5,7 +5,9 @@
 
 namespace atfd {
 
-int fast3d_default_depth(bool f64) { return f64 ? 2 : 4; }
+int fast3d_default_depth(bool f64) { return f64 ? 2 : 10; }
+
+bool fast3d_valid_variant(int v) { return v == 1 || v == 2 || v == 4 || v == 9 || v == 10 || v == 12; }
 
 bool fast3d_applies(const StepParams& p, bool f64) {
   (void)f64;
@@ -13,7 +15,7 @@ bool fast3d_applies(const StepParams& p, bool f64) {
   // generic kernel
   const bool levels_ok = p.mode == AT_SYNC || p.T == p.s + 1;
   return p.ndim == 3 && p.bx == fast3d::kB && p.by == fast3d::kB && levels_ok &&
-         (p.depth == 1 || p.depth == 2 || p.depth == 4) && p.bz % p.depth == 0;
+         fast3d_valid_variant(p.depth) && p.bz % (p.depth & 7) == 0;
 }
 
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st) {

@@ -2,13 +2,13 @@
 // template, instantiated per precision and half-width in fast3d_*.hip.
 //
 // Same scheme as the generic sweep in step.hip, organised for HBM bandwidth:
-//  - 256 threads (4 waves) per workgroup, one PE per workgroup; each thread
-//    owns a quad of 4 consecutive x points of one row and streams the PE's
-//    z-planes, so every bulk global access is a 16-byte vector access;
-//  - the z neighbours of a quad live in a register queue of 2s+1 quads; x/y
-//    neighbours come from a double-buffered LDS plane (row stride 40 with the
-//    x halo at columns 4-s..3 and 36..35+s, so quads stay 16-byte aligned),
-//    one barrier per plane;
+//  - one PE per workgroup; each thread owns V consecutive x points of one row
+//    (V = 4: 256 threads, V = 2: 512 threads) and streams the PE's z-planes,
+//    so every bulk global access is an 8- or 16-byte vector access;
+//  - the z neighbours of a thread's points live in a register queue of 2s+1
+//    vectors; x/y neighbours come from a double-buffered LDS plane (row
+//    stride 40 with the x halo at columns 4-s..3 and 36..35+s, so vectors stay
+//    aligned), one barrier per plane;
 //  - reads of u^n, of the integrator history and of the halo values (the AT
 //    combination of T delayed ring levels, in double) are issued D planes
 //    ahead in a rotating set of registers: the slot consumed for plane z is
@@ -16,12 +16,15 @@
 //  - the integrator stage and the equation are template parameters and the
 //    stencil taps arrive pre-folded with velocity and diffusivity; every
 //    neighbour enters as (v - u0), which keeps float rounding relative to the
-//    O(dx) differences instead of the O(1/dx^2) taps.
+//    O(dx) differences instead of the O(1/dx^2) taps; each axis accumulates
+//    into its own partial sum (three independent FMA chains per point).
 // Halo items are quads (x faces are stored [z][d][y], y faces [z][d][x]); the
 // ring slot and weight of every live delayed level of a face sit in LDS, and
-// a level with zero weight re-reads level n-k with weight 0.
-
+// a level with zero weight re-reads level n-k with weight 0 so that no read
+// sits behind a branch.
 #pragma once
+
+#include <type_traits>
 
 #include "atfd_internal.hpp"
 
@@ -29,37 +32,66 @@ namespace atfd {
 namespace fast3d {
 
 constexpr int kB = 32;           // PE edge in x and y for this path
-constexpr int kQ = kB / 4;       // quads per row
-constexpr int kQThreads = kB * kQ;
 constexpr int kRS = 40;          // LDS row stride (elements)
 constexpr int kHO = 4;           // LDS column of x = 0
 
 enum Kind : int { kEuler = 0, kAb2 = 1, kAb3 = 2, kRk1 = 3, kRk2 = 4 };
 
-template <typename Real>
-struct Q4 {
-  Real v[4];
+template <typename Real, int V>
+struct Vec {
+  Real v[V];
 };
 
-__device__ inline Q4<float> ldq(const float* p) {
-  const float4 t = *reinterpret_cast<const float4*>(p);
-  return Q4<float>{{t.x, t.y, t.z, t.w}};
+// Vector loads/stores through a 32-bit byte offset from a uniform base, so the
+// compiler can address with a scalar base register plus one VGPR.
+template <typename Real, int V>
+__device__ inline Vec<Real, V> ldv(const Real* base, uint32_t elem) {
+  const char* p = reinterpret_cast<const char*>(base) + elem * static_cast<uint32_t>(sizeof(Real));
+  Vec<Real, V> r;
+  if constexpr (sizeof(Real) * V == 16) {
+    if constexpr (sizeof(Real) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+    } else {
+      const double2 t = *reinterpret_cast<const double2*>(p);
+      r.v[0] = t.x; r.v[1] = t.y;
+    }
+  } else if constexpr (sizeof(Real) * V == 8) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    r.v[0] = t.x; r.v[1] = t.y;
+  } else {   // 32 bytes: two 16-byte halves
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 16);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
 }
-__device__ inline Q4<double> ldq(const double* p) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
-  return Q4<double>{{a.x, a.y, b.x, b.y}};
+template <typename Real, int V>
+__device__ inline void stv(Real* base, uint32_t elem, const Vec<Real, V>& q) {
+  char* p = reinterpret_cast<char*>(base) + elem * static_cast<uint32_t>(sizeof(Real));
+  if constexpr (sizeof(Real) * V == 16) {
+    if constexpr (sizeof(Real) == 4)
+      *reinterpret_cast<float4*>(p) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    else
+      *reinterpret_cast<double2*>(p) = make_double2(q.v[0], q.v[1]);
+  } else if constexpr (sizeof(Real) * V == 8) {
+    *reinterpret_cast<float2*>(p) = make_float2(q.v[0], q.v[1]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(q.v[0], q.v[1]);
+    *reinterpret_cast<double2*>(p + 16) = make_double2(q.v[2], q.v[3]);
+  }
 }
-__device__ inline void stq(float* p, const Q4<float>& q) {
-  *reinterpret_cast<float4*>(p) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+// Same through a full pointer (ring strips may exceed 4 GB).
+template <typename Real, int V>
+__device__ inline Vec<Real, V> ldp(const Real* p) {
+  return ldv<Real, V>(p, 0u);
 }
-__device__ inline void stq(double* p, const Q4<double>& q) {
-  *reinterpret_cast<double2*>(p) = make_double2(q.v[0], q.v[1]);
-  *reinterpret_cast<double2*>(p + 2) = make_double2(q.v[2], q.v[3]);
-}
-template <typename Real>
-__device__ inline Q4<Real> zero4() {
-  return Q4<Real>{{Real(0), Real(0), Real(0), Real(0)}};
+template <typename Real, int V>
+__device__ inline Vec<Real, V> zerov() {
+  Vec<Real, V> r;
+#pragma unroll
+  for (int i = 0; i < V; ++i) r.v[i] = Real(0);
+  return r;
 }
 
 __device__ inline int neighbour_pe(const StepParams& p, int pid, int f) {
@@ -95,13 +127,30 @@ struct Taps<float> {
   __device__ static float d1(const StepParams& p, int a, int o) { return p.c1f[a][o]; }
 };
 
-template <typename Real, int S, int D, int KIND, int EQ, int TT>
-__global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p) {
+// combine raw level values (already loaded) in double
+template <typename Real, int W, int TT>
+__device__ inline Vec<Real, W> combine_levels(const double* w, const Vec<Real, W>* raw, bool sync) {
+  if (sync) return raw[0];
+  Vec<Real, W> r;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < TT; ++m) acc += w[m] * static_cast<double>(raw[m].v[j]);
+    r.v[j] = static_cast<Real>(acc);
+  }
+  return r;
+}
+
+template <typename Real, int S, int V, int D, int KIND, int EQ, int TT>
+__global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams p) {
   static_assert(S <= kHO, "the x halo must fit left of column kHO");
   static_assert(TT >= 1 && TT <= kMaxT, "levels per halo value");
+  using VR = Vec<Real, V>;
+  using Q = Vec<Real, 4>;
+  constexpr int NT = kB * kB / V;         // threads
+  constexpr int VPR = kB / V;             // vectors per row
   constexpr int ROWS = kB + 2 * S;
-  constexpr int NX = 2 * S * kB;          // x-halo scalar items
-  constexpr int NY = 2 * S * kQ;          // y-halo quad items
   constexpr bool kHist = KIND == kAb2 || KIND == kAb3 || KIND == kRk2;
   constexpr bool kSync = TT == 1;         // synchronous arm: neighbours' u^n directly
   __shared__ __align__(16) Real buf[2][ROWS * kRS];
@@ -111,8 +160,8 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
   __shared__ int s_nbr[6];
 
   const int tid = threadIdx.x;
-  const int qi = tid & (kQ - 1), y = tid >> 3;
-  const int x = 4 * qi;
+  const int vi = tid % VPR, y = tid / VPR;
+  const int x = V * vi;
   const int64_t n = p.counter[0];
   const int pid = blockIdx.x;
   const int pex = pid % p.px, pey = (pid / p.px) % p.py, pez = pid / (p.px * p.py);
@@ -146,9 +195,9 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
   const uint32_t col = (static_cast<uint32_t>(z0) * p.ny + (y0 + y)) * p.nx + (x0 + x);
   const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
 
-  // A halo source: one pointer per level (TT of them) to the element of plane
-  // 0, a per-plane stride and the level weights. AT: the neighbour's strip in
-  // the ring slots of the delayed levels; SYNC: the neighbour's u^n.
+  // A halo source: one pointer per level to the element of plane 0, a
+  // per-plane stride and the level weights. AT: the neighbour's strip in the
+  // ring slots of the delayed levels; SYNC: the neighbour's u^n.
   struct Src {
     const Real* lvl[TT];
     double w[TT];
@@ -171,35 +220,25 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
     r.stride = qstride;
     return r;
   };
-  // combine raw level values (already loaded) in double
-  auto combine4 = [&](const Src& h, const Q4<Real>* raw) -> Q4<Real> {
-    if (kSync) return raw[0];
-    Q4<Real> r;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < TT; ++m) acc += h.w[m] * static_cast<double>(raw[m].v[j]);
-      r.v[j] = static_cast<Real>(acc);
-    }
-    return r;
-  };
 
   // Halo items, all quads so that every thread issues the same reads:
   // x items (side, depth d, rows yq..yq+3; producer strip [z][d][y]) and y
   // items (side, depth d, columns xq..xq+3; strip [z][d][x]). Each wave owns a
-  // contiguous quarter of the items in its low lanes; other lanes alias item 0
+  // contiguous share of the items in its low lanes; other lanes alias item 0
   // (their reads hit the same lines and are discarded).
-  constexpr int NHX = 2 * S * kQ;
+  constexpr int QPR = kB / 4;
+  constexpr int NHX = 2 * S * QPR;
   constexpr int NH = 2 * NHX;
-  constexpr int NHW = NH / 4;
+  constexpr int NW = NT / 64;
+  constexpr int NHW = NH / NW;
+  static_assert(NH % NW == 0 && NHW <= 64, "halo items per wave");
   const int lane = tid & 63;
   const bool is_h = lane < NHW;
   const int hid = is_h ? (tid >> 6) * NHW + lane : 0;
   Src hs;
   int hpos, lstride, estride;       // LDS position / stride of the 4 values, element stride (SYNC)
   if (hid < NHX) {
-    const int side = hid / (S * kQ), r = hid % (S * kQ), d = r / kQ, yq = 4 * (r % kQ);
+    const int side = hid / (S * QPR), r = hid % (S * QPR), d = r / QPR, yq = 4 * (r % QPR);
     const int xl = side ? kB + d : d - S;
     const int gx = (x0 + xl + p.nx) % p.nx;
     hpos = (yq + S) * kRS + kHO + xl;
@@ -209,7 +248,7 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
                   (static_cast<int64_t>(z0) * p.ny + y0 + yq) * p.nx + gx);
   } else {
     const int h = hid - NHX;
-    const int side = h / (S * kQ), r = h % (S * kQ), d = r / kQ, xq = 4 * (r % kQ);
+    const int side = h / (S * QPR), r = h % (S * QPR), d = r / QPR, xq = 4 * (r % QPR);
     const int yl = side ? kB + d : d - S;
     const int gy = (y0 + yl + p.ny) % p.ny;
     hpos = (yl + S) * kRS + kHO + xq;
@@ -219,16 +258,16 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
                   (static_cast<int64_t>(z0) * p.ny + gy) * p.nx + x0 + xq);
   }
   // raw read of level m of this thread's halo item at plane zz
-  auto halo_raw = [&](int zz, int m) -> Q4<Real> {
-    if (!kSync) return ldq(hs.lvl[m] + zz * hs.stride);
+  auto halo_raw = [&](int zz, int m) -> Q {
+    if (!kSync) return ldp<Real, 4>(hs.lvl[m] + zz * hs.stride);
     const Real* b = hs.lvl[0] + zz * hs.stride;
-    return Q4<Real>{{b[0], b[estride], b[2 * estride], b[3 * estride]}};
+    return Q{{b[0], b[estride], b[2 * estride], b[3 * estride]}};
   };
 
   // The 2S planes beyond the PE's z faces (strip [d][y][x]) are loaded and
   // combined once, before the sweep; the upper ones wait in LDS (they are
   // picked by a run-time plane index).
-  Q4<Real> zlo[S];
+  VR zlo[S];
   {
     const int gzl = (z0 - S + p.nz) % p.nz, gzh = (z0 + bz) % p.nz;
     const int64_t q0 = static_cast<int64_t>(y) * kB + x;
@@ -238,21 +277,22 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
                             (static_cast<int64_t>(gzh) * p.ny + y0 + y) * p.nx + x0 + x);
 #pragma unroll
     for (int d = 0; d < S; ++d) {
-      Q4<Real> rl[TT], rh[TT];
+      VR rl[TT], rh[TT];
 #pragma unroll
       for (int m = 0; m < TT; ++m) {
-        rl[m] = ldq(lo.lvl[m] + d * lo.stride);
-        rh[m] = ldq(hi.lvl[m] + d * hi.stride);
+        rl[m] = ldp<Real, V>(lo.lvl[m] + d * lo.stride);
+        rh[m] = ldp<Real, V>(hi.lvl[m] + d * hi.stride);
       }
-      zlo[d] = combine4(lo, rl);
-      stq(zhi_lds + (d * kB + y) * kB + x, combine4(hi, rh));
+      zlo[d] = combine_levels<Real, V, TT>(lo.w, rl, kSync);
+      stv<Real, V>(zhi_lds, static_cast<uint32_t>((d * kB + y) * kB + x),
+                   combine_levels<Real, V, TT>(hi.w, rh, kSync));
     }
   }
-  // u quad of plane zz in [0, bz + S): interior planes from u^n, the last S
+  // values of plane zz in [0, bz + S): interior planes from u^n, the last S
   // from LDS (each thread reads back what it wrote)
-  auto plane_quad = [&](int zz) -> Q4<Real> {
-    if (zz < bz) return ldq(centre + (col + zz * zstride));
-    return ldq(zhi_lds + ((zz - bz) * kB + y) * kB + x);
+  auto plane_vec = [&](int zz) -> VR {
+    if (zz < bz) return ldv<Real, V>(centre, col + zz * zstride);
+    return ldv<Real, V>(zhi_lds, static_cast<uint32_t>(((zz - bz) * kB + y) * kB + x));
   };
 
   // integrator history: f^{n-1} (AB2, AB3), u^n (second RK2 stage). AB3 keeps
@@ -267,12 +307,8 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
   // where f^n goes
   Real* fout = KIND == kAb2 ? fb0
              : KIND == kAb3 ? (n == 0 ? fb0 : n == 1 ? static_cast<Real*>(p.fbuf[1]) : fm2) : nullptr;
-  auto hist1 = [&](int z) -> Q4<Real> {
-    return kHist ? ldq(hist + (col + z * zstride)) : zero4<Real>();
-  };
-  auto hist2 = [&](int z) -> Q4<Real> {
-    return KIND == kAb3 ? ldq(fm2 + (col + z * zstride)) : zero4<Real>();
-  };
+  auto hist1 = [&](int z) -> VR { return kHist ? ldv<Real, V>(hist, col + z * zstride) : zerov<Real, V>(); };
+  auto hist2 = [&](int z) -> VR { return KIND == kAb3 ? ldv<Real, V>(fm2, col + z * zstride) : zerov<Real, V>(); };
 
   const Real dt = static_cast<Real>(p.dt);
   Real* unext = static_cast<Real*>(KIND == kRk1 ? p.ustar : p.ubuf[(n + 1) & 1]);
@@ -281,86 +317,90 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
   Real* pstrip = kSync ? nullptr : pub + (static_cast<int64_t>(pslot) * p.npe + pid) * p.pe_block;
 
   // z queue (planes z-S .. z+S) and the rotating prefetch slots
-  Q4<Real> qz[2 * S + 1];
+  VR qz[2 * S + 1];
 #pragma unroll
   for (int i = 0; i < S; ++i) qz[i] = zlo[i];
 #pragma unroll
-  for (int i = 0; i < S; ++i) qz[S + i] = plane_quad(i);
-  Q4<Real> A[D], F1[D], F2[D], HR[D][TT];
+  for (int i = 0; i < S; ++i) qz[S + i] = plane_vec(i);
+  VR A[D], F1[D], F2[D];
+  Q HR[D][TT];
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    A[j] = plane_quad(j + S);
+    A[j] = plane_vec(j + S);
     F1[j] = hist1(j);
     F2[j] = hist2(j);
 #pragma unroll
     for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(j, m);
   }
 
-  const int c_at = (y + S) * kRS + kHO + x;     // LDS index of this quad's first point
+  const int c_at = (y + S) * kRS + kHO + x;     // LDS index of this thread's first point
   for (int zb = 0; zb < bz; zb += D) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       const int z = zb + j;
       qz[2 * S] = A[j];
-      const Q4<Real> fo1 = F1[j], fo2 = F2[j];
+      const VR fo1 = F1[j], fo2 = F2[j];
       Real* Lp = buf[z & 1];
-      stq(Lp + c_at, qz[S]);
+      stv<Real, V>(Lp, static_cast<uint32_t>(c_at), qz[S]);
       if (is_h) {
-        const Q4<Real> hv = combine4(hs, HR[j]);
+        const Q hv = combine_levels<Real, 4, TT>(hs.w, HR[j], kSync);
 #pragma unroll
         for (int i = 0; i < 4; ++i) Lp[hpos + i * lstride] = hv.v[i];
       }
       // refill the slot with what iteration z + D consumes
       if (z + D < bz) {
-        A[j] = plane_quad(z + D + S);
+        A[j] = plane_vec(z + D + S);
         F1[j] = hist1(z + D);
         F2[j] = hist2(z + D);
 #pragma unroll
         for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(z + D, m);
       }
       __syncthreads();
-      // x row segment [x - S, x + 3 + S] and the y neighbour quads
-      Real row[4 + 2 * S];
+      // x row segment [x - S, x + V - 1 + S] and the y neighbour vectors
+      Real row[V + 2 * S];
 #pragma unroll
-      for (int i = 0; i < 4 + 2 * S; ++i) row[i] = Lp[c_at - S + i];
-      Q4<Real> ym[S], yp[S];
+      for (int i = 0; i < V + 2 * S; ++i) row[i] = Lp[c_at - S + i];
+      VR ym[S], yp[S];
 #pragma unroll
       for (int o = 1; o <= S; ++o) {
-        ym[o - 1] = ldq(Lp + c_at - o * kRS);
-        yp[o - 1] = ldq(Lp + c_at + o * kRS);
+        ym[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at - o * kRS));
+        yp[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at + o * kRS));
       }
-      Q4<Real> un, fq;
+      VR un, fq;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < V; ++e) {
         const Real u0 = qz[S].v[e];
         Real fval;
         if (EQ == AT_ADVDIFF) {
-          Real acc = 0;
+          // f = sum over axes and taps of (alpha c2 - vel c1) (v - u0), one
+          // partial sum per axis
+          Real ax = 0, ay = 0, az = 0;
 #pragma unroll
           for (int o = 1; o <= S; ++o) {
-            acc += Taps<Real>::kad(p, 0, S - o) * (row[S + e - o] - u0);
-            acc += Taps<Real>::kad(p, 0, S + o) * (row[S + e + o] - u0);
-            acc += Taps<Real>::kad(p, 1, S - o) * (ym[o - 1].v[e] - u0);
-            acc += Taps<Real>::kad(p, 1, S + o) * (yp[o - 1].v[e] - u0);
-            acc += Taps<Real>::kad(p, 2, S - o) * (qz[S - o].v[e] - u0);
-            acc += Taps<Real>::kad(p, 2, S + o) * (qz[S + o].v[e] - u0);
+            ax += Taps<Real>::kad(p, 0, S - o) * (row[S + e - o] - u0);
+            ay += Taps<Real>::kad(p, 1, S - o) * (ym[o - 1].v[e] - u0);
+            az += Taps<Real>::kad(p, 2, S - o) * (qz[S - o].v[e] - u0);
+            ax += Taps<Real>::kad(p, 0, S + o) * (row[S + e + o] - u0);
+            ay += Taps<Real>::kad(p, 1, S + o) * (yp[o - 1].v[e] - u0);
+            az += Taps<Real>::kad(p, 2, S + o) * (qz[S + o].v[e] - u0);
           }
-          fval = acc;
+          fval = (ax + ay) + az;
         } else {
-          Real lap = 0, grad = 0;
+          // f = alpha lap u - u (sum_d du/dx_d)
+          Real lx = 0, ly = 0, lz = 0, gx = 0, gy = 0, gz = 0;
 #pragma unroll
           for (int o = 1; o <= S; ++o) {
             const Real xm = row[S + e - o] - u0, xp = row[S + e + o] - u0;
             const Real ymv = ym[o - 1].v[e] - u0, ypv = yp[o - 1].v[e] - u0;
             const Real zm = qz[S - o].v[e] - u0, zp = qz[S + o].v[e] - u0;
-            lap += Taps<Real>::d2a(p, 0, S - o) * xm + Taps<Real>::d2a(p, 0, S + o) * xp;
-            lap += Taps<Real>::d2a(p, 1, S - o) * ymv + Taps<Real>::d2a(p, 1, S + o) * ypv;
-            lap += Taps<Real>::d2a(p, 2, S - o) * zm + Taps<Real>::d2a(p, 2, S + o) * zp;
-            grad += Taps<Real>::d1(p, 0, S - o) * xm + Taps<Real>::d1(p, 0, S + o) * xp;
-            grad += Taps<Real>::d1(p, 1, S - o) * ymv + Taps<Real>::d1(p, 1, S + o) * ypv;
-            grad += Taps<Real>::d1(p, 2, S - o) * zm + Taps<Real>::d1(p, 2, S + o) * zp;
+            lx += Taps<Real>::d2a(p, 0, S - o) * xm + Taps<Real>::d2a(p, 0, S + o) * xp;
+            ly += Taps<Real>::d2a(p, 1, S - o) * ymv + Taps<Real>::d2a(p, 1, S + o) * ypv;
+            lz += Taps<Real>::d2a(p, 2, S - o) * zm + Taps<Real>::d2a(p, 2, S + o) * zp;
+            gx += Taps<Real>::d1(p, 0, S - o) * xm + Taps<Real>::d1(p, 0, S + o) * xp;
+            gy += Taps<Real>::d1(p, 1, S - o) * ymv + Taps<Real>::d1(p, 1, S + o) * ypv;
+            gz += Taps<Real>::d1(p, 2, S - o) * zm + Taps<Real>::d1(p, 2, S + o) * zp;
           }
-          fval = lap - u0 * grad;
+          fval = ((lx + ly) + lz) - u0 * ((gx + gy) + gz);
         }
         fq.v[e] = fval;
         Real r;
@@ -378,25 +418,24 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
         un.v[e] = r;
       }
       const uint32_t g = col + z * zstride;
-      stq(unext + g, un);
-      if (KIND == kAb2 || KIND == kAb3) stq(fout + g, fq);
+      stv<Real, V>(unext, g, un);
+      if (KIND == kAb2 || KIND == kAb3) stv<Real, V>(fout, g, fq);
       if (!kSync) {
-        // publish the new edge values into the ring slot of their level
+        // publish the new edge values into the ring slot of their level;
         // x faces: strip [z][d][y]
-        if (qi == 0) {
 #pragma unroll
-          for (int e = 0; e < S; ++e)
-            pstrip[p.face_off[0] + (static_cast<int64_t>(z) * S + e) * kB + y] = un.v[e];
+        for (int e = 0; e < V; ++e) {
+          if (x + e < S)
+            pstrip[p.face_off[0] + (static_cast<int64_t>(z) * S + x + e) * kB + y] = un.v[e];
+          if (x + e >= kB - S)
+            pstrip[p.face_off[1] + (static_cast<int64_t>(z) * S + x + e - (kB - S)) * kB + y] = un.v[e];
         }
-        if (qi == kQ - 1) {
-#pragma unroll
-          for (int e = 4 - S; e < 4; ++e)
-            pstrip[p.face_off[1] + (static_cast<int64_t>(z) * S + e - (4 - S)) * kB + y] = un.v[e];
-        }
-        if (y < S) stq(pstrip + p.face_off[2] + (static_cast<int64_t>(z) * S + y) * kB + x, un);
-        if (y >= kB - S) stq(pstrip + p.face_off[3] + (static_cast<int64_t>(z) * S + y - (kB - S)) * kB + x, un);
-        if (z < S) stq(pstrip + p.face_off[4] + (static_cast<int64_t>(z) * kB + y) * kB + x, un);
-        if (z >= bz - S) stq(pstrip + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * kB + y) * kB + x, un);
+        if (y < S) stv<Real, V>(pstrip + p.face_off[2], static_cast<uint32_t>((z * S + y) * kB + x), un);
+        if (y >= kB - S)
+          stv<Real, V>(pstrip + p.face_off[3], static_cast<uint32_t>((z * S + y - (kB - S)) * kB + x), un);
+        if (z < S) stv<Real, V>(pstrip + p.face_off[4], static_cast<uint32_t>((z * kB + y) * kB + x), un);
+        if (z >= bz - S)
+          stv<Real, V>(pstrip + p.face_off[5], static_cast<uint32_t>(((z - (bz - S)) * kB + y) * kB + x), un);
       }
 #pragma unroll
       for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];
@@ -420,46 +459,51 @@ __global__ __launch_bounds__(kQThreads) void at_step3d_fast_kernel(StepParams p)
   }
 }
 
-template <typename Real, int S, int D, int KIND, int TT>
+template <typename Real, int S, int V, int D, int KIND, int TT>
 hipError_t launch_eq(const StepParams& p, hipStream_t st) {
+  constexpr int NT = kB * kB / V;
   if (p.equation == AT_ADVDIFF)
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, D, KIND, AT_ADVDIFF, TT>), dim3(p.npe),
-                       dim3(kQThreads), 0, st, p);
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_ADVDIFF, TT>), dim3(p.npe),
+                       dim3(NT), 0, st, p);
   else
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, D, KIND, AT_BURGERS, TT>), dim3(p.npe),
-                       dim3(kQThreads), 0, st, p);
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_BURGERS, TT>), dim3(p.npe),
+                       dim3(NT), 0, st, p);
   return hipGetLastError();
 }
 
 // The synchronous arm reads one value per halo point; the AT schemes read the
 // T = s + 1 delayed levels of the time-expanded family.
-template <typename Real, int S, int D, int KIND>
+template <typename Real, int S, int V, int D, int KIND>
 hipError_t launch_kind(const StepParams& p, hipStream_t st) {
-  if (p.mode == AT_SYNC) return launch_eq<Real, S, D, KIND, 1>(p, st);
-  return launch_eq<Real, S, D, KIND, S + 1>(p, st);
+  if (p.mode == AT_SYNC) return launch_eq<Real, S, V, D, KIND, 1>(p, st);
+  return launch_eq<Real, S, V, D, KIND, S + 1>(p, st);
 }
 
-template <typename Real, int S, int D>
+template <typename Real, int S, int V, int D>
 hipError_t launch_fast_d(const StepParams& p, hipStream_t st) {
-  if (p.stage == kStageRk1) return launch_kind<Real, S, D, kRk1>(p, st);
-  if (p.stage == kStageRk2) return launch_kind<Real, S, D, kRk2>(p, st);
+  if (p.stage == kStageRk1) return launch_kind<Real, S, V, D, kRk1>(p, st);
+  if (p.stage == kStageRk2) return launch_kind<Real, S, V, D, kRk2>(p, st);
   switch (p.integrator) {
-    case AT_EULER: return launch_kind<Real, S, D, kEuler>(p, st);
-    case AT_AB2: return launch_kind<Real, S, D, kAb2>(p, st);
-    case AT_AB3: return launch_kind<Real, S, D, kAb3>(p, st);
+    case AT_EULER: return launch_kind<Real, S, V, D, kEuler>(p, st);
+    case AT_AB2: return launch_kind<Real, S, V, D, kAb2>(p, st);
+    case AT_AB3: return launch_kind<Real, S, V, D, kAb3>(p, st);
   }
   return hipErrorInvalidValue;
 }
 
-// Planes of reads kept in flight per thread: the tunable of this path. All
-// depths compute bit-identical results; they trade registers for bytes in
-// flight.
+// Schedule variants (the tunables of this path): planes of reads in flight
+// D in {1, 2, 4} and points per thread V in {2, 4}, encoded as
+// variant = D for V = 4 and 8 + D for V = 2. All variants compute
+// bit-identical results.
 template <typename Real, int S>
 hipError_t launch_fast_t(const StepParams& p, hipStream_t st) {
   switch (p.depth) {
-    case 1: return launch_fast_d<Real, S, 1>(p, st);
-    case 2: return launch_fast_d<Real, S, 2>(p, st);
-    case 4: return launch_fast_d<Real, S, 4>(p, st);
+    case 1: return launch_fast_d<Real, S, 4, 1>(p, st);
+    case 2: return launch_fast_d<Real, S, 4, 2>(p, st);
+    case 4: return launch_fast_d<Real, S, 4, 4>(p, st);
+    case 9: return launch_fast_d<Real, S, 2, 1>(p, st);
+    case 10: return launch_fast_d<Real, S, 2, 2>(p, st);
+    case 12: return launch_fast_d<Real, S, 2, 4>(p, st);
   }
   return hipErrorInvalidValue;
 }

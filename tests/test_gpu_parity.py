@@ -232,7 +232,8 @@ def test_schedule_depths_bit_identical_and_autotune_restores_state(precision):
     case = _case("3d_fast_o4_ab2_bz16")
     u0 = torch.from_numpy(initial_field(case))
     outs = []
-    for depth in (1, 2, 4):
+    from paper_1702_00496_amd import VARIANTS
+    for depth in VARIANTS:
         s = solver_for(case, precision)
         s.set_tuning(depth)
         assert s.tuning() == depth
@@ -245,7 +246,7 @@ def test_schedule_depths_bit_identical_and_autotune_restores_state(precision):
     s.step(4)
     before = s.state()
     best, ms = s.autotune(nsteps=3)
-    assert best in (1, 2, 4) and set(ms) == {1, 2, 4}
+    assert best in VARIANTS and set(ms) == set(VARIANTS)
     assert torch.equal(s.state(), before) and s.n_step == 4
     s.step(5)
     assert torch.equal(s.state(), outs[0])
