@@ -68,6 +68,28 @@ __host__ __device__ inline void level_weights(int k, int T, double* w) {
 }
 
 // ---------------------------------------------------------------- kernels
+// Workgroup -> PE map. Workgroups are handed to the 8 XCDs round-robin; this
+// gives each XCD one contiguous range of PE ids (a slab of neighbouring PEs),
+// so a halo row that one PE reads from its neighbour's field was most likely
+// fetched into the same L2 by that neighbour.
+__device__ inline int pe_of_workgroup(int b, int g) {
+  return (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+}
+
+// Called by one thread of every workgroup after the step's last access to
+// n = counter[0]: the last workgroup to arrive sets counter[0] = n + 1.
+// Only the atomics order anything here; the field and ring stores need no
+// fence because no workgroup of this launch reads them, and the launch
+// boundary makes them visible to the next step.
+__device__ inline void advance_counter(int64_t* counter, int64_t n) {
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(counter);
+  const unsigned long long prev = atomicAdd(&c[1], 1ull);
+  if (prev == static_cast<unsigned long long>(gridDim.x) - 1ull) {
+    atomicExch(&c[1], 0ull);
+    atomicExch(&c[0], static_cast<unsigned long long>(n + 1));
+  }
+}
+
 enum Stage : int { kStageSingle = 0, kStageRk1 = 1, kStageRk2 = 2 };
 
 // Everything one sweep needs. Passed by value.

@@ -312,19 +312,9 @@ __global__ __launch_bounds__(kThreads) void at_step_kernel(StepParams p) {
   }
 
   if (p.advance) {
-    // The last workgroup to finish advances the step counter. Every other
-    // workgroup has read n before its own increment below.
+    // every workgroup has read n before its own increment
     __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const unsigned long long prev =
-          atomicAdd(reinterpret_cast<unsigned long long*>(&p.counter[1]), 1ull);
-      if (prev == static_cast<unsigned long long>(gridDim.x) - 1ull) {
-        p.counter[1] = 0;
-        p.counter[0] = n + 1;
-        __threadfence();
-      }
-    }
+    if (tid == 0) advance_counter(p.counter, n);
   }
 }
 

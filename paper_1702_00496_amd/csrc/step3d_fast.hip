@@ -5,7 +5,7 @@
 
 namespace atfd {
 
-int fast3d_default_depth(bool f64) { return f64 ? 2 : 10; }
+int fast3d_default_depth(bool f64) { (void)f64; return 2; }
 
 bool fast3d_valid_variant(int v) { return v == 1 || v == 2 || v == 4 || v == 9 || v == 10 || v == 12; }
 

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   const int vi = tid % VPR, y = tid / VPR;
   const int x = V * vi;
   const int64_t n = p.counter[0];
-  const int pid = blockIdx.x;
+  const int pid = pe_of_workgroup(blockIdx.x, gridDim.x);
   const int pex = pid % p.px, pey = (pid / p.px) % p.py, pez = pid / (p.px * p.py);
   const int x0 = pex * kB, y0 = pey * kB, z0 = pez * p.bz;
   const int bz = p.bz;
@@ -443,19 +443,9 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   }
 
   if (KIND != kRk1) {
-    // The last workgroup to finish advances the step counter; every other
-    // workgroup read n before its own increment.
+    // every workgroup has read n before its own increment
     __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const unsigned long long prev =
-          atomicAdd(reinterpret_cast<unsigned long long*>(&p.counter[1]), 1ull);
-      if (prev == static_cast<unsigned long long>(gridDim.x) - 1ull) {
-        p.counter[1] = 0;
-        p.counter[0] = n + 1;
-        __threadfence();
-      }
-    }
+    if (tid == 0) advance_counter(p.counter, n);
   }
 }
 
