@@ -32,8 +32,9 @@ p.add_argument("--n", type=int, default=256)
 p.add_argument("--b", type=int, default=32)
 p.add_argument("--no-cpu-baseline", action="store_true")
 p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to time")
-p.add_argument("--cpu-steps", type=int, default=4)
+p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
+p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
 args = p.parse_args()
 
 if args.gpus != 1:
@@ -81,7 +82,9 @@ def time_arm(precision, mode):
     s = make(precision, mode)
     s.set_state(u0)
     tuned = None
-    if not args.no_autotune:
+    if args.variant:
+        s.set_tuning(args.variant)
+    elif not args.no_autotune:
         s.step(3)
         tuned = s.autotune(nsteps=20)       # schedule choice, state restored
     if args.graph:
@@ -127,6 +130,31 @@ def copy_bandwidth():
     return gbs
 
 
+KERNEL_SOURCES = ("step3d_fast.hpp", "atfd_internal.hpp", "fast3d_f32_s2.hip", "fast3d_f64_s2.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "at_step3d_fast_256cube_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, per arm; None where the kernel sources changed since it was taken
+    or the workload differs."""
+    import hashlib
+    if args.n != 256 or args.b != 32 or not os.path.exists(TRAFFIC_FILE):
+        return {}
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1702_00496_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    with open(TRAFFIC_FILE) as fh:
+        line = next((ln for ln in fh if ln.startswith("bench-traffic: ")), None)
+    if line is None:
+        return {}
+    meta = json.loads(line[len("bench-traffic: "):])
+    if meta.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
+        return {}
+    return {arm: (r["traffic_bytes"], meta.get("variant")) for arm, r in meta["arms"].items()}
+
+
 def cpu_baseline():
     """The FP64 oracle on the host cores: the first cpu_steps steps of the same
     workload (a bounded sample of the run)."""
@@ -153,7 +181,12 @@ for arm in args.arms.split(","):
           f"{arms[arm]['updates_per_s']:.3e} upd/s {arms[arm]['achieved_gbs']:.0f} GB/s "
           f"l2={arms[arm]['l2_error']:.3e}", file=sys.stderr, flush=True)
 
-head = arms.get("f32") or next(iter(arms.values()))
+traffic = measured_traffic()
+for arm, r in arms.items():
+    t = traffic.get(arm)
+    r["traffic_bytes"] = t[0] if t and t[1] == r["depth"] else None
+head_arm = "f32" if "f32" in arms else next(iter(arms))
+head = arms[head_arm]
 copy_gbs = copy_bandwidth()
 out = {
     "metric": "AT stencil grid-pt updates/s, % HBM roofline, vs standard at matched error",
@@ -173,8 +206,9 @@ out = {
                "grid": N, "pe_edge": args.b, "order": 4, "L": cfg["L"], "integrator": "ab2",
                "dt": cfg["dt"], "graph_chunk": args.graph},
     "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "frac": head["frac"], "traffic": None,
-                 "kernel": f"at_step3d_fast_kernel<float, s=2, depth={head['depth']}, AB2, advection-diffusion>",
+                 "unit": "GB/s", "frac": head["frac"], "traffic": head["traffic_bytes"],
+                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
+                 "kernel": f"at_step3d_fast_kernel<{'float' if head['precision'] == 'f32' else 'double'}, s=2, variant={head['depth']}, AB2, advection-diffusion>",
                  "bytes_per_update": head["bytes_per_update"],
                  "measured_copy_gbs": copy_gbs},
     "arms": arms,
