@@ -11,7 +11,7 @@
  * drawn per step and per face from a counter-based generator (Sec. 5.1).
  * Points whose stencil crosses a face combine T successive delayed levels with
  * weights c_m(k) so that the delay error cancels to the scheme's order
- * (Sec. 3.3 Example 3 eq. cd4-at; Tables atschemes-left/right); all other
+ * (Sec. 3.4 Example 3 eq. cd4-at; Tables atschemes-left/right); all other
  * points take the standard central difference (Sec. 2 eq. general_deriv).
  * The right-hand side is advection-diffusion or viscous Burgers (Sec. 5 eq.
  * general) and is advanced with Euler, AB2, AB3 (Sec. 4.1 eqs. time_disc,

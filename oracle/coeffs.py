@@ -11,7 +11,7 @@ Paper passages followed:
   coefficient must be one.
 - Sec. 3.1 (derivation recipe): rank(A) vs rank(A|b) decides between a
   unique solution, no solution and infinitely many.
-- Sec. 3.2 / Sec. 3.3 Example 3: the step-by-step route. First the symmetric
+- Sec. 3.3 / Sec. 3.4 Example 3: the step-by-step route. First the symmetric
   synchronous central difference (eq. general_deriv_cds); then a small system
   over successive delayed time levels k, k+1, ..., k+T-1 that cancels the
   asynchrony terms (the third linear system of Example 3).
@@ -125,7 +125,7 @@ def derive_scheme(stencil, d, a, r):
 
 
 def central_difference(d, a):
-    """Synchronous central difference taps c_{-s..s} (Sec. 3.2, eq. general_deriv_cds).
+    """Synchronous central difference taps c_{-s..s} (Sec. 3.3, eq. general_deriv_cds).
 
     Step one of Example 3: use the symmetric combination u_{i+j} + (-1)^d u_{i-j}
     for j = 0..s (s = a/2, d = 1 or 2) and impose the q = 0 conditions
@@ -163,7 +163,7 @@ def central_difference(d, a):
 
 
 def time_level_weights(k, T):
-    """Weights c_m, m = 0..T-1, over delayed levels n-k-m (Sec. 3.3 Example 3).
+    """Weights c_m, m = 0..T-1, over delayed levels n-k-m (Sec. 3.4 Example 3).
 
     The third system of Example 3: after the spatial step, the asynchrony
     terms with the same power q of dt are all equivalent, so one condition per

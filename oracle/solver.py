@@ -9,7 +9,7 @@ What one step n -> n+1 computes:
    Every PE p draws, for each axis and each side, one delay k in [0, L-1]
    (uniform over all buffer points of that face, the "uniform delay" class of
    Table class). Start-up clamp: k <= max(0, n - T + 1).
-2. Spatial derivatives (Sec. 2 eq. general_deriv; Sec. 3.3 Example 3 eq.
+2. Spatial derivatives (Sec. 2 eq. general_deriv; Sec. 3.4 Example 3 eq.
    cd4-at; Tables atschemes-left/right). Points whose stencil stays inside
    their PE (the set I_I) take the standard central difference CD_a on level
    n. A point of I_B, whose stencil reaches taps in the buffer set B across

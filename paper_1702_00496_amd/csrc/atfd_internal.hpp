@@ -50,7 +50,7 @@ __host__ __device__ inline int clamp_startup(int k, int64_t n, int T) {
 }
 
 // Weights over delayed levels n-k-m, m = 0..T-1, of the time-expanded AT
-// schemes (Sec. 3.3 Example 3, eq. cd4-at; Tables atschemes-left/right): the
+// schemes (Sec. 3.4 Example 3, eq. cd4-at; Tables atschemes-left/right): the
 // values that extrapolate T successive past levels back to level n, i.e. the
 // Lagrange basis on nodes k, k+1, .., k+T-1 evaluated at 0:
 //   w_m(k) = prod_{i != m} (k + i) / (i - m).

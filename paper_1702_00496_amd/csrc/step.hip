@@ -5,7 +5,7 @@
 // plus an s-wide frame of x/y halo values; the z neighbours are the planes
 // above and below in the LDS ring. Halo values across a PE face are the AT
 // combination of T delayed levels of the neighbour's edge strip (computed in
-// double, Sec. 3.3 eq. cd4-at), so every point then applies the standard
+// double, Sec. 3.4 eq. cd4-at), so every point then applies the standard
 // central difference (Sec. 2 eq. general_deriv) to LDS data: interior points
 // (set I_I) see only level-n values, buffer-adjacent points (set I_B) see the
 // extrapolated halo exactly as in Tables atschemes-left/right.

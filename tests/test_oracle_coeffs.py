@@ -45,7 +45,7 @@ def test_time_level_weights_match_printed_polynomials(T):
 
 
 def test_time_level_weights_reduce_to_synchronous_at_k0():
-    """Sec. 3.3 Example 3: with k = 0 the AT scheme is the standard CD."""
+    """Sec. 3.4 Example 3: with k = 0 the AT scheme is the standard CD."""
     for T in (1, 2, 3, 4):
         assert coeffs.time_level_weights(0, T) == [1] + [0] * (T - 1)
 

@@ -1,6 +1,6 @@
 """Pins of the oracle's AT time step against what the paper and mathematics fix.
 
-- k = 0 everywhere reproduces the synchronous scheme bit for bit (Sec. 3.3,
+- k = 0 everywhere reproduces the synchronous scheme bit for bit (Sec. 3.4,
   remark after eq. cd4-at).
 - The synchronous scheme equals the exact discrete Fourier solution built
   from the printed central-difference taps (closed form).
