@@ -197,6 +197,83 @@ at_status at_destroy(at_ctx* ctx);
 /* Text of the last failure of `ctx`, or of the calling thread for NULL. */
 const char* at_last_error(const at_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Delay ensembles: many independent 1-D advection-diffusion problems, each
+ * with its own grid, PE count, scheme, L and generator key, advanced together
+ * in one persistent launch. Their errors give the statistics over delay
+ * realisations and grid spacings that the paper's error analysis averages
+ * over (Sec. 4 ensemble averages; Sec. 5.1 realisations of the delays).
+ * Member fields are packed one after another, member i starting at
+ * sum_{j<i} n_j, in the bulk precision.
+ */
+typedef struct at_ens_member {
+  int64_t n;                 /* points of this periodic 1-D problem              */
+  int32_t pe;                /* PEs; n % pe == 0 and n / pe >= 2s                */
+  int32_t order;             /* 2, 4 or 6                                        */
+  int32_t integrator;        /* AT_EULER | AT_AB2                                */
+  int32_t L;                 /* 1..8                                             */
+  int32_t T;                 /* 0 = order/2+1; 1..4                              */
+  int32_t mode;              /* AT_DELAY_RNG | AT_DELAY_ZERO | AT_SYNC           */
+  double length;             /* box length                                       */
+  double c;                  /* advection speed                                  */
+  double alpha;              /* diffusivity                                      */
+  double dt;                 /* time step                                        */
+  uint64_t seed;             /* generator key of this member (as at_delay.seed)  */
+  const uint32_t* weights;   /* host, L integer bin weights; NULL = uniform      */
+} at_ens_member;
+
+/* Workspace bytes for `count` members (descriptors, schedule, two packed
+ * field buffers, the packed AB2 history, every member's ring of L+T slots,
+ * counters, norm results). */
+at_status at_ens_workspace_size(int32_t count, const at_ens_member* members, int32_t precision,
+                                size_t* bytes);
+
+/* Create an ensemble on `ws_dev` (>= at_ens_workspace_size bytes, 256-B
+ * aligned), queuing work on `hip_stream`. `precision` is AT_F64 or
+ * AT_F32_F64B. Members are spread over workgroups by a longest-first balance
+ * of their work; a member never spans two workgroups. Every member is
+ * validated like at_create validates a problem. Synchronises the stream. */
+at_status at_ens_create(int32_t count, const at_ens_member* members, int32_t precision, void* ws_dev,
+                        size_t ws_bytes, void* hip_stream, at_ens** out);
+
+/* Set u^0 of every member (packed, device, bulk precision), fill every ring
+ * slot with its edge strips and reset the step counter to 0. */
+at_status at_ens_set_state(at_ens* ens, const void* u0_dev);
+
+/* Advance every member nsteps steps in ONE persistent launch: a workgroup
+ * loops over the steps of its members with a workgroup barrier between
+ * steps. The launch is captured into a HIP graph the first time a given
+ * nsteps is run and the graph is replayed afterwards (the start step is read
+ * from a device counter). */
+at_status at_ens_run(at_ens* ens, int64_t nsteps);
+
+/* Schedule: workgroups per compute unit (1, 2 or 4) and threads per
+ * workgroup (256, 512 or 1024); 0 keeps the current value. Results are
+ * bit-identical for every choice. */
+at_status at_ens_set_tuning(at_ens* ens, int32_t groups_per_cu, int32_t threads);
+
+/* Copy the packed current fields to `u_dev`. */
+at_status at_ens_get_state(at_ens* ens, void* u_dev);
+
+/* Current step number n (host-side mirror; no synchronisation). */
+at_status at_ens_get_step(const at_ens* ens, int64_t* n);
+
+/* Per-member error norms in double with a fixed reduction order:
+ * out[count][3] = mean|E|, rms E, max|E|. Reference: the exact decaying
+ * advected Fourier series of Sec. 5.1 eq. ana_sol (nmodes > 0: kappa and amp
+ * [nmodes] shared by all members, phase [count][nmodes] per member, evaluated
+ * at t = n dt of each member), or, with nmodes == 0, the packed double field
+ * `ref_dev`. Returns AT_EUNSTABLE if any value is not finite. Synchronises the
+ * stream. At most 16 modes. */
+at_status at_ens_norms(at_ens* ens, int32_t nmodes, const int32_t* kappa, const double* amp,
+                       const double* phase, const double* ref_dev, double* out);
+
+/* Release the ensemble (device memory stays with the caller). */
+at_status at_ens_destroy(at_ens* ens);
+
+/* Text of the last failure of `ens`, or of the calling thread for NULL. */
+const char* at_ens_last_error(const at_ens* ens);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,9 +12,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ATError, AtDelay, AtProblem, check
+from ._lib import ATError, AtDelay, AtEnsMember, AtProblem, check
 
-__all__ = ["Solver", "ATError", "lib", "VARIANTS"]
+__all__ = ["Solver", "Ensemble", "ATError", "lib", "VARIANTS"]
 
 # schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
 VARIANTS = (1, 2, 4, 9, 10, 12)
@@ -176,3 +176,112 @@ class Solver:
 
     def load(self, buf):
         check(self._lib.at_load(self._ctx, _as_ptr(buf)), self._ctx)
+
+
+class Ensemble:
+    """Many independent 1-D AT problems advanced in one persistent launch
+    (``at_ens_create`` .. ``at_ens_destroy``).
+
+    ``members``: list of dicts with keys n, pe, order, integrator ("euler" |
+    "ab2"), L, T (0 = order/2+1), mode ("rng" | "zero" | "sync"), length, c,
+    alpha, dt, seed (the member's generator key), weights (optional)."""
+
+    def __init__(self, members, precision="f32", device="cuda"):
+        L_ = _lib.load()
+        self.count = len(members)
+        arr = (AtEnsMember * self.count)()
+        self._keep = []
+        self.sizes = []
+        for i, m in enumerate(members):
+            a = arr[i]
+            a.n = int(m["n"])
+            a.pe = int(m["pe"])
+            a.order = int(m["order"])
+            a.integrator = _lib.INTEGRATORS[m.get("integrator", "euler")]
+            a.L = int(m.get("L", 1))
+            a.T = int(m.get("T", 0))
+            a.mode = _lib.MODES[m.get("mode", "rng")]
+            a.length = float(m.get("length", 2.0 * math.pi))
+            a.c = float(m.get("c", 0.0))
+            a.alpha = float(m.get("alpha", 0.0))
+            a.dt = float(m["dt"])
+            a.seed = int(m.get("seed", 0)) & (2 ** 64 - 1)
+            if m.get("weights") is not None:
+                w = (ctypes.c_uint32 * len(m["weights"]))(*[int(v) for v in m["weights"]])
+                self._keep.append(w)
+                a.weights = ctypes.cast(w, ctypes.POINTER(ctypes.c_uint32))
+            self.sizes.append(a.n)
+        self._arr = arr
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.device = torch.device(device)
+        self.total = sum(self.sizes)
+        prec = _lib.PRECISIONS[precision]
+        nbytes = ctypes.c_size_t(0)
+        check(L_.at_ens_workspace_size(self.count, arr, prec, ctypes.byref(nbytes)), None, ens=True)
+        self.workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        check(L_.at_ens_create(self.count, arr, prec, _as_ptr(self.workspace), nbytes.value,
+                               _stream_ptr(), ctypes.byref(ctx)), None, ens=True)
+        self._ctx = ctx
+        self._lib = L_
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.at_ens_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        check(st, self._ctx, ens=True)
+
+    def set_state(self, u0):
+        """u0: packed 1-D tensor of all members' initial fields."""
+        u0 = u0.to(device=self.device, dtype=self.dtype).contiguous().reshape(-1)
+        if u0.numel() != self.total:
+            raise ValueError(f"u0 has {u0.numel()} values, members need {self.total}")
+        self._u0_keep = u0
+        self._check(self._lib.at_ens_set_state(self._ctx, _as_ptr(u0)))
+
+    def run(self, nsteps):
+        self._check(self._lib.at_ens_run(self._ctx, int(nsteps)))
+
+    def set_tuning(self, groups_per_cu=0, threads=0):
+        self._check(self._lib.at_ens_set_tuning(self._ctx, int(groups_per_cu), int(threads)))
+
+    def state(self):
+        out = torch.empty(self.total, dtype=self.dtype, device=self.device)
+        self._check(self._lib.at_ens_get_state(self._ctx, _as_ptr(out)))
+        return out
+
+    def split(self, packed):
+        return list(torch.split(packed, self.sizes))
+
+    @property
+    def n_step(self):
+        v = ctypes.c_int64(0)
+        self._check(self._lib.at_ens_get_step(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def norms(self, kappas=None, amps=None, phases=None, ref=None):
+        """Per-member (mean|E|, rms E, max|E|) as a (count, 3) numpy array, vs the
+        exact series (kappas, amps shared; phases [count][nmodes]) or a packed
+        float64 reference field."""
+        out = np.zeros((self.count, 3), dtype=np.float64)
+        optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if kappas is not None:
+            nm = len(kappas)
+            kap = (ctypes.c_int32 * nm)(*[int(k) for k in kappas])
+            amp = (ctypes.c_double * nm)(*[float(a) for a in amps])
+            ph = np.ascontiguousarray(phases, dtype=np.float64).reshape(self.count, nm)
+            st = self._lib.at_ens_norms(self._ctx, nm, kap, amp,
+                                        ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, optr)
+        else:
+            ref = ref.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+            st = self._lib.at_ens_norms(self._ctx, 0, None, None, None, _as_ptr(ref), optr)
+        self._check(st)
+        return out

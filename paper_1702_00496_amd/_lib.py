@@ -55,12 +55,13 @@ class AtEnsMember(ctypes.Structure):
         ("integrator", ctypes.c_int32),
         ("L", ctypes.c_int32),
         ("T", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
         ("length", ctypes.c_double),
         ("c", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("weights", ctypes.POINTER(ctypes.c_uint32)),
     ]
 
 
@@ -90,6 +91,16 @@ SIGNATURES = {
     "at_load": (I32, [P, P]),
     "at_destroy": (I32, [P]),
     "at_last_error": (ctypes.c_char_p, [P]),
+    "at_ens_workspace_size": (I32, [I32, ctypes.POINTER(AtEnsMember), I32, ctypes.POINTER(SZ)]),
+    "at_ens_create": (I32, [I32, ctypes.POINTER(AtEnsMember), I32, P, SZ, P, ctypes.POINTER(P)]),
+    "at_ens_set_state": (I32, [P, P]),
+    "at_ens_run": (I32, [P, I64]),
+    "at_ens_set_tuning": (I32, [P, I32, I32]),
+    "at_ens_get_state": (I32, [P, P]),
+    "at_ens_get_step": (I32, [P, ctypes.POINTER(I64)]),
+    "at_ens_norms": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),
+    "at_ens_destroy": (I32, [P]),
+    "at_ens_last_error": (ctypes.c_char_p, [P]),
 }
 
 _lib = None
@@ -119,8 +130,8 @@ class ATError(RuntimeError):
         self.status = status
 
 
-def check(status, ctx=None):
+def check(status, ctx=None, ens=False):
     if status != AT_OK:
         lib = load()
-        msg = lib.at_last_error(ctx)
+        msg = lib.at_ens_last_error(ctx) if ens else lib.at_last_error(ctx)
         raise ATError(status, msg.decode() if msg else "")

@@ -12,48 +12,18 @@
 #include <vector>
 
 #include "atfd_internal.hpp"
+#include "host_common.hpp"
 
 using namespace atfd;
 
+std::string& atfd::thread_error() {
+  thread_local std::string err;
+  return err;
+}
+
 namespace {
 
-thread_local std::string g_thread_error;
-
-constexpr size_t kAlign = 256;
 constexpr int kNormBlocks = 1024;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Integer-only cumulative thresholds floor(2^53 * W_j / W_total).
-bool make_thresholds(int L, const uint32_t* weights, uint64_t* thr) {
-  unsigned __int128 total = 0;
-  for (int j = 0; j < L; ++j) total += weights ? weights[j] : 1u;
-  if (total == 0) return false;
-  unsigned __int128 cum = 0;
-  for (int j = 0; j < L; ++j) {
-    cum += weights ? weights[j] : 1u;
-    thr[j] = static_cast<uint64_t>((cum << 53) / total);
-  }
-  return true;
-}
-
-// Central-difference taps of Sec. 2 eq. general_deriv (the synchronous parts
-// of Tables atschemes-left/right and the textbook sixth-order first
-// derivative), indexed o = -s..s.
-bool cd_taps(int d, int order, double* t) {
-  static const double d1_2[] = {-0.5, 0.0, 0.5};
-  static const double d1_4[] = {1.0 / 12, -8.0 / 12, 0.0, 8.0 / 12, -1.0 / 12};
-  static const double d1_6[] = {-1.0 / 60, 9.0 / 60, -45.0 / 60, 0.0, 45.0 / 60, -9.0 / 60, 1.0 / 60};
-  static const double d2_2[] = {1.0, -2.0, 1.0};
-  static const double d2_4[] = {-1.0 / 12, 16.0 / 12, -30.0 / 12, 16.0 / 12, -1.0 / 12};
-  static const double d2_6[] = {2.0 / 180, -27.0 / 180, 270.0 / 180, -490.0 / 180, 270.0 / 180, -27.0 / 180, 2.0 / 180};
-  const double* src = nullptr;
-  if (d == 1) src = order == 2 ? d1_2 : order == 4 ? d1_4 : order == 6 ? d1_6 : nullptr;
-  if (d == 2) src = order == 2 ? d2_2 : order == 4 ? d2_4 : order == 6 ? d2_6 : nullptr;
-  if (!src) return false;
-  for (int i = 0; i <= order; ++i) t[i] = src[i];
-  return true;
-}
 
 struct Layout {
   size_t field_bytes = 0, ring_bytes = 0, host_tab_bytes = 0;
@@ -107,7 +77,7 @@ at_status fail(at_ctx* ctx, at_status st, const char* fmt, ...) {
   vsnprintf(buf, sizeof(buf), fmt, ap);
   va_end(ap);
   if (ctx) ctx->err = buf;
-  g_thread_error = buf;
+  thread_error() = buf;
   return st;
 }
 
@@ -623,7 +593,7 @@ at_status at_destroy(at_ctx* c) {
 
 const char* at_last_error(const at_ctx* c) {
   if (c) return c->err.c_str();
-  return g_thread_error.c_str();
+  return thread_error().c_str();
 }
 
 }  // extern "C"

@@ -1,0 +1,393 @@
+// libatfd host side of the delay ensembles (at_ens_* in include/atfd.h):
+// member validation, the workgroup schedule, workspace layout, the persistent
+// launch and its HIP graph.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ensemble.hpp"
+#include "host_common.hpp"
+
+using namespace atfd;
+
+struct at_ens {
+  int count = 0;
+  bool f64 = false;
+  std::vector<EnsMember> mem;
+  std::vector<int> bin_start, order;
+  int groups_per_cu = 1, threads = 1024, nbins = 0, cus = 256;
+  size_t total_points = 0, field_bytes = 0, ring_elems = 0, halo_elems = 0;
+  size_t off_mem = 0, off_bins = 0, off_order = 0, off_u[2] = {0, 0}, off_f = 0, off_ring = 0, off_hbuf = 0;
+  size_t off_counter = 0, off_out = 0, off_phase = 0, total = 0;
+  bool any_ab2 = false;
+  EnsParams ep{};
+  unsigned char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t n = 0;
+  bool state_set = false;
+  std::string err;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_nsteps = 0;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+constexpr int kPhaseMax = 1 << 16;   // doubles of per-member phases staged for at_ens_norms
+
+at_status efail(at_ens* e, at_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (e) e->err = buf;
+  thread_error() = buf;
+  return st;
+}
+
+#define ENS_TRY(e, call)                                                                 \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return efail(e, AT_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+at_status check_member(int i, const at_ens_member& m) {
+  const int s = m.order / 2;
+  if (m.order != 2 && m.order != 4 && m.order != 6)
+    return efail(nullptr, AT_EINVAL, "member %d: order must be 2, 4 or 6", i);
+  if (m.n < 1 || m.pe < 1 || m.n % m.pe) return efail(nullptr, AT_EINVAL, "member %d: n must be a multiple of pe", i);
+  if (m.n > (int64_t(1) << 30)) return efail(nullptr, AT_EINVAL, "member %d: n too large", i);
+  if (m.n / m.pe < 2 * s) return efail(nullptr, AT_EINVAL, "member %d: PE edge < 2s", i);
+  if (m.integrator != AT_EULER && m.integrator != AT_AB2)
+    return efail(nullptr, AT_EINVAL, "member %d: integrator must be AT_EULER or AT_AB2", i);
+  if (m.mode != AT_DELAY_RNG && m.mode != AT_DELAY_ZERO && m.mode != AT_SYNC)
+    return efail(nullptr, AT_EINVAL, "member %d: mode must be RNG, ZERO or SYNC", i);
+  if (!(m.dt > 0) || !(m.length > 0)) return efail(nullptr, AT_EINVAL, "member %d: dt and length must be > 0", i);
+  if (m.mode != AT_SYNC) {
+    const int T = m.T == 0 ? s + 1 : m.T;
+    if (m.L < 1 || m.L > kMaxL) return efail(nullptr, AT_EINVAL, "member %d: L must be 1..%d", i, kMaxL);
+    if (T < 1 || T > kMaxT) return efail(nullptr, AT_EINVAL, "member %d: T must be 1..%d", i, kMaxT);
+    uint64_t thr[kMaxL];
+    if (!make_thresholds(m.L, m.weights, thr)) return efail(nullptr, AT_EINVAL, "member %d: bin weights sum to 0", i);
+  }
+  return AT_OK;
+}
+
+// Descriptors and workspace layout; fills `e` (without the workspace pointer).
+at_status plan(at_ens* e, int32_t count, const at_ens_member* m, int32_t precision) {
+  if (count < 1 || !m) return efail(nullptr, AT_EINVAL, "need at least one member");
+  if (precision != AT_F64 && precision != AT_F32_F64B) return efail(nullptr, AT_EINVAL, "unknown precision");
+  e->count = count;
+  e->f64 = precision == AT_F64;
+  e->mem.assign(count, EnsMember{});
+  size_t pts = 0, ring = 0, halo = 0;
+  for (int i = 0; i < count; ++i) {
+    at_status st = check_member(i, m[i]);
+    if (st != AT_OK) return st;
+    EnsMember& d = e->mem[i];
+    d.off = static_cast<int64_t>(pts);
+    d.n = m[i].n;
+    d.npe = m[i].pe;
+    d.b = static_cast<int>(m[i].n / m[i].pe);
+    d.s = m[i].order / 2;
+    d.T = m[i].mode == AT_SYNC ? 1 : (m[i].T == 0 ? d.s + 1 : m[i].T);
+    d.L = m[i].mode == AT_SYNC ? 1 : m[i].L;
+    d.nslots = m[i].mode == AT_SYNC ? 0 : d.L + d.T;
+    d.integrator = m[i].integrator;
+    d.mode = m[i].mode;
+    d.key = m[i].seed;
+    make_thresholds(d.L, m[i].mode == AT_SYNC ? nullptr : m[i].weights, d.thr);
+    for (int k = 0; k < d.L; ++k) level_weights(k, d.T, d.wt[k]);
+    d.dt = m[i].dt;
+    d.length = m[i].length;
+    d.c = m[i].c;
+    d.alpha = m[i].alpha;
+    double t1[2 * kMaxS + 1] = {0}, t2[2 * kMaxS + 1] = {0};
+    cd_taps(1, m[i].order, t1);
+    cd_taps(2, m[i].order, t2);
+    const double dx = m[i].length / static_cast<double>(m[i].n);
+    for (int o = 0; o <= 2 * d.s; ++o) {
+      d.kad[o] = m[i].alpha * t2[o] / (dx * dx) - m[i].c * t1[o] / dx;
+      d.kadf[o] = static_cast<float>(d.kad[o]);
+    }
+    d.ring_off = static_cast<int64_t>(ring);
+    ring += static_cast<size_t>(d.nslots) * d.npe * 2 * d.s;
+    d.hoff = static_cast<int64_t>(halo);
+    halo += static_cast<size_t>(d.npe) * 2 * d.s;
+    d.vec = (d.b % 4 == 0 && pts % 4 == 0) ? 1 : 0;
+    pts += static_cast<size_t>(m[i].n);
+    e->any_ab2 = e->any_ab2 || m[i].integrator == AT_AB2;
+  }
+  e->total_points = pts;
+  e->ring_elems = ring;
+  e->halo_elems = halo;
+  const size_t w = e->f64 ? 8 : 4;
+  e->field_bytes = pts * w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  e->off_mem = take(sizeof(EnsMember) * count);
+  e->off_bins = take(sizeof(int) * (count + 1));
+  e->off_order = take(sizeof(int) * count);
+  e->off_u[0] = take(e->field_bytes);
+  e->off_u[1] = take(e->field_bytes);
+  e->off_f = e->any_ab2 ? take(e->field_bytes) : 0;
+  e->off_ring = ring ? take(ring * w) : 0;
+  e->off_hbuf = take(halo * w);
+  e->off_counter = take(2 * sizeof(int64_t));
+  e->off_out = take(sizeof(double) * 4 * count);
+  e->off_phase = take(sizeof(double) * kPhaseMax);
+  e->total = off;
+  return AT_OK;
+}
+
+// Longest-first balance: members sorted by work, each to the least loaded
+// workgroup; workgroups ordered by load so the heaviest start first.
+void schedule(at_ens* e) {
+  const int count = e->count;
+  int nb = std::min(count, std::max(1, e->groups_per_cu * e->cus));
+  std::vector<int> idx(count);
+  for (int i = 0; i < count; ++i) idx[i] = i;
+  auto work = [&](int i) {
+    const EnsMember& d = e->mem[i];
+    return static_cast<double>(d.n) * (d.integrator == AT_AB2 ? 1.5 : 1.0);
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<double> load(nb, 0.0);
+  std::vector<std::vector<int>> bins(nb);
+  for (int i : idx) {
+    int best = 0;
+    for (int j = 1; j < nb; ++j)
+      if (load[j] < load[best]) best = j;
+    load[best] += work(i);
+    bins[best].push_back(i);
+  }
+  std::vector<int> bo(nb);
+  for (int j = 0; j < nb; ++j) bo[j] = j;
+  std::stable_sort(bo.begin(), bo.end(), [&](int a, int b) { return load[a] > load[b]; });
+  e->bin_start.assign(1, 0);
+  e->order.clear();
+  for (int j : bo) {
+    for (int i : bins[j]) e->order.push_back(i);
+    e->bin_start.push_back(static_cast<int>(e->order.size()));
+  }
+  e->nbins = nb;
+}
+
+at_status upload_schedule(at_ens* e) {
+  ENS_TRY(e, hipMemcpyAsync(e->ws + e->off_bins, e->bin_start.data(), sizeof(int) * e->bin_start.size(),
+                            hipMemcpyHostToDevice, e->stream));
+  ENS_TRY(e, hipMemcpyAsync(e->ws + e->off_order, e->order.data(), sizeof(int) * e->order.size(),
+                            hipMemcpyHostToDevice, e->stream));
+  ENS_TRY(e, hipStreamSynchronize(e->stream));
+  return AT_OK;
+}
+
+void drop_graph(at_ens* e) {
+  if (e->graph_exec) hipGraphExecDestroy(e->graph_exec);
+  if (e->graph) hipGraphDestroy(e->graph);
+  e->graph_exec = nullptr;
+  e->graph = nullptr;
+  e->graph_nsteps = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+at_status at_ens_workspace_size(int32_t count, const at_ens_member* members, int32_t precision,
+                                size_t* bytes) {
+  if (!bytes) return efail(nullptr, AT_EINVAL, "null argument");
+  at_ens tmp;
+  at_status st = plan(&tmp, count, members, precision);
+  if (st != AT_OK) return st;
+  *bytes = tmp.total;
+  return AT_OK;
+}
+
+at_status at_ens_create(int32_t count, const at_ens_member* members, int32_t precision, void* ws_dev,
+                        size_t ws_bytes, void* hip_stream, at_ens** out) {
+  if (!out || !ws_dev) return efail(nullptr, AT_EINVAL, "null argument");
+  *out = nullptr;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign)
+    return efail(nullptr, AT_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+  at_ens* e = new (std::nothrow) at_ens;
+  if (!e) return efail(nullptr, AT_ENOMEM, "host allocation failed");
+  at_status st = plan(e, count, members, precision);
+  if (st != AT_OK) {
+    delete e;
+    return st;
+  }
+  if (ws_bytes < e->total) {
+    const size_t need = e->total;
+    delete e;
+    return efail(nullptr, AT_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  }
+  e->ws = static_cast<unsigned char*>(ws_dev);
+  e->stream = static_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      prop.multiProcessorCount > 0)
+    e->cus = prop.multiProcessorCount;
+  schedule(e);
+  EnsParams& p = e->ep;
+  p.mem = reinterpret_cast<const EnsMember*>(e->ws + e->off_mem);
+  p.bin_start = reinterpret_cast<const int*>(e->ws + e->off_bins);
+  p.order = reinterpret_cast<const int*>(e->ws + e->off_order);
+  p.u[0] = e->ws + e->off_u[0];
+  p.u[1] = e->ws + e->off_u[1];
+  p.f = e->any_ab2 ? e->ws + e->off_f : nullptr;
+  p.ring = e->ring_elems ? e->ws + e->off_ring : nullptr;
+  p.hbuf = e->ws + e->off_hbuf;
+  p.counter = reinterpret_cast<int64_t*>(e->ws + e->off_counter);
+  hipError_t he = hipMemcpyAsync(e->ws + e->off_mem, e->mem.data(), sizeof(EnsMember) * count,
+                                 hipMemcpyHostToDevice, e->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(p.counter, 0, 2 * sizeof(int64_t), e->stream);
+  if (he != hipSuccess) {
+    delete e;
+    return efail(nullptr, AT_EHIP, "ensemble set-up: %s", hipGetErrorString(he));
+  }
+  st = upload_schedule(e);
+  if (st != AT_OK) {
+    delete e;
+    return st;
+  }
+  *out = e;
+  return AT_OK;
+}
+
+at_status at_ens_set_state(at_ens* e, const void* u0_dev) {
+  if (!e || !u0_dev) return efail(e, AT_EINVAL, "null argument");
+  ENS_TRY(e, hipMemcpyAsync(e->ep.u[0], u0_dev, e->field_bytes, hipMemcpyDeviceToDevice, e->stream));
+  ENS_TRY(e, hipMemsetAsync(e->ep.counter, 0, 2 * sizeof(int64_t), e->stream));
+  if (e->ring_elems) ENS_TRY(e, launch_ens_publish_all(e->ep, e->f64, e->count, e->stream));
+  e->n = 0;
+  e->state_set = true;
+  return AT_OK;
+}
+
+at_status at_ens_run(at_ens* e, int64_t nsteps) {
+  if (!e || nsteps < 0) return efail(e, AT_EINVAL, "bad arguments");
+  if (!e->state_set) return efail(e, AT_ESTATE, "at_ens_run before at_ens_set_state");
+  if (nsteps == 0) return AT_OK;
+  if (e->graph_nsteps != nsteps) {
+    drop_graph(e);
+    if (!e->cap_stream) ENS_TRY(e, hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking));
+    EnsParams p = e->ep;
+    p.nsteps = nsteps;
+    ENS_TRY(e, hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_ens_steps(p, e->f64, e->nbins, e->threads, e->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t ce = hipStreamEndCapture(e->cap_stream, &gr);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (gr) hipGraphDestroy(gr);
+      return efail(e, AT_EHIP, "ensemble graph capture: %s",
+                   hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    e->graph = gr;
+    ENS_TRY(e, hipGraphInstantiate(&e->graph_exec, e->graph, nullptr, nullptr, 0));
+    e->graph_nsteps = nsteps;
+  }
+  ENS_TRY(e, hipGraphLaunch(e->graph_exec, e->stream));
+  e->n += nsteps;
+  return AT_OK;
+}
+
+at_status at_ens_set_tuning(at_ens* e, int32_t groups_per_cu, int32_t threads) {
+  if (!e) return efail(nullptr, AT_EINVAL, "null ensemble");
+  if (groups_per_cu != 0 && groups_per_cu != 1 && groups_per_cu != 2 && groups_per_cu != 4)
+    return efail(e, AT_EINVAL, "workgroups per CU must be 1, 2 or 4");
+  if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+    return efail(e, AT_EINVAL, "threads must be 256, 512 or 1024");
+  const int g = groups_per_cu ? groups_per_cu : e->groups_per_cu;
+  const int t = threads ? threads : e->threads;
+  if (g == e->groups_per_cu && t == e->threads) return AT_OK;
+  drop_graph(e);
+  e->threads = t;
+  if (g != e->groups_per_cu) {
+    e->groups_per_cu = g;
+    schedule(e);
+    return upload_schedule(e);
+  }
+  return AT_OK;
+}
+
+at_status at_ens_get_state(at_ens* e, void* u_dev) {
+  if (!e || !u_dev) return efail(e, AT_EINVAL, "null argument");
+  ENS_TRY(e, hipMemcpyAsync(u_dev, e->ep.u[e->n & 1], e->field_bytes, hipMemcpyDeviceToDevice, e->stream));
+  return AT_OK;
+}
+
+at_status at_ens_get_step(const at_ens* e, int64_t* n) {
+  if (!e || !n) return efail(nullptr, AT_EINVAL, "null argument");
+  *n = e->n;
+  return AT_OK;
+}
+
+at_status at_ens_norms(at_ens* e, int32_t nmodes, const int32_t* kappa, const double* amp,
+                       const double* phase, const double* ref_dev, double* out) {
+  if (!e || !out) return efail(e, AT_EINVAL, "null argument");
+  if (nmodes < 0 || nmodes > kMaxModes) return efail(e, AT_EINVAL, "0..%d modes", kMaxModes);
+  if (nmodes > 0 && (!kappa || !amp || !phase)) return efail(e, AT_EINVAL, "modes need kappa, amp, phase");
+  if (nmodes == 0 && !ref_dev) return efail(e, AT_EINVAL, "need modes or a reference field");
+  if (static_cast<int64_t>(e->count) * nmodes > kPhaseMax) return efail(e, AT_EINVAL, "too many phases");
+  EnsNormParams p{};
+  p.mem = e->ep.mem;
+  p.u = e->ep.u[e->n & 1];
+  p.ref = ref_dev;
+  p.nstep = e->n;
+  p.nmodes = nmodes;
+  for (int m = 0; m < nmodes; ++m) {
+    p.kap[m] = kappa[m];
+    p.amp[m] = amp[m];
+  }
+  double* dphase = reinterpret_cast<double*>(e->ws + e->off_phase);
+  p.phase = dphase;
+  p.out = reinterpret_cast<double*>(e->ws + e->off_out);
+  if (nmodes > 0)
+    ENS_TRY(e, hipMemcpyAsync(dphase, phase, sizeof(double) * e->count * nmodes, hipMemcpyHostToDevice,
+                              e->stream));
+  ENS_TRY(e, launch_ens_norms(p, e->f64, e->count, e->stream));
+  std::vector<double> host(static_cast<size_t>(e->count) * 4);
+  ENS_TRY(e, hipMemcpyAsync(host.data(), p.out, sizeof(double) * host.size(), hipMemcpyDeviceToHost, e->stream));
+  ENS_TRY(e, hipStreamSynchronize(e->stream));
+  bool bad = false;
+  for (int i = 0; i < e->count; ++i) {
+    const double nn = static_cast<double>(e->mem[i].n);
+    out[3 * i + 0] = host[4 * i + 0] / nn;
+    out[3 * i + 1] = std::sqrt(host[4 * i + 1] / nn);
+    out[3 * i + 2] = host[4 * i + 2];
+    if (host[4 * i + 3] > 0 || !std::isfinite(out[3 * i + 1])) bad = true;
+  }
+  if (bad) return efail(e, AT_EUNSTABLE, "non-finite values in the ensemble at step %lld", (long long)e->n);
+  return AT_OK;
+}
+
+at_status at_ens_destroy(at_ens* e) {
+  if (!e) return AT_OK;
+  drop_graph(e);
+  if (e->cap_stream) hipStreamDestroy(e->cap_stream);
+  delete e;
+  return AT_OK;
+}
+
+const char* at_ens_last_error(const at_ens* e) {
+  if (e) return e->err.c_str();
+  return thread_error().c_str();
+}
+
+}  // extern "C"

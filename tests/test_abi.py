@@ -116,3 +116,54 @@ def test_host_delay_table_is_validated():
     tab[2, 1, 0, 1] = 2
     st, _ = _size(L, lib, p, d)
     assert st == L.AT_OK
+
+
+def _members(specs):
+    L, _ = _lib()
+    arr = (L.AtEnsMember * len(specs))()
+    for i, sp in enumerate(specs):
+        m = dict(n=128, pe=4, order=2, integrator=0, L=3, T=0, mode=0, length=2 * math.pi, c=1.0,
+                 alpha=0.1, dt=1e-4, seed=i)
+        m.update(sp)
+        for k, v in m.items():
+            setattr(arr[i], k, v)
+    return arr
+
+
+def test_ensemble_workspace_size_accounts_for_members():
+    L, lib = _lib()
+    arr = _members([{}, dict(n=256, pe=4, order=4, integrator=1, L=4)])
+    size = ctypes.c_size_t(0)
+    assert lib.at_ens_workspace_size(2, arr, 1, ctypes.byref(size)) == L.AT_OK
+    # two fields + the AB2 history of 384 floats, rings of 5 and 7 slots
+    ring = (5 * 4 * 2 * 1 + 7 * 4 * 2 * 2) * 4
+    assert size.value >= 3 * 384 * 4 + ring
+    size64 = ctypes.c_size_t(0)
+    assert lib.at_ens_workspace_size(2, arr, 0, ctypes.byref(size64)) == L.AT_OK
+    assert size64.value > size.value
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=100, pe=3),              # n not a multiple of pe
+    dict(n=6, pe=2, order=4),       # PE edge 3 < 2s
+    dict(order=5),
+    dict(integrator=3),             # RK2 is not offered for ensembles
+    dict(L=9),
+    dict(T=5),
+    dict(mode=2),                   # host delay tables are not offered for ensembles
+    dict(dt=0.0),
+])
+def test_ensemble_invalid_members_are_rejected(bad):
+    L, lib = _lib()
+    arr = _members([{}, bad])
+    size = ctypes.c_size_t(0)
+    assert lib.at_ens_workspace_size(2, arr, 1, ctypes.byref(size)) == L.AT_EINVAL
+    assert b"member 1" in lib.at_ens_last_error(None)
+
+
+def test_ensemble_needs_members_and_precision():
+    L, lib = _lib()
+    arr = _members([{}])
+    size = ctypes.c_size_t(0)
+    assert lib.at_ens_workspace_size(0, arr, 1, ctypes.byref(size)) == L.AT_EINVAL
+    assert lib.at_ens_workspace_size(1, arr, 7, ctypes.byref(size)) == L.AT_EINVAL

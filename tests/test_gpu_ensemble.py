@@ -1,0 +1,210 @@
+"""GPU parity of the delay ensemble (one persistent launch for all members and
+steps) against the FP64 oracle run member by member.
+
+Each member is an independent periodic 1-D advection-diffusion problem with
+its own grid, PEs, scheme, L and generator key; the oracle runs it as a
+single problem with the same key. Tolerances as for single problems:
+relative L2 <= 1e-12 (FP64), <= 1e-5 (FP32 bulk, FP64 AT combination).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.analytic import advected_modes
+from oracle.norms import error_norms
+from oracle.solver import DelayModel, Oracle, Problem
+from tests._cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+KAPPAS, AMPS = (1, 2, 3), (1.0, 0.5, 0.25)
+
+# ragged PE edges (12, 20), every order, both integrators, L from 1 to 8,
+# non-uniform bins, the asynchronous standard scheme (T = 1), ZERO and SYNC
+MEMBERS = [
+    dict(n=128, pe=4, order=2, integrator="euler", L=3, mode="rng", c=1.0, ra=0.1, seed=11),
+    dict(n=192, pe=6, order=4, integrator="ab2", L=4, mode="rng", c=-0.5, ra=0.02, seed=12),
+    dict(n=96, pe=3, order=4, integrator="ab2", L=8, mode="rng", c=0.3, ra=0.005, seed=13),
+    dict(n=60, pe=5, order=2, integrator="euler", L=2, mode="zero", c=1.0, ra=0.1, seed=14),
+    dict(n=64, pe=4, order=4, integrator="ab2", L=1, mode="sync", c=1.0, ra=0.02, seed=15),
+    dict(n=120, pe=6, order=6, integrator="ab2", L=3, mode="rng", c=0.7, ra=0.004, seed=16),
+    dict(n=256, pe=4, order=2, integrator="euler", L=3, mode="rng", c=1.0, ra=0.1, seed=17, weights=[6, 3, 1]),
+    dict(n=72, pe=6, order=4, integrator="ab2", L=3, T=1, mode="rng", c=1.0, ra=0.02, seed=18),
+    dict(n=64, pe=1, order=4, integrator="euler", L=2, mode="rng", c=1.0, ra=0.02, seed=19),
+]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _members(spec):
+    out = []
+    for m in spec:
+        m = dict(m)
+        ra = m.pop("ra")
+        dx = 2 * math.pi / m["n"]
+        m.setdefault("alpha", 0.1)
+        m["dt"] = ra * dx * dx / m["alpha"]
+        m.setdefault("T", 0)
+        m.setdefault("length", 2 * math.pi)
+        out.append(m)
+    return out
+
+
+def _phases(count, seed=21):
+    return np.random.Generator(np.random.PCG64(seed)).uniform(0, 2 * math.pi, size=(count, len(KAPPAS)))
+
+
+def _u0(members, phases):
+    parts = []
+    for m, ph in zip(members, phases):
+        modes = W.make_modes([(k,) for k in KAPPAS], AMPS, phis=list(ph))
+        parts.append(W.eval_modes(modes, (m["n"],), 1).reshape(-1))
+    return np.concatenate(parts)
+
+
+def _oracle(m, u0):
+    prob = Problem(ndim=1, n=(m["n"],), pe=(m["pe"],), dt=m["dt"], order=m["order"], c=(m["c"],),
+                   alpha=m["alpha"], integrator=m["integrator"])
+    dm = DelayModel(L=m["L"], T=m["T"], mode=m["mode"], seed=m["seed"], weights=m.get("weights"))
+    return Oracle(prob, dm, torch.as_tensor(u0, dtype=torch.float64).reshape(1, 1, -1))
+
+
+def _ensemble(members, precision):
+    from paper_1702_00496_amd import Ensemble
+    return Ensemble(members, precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_ensemble_matches_oracle_member_by_member(precision):
+    members = _members(MEMBERS)
+    ph = _phases(len(members))
+    u0 = _u0(members, ph)
+    steps = 60
+    _say(f"[ens] parity {precision}: {len(members)} members, {steps} steps")
+    ens = _ensemble(members, precision)
+    ens.set_state(torch.from_numpy(u0))
+    ens.run(steps)
+    got = ens.split(ens.state().cpu())
+    off = 0
+    for i, m in enumerate(members):
+        o = _oracle(m, u0[off:off + m["n"]])
+        o.run(steps)
+        err = rel_l2(got[i], o.u.reshape(-1))
+        _say(f"[ens]   member {i} n={m['n']} order={m['order']} {m['integrator']} L={m['L']} {m['mode']}: {err:.3e}")
+        assert err <= TOL[precision], (i, err)
+        off += m["n"]
+
+
+def test_ensemble_zero_delays_equal_synchronous_bitwise():
+    base = [dict(m, mode="zero") for m in MEMBERS]
+    sync = [dict(m, mode="sync") for m in MEMBERS]
+    a_m, b_m = _members(base), _members(sync)
+    u0 = torch.from_numpy(_u0(a_m, _phases(len(a_m))))
+    out = []
+    for mem in (a_m, b_m):
+        e = _ensemble(mem, "f32")
+        e.set_state(u0)
+        e.run(50)
+        out.append(e.state().cpu())
+    assert torch.equal(out[0], out[1])
+
+
+def test_ensemble_schedules_and_run_splits_are_bit_identical():
+    members = _members(MEMBERS)
+    u0 = torch.from_numpy(_u0(members, _phases(len(members))))
+    ref = _ensemble(members, "f32")
+    ref.set_state(u0)
+    ref.run(40)
+    want = ref.state().cpu()
+    for g, t in ((1, 256), (4, 1024), (2, 512)):
+        e = _ensemble(members, "f32")
+        e.set_tuning(g, t)
+        e.set_state(u0)
+        e.run(40)
+        assert torch.equal(e.state().cpu(), want), (g, t)
+    # the same 40 steps as 15 + 25 and as a replayed 10-step graph
+    e = _ensemble(members, "f32")
+    e.set_state(u0)
+    e.run(15)
+    e.run(25)
+    assert torch.equal(e.state().cpu(), want)
+    e.set_state(u0)
+    for _ in range(4):
+        e.run(10)
+    assert e.n_step == 40
+    assert torch.equal(e.state().cpu(), want)
+
+
+def test_ensemble_norms_match_oracle_norms():
+    members = _members(MEMBERS)
+    ph = _phases(len(members))
+    u0 = _u0(members, ph)
+    steps = 30
+    ens = _ensemble(members, "f64")
+    ens.set_state(torch.from_numpy(u0))
+    ens.run(steps)
+    got = ens.norms(KAPPAS, AMPS, ph)
+    packed = ens.state().cpu()
+    parts = ens.split(packed)
+    refs = []
+    for i, m in enumerate(members):
+        prob = Problem(ndim=1, n=(m["n"],), pe=(m["pe"],), dt=m["dt"], order=m["order"], c=(m["c"],),
+                       alpha=m["alpha"])
+        modes = W.make_modes([(k,) for k in KAPPAS], AMPS, phis=list(ph[i]))
+        ua = advected_modes(prob, modes, steps * m["dt"]).reshape(-1)
+        refs.append(ua)
+        e = error_norms(parts[i].to(torch.float64), ua)
+        assert got[i, 0] == pytest.approx(e["l1"], rel=1e-9)
+        assert got[i, 1] == pytest.approx(e["l2"], rel=1e-9)
+        assert got[i, 2] == pytest.approx(e["linf"], rel=1e-9)
+    # against a packed reference field the same numbers come back
+    again = ens.norms(ref=torch.cat(refs))
+    # (the two references differ by a few ulps of the O(1) field)
+    assert np.allclose(again, got, rtol=1e-9, atol=1e-12)
+
+
+def test_ensemble_rejects_bad_members():
+    from paper_1702_00496_amd import ATError
+    bad = _members([dict(n=100, pe=3, order=2, integrator="euler", L=3, mode="rng", c=1.0, ra=0.1, seed=1)])
+    with pytest.raises(ATError):
+        _ensemble(bad, "f32")
+
+
+def test_ensemble_full_workload_properties():
+    """The 512-member, 2000-step delay ensemble in FP32: finite everywhere,
+    every member's error against the exact solution small, and the two
+    smallest members equal to the FP64 oracle."""
+    inst = W.ensemble_instances()
+    members = [dict(n=m["n"], pe=m["pe"], order=m["order"], integrator=m["integrator"], L=m["L"], T=m["T"],
+                    mode="rng", length=2 * math.pi, c=m["c"], alpha=m["alpha"], dt=m["dt"], seed=m["seed"])
+               for m in inst]
+    ph = np.array([[mo[2] for mo in m["modes"]] for m in inst])
+    kap = [mo[0][0] for mo in inst[0]["modes"]]
+    amp = [mo[1] for mo in inst[0]["modes"]]
+    parts = [W.eval_modes(m["modes"], (m["n"],), 1).reshape(-1) for m in inst]
+    u0 = np.concatenate(parts)
+    steps = 2000
+    _say(f"[ens] full workload: {len(members)} members, {u0.size} points, {steps} steps")
+    ens = _ensemble(members, "f32")
+    ens.set_state(torch.from_numpy(u0))
+    ens.run(steps)
+    err = ens.norms(kap, amp, ph)
+    assert np.isfinite(err).all()
+    # the delay error of these schemes is far below the field's O(1) size
+    assert err[:, 1].max() < 1e-2, err[:, 1].max()
+    got = ens.split(ens.state().cpu())
+    small = sorted(range(len(members)), key=lambda i: members[i]["n"])[:2]
+    for i in small:
+        o = _oracle(members[i], parts[i])
+        o.run(steps)
+        r = rel_l2(got[i], o.u.reshape(-1))
+        _say(f"[ens]   member {i} n={members[i]['n']} order={members[i]['order']} L={members[i]['L']}: {r:.3e}")
+        assert r <= TOL["f32"], (i, r)
