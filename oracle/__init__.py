@@ -15,8 +15,11 @@ schemes for partial differential equations" (arXiv 1702.00496) define:
                time_disc / time_ab2; Sec. 5 eq. general);
 - ``analytic`` the exact decaying advected Fourier series (Sec. 5.1 eq. ana_sol);
 - ``norms``    space averages of the error (Sec. 4) and ensemble statistics;
-- ``ensemble`` many independent 1-D delay realisations;
-- ``adjoint``  gradients of a final-time misfit through torch CPU autograd.
+- ``adjoint``  gradients of a final-time function through torch CPU autograd
+               of the forward steps.
+
+A delay ensemble member is a single 1-D problem of ``solver`` with its own
+generator key, so ensembles need no module of their own.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import anything from here. The product library never does and
