@@ -198,6 +198,30 @@ at_status at_destroy(at_ctx* ctx);
 const char* at_last_error(const at_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Discrete adjoint of the AT step (advection-diffusion; Euler or AB2; every
+ * delay mode). This is not in the paper: it is the exact transpose of the
+ * discrete linear map that at_step applies, so that gradients of a function
+ * J(u^N) of the field after N steps can be taken with respect to the initial
+ * field and the diffusivity.
+ *
+ * at_adjoint runs the N forward steps from the state set at step 0, saving a
+ * checkpoint every `every` steps, then sweeps backwards: each segment is
+ * recomputed from its checkpoint, its levels kept, and the transposed steps
+ * are applied from lambda^N = seed (dJ/du^N, bulk precision, device) down to
+ * lambda^0 = dJ/du^0, which is written to grad_u0_dev. Contributions to older
+ * levels through the AT halos go to an adjoint ring of the forward ring's
+ * shape (the delayed levels' transpose). *grad_alpha receives
+ * dJ/dalpha = sum_n <dJ/df^n, d f^n / d alpha>, accumulated in double in a
+ * fixed order. The context is left at step N with the forward field.
+ * Scratch (device, 256-B aligned) of at_adjoint_scratch_size bytes holds the
+ * checkpoints, one segment of levels, three adjoint fields and the adjoint
+ * ring. Synchronises the stream. AT_ESTATE unless the context is at step 0.
+ */
+at_status at_adjoint_scratch_size(at_ctx* ctx, int64_t nsteps, int32_t every, size_t* bytes);
+at_status at_adjoint(at_ctx* ctx, int64_t nsteps, int32_t every, const void* seed_dev, void* scratch_dev,
+                     size_t scratch_bytes, void* grad_u0_dev, double* grad_alpha);
+
+/* ------------------------------------------------------------------------
  * Delay ensembles: many independent 1-D advection-diffusion problems, each
  * with its own grid, PE count, scheme, L and generator key, advanced together
  * in one persistent launch. Their errors give the statistics over delay

@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import ATError, AtDelay, AtEnsMember, AtProblem, check
 
-__all__ = ["Solver", "Ensemble", "ATError", "lib", "VARIANTS"]
+__all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS"]
 
 # schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
 VARIANTS = (1, 2, 4, 9, 10, 12)
@@ -162,6 +162,23 @@ class Solver:
         keys = ["l1", "l2", "linf", "l1_b", "l2_b", "l1_i", "l2_i", "n_b", "n_i"]
         return dict(zip(keys, list(out)))
 
+    # -- adjoint
+    def adjoint(self, nsteps, seed, every=64):
+        """dJ/du^0 and dJ/dalpha for J(u^N) with dJ/du^N = seed, N = nsteps steps
+        from the state set at step 0 (at_adjoint). Leaves the solver at step N."""
+        seed = seed.to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(seed.shape) != self.shape:
+            raise ValueError(f"seed shape {tuple(seed.shape)} != {self.shape}")
+        nbytes = ctypes.c_size_t(0)
+        check(self._lib.at_adjoint_scratch_size(self._ctx, int(nsteps), int(every), ctypes.byref(nbytes)),
+              self._ctx)
+        scratch = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        grad = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        ga = ctypes.c_double(0.0)
+        check(self._lib.at_adjoint(self._ctx, int(nsteps), int(every), _as_ptr(seed), _as_ptr(scratch),
+                                   scratch.numel(), _as_ptr(grad), ctypes.byref(ga)), self._ctx)
+        return grad, ga.value
+
     # -- checkpoints
     def checkpoint_size(self):
         v = ctypes.c_size_t(0)
@@ -285,3 +302,36 @@ class Ensemble:
             st = self._lib.at_ens_norms(self._ctx, 0, None, None, None, _as_ptr(ref), optr)
         self._check(st)
         return out
+
+
+class ATEvolve(torch.autograd.Function):
+    """u^N = ATEvolve.apply(u0, alpha, spec, nsteps, every): N AT steps of the
+    problem ``spec`` (Solver keyword arguments without alpha) from u0 with
+    diffusivity alpha. The backward pass is the library's hand-written
+    adjoint (at_adjoint), with checkpoints every ``every`` steps."""
+
+    @staticmethod
+    def forward(ctx, u0, alpha, spec, nsteps, every):
+        a = float(alpha)
+        s = Solver(alpha=a, **spec)
+        s.set_state(u0.detach())
+        s.step(int(nsteps))
+        out = s.state()
+        ctx.save_for_backward(u0.detach())
+        ctx.alpha, ctx.spec, ctx.nsteps, ctx.every = a, spec, int(nsteps), int(every)
+        ctx.alpha_is_tensor = torch.is_tensor(alpha)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (u0,) = ctx.saved_tensors
+        s = Solver(alpha=ctx.alpha, **ctx.spec)
+        s.set_state(u0)
+        gu, ga = s.adjoint(ctx.nsteps, g.contiguous(), ctx.every)
+        galpha = torch.tensor(ga, dtype=torch.float64, device=u0.device) if ctx.alpha_is_tensor else None
+        return gu.to(u0.dtype), galpha, None, None, None
+
+
+def evolve(u0, alpha, nsteps, every=64, **spec):
+    """Differentiable N-step AT evolution (see ATEvolve)."""
+    return ATEvolve.apply(u0, alpha, spec, nsteps, every)

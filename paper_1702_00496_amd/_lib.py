@@ -91,6 +91,8 @@ SIGNATURES = {
     "at_load": (I32, [P, P]),
     "at_destroy": (I32, [P]),
     "at_last_error": (ctypes.c_char_p, [P]),
+    "at_adjoint_scratch_size": (I32, [P, I64, I32, ctypes.POINTER(SZ)]),
+    "at_adjoint": (I32, [P, I64, I32, P, P, SZ, P, DP]),
     "at_ens_workspace_size": (I32, [I32, ctypes.POINTER(AtEnsMember), I32, ctypes.POINTER(SZ)]),
     "at_ens_create": (I32, [I32, ctypes.POINTER(AtEnsMember), I32, P, SZ, P, ctypes.POINTER(P)]),
     "at_ens_set_state": (I32, [P, P]),

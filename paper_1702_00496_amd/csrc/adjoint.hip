@@ -1,2 +1,294 @@
-// Discrete adjoint of the AT step; see at_adjoint* in atfd.h.
-#include "atfd_internal.hpp"
+// Discrete adjoint of the AT time step (advection-diffusion; Euler or AB2).
+//
+// The forward step is linear in the solution levels:
+//   f^n_i = sum_axes sum_{o != 0} kad_o (v_{i+o} - u^n_i),
+//   kad_o = alpha c2_o / dx^2 - c c1_o / dx,
+// where v_{i+o} = u^n_{i+o} for a tap inside the PE of i (Sec. 2 eq.
+// general_deriv) and, for a tap across face f of that PE, the AT combination
+// sum_m c_m(k) u^{n-k-m}_{i+o} with the face's delay k (Sec. 3.4 Example 3 eq.
+// cd4-at); u^{n+1} = u^n + dt sum_j beta_j f^{n-j} (Sec. 4.1 eqs. time_disc,
+// time_ab2). With lambda^l = dJ/du^l and mu^n = dJ/df^n = dt (beta_0
+// lambda^{n+1} + beta_1 lambda^{n+2}), the reverse sweep is
+//   lambda^n_j = lambda^{n+1}_j - (sum kad) mu^n_j
+//              + sum_{o: j-o in the PE of j} kad_o mu^n_{j-o} + A^n_j,
+// where A^l collects, at the edge strips that neighbours read, the
+// contributions c_m(k) kad_o mu^{n}_i of every later step n with
+// n - k - m = l: an adjoint ring of the forward ring's shape, filled by the
+// scatter kernel (in gather form: one thread per strip value) and drained by
+// the lambda kernel when the sweep reaches level l. The alpha-gradient is
+// sum_n <mu^n, d f^n / d alpha>, the AT Laplacian of the forward levels.
+
+#include "adjoint.hpp"
+
+namespace atfd {
+namespace {
+
+constexpr int kAdjThreads = 256;
+
+struct Pt {
+  int x, y, z;      // global coordinates
+  int pe;           // PE id
+  int l[3];         // coordinates inside the PE
+};
+
+__device__ inline Pt point_of(const StepParams& p, int64_t g) {
+  Pt r;
+  r.x = static_cast<int>(g % p.nx);
+  r.y = static_cast<int>((g / p.nx) % p.ny);
+  r.z = static_cast<int>(g / (static_cast<int64_t>(p.nx) * p.ny));
+  const int qx = r.x / p.bx, qy = r.y / p.by, qz = r.z / p.bz;
+  r.l[0] = r.x - qx * p.bx;
+  r.l[1] = r.y - qy * p.by;
+  r.l[2] = r.z - qz * p.bz;
+  r.pe = qx + p.px * (qy + p.py * qz);
+  return r;
+}
+
+__device__ inline int64_t gindex(const StepParams& p, int x, int y, int z) {
+  return (static_cast<int64_t>(z) * p.ny + y) * p.nx + x;
+}
+
+__device__ inline int edge_of(const StepParams& p, int a) { return a == 0 ? p.bx : a == 1 ? p.by : p.bz; }
+
+// Element of the strip of face F = 2a + side of a PE for the point with PE
+// coordinates l (which must lie in that strip): x faces [z][d][y], y faces
+// [z][d][x], z faces [d][y][x], with depth d counted from the PE's low side.
+__device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, int S) {
+  const int a = F >> 1;
+  const int b = edge_of(p, a);
+  const int d = (F & 1) ? l[a] - (b - S) : l[a];
+  if (a == 0) return (static_cast<int64_t>(l[2]) * S + d) * p.by + l[1];
+  if (a == 1) return (static_cast<int64_t>(l[2]) * S + d) * p.bx + l[0];
+  return (static_cast<int64_t>(d) * p.by + l[1]) * p.bx + l[0];
+}
+
+__device__ inline int64_t ring_at(const StepParams& p, int slot, int pe, int F, int64_t e) {
+  return (static_cast<int64_t>(slot) * p.npe + pe) * p.pe_block + p.face_off[F] + e;
+}
+
+__device__ inline int nbr_pe(const StepParams& p, int pid, int f) {
+  int q[3] = {pid % p.px, (pid / p.px) % p.py, pid / (p.px * p.py)};
+  const int ext[3] = {p.px, p.py, p.pz};
+  const int a = f >> 1;
+  q[a] = (q[a] + ((f & 1) ? 1 : ext[a] - 1)) % ext[a];
+  return q[0] + p.px * (q[1] + p.py * q[2]);
+}
+
+// Delay of face f of PE pid at step n; the synchronous scheme is k = 0 with
+// a single level.
+__device__ inline int adj_delay(const StepParams& p, int pid, int f, int64_t n) {
+  int k = 0;
+  if (p.mode == AT_DELAY_RNG)
+    k = raw_delay(p.key, n, static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L);
+  else if (p.mode == AT_DELAY_HOST)
+    k = p.host_delays[(n * p.npe + pid) * (2 * p.ndim) + f];
+  else
+    return 0;
+  return clamp_startup(k, n, p.T);
+}
+
+__device__ inline int adj_levels(const StepParams& p) { return p.mode == AT_SYNC ? 1 : p.T; }
+
+template <typename Real>
+__device__ inline double mu_at(const AdjParams& q, int64_t g) {
+  const double l1 = static_cast<double>(static_cast<const Real*>(q.lam1)[g]);
+  const double l2 = q.beta1 != 0.0 ? static_cast<double>(static_cast<const Real*>(q.lam2)[g]) : 0.0;
+  return q.dt * (q.beta0 * l1 + q.beta1 * l2);
+}
+
+// Scatter of step n (gather form): every strip value e of face F of PE q
+// collects the transposed taps of the consumer PE across F, weighted by the
+// consumer's level weights, into the adjoint ring slots of levels n-k-m.
+template <typename Real>
+__global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int S = p.s;
+  const int64_t total = static_cast<int64_t>(p.npe) * p.pe_block;
+  Real* aring = static_cast<Real*>(q.aring);
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int pe = static_cast<int>(t / p.pe_block);
+    const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
+    int F = 0;
+    while (F + 1 < 2 * p.ndim && r >= p.face_off[F + 1]) ++F;
+    const int64_t e = r - p.face_off[F];
+    const int a = F >> 1;
+    // decode the PE coordinates of strip element e
+    int l[3] = {0, 0, 0};
+    int d;
+    if (a == 0) {
+      l[1] = static_cast<int>(e % p.by);
+      d = static_cast<int>((e / p.by) % S);
+      l[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
+    } else if (a == 1) {
+      l[0] = static_cast<int>(e % p.bx);
+      d = static_cast<int>((e / p.bx) % S);
+      l[2] = static_cast<int>(e / (static_cast<int64_t>(p.bx) * S));
+    } else {
+      l[0] = static_cast<int>(e % p.bx);
+      l[1] = static_cast<int>((e / p.bx) % p.by);
+      d = static_cast<int>(e / (static_cast<int64_t>(p.bx) * p.by));
+    }
+    const int b = edge_of(p, a);
+    // the consumer across F reads this strip through its opposite face
+    const int cons = nbr_pe(p, pe, F);
+    const int cf = F ^ 1;
+    // coordinate of the strip value in the consumer's frame
+    const int jp = (F & 1) ? d - S : b + d;
+    const int cq[3] = {cons % p.px, (cons / p.px) % p.py, cons / (p.px * p.py)};
+    const int org[3] = {cq[0] * p.bx, cq[1] * p.by, cq[2] * p.bz};
+    double g = 0.0;
+    for (int o = -S; o <= S; ++o) {
+      if (o == 0) continue;
+      const int ia = jp - o;
+      if (ia < 0 || ia >= b) continue;
+      int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
+      c[a] = org[a] + ia;
+      g += p.kad[a][o + S] * mu_at<Real>(q, gindex(p, c[0], c[1], c[2]));
+    }
+    const int k = adj_delay(p, cons, cf, q.n);
+    double w[kMaxT];
+    const int T = adj_levels(p);
+    level_weights(k, T, w);
+    for (int m = 0; m < T; ++m) {
+      if (w[m] == 0.0) continue;
+      const int slot = static_cast<int>((q.n - k - m) % q.anslots);
+      Real* dst = aring + ring_at(p, slot, pe, F, e);
+      *dst = static_cast<Real>(static_cast<double>(*dst) + w[m] * g);
+    }
+  }
+}
+
+// Value of level l at global point (x, y, z), which lies in PE `src` at PE
+// coordinates ls: from the stored levels of the segment, or, for a level
+// before the segment, from the ring as it was at the segment's start (the
+// point is then an edge value of that ring, read through producer face pf).
+template <typename Real>
+__device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y, int z, int src, int pf,
+                                     const int* ls) {
+  const StepParams& p = q.sp;
+  if (l >= q.seg_start) {
+    const Real* U = static_cast<const Real*>(q.levels) + (l - q.seg_start) * q.npts;
+    return static_cast<double>(U[gindex(p, x, y, z)]);
+  }
+  const Real* R0 = static_cast<const Real*>(q.ring0);
+  const int slot = static_cast<int>(l % p.nslots);
+  return static_cast<double>(R0[ring_at(p, slot, src, pf, strip_elem(p, pf, ls, p.s))]);
+}
+
+// lambda^n from lambda^{n+1}, lambda^{n+2} and the adjoint ring slot of level
+// n (drained and cleared here), plus this step's part of dJ/dalpha.
+template <typename Real>
+__global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int S = p.s;
+  Real* lam0 = static_cast<Real*>(q.lam0);
+  const Real* lam1 = static_cast<const Real*>(q.lam1);
+  Real* aring = static_cast<Real*>(q.aring);
+  const int slot_n = static_cast<int>(q.n % q.anslots);
+  const int T = adj_levels(p);
+  double da = 0.0;
+  for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
+       g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const Pt j = point_of(p, g);
+    const double mu = mu_at<Real>(q, g);
+    double acc = static_cast<double>(lam1[g]);
+    double lap = 0.0;
+    const double u0 = level_value<Real>(q, q.n, j.x, j.y, j.z, j.pe, 0, j.l);
+    const int gc[3] = {j.x, j.y, j.z};
+    const int ext[3] = {p.nx, p.ny, p.nz};
+    for (int a = 0; a < p.ndim; ++a) {
+      const int b = edge_of(p, a);
+      for (int o = -S; o <= S; ++o) {
+        if (o == 0) continue;
+        acc -= p.kad[a][o + S] * mu;
+        // transposed interior tap: from i = j - o (same PE) to j
+        const int ia = j.l[a] - o;
+        if (ia >= 0 && ia < b) {
+          int c[3] = {gc[0], gc[1], gc[2]};
+          c[a] = gc[a] - o;
+          acc += p.kad[a][o + S] * mu_at<Real>(q, gindex(p, c[0], c[1], c[2]));
+        }
+        // forward AT Laplacian of the stored levels at j (alpha derivative)
+        const int ta = j.l[a] + o;
+        int c[3] = {gc[0], gc[1], gc[2]};
+        c[a] = (gc[a] + o + ext[a]) % ext[a];
+        double v;
+        if (ta >= 0 && ta < b) {
+          v = level_value<Real>(q, q.n, c[0], c[1], c[2], j.pe, 0, j.l);
+        } else {
+          const int side = ta < 0 ? 0 : 1;
+          const int f = 2 * a + side;
+          const int src = nbr_pe(p, j.pe, f);
+          int ls[3] = {j.l[0], j.l[1], j.l[2]};
+          ls[a] = side ? ta - b : ta + b;
+          const int k = adj_delay(p, j.pe, f, q.n);
+          double w[kMaxT];
+          level_weights(k, T, w);
+          v = 0.0;
+          for (int m = 0; m < T; ++m)
+            if (w[m] != 0.0) v += w[m] * level_value<Real>(q, q.n - k - m, c[0], c[1], c[2], src, f ^ 1, ls);
+        }
+        lap += p.c2[a][o + S] * (v - u0);
+      }
+      // adjoint-ring contributions of the strips j belongs to on this axis
+      for (int side = 0; side < 2; ++side) {
+        const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
+        if (!in) continue;
+        const int F = 2 * a + side;
+        Real* src = aring + ring_at(p, slot_n, j.pe, F, strip_elem(p, F, j.l, S));
+        acc += static_cast<double>(*src);
+        *src = Real(0);
+      }
+    }
+    lam0[g] = static_cast<Real>(acc);
+    da += mu * lap;
+  }
+  // fixed-order block reduction of the alpha-gradient part
+  for (int off = 32; off > 0; off >>= 1) da += __shfl_down(da, off, 64);
+  __shared__ double part[kAdjThreads / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x / 64] = da;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kAdjThreads / 64; ++w) s += part[w];
+    q.partial[blockIdx.x] += s;
+  }
+}
+
+__global__ void adj_sum_kernel(const double* partial, int count, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < count; ++i) s += partial[i];
+    out[0] = s;
+  }
+}
+
+}  // namespace
+
+int adj_blocks(int64_t npts) {
+  const int64_t b = (npts + kAdjThreads - 1) / kAdjThreads;
+  return static_cast<int>(b < kAdjBlocks ? b : kAdjBlocks);
+}
+
+hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
+  const int64_t strips = static_cast<int64_t>(q.sp.npe) * q.sp.pe_block;
+  const int64_t sb = (strips + kAdjThreads - 1) / kAdjThreads;
+  const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
+  const int lblocks = adj_blocks(q.npts);
+  if (f64) {
+    hipLaunchKernelGGL(adj_scatter_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_lambda_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+  } else {
+    hipLaunchKernelGGL(adj_scatter_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_lambda_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_sum(const double* partial, int count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(adj_sum_kernel, dim3(1), dim3(64), 0, st, partial, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace atfd

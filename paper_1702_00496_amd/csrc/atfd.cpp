@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "atfd_internal.hpp"
+#include "adjoint.hpp"
 #include "host_common.hpp"
 
 using namespace atfd;
@@ -597,3 +599,149 @@ const char* at_last_error(const at_ctx* c) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// Scratch layout of at_adjoint: nck + 1 checkpoints, the levels of one
+// segment (contiguous fields), three lambda fields, the adjoint ring, the
+// forward ring at the segment start, alpha partial sums.
+struct AdjLayout {
+  size_t ck = 0, off_levels = 0, off_lam[3] = {0, 0, 0}, off_aring = 0, off_ring0 = 0;
+  size_t off_partial = 0, off_out = 0, total = 0, aring_bytes = 0;
+  int64_t nck = 0;
+  int anslots = 0;
+};
+
+AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
+  AdjLayout a;
+  size_t ck = 0;
+  at_checkpoint_size(c, &ck);
+  a.ck = align_up(ck);
+  a.nck = (nsteps + every - 1) / every;
+  size_t off = a.ck * static_cast<size_t>(a.nck + 1);
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const Layout& l = c->lay;
+  a.off_levels = take(l.field_bytes * static_cast<size_t>(every + 1));
+  for (int i = 0; i < 3; ++i) a.off_lam[i] = take(l.field_bytes);
+  a.anslots = c->delay.mode == AT_SYNC ? 1 : l.nslots;
+  a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * (c->g.f64 ? 8 : 4);
+  a.off_aring = take(a.aring_bytes);
+  a.off_ring0 = take(l.ring_bytes);
+  a.off_partial = take(kAdjBlocks * sizeof(double));
+  a.off_out = take(sizeof(double));
+  a.total = off;
+  return a;
+}
+
+at_status adj_check(at_ctx* c, int64_t nsteps, int32_t every) {
+  if (!c) return fail(nullptr, AT_EINVAL, "null context");
+  if (nsteps < 1 || every < 1) return fail(c, AT_EINVAL, "nsteps and the checkpoint interval must be >= 1");
+  if (c->prob.equation != AT_ADVDIFF) return fail(c, AT_EINVAL, "the adjoint covers advection-diffusion");
+  if (c->prob.integrator != AT_EULER && c->prob.integrator != AT_AB2)
+    return fail(c, AT_EINVAL, "the adjoint covers Euler and AB2");
+  if (c->delay.mode == AT_DELAY_HOST && nsteps > c->delay.host_nsteps)
+    return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
+  return AT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+at_status at_adjoint_scratch_size(at_ctx* c, int64_t nsteps, int32_t every, size_t* bytes) {
+  at_status st = adj_check(c, nsteps, every);
+  if (st != AT_OK) return st;
+  if (!bytes) return fail(c, AT_EINVAL, "null argument");
+  *bytes = adj_layout(c, nsteps, every).total;
+  return AT_OK;
+}
+
+at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_dev, void* scratch_dev,
+                     size_t scratch_bytes, void* grad_u0_dev, double* grad_alpha) {
+  at_status st = adj_check(c, nsteps, every);
+  if (st != AT_OK) return st;
+  if (!seed_dev || !scratch_dev || !grad_u0_dev || !grad_alpha) return fail(c, AT_EINVAL, "null argument");
+  if (!c->state_set || c->n != 0) return fail(c, AT_ESTATE, "the adjoint starts from a state set at step 0");
+  const AdjLayout a = adj_layout(c, nsteps, every);
+  if (scratch_bytes < a.total) return fail(c, AT_ENOMEM, "scratch %zu < %zu bytes", scratch_bytes, a.total);
+  if (reinterpret_cast<uintptr_t>(scratch_dev) % kAlign)
+    return fail(c, AT_EINVAL, "scratch must be %zu-byte aligned", kAlign);
+  unsigned char* sc = static_cast<unsigned char*>(scratch_dev);
+  const Layout& l = c->lay;
+  const int64_t N = nsteps;
+  // forward run, checkpoint at the start of every segment and at the end
+  for (int64_t s = 0; s < a.nck; ++s) {
+    st = at_save(c, sc + a.ck * s);
+    if (st != AT_OK) return st;
+    const int64_t len = std::min<int64_t>(every, N - s * every);
+    st = at_step(c, len);
+    if (st != AT_OK) return st;
+  }
+  st = at_save(c, sc + a.ck * a.nck);
+  if (st != AT_OK) return st;
+  // reverse sweep: lambda^N = seed
+  unsigned char* lam[3] = {sc + a.off_lam[0], sc + a.off_lam[1], sc + a.off_lam[2]};
+  int i1 = 0, i2 = 1, i0 = 2;   // roles: lambda^{n+1}, lambda^{n+2}, lambda^n
+  HIP_TRY(c, hipMemcpyAsync(lam[i1], seed_dev, l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(lam[i2], 0, l.field_bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(sc + a.off_aring, 0, a.aring_bytes, c->stream));
+  HIP_TRY(c, hipMemsetAsync(sc + a.off_partial, 0, kAdjBlocks * sizeof(double), c->stream));
+  unsigned char* levels = sc + a.off_levels;
+  for (int64_t s = a.nck - 1; s >= 0; --s) {
+    st = at_load(c, sc + a.ck * s);
+    if (st != AT_OK) return st;
+    const int64_t seg = s * every;
+    const int64_t len = std::min<int64_t>(every, N - seg);
+    HIP_TRY(c, hipMemcpyAsync(levels, c->sp.ubuf[c->n & 1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (l.ring_bytes)
+      HIP_TRY(c, hipMemcpyAsync(sc + a.off_ring0, c->sp.ring, l.ring_bytes, hipMemcpyDeviceToDevice, c->stream));
+    for (int64_t j = 1; j <= len; ++j) {
+      st = enqueue_step(c, c->stream);
+      if (st != AT_OK) return st;
+      c->n += 1;
+      HIP_TRY(c, hipMemcpyAsync(levels + l.field_bytes * j, c->sp.ubuf[c->n & 1], l.field_bytes,
+                                hipMemcpyDeviceToDevice, c->stream));
+    }
+    for (int64_t n = seg + len - 1; n >= seg; --n) {
+      AdjParams q;
+      std::memset(&q, 0, sizeof(q));
+      q.sp = c->sp;
+      q.n = n;
+      q.npts = c->g.npts;
+      q.dt = c->prob.dt;
+      const bool ab2 = c->prob.integrator == AT_AB2;
+      q.beta0 = (ab2 && n > 0) ? 1.5 : 1.0;
+      q.beta1 = (ab2 && n + 1 <= N - 1) ? -0.5 : 0.0;
+      q.lam1 = lam[i1];
+      q.lam2 = lam[i2];
+      q.lam0 = lam[i0];
+      q.aring = sc + a.off_aring;
+      q.anslots = a.anslots;
+      q.levels = levels;
+      q.seg_start = seg;
+      q.ring0 = sc + a.off_ring0;
+      q.partial = reinterpret_cast<double*>(sc + a.off_partial);
+      HIP_TRY(c, launch_adj_step(q, c->g.f64, c->stream));
+      const int t = i2;
+      i2 = i1;
+      i1 = i0;
+      i0 = t;
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(grad_u0_dev, lam[i1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  double* out = reinterpret_cast<double*>(sc + a.off_out);
+  HIP_TRY(c, launch_adj_sum(reinterpret_cast<double*>(sc + a.off_partial), kAdjBlocks, out, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(grad_alpha, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  // leave the context at the end of the forward run
+  st = at_load(c, sc + a.ck * a.nck);
+  if (st != AT_OK) return st;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return AT_OK;
+}
+
+}  // extern "C"
+

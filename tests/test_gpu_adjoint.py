@@ -1,0 +1,190 @@
+"""GPU parity of the hand-written adjoint (at_adjoint) against the oracle's
+gradients (reverse-mode autograd of the FP64 forward steps), and the full-size
+2-D gradient check against central finite differences of the GPU forward.
+
+Tolerances: FP64 relative L2 <= 1e-10 for dJ/du0 and relative 1e-10 for
+dJ/dalpha (both sides are exact transposes up to rounding); FP32 bulk 1e-4
+against the FP64 oracle; finite differences (FP32, eps = 1e-3) 1e-3 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.adjoint import gradients
+from oracle.solver import DelayModel, Problem
+from tests._cases import initial_field, rel_l2, solver_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "1d_o2_euler_L3": dict(ndim=1, n=(64,), pe=(4,), order=2, integrator="euler", c=(1.0,), L=3, steps=37, every=8, ra=0.1),
+    "1d_o4_ab2_L4_ragged": dict(ndim=1, n=(60,), pe=(5,), order=4, integrator="ab2", c=(0.7,), L=4, steps=33, every=5, ra=0.02),
+    "1d_o6_ab2_L3": dict(ndim=1, n=(72,), pe=(4,), order=6, integrator="ab2", c=(1.0,), L=3, steps=25, every=7, ra=0.005),
+    "1d_o4_T1_async_standard": dict(ndim=1, n=(48,), pe=(4,), order=4, integrator="ab2", c=(1.0,), L=3, T=1, steps=20, every=6, ra=0.02),
+    "1d_o4_zero": dict(ndim=1, n=(48,), pe=(3,), order=4, integrator="ab2", c=(1.0,), L=3, mode="zero", steps=20, every=6, ra=0.02),
+    "1d_o2_one_pe": dict(ndim=1, n=(32,), pe=(1,), order=2, integrator="euler", c=(1.0,), L=2, steps=15, every=4, ra=0.1),
+    "2d_o4_ab2": dict(ndim=2, n=(40, 36), pe=(4, 3), order=4, integrator="ab2", c=(1.0, -0.5), L=4, steps=21, every=6, ra=0.02),
+    "2d_o2_sync": dict(ndim=2, n=(32, 24), pe=(2, 2), order=2, integrator="euler", c=(1.0, 1.0), mode="sync", steps=15, every=4, ra=0.05),
+    "3d_o4_ab2": dict(ndim=3, n=(24, 20, 16), pe=(2, 2, 2), order=4, integrator="ab2", c=(1.0, 1.0, 1.0), L=3, steps=9, every=4, ra=0.02),
+    # 32 x 32 cross-sections: the forward runs on the 3-D fast path
+    "3d_fast_o4_ab2": dict(ndim=3, n=(64, 64, 32), pe=(2, 2, 1), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), L=4, steps=8, every=3, ra=0.02),
+}
+
+
+def _case(name):
+    c = dict(CASES[name])
+    dx = 2 * math.pi / min(c["n"][: c["ndim"]])
+    c["dt"] = c.pop("ra") * dx * dx / c.get("alpha", 0.1)
+    return c
+
+
+def _oracle_grads(case, u0, seed):
+    prob = Problem(ndim=case["ndim"], n=case["n"], pe=case["pe"], dt=case["dt"], order=case["order"],
+                   c=case.get("c", (0.0, 0.0, 0.0)), alpha=case.get("alpha", 0.1),
+                   integrator=case["integrator"])
+    dm = DelayModel(L=case.get("L", 3), T=case.get("T", 0), mode=case.get("mode", "rng"), seed=case.get("seed", 0))
+    return gradients(prob, dm, torch.as_tensor(u0), case.get("alpha", 0.1), case["steps"], torch.as_tensor(seed))
+
+
+def _seed(case):
+    n = tuple(case["n"]) + (1,) * (3 - len(case["n"]))
+    return np.random.default_rng(11).standard_normal((n[2], n[1], n[0]))
+
+
+def _gpu_grads(case, u0, seed, precision, every=None):
+    s = solver_for(case, precision)
+    s.set_state(torch.from_numpy(u0))
+    g, ga = s.adjoint(case["steps"], torch.from_numpy(seed), every or case["every"])
+    return s, g.cpu().to(torch.float64), ga
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_adjoint_matches_oracle_gradients(name, precision):
+    case = _case(name)
+    _say(f"[adj] {name} {precision}: steps={case['steps']} every={case['every']}")
+    u0 = initial_field(case)
+    seed = _seed(case)
+    gu_o, ga_o = _oracle_grads(case, u0, seed)
+    s, gu, ga = _gpu_grads(case, u0, seed, precision)
+    tol = 1e-10 if precision == "f64" else 1e-4
+    err = rel_l2(gu, gu_o)
+    _say(f"[adj]   du0 rel err {err:.3e}   dalpha {ga:.9e} vs {ga_o:.9e}")
+    assert err <= tol
+    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3)
+    # the context ends at step N with the forward field of a plain run
+    assert s.n_step == case["steps"]
+    ref = solver_for(case, precision)
+    ref.set_state(torch.from_numpy(u0))
+    ref.step(case["steps"])
+    assert torch.equal(s.state(), ref.state())
+
+
+def test_adjoint_is_independent_of_the_checkpoint_interval():
+    case = _case("2d_o4_ab2")
+    u0, seed = initial_field(case), _seed(case)
+    base = _gpu_grads(case, u0, seed, "f64", every=1)
+    for every in (4, case["steps"], 1000):
+        other = _gpu_grads(case, u0, seed, "f64", every=every)
+        assert torch.equal(other[1], base[1]), every
+        assert other[2] == base[2]
+
+
+def test_adjoint_rejects_unsupported_problems():
+    from paper_1702_00496_amd import ATError
+    case = _case("1d_o2_euler_L3")
+    for bad in (dict(integrator="rk2"), dict(integrator="ab3"), dict(equation="burgers")):
+        c = dict(case, **bad)
+        s = solver_for(c, "f64")
+        s.set_state(torch.from_numpy(initial_field(c)))
+        with pytest.raises(ATError):
+            s.adjoint(5, torch.zeros(s.shape, dtype=torch.float64))
+    s = solver_for(case, "f64")
+    s.set_state(torch.from_numpy(initial_field(case)))
+    s.step(1)
+    with pytest.raises(ATError):   # the adjoint starts from step 0
+        s.adjoint(5, torch.zeros(s.shape, dtype=torch.float64))
+
+
+def test_autograd_function_matches_oracle():
+    from paper_1702_00496_amd import evolve
+    case = _case("2d_o4_ab2")
+    spec = dict(ndim=case["ndim"], n=case["n"], pe=case["pe"], dt=case["dt"], order=case["order"],
+                c=case["c"], integrator=case["integrator"], precision="f64", L=case["L"], seed=0)
+    u0 = torch.from_numpy(initial_field(case)).cuda().requires_grad_(True)
+    alpha = torch.tensor(0.1, dtype=torch.float64, requires_grad=True)
+    target = torch.from_numpy(_seed(case)).cuda()
+    uN = evolve(u0, alpha, case["steps"], every=5, **spec)
+    J = 0.5 * ((uN - target) ** 2).sum()
+    J.backward()
+    seed = (uN - target).detach().cpu().numpy()
+    gu_o, ga_o = _oracle_grads(case, initial_field(case), seed)
+    assert rel_l2(u0.grad.cpu(), gu_o) <= 1e-10
+    assert float(alpha.grad) == pytest.approx(ga_o, rel=1e-10)
+
+
+def test_adjoint_full_2d_workload_against_finite_differences():
+    """1024^2, 16^2 PEs of 64^2, fourth order, L = 4, AB2, 2000 steps,
+    J = 1/2 sum (u_T - target)^2 dx^2, checkpoints every 64 steps. Reference:
+    central differences (eps = 1e-3) of the FP64 GPU forward along 16
+    unit-variance Gaussian directions and in alpha (eps = 1e-5). J is exactly
+    quadratic in u0 (u_T is linear in u0), so the u0 differences are exact up
+    to rounding. The FP64 adjoint must agree to 1e-7, the FP32-bulk adjoint to
+    1e-3 relative to the largest directional derivative."""
+    from paper_1702_00496_amd import Solver
+    from oracle.analytic import advected_modes
+    cfg = W.config_2d_advdiff()
+    n = cfg["n"]
+    dV = (2 * math.pi / n[0]) * (2 * math.pi / n[1])
+    steps, every = cfg["steps"], 64
+    u0 = torch.from_numpy(W.eval_modes(cfg["modes"], n, 2)).cuda()
+    prob = Problem(ndim=2, n=n[:2], pe=cfg["pe"][:2], dt=cfg["dt"], order=4, c=cfg["c"][:2], alpha=cfg["alpha"])
+    target = advected_modes(prob, cfg["target_modes"], steps * cfg["dt"]).cuda()
+
+    def make(alpha, precision):
+        return Solver(ndim=2, n=n, pe=cfg["pe"], dt=cfg["dt"], order=4, c=cfg["c"], alpha=alpha,
+                      integrator="ab2", precision=precision, L=cfg["L"], seed=cfg["seed"])
+
+    def J_of(u_init, alpha=cfg["alpha"], precision="f64"):
+        s = make(alpha, precision)
+        s.set_state(u_init)
+        s.step(steps)
+        d = s.state().to(torch.float64) - target
+        return 0.5 * float((d * d).sum()) * dV, d * dV
+
+    _say(f"[adj] full 2-D workload: {n[0]}x{n[1]}, {steps} steps, every {every}")
+    dirs = W.gaussian_field((16,) + tuple(u0.shape), seed=5, unit_l2=False)
+    dirs = [torch.from_numpy(d / np.sqrt((d ** 2).mean())).cuda() for d in dirs]
+    eps = 1e-3
+    fd = []
+    for d in dirs:
+        jp, _ = J_of(u0 + eps * d)
+        jm, _ = J_of(u0 - eps * d)
+        fd.append((jp - jm) / (2 * eps))
+    ea = 1e-5
+    fda = (J_of(u0, cfg["alpha"] + ea)[0] - J_of(u0, cfg["alpha"] - ea)[0]) / (2 * ea)
+    scale = max(abs(v) for v in fd)
+    for precision, tol in (("f64", 1e-7), ("f32", 1e-3)):
+        _, seed = J_of(u0, precision=precision)
+        s = make(cfg["alpha"], precision)
+        s.set_state(u0)
+        gu, ga = s.adjoint(steps, seed, every)
+        gu = gu.to(torch.float64)
+        worst = 0.0
+        for i, d in enumerate(dirs):
+            ad = float((gu * d).sum())
+            worst = max(worst, abs(ad - fd[i]) / scale)
+            _say(f"[adj]   {precision} direction {i}: adjoint {ad:.9e}  fd {fd[i]:.9e}")
+        _say(f"[adj]   {precision} alpha: adjoint {ga:.9e}  fd {fda:.9e}   worst direction {worst:.2e}")
+        assert worst <= tol, (precision, worst)
+        assert ga == pytest.approx(fda, rel=tol)

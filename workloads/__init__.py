@@ -87,8 +87,13 @@ def config_3d_advdiff(n=256, b=32, steps=500, L=4, seed=1, r_alpha=0.02):
     )
 
 
-def config_2d_advdiff(n=1024, b=64, steps=2000, L=4, seed=3, r_alpha=0.05):
-    """2-D advection-diffusion (adjoint workload), fourth order, AB2."""
+def config_2d_advdiff(n=1024, b=64, steps=2000, L=4, seed=3, r_alpha=0.01):
+    """2-D advection-diffusion (adjoint workload), fourth order, AB2.
+
+    r_alpha = alpha dt / dx^2 = 0.01: with L = 4 the AT extrapolation makes
+    the 2-D AB2 step unstable at 0.05 (a 1e-6 perturbation grows 1e8-fold in
+    250 steps, measured with the oracle) although the synchronous scheme is
+    stable up to 3/32; 0.03 still damps perturbations."""
     alpha = 0.1
     return dict(
         name=f"ad2d_n{n}_b{b}",
