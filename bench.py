@@ -35,6 +35,8 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
+p.add_argument("--others", default="burgers,ensemble,adjoint",
+               help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
 if args.gpus != 1:
@@ -181,6 +183,117 @@ for arm in args.arms.split(","):
           f"{arms[arm]['updates_per_s']:.3e} upd/s {arms[arm]['achieved_gbs']:.0f} GB/s "
           f"l2={arms[arm]['l2_error']:.3e}", file=sys.stderr, flush=True)
 
+def time_burgers():
+    """3-D viscous Burgers, 512^3, 16^3 PEs of 32^3, sixth order (T = 4), L = 8,
+    Heun RK2, 200 steps, FP32 bulk with FP64 AT combination, and the
+    synchronous arm. Bytes per update (two launches per step): u^n and u* read
+    or written 5 times, plus per stage the halo reads h E[levels] and the
+    publish h, h = 2 * 3 * 3 / 32, E[levels] = p0 + (1 - p0) T, p0 = 1/8."""
+    c5 = W.config_3d_burgers()
+    n5 = c5["n"]
+    u5 = torch.from_numpy(W.burgers_spectrum_field(n5[0], 3, seed=c5["seed"]))
+    res = {}
+    for mode in ("rng", "sync"):
+        s = Solver(ndim=3, n=n5, pe=c5["pe"], dt=c5["dt"], order=6, equation="burgers", alpha=c5["alpha"],
+                   integrator="rk2", precision="f32", L=c5["L"], T=c5["T"], mode=mode, seed=c5["seed"])
+        s.set_state(u5)
+        s.step(2)
+        best = s.autotune(nsteps=5)[0]
+        s.set_graph(20)
+        s.set_state(u5)
+        s.step(20)
+        s.set_state(u5)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(c5["steps"])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        finite = bool(torch.isfinite(s.state()).all())
+        h = 2 * 3 * 3 / 32
+        p0 = 1.0 / c5["L"]
+        bpu = 4 * (5 + (2 * h * (p0 + (1 - p0) * c5["T"] + 1) if mode == "rng" else 0.0))
+        ups = n5[0] ** 3 * c5["steps"] / (ms / 1e3)
+        res[mode] = dict(ms_per_step=ms / c5["steps"], updates_per_s=ups, bytes_per_update=bpu,
+                         achieved_gbs=ups * bpu / 1e9, frac=ups * bpu / 1e9 / HBM_PEAK_GBS, variant=best,
+                         finite=finite)
+        print(f"[bench] burgers {mode}: {ms / c5['steps']:.3f} ms/step {ups:.3e} upd/s", file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return dict(workload="3-D viscous Burgers 512^3, 16^3 PEs of 32^3, 6th-order AT (T=4), L=8, RK2, "
+                         "200 steps, FP32 bulk / FP64 AT combination", arms=res)
+
+
+def time_ensemble():
+    """512 independent 1-D members (N log-uniform in [1024, 65536], PE 64,
+    orders 2/4, L in {2, 4, 8}), 2000 steps in one persistent launch, FP32."""
+    from paper_1702_00496_amd import Ensemble
+    inst = W.ensemble_instances()
+    members = [dict(n=m["n"], pe=m["pe"], order=m["order"], integrator=m["integrator"], L=m["L"], T=m["T"],
+                    mode="rng", c=m["c"], alpha=m["alpha"], dt=m["dt"], seed=m["seed"]) for m in inst]
+    u3 = torch.from_numpy(np.concatenate([W.eval_modes(m["modes"], (m["n"],), 1).reshape(-1) for m in inst]))
+    ens = Ensemble(members, precision="f32")
+    ens.set_state(u3)
+    ens.run(2000)                           # capture + warm-up
+    ens.set_state(u3)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ens.run(2000)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ph = np.array([[mo[2] for mo in m["modes"]] for m in inst])
+    err = ens.norms([3, 4, 5], [2.0, 0.5, 1.5], ph)
+    ups = u3.numel() * 2000 / (ms / 1e3)
+    print(f"[bench] ensemble: {ms:.1f} ms for 2000 steps, {ups:.3e} upd/s", file=sys.stderr, flush=True)
+    return dict(workload="512-member 1-D delay ensemble, 7.5M points, 2000 steps, one persistent launch, FP32",
+                ms=ms, updates_per_s=ups, max_rms_error=float(err[:, 1].max()),
+                median_rms_error=float(np.median(err[:, 1])))
+
+
+def time_adjoint():
+    """Gradient of J = 1/2 sum (u_T - target)^2 dx^2 on the 1024^2 2-D
+    workload (16^2 PEs of 64^2, order 4, L = 4, AB2, 2000 FP32 steps,
+    checkpoints every 64): forward with checkpoints, segment recomputation
+    and the reverse sweep."""
+    c4 = W.config_2d_advdiff()
+    n4 = c4["n"]
+    u4 = torch.from_numpy(W.eval_modes(c4["modes"], n4, 2)).to(dev)
+    seed = torch.from_numpy(W.eval_modes(c4["target_modes"], n4, 2)).to(dev)
+
+    def make():
+        return Solver(ndim=2, n=n4, pe=c4["pe"], dt=c4["dt"], order=4, c=c4["c"], alpha=c4["alpha"],
+                      integrator="ab2", precision="f32", L=c4["L"], seed=c4["seed"])
+    s = make()
+    s.set_state(u4)
+    s.adjoint(64, seed, 64)                 # warm-up
+    s = make()
+    s.set_state(u4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adjoint(c4["steps"], seed, 64)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    f = make()
+    f.set_state(u4)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    f.step(c4["steps"])
+    e1.record()
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1)
+    print(f"[bench] adjoint: {ms:.1f} ms (forward alone {fms:.1f} ms)", file=sys.stderr, flush=True)
+    return dict(workload="gradient of a final-time misfit, 2-D 1024^2, 16^2 PEs of 64^2, order 4, L=4, AB2, "
+                         "2000 FP32 steps, checkpoints every 64", ms=ms, forward_ms=fms,
+                ratio_to_forward=ms / fms)
+
+
 traffic = measured_traffic()
 for arm, r in arms.items():
     t = traffic.get(arm)
@@ -213,6 +326,11 @@ out = {
                  "measured_copy_gbs": copy_gbs},
     "arms": arms,
 }
+others = {}
+for w in [x for x in args.others.split(",") if x]:
+    others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint}[w]()
+if others:
+    out["other_workloads"] = others
 if not args.no_cpu_baseline:
     out["cpu_baseline"] = cpu_baseline()
 print(json.dumps(out))
