@@ -326,6 +326,14 @@ out = {
                  "measured_copy_gbs": copy_gbs},
     "arms": arms,
 }
+if "f32" in arms and "sync32" in arms:
+    # the standard synchronous scheme on the same GPU, same grid and steps:
+    # matched error when the L2 errors agree
+    a, b = arms["f32"], arms["sync32"]
+    out["vs_standard"] = {"at_ms_per_step": a["ms_per_step"], "sync_ms_per_step": b["ms_per_step"],
+                          "time_ratio": a["ms_per_step"] / b["ms_per_step"],
+                          "at_l2_error": a["l2_error"], "sync_l2_error": b["l2_error"],
+                          "error_ratio": a["l2_error"] / b["l2_error"]}
 others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint}[w]()
