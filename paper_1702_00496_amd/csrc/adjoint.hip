@@ -31,11 +31,14 @@ struct Pt {
   int l[3];         // coordinates inside the PE
 };
 
-__device__ inline Pt point_of(const StepParams& p, int64_t g) {
+// (fields below 2^31 points: the host checks)
+__device__ inline Pt point_of(const StepParams& p, int64_t g64) {
   Pt r;
-  r.x = static_cast<int>(g % p.nx);
-  r.y = static_cast<int>((g / p.nx) % p.ny);
-  r.z = static_cast<int>(g / (static_cast<int64_t>(p.nx) * p.ny));
+  const uint32_t g = static_cast<uint32_t>(g64);
+  const uint32_t row = g / static_cast<uint32_t>(p.nx);
+  r.x = static_cast<int>(g - row * static_cast<uint32_t>(p.nx));
+  r.z = static_cast<int>(row / static_cast<uint32_t>(p.ny));
+  r.y = static_cast<int>(row - static_cast<uint32_t>(r.z) * static_cast<uint32_t>(p.ny));
   const int qx = r.x / p.bx, qy = r.y / p.by, qz = r.z / p.bz;
   r.l[0] = r.x - qx * p.bx;
   r.l[1] = r.y - qy * p.by;
@@ -91,9 +94,21 @@ __device__ inline int adj_levels(const StepParams& p) { return p.mode == AT_SYNC
 
 template <typename Real>
 __device__ inline double mu_at(const AdjParams& q, int64_t g) {
-  const double l1 = static_cast<double>(static_cast<const Real*>(q.lam1)[g]);
-  const double l2 = q.beta1 != 0.0 ? static_cast<double>(static_cast<const Real*>(q.lam2)[g]) : 0.0;
-  return q.dt * (q.beta0 * l1 + q.beta1 * l2);
+  return static_cast<double>(static_cast<const Real*>(q.mu)[g]);
+}
+
+// mu^n = dJ/df^n = dt (beta0 lambda^{n+1} + beta1 lambda^{n+2}), stored once
+// per reversed step for both sweeps to gather.
+template <typename Real>
+__global__ __launch_bounds__(kAdjThreads) void adj_mu_kernel(AdjParams q) {
+  const Real* l1 = static_cast<const Real*>(q.lam1);
+  const Real* l2 = static_cast<const Real*>(q.lam2);
+  Real* mu = static_cast<Real*>(q.mu);
+  for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
+       g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double b = q.beta1 != 0.0 ? q.beta1 * static_cast<double>(l2[g]) : 0.0;
+    mu[g] = static_cast<Real>(q.dt * (q.beta0 * static_cast<double>(l1[g]) + b));
+  }
 }
 
 // Scatter of step n (gather form): every strip value e of face F of PE q
@@ -176,6 +191,55 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y
   return static_cast<double>(R0[ring_at(p, slot, src, pf, strip_elem(p, pf, ls, p.s))]);
 }
 
+// The forward halo values of step n, for the alpha-derivative: for every
+// consumer PE, face f and element e of the producer strip it reads, the AT
+// combination of the stored levels (the synchronous scheme: level n).
+// hbuf[pe * pe_block + face_off[f] + e].
+template <typename Real>
+__global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
+  const StepParams& p = q.sp;
+  const int S = p.s;
+  const int T = adj_levels(p);
+  const int64_t total = static_cast<int64_t>(p.npe) * p.pe_block;
+  Real* hb = static_cast<Real*>(q.hbuf);
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int pe = static_cast<int>(t / p.pe_block);
+    const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
+    int f = 0;
+    while (f + 1 < 2 * p.ndim && r >= p.face_off[f + 1]) ++f;
+    const int64_t e = r - p.face_off[f];
+    const int a = f >> 1, pf = f ^ 1;
+    int ls[3] = {0, 0, 0};
+    int d;
+    if (a == 0) {
+      ls[1] = static_cast<int>(e % p.by);
+      d = static_cast<int>((e / p.by) % S);
+      ls[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
+    } else if (a == 1) {
+      ls[0] = static_cast<int>(e % p.bx);
+      d = static_cast<int>((e / p.bx) % S);
+      ls[2] = static_cast<int>(e / (static_cast<int64_t>(p.bx) * S));
+    } else {
+      ls[0] = static_cast<int>(e % p.bx);
+      ls[1] = static_cast<int>((e / p.bx) % p.by);
+      d = static_cast<int>(e / (static_cast<int64_t>(p.bx) * p.by));
+    }
+    const int b = edge_of(p, a);
+    ls[a] = (pf & 1) ? b - S + d : d;
+    const int src = nbr_pe(p, pe, f);
+    const int sq[3] = {src % p.px, (src / p.px) % p.py, src / (p.px * p.py)};
+    const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
+    const int k = adj_delay(p, pe, f, q.n);
+    double w[kMaxT];
+    level_weights(k, T, w);
+    double v = 0.0;
+    for (int m = 0; m < T; ++m)
+      if (w[m] != 0.0) v += w[m] * level_value<Real>(q, q.n - k - m, gx, gy, gz, src, pf, ls);
+    hb[t] = static_cast<Real>(v);
+  }
+}
+
 // lambda^n from lambda^{n+1}, lambda^{n+2} and the adjoint ring slot of level
 // n (drained and cleared here), plus this step's part of dJ/dalpha.
 template <typename Real>
@@ -194,6 +258,29 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
     const double mu = mu_at<Real>(q, g);
     double acc = static_cast<double>(lam1[g]);
     double lap = 0.0;
+    bool inner = true;
+    for (int a = 0; a < p.ndim; ++a) {
+      const int b = edge_of(p, a);
+      inner = inner && j.l[a] >= S && j.l[a] < b - S;
+    }
+    if (inner) {
+      // every tap of j and every tap reaching j stays inside the PE: level n
+      // only, no wrap, no adjoint-ring entry
+      const Real* Un = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
+      const Real* M = static_cast<const Real*>(q.mu);
+      const double u0 = static_cast<double>(Un[g]);
+      const int64_t st[3] = {1, p.nx, static_cast<int64_t>(p.nx) * p.ny};
+      for (int a = 0; a < p.ndim; ++a) {
+        for (int o = -S; o <= S; ++o) {
+          if (o == 0) continue;
+          acc += p.kad[a][o + S] * (static_cast<double>(M[g - o * st[a]]) - mu);
+          lap += p.c2[a][o + S] * (static_cast<double>(Un[g + o * st[a]]) - u0);
+        }
+      }
+      lam0[g] = static_cast<Real>(acc);
+      da += mu * lap;
+      continue;
+    }
     const double u0 = level_value<Real>(q, q.n, j.x, j.y, j.z, j.pe, 0, j.l);
     const int gc[3] = {j.x, j.y, j.z};
     const int ext[3] = {p.nx, p.ny, p.nz};
@@ -217,17 +304,13 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
         if (ta >= 0 && ta < b) {
           v = level_value<Real>(q, q.n, c[0], c[1], c[2], j.pe, 0, j.l);
         } else {
+          // the forward halo value of this tap, combined once per step
           const int side = ta < 0 ? 0 : 1;
           const int f = 2 * a + side;
-          const int src = nbr_pe(p, j.pe, f);
           int ls[3] = {j.l[0], j.l[1], j.l[2]};
           ls[a] = side ? ta - b : ta + b;
-          const int k = adj_delay(p, j.pe, f, q.n);
-          double w[kMaxT];
-          level_weights(k, T, w);
-          v = 0.0;
-          for (int m = 0; m < T; ++m)
-            if (w[m] != 0.0) v += w[m] * level_value<Real>(q, q.n - k - m, c[0], c[1], c[2], src, f ^ 1, ls);
+          v = static_cast<double>(static_cast<const Real*>(q.hbuf)[static_cast<int64_t>(j.pe) * p.pe_block +
+                                                                  p.face_off[f] + strip_elem(p, f ^ 1, ls, S)]);
         }
         lap += p.c2[a][o + S] * (v - u0);
       }
@@ -277,9 +360,13 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
   const int lblocks = adj_blocks(q.npts);
   if (f64) {
+    hipLaunchKernelGGL(adj_mu_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_halo_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_lambda_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
   } else {
+    hipLaunchKernelGGL(adj_mu_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_halo_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_lambda_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
   }

@@ -16,6 +16,8 @@ struct AdjParams {
   const void* lam1;                // lambda^{n+1}
   const void* lam2;                // lambda^{n+2}
   void* lam0;                      // lambda^n (output)
+  void* mu;                        // mu^n (written by the first kernel of the step)
+  void* hbuf;                      // forward halo values of step n [pe][face strips]
   void* aring;                     // adjoint ring, forward ring layout, anslots slots
   int anslots;
   const void* levels;              // forward levels seg_start .. seg_start + len, npts apart

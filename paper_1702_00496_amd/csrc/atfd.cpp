@@ -606,7 +606,7 @@ namespace {
 // segment (contiguous fields), three lambda fields, the adjoint ring, the
 // forward ring at the segment start, alpha partial sums.
 struct AdjLayout {
-  size_t ck = 0, off_levels = 0, off_lam[3] = {0, 0, 0}, off_aring = 0, off_ring0 = 0;
+  size_t ck = 0, off_levels = 0, off_lam[3] = {0, 0, 0}, off_mu = 0, off_hbuf = 0, off_aring = 0, off_ring0 = 0;
   size_t off_partial = 0, off_out = 0, total = 0, aring_bytes = 0;
   int64_t nck = 0;
   int anslots = 0;
@@ -627,6 +627,8 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   const Layout& l = c->lay;
   a.off_levels = take(l.field_bytes * static_cast<size_t>(every + 1));
   for (int i = 0; i < 3; ++i) a.off_lam[i] = take(l.field_bytes);
+  a.off_mu = take(l.field_bytes);
+  a.off_hbuf = take(static_cast<size_t>(c->g.npe) * l.pe_block * (c->g.f64 ? 8 : 4));
   a.anslots = c->delay.mode == AT_SYNC ? 1 : l.nslots;
   a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * (c->g.f64 ? 8 : 4);
   a.off_aring = take(a.aring_bytes);
@@ -645,6 +647,7 @@ at_status adj_check(at_ctx* c, int64_t nsteps, int32_t every) {
     return fail(c, AT_EINVAL, "the adjoint covers Euler and AB2");
   if (c->delay.mode == AT_DELAY_HOST && nsteps > c->delay.host_nsteps)
     return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
+  if (c->g.npts >= (int64_t(1) << 31)) return fail(c, AT_EINVAL, "the adjoint covers fields below 2^31 points");
   return AT_OK;
 }
 
@@ -719,6 +722,8 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       q.lam1 = lam[i1];
       q.lam2 = lam[i2];
       q.lam0 = lam[i0];
+      q.mu = sc + a.off_mu;
+      q.hbuf = sc + a.off_hbuf;
       q.aring = sc + a.off_aring;
       q.anslots = a.anslots;
       q.levels = levels;
