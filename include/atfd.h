@@ -198,11 +198,12 @@ at_status at_destroy(at_ctx* ctx);
 const char* at_last_error(const at_ctx* ctx);
 
 /* ------------------------------------------------------------------------
- * Discrete adjoint of the AT step (advection-diffusion; Euler or AB2; every
- * delay mode). This is not in the paper: it is the exact transpose of the
- * discrete linear map that at_step applies, so that gradients of a function
- * J(u^N) of the field after N steps can be taken with respect to the initial
- * field and the diffusivity.
+ * Discrete adjoint of the AT step (advection-diffusion or viscous Burgers;
+ * Euler, AB2 or Heun RK2; every delay mode; AB3 is not covered). This is not
+ * in the paper: it is the exact transpose of the linearised discrete map that
+ * at_step applies, so that gradients of a function J(u^N) of the field after
+ * N steps can be taken with respect to the initial field and the diffusivity
+ * (viscosity).
  *
  * at_adjoint runs the N forward steps from the state set at step 0, saving a
  * checkpoint every `every` steps, then sweeps backwards: each segment is
@@ -210,7 +211,9 @@ const char* at_last_error(const at_ctx* ctx);
  * are applied from lambda^N = seed (dJ/du^N, bulk precision, device) down to
  * lambda^0 = dJ/du^0, which is written to grad_u0_dev. Contributions to older
  * levels through the AT halos go to an adjoint ring of the forward ring's
- * shape (the delayed levels' transpose). *grad_alpha receives
+ * shape (the delayed levels' transpose); RK2 keeps a second one for the
+ * predictor's levels. Burgers linearises around the recomputed forward
+ * levels of the segment. *grad_alpha receives
  * dJ/dalpha = sum_n <dJ/df^n, d f^n / d alpha>, accumulated in double in a
  * fixed order. The context is left at step N with the forward field.
  * Scratch (device, 256-B aligned) of at_adjoint_scratch_size bytes holds the

@@ -1,22 +1,30 @@
-// Discrete adjoint of the AT time step (advection-diffusion; Euler or AB2).
+// Discrete adjoint of the AT time step (advection-diffusion or viscous
+// Burgers; Euler, AB2 or Heun RK2).
 //
-// The forward step is linear in the solution levels:
-//   f^n_i = sum_axes sum_{o != 0} kad_o (v_{i+o} - u^n_i),
-//   kad_o = alpha c2_o / dx^2 - c c1_o / dx,
-// where v_{i+o} = u^n_{i+o} for a tap inside the PE of i (Sec. 2 eq.
-// general_deriv) and, for a tap across face f of that PE, the AT combination
-// sum_m c_m(k) u^{n-k-m}_{i+o} with the face's delay k (Sec. 3.4 Example 3 eq.
-// cd4-at); u^{n+1} = u^n + dt sum_j beta_j f^{n-j} (Sec. 4.1 eqs. time_disc,
-// time_ab2). With lambda^l = dJ/du^l and mu^n = dJ/df^n = dt (beta_0
-// lambda^{n+1} + beta_1 lambda^{n+2}), the reverse sweep is
-//   lambda^n_j = lambda^{n+1}_j - (sum kad) mu^n_j
-//              + sum_{o: j-o in the PE of j} kad_o mu^n_{j-o} + A^n_j,
-// where A^l collects, at the edge strips that neighbours read, the
-// contributions c_m(k) kad_o mu^{n}_i of every later step n with
-// n - k - m = l: an adjoint ring of the forward ring's shape, filled by the
-// scatter kernel (in gather form: one thread per strip value) and drained by
-// the lambda kernel when the sweep reaches level l. The alpha-gradient is
-// sum_n <mu^n, d f^n / d alpha>, the AT Laplacian of the forward levels.
+// One stage of the forward step computes, at every point i from a stage field
+// c (u for Euler/AB2 and the first RK2 stage, the predictor u* for the second),
+//   F_i = alpha sum_{a,o} c2_o (v_{a,o} - c_i) - [c . grad] ,
+// where v_{a,o} = c_{i+o} for a tap inside the PE of i (Sec. 2 eq.
+// general_deriv) and, for a tap across face f, the AT combination
+// sum_m c_m(k) c^{n-k-m}_{i+o} of that field's history with the face's delay k
+// (Sec. 3.4 Example 3 eq. cd4-at); the advection term is sum c_a c1_o (v - c_i)
+// (advection-diffusion) or c_i sum c1_o (v - c_i) (Burgers; Sec. 5 eq.
+// general). Linearised, dF_i = sum K_{i,a,o} dv_{a,o} + D_i dc_i with
+//   K_{i,a,o} = alpha c2_o - c_a c1_o  or  alpha c2_o - c_i c1_o,
+//   D_i = -sum K_{i,a,o}  (- G_i = -sum c1_o (v - c_i) for Burgers).
+// Given mu = dJ/dF (one field), the stage adjoint is
+//   out_j = (base terms) + D_j mu_j + sum_{o: j-o in the PE of j} K_{j-o,a,o} mu_{j-o} + A^n_j,
+// where A^l gathers, at the edge strips that neighbours read, K_{i,a,o} c_m(k)
+// mu_i of every later step with n - k - m = l: an adjoint ring of the forward
+// ring's shape, filled by the scatter kernel (in gather form: one thread per
+// strip value) and drained when the sweep reaches level l. The
+// alpha-gradient adds <mu, dF/dalpha> = <mu, AT Laplacian of c>.
+//
+// Euler/AB2 (Sec. 4.1 eqs. time_disc, time_ab2): one stage per step, mu =
+// dt (beta0 lambda^{n+1} + beta1 lambda^{n+2}), out = lambda^n with base
+// lambda^{n+1}. Heun: stage 2 with mu = dt/2 lambda^{n+1} gives sigma = dJ/du*
+// (base lambda^{n+1}/2, predictor ring), then stage 1 with mu = dt sigma gives
+// lambda^n (base lambda^{n+1}/2 + sigma, solution ring).
 
 #include "adjoint.hpp"
 
@@ -97,17 +105,29 @@ __device__ inline double mu_at(const AdjParams& q, int64_t g) {
   return static_cast<double>(static_cast<const Real*>(q.mu)[g]);
 }
 
-// mu^n = dJ/df^n = dt (beta0 lambda^{n+1} + beta1 lambda^{n+2}), stored once
-// per reversed step for both sweeps to gather.
+template <typename Real>
+__device__ inline double centre_at(const AdjParams& q, int64_t g) {
+  return static_cast<double>(static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + g]);
+}
+
+// Tap K_{i,a,o} at a consumer point with stage value ci.
+__device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
+  const StepParams& p = q.sp;
+  if (q.burgers) return p.alpha * p.c2[a][o + p.s] - ci * p.c1[a][o + p.s];
+  return p.kad[a][o + p.s];
+}
+
+// mu = m0 y0 + m1 y1 (dJ/dF of this stage), stored once per stage for both
+// sweeps to gather.
 template <typename Real>
 __global__ __launch_bounds__(kAdjThreads) void adj_mu_kernel(AdjParams q) {
-  const Real* l1 = static_cast<const Real*>(q.lam1);
-  const Real* l2 = static_cast<const Real*>(q.lam2);
+  const Real* y0 = static_cast<const Real*>(q.y0);
+  const Real* y1 = static_cast<const Real*>(q.y1);
   Real* mu = static_cast<Real*>(q.mu);
   for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
        g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double b = q.beta1 != 0.0 ? q.beta1 * static_cast<double>(l2[g]) : 0.0;
-    mu[g] = static_cast<Real>(q.dt * (q.beta0 * static_cast<double>(l1[g]) + b));
+    const double b = q.m1 != 0.0 ? q.m1 * static_cast<double>(y1[g]) : 0.0;
+    mu[g] = static_cast<Real>(q.m0 * static_cast<double>(y0[g]) + b);
   }
 }
 
@@ -159,7 +179,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
       if (ia < 0 || ia >= b) continue;
       int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
       c[a] = org[a] + ia;
-      g += p.kad[a][o + S] * mu_at<Real>(q, gindex(p, c[0], c[1], c[2]));
+      const int64_t gi = gindex(p, c[0], c[1], c[2]);
+      g += tap_k(q, a, o, q.burgers ? centre_at<Real>(q, gi) : 0.0) * mu_at<Real>(q, gi);
     }
     const int k = adj_delay(p, cons, cf, q.n);
     double w[kMaxT];
@@ -240,91 +261,96 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
   }
 }
 
-// lambda^n from lambda^{n+1}, lambda^{n+2} and the adjoint ring slot of level
-// n (drained and cleared here), plus this step's part of dJ/dalpha.
+// The stage adjoint out = b0 x0 + b1 x1 + D mu + transposed taps + the adjoint
+// ring slot of level n (drained and cleared here), plus this stage's part of
+// dJ/dalpha.
 template <typename Real>
 __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
   const StepParams& p = q.sp;
   const int S = p.s;
-  Real* lam0 = static_cast<Real*>(q.lam0);
-  const Real* lam1 = static_cast<const Real*>(q.lam1);
+  Real* out = static_cast<Real*>(q.out);
+  const Real* x0 = static_cast<const Real*>(q.x0);
+  const Real* x1 = static_cast<const Real*>(q.x1);
+  const Real* C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
+  const Real* M = static_cast<const Real*>(q.mu);
   Real* aring = static_cast<Real*>(q.aring);
   const int slot_n = static_cast<int>(q.n % q.anslots);
-  const int T = adj_levels(p);
+  const int64_t st[3] = {1, p.nx, static_cast<int64_t>(p.nx) * p.ny};
   double da = 0.0;
   for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
        g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const Pt j = point_of(p, g);
-    const double mu = mu_at<Real>(q, g);
-    double acc = static_cast<double>(lam1[g]);
-    double lap = 0.0;
+    const double mu = static_cast<double>(M[g]);
+    const double cj = static_cast<double>(C[g]);
+    double acc = q.b0 * static_cast<double>(x0[g]);
+    if (q.b1 != 0.0) acc += q.b1 * static_cast<double>(x1[g]);
+    double lap = 0.0, grad = 0.0, sumk = 0.0;
     bool inner = true;
-    for (int a = 0; a < p.ndim; ++a) {
-      const int b = edge_of(p, a);
-      inner = inner && j.l[a] >= S && j.l[a] < b - S;
-    }
+    for (int a = 0; a < p.ndim; ++a) inner = inner && j.l[a] >= S && j.l[a] < edge_of(p, a) - S;
     if (inner) {
       // every tap of j and every tap reaching j stays inside the PE: level n
       // only, no wrap, no adjoint-ring entry
-      const Real* Un = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
-      const Real* M = static_cast<const Real*>(q.mu);
-      const double u0 = static_cast<double>(Un[g]);
-      const int64_t st[3] = {1, p.nx, static_cast<int64_t>(p.nx) * p.ny};
       for (int a = 0; a < p.ndim; ++a) {
         for (int o = -S; o <= S; ++o) {
           if (o == 0) continue;
-          acc += p.kad[a][o + S] * (static_cast<double>(M[g - o * st[a]]) - mu);
-          lap += p.c2[a][o + S] * (static_cast<double>(Un[g + o * st[a]]) - u0);
+          const double v = static_cast<double>(C[g + o * st[a]]) - cj;
+          lap += p.c2[a][o + S] * v;
+          grad += p.c1[a][o + S] * v;
+          sumk += tap_k(q, a, o, cj);
+          const int64_t gi = g - o * st[a];
+          acc += tap_k(q, a, o, q.burgers ? static_cast<double>(C[gi]) : 0.0) * static_cast<double>(M[gi]);
         }
       }
-      lam0[g] = static_cast<Real>(acc);
-      da += mu * lap;
-      continue;
+    } else {
+      const int gc[3] = {j.x, j.y, j.z};
+      const int ext[3] = {p.nx, p.ny, p.nz};
+      const Real* hb = static_cast<const Real*>(q.hbuf);
+      for (int a = 0; a < p.ndim; ++a) {
+        const int b = edge_of(p, a);
+        for (int o = -S; o <= S; ++o) {
+          if (o == 0) continue;
+          sumk += tap_k(q, a, o, cj);
+          // transposed interior tap: from i = j - o (same PE) to j
+          const int ia = j.l[a] - o;
+          if (ia >= 0 && ia < b) {
+            int c[3] = {gc[0], gc[1], gc[2]};
+            c[a] = gc[a] - o;
+            const int64_t gi = gindex(p, c[0], c[1], c[2]);
+            acc += tap_k(q, a, o, q.burgers ? static_cast<double>(C[gi]) : 0.0) * static_cast<double>(M[gi]);
+          }
+          // forward stencil of the stage field at j (Laplacian and gradient)
+          const int ta = j.l[a] + o;
+          double v;
+          if (ta >= 0 && ta < b) {
+            int c[3] = {gc[0], gc[1], gc[2]};
+            c[a] = (gc[a] + o + ext[a]) % ext[a];
+            v = static_cast<double>(C[gindex(p, c[0], c[1], c[2])]);
+          } else {
+            // the forward halo value of this tap, combined once per stage
+            const int side = ta < 0 ? 0 : 1;
+            const int f = 2 * a + side;
+            int ls[3] = {j.l[0], j.l[1], j.l[2]};
+            ls[a] = side ? ta - b : ta + b;
+            v = static_cast<double>(hb[static_cast<int64_t>(j.pe) * p.pe_block + p.face_off[f] +
+                                       strip_elem(p, f ^ 1, ls, S)]);
+          }
+          lap += p.c2[a][o + S] * (v - cj);
+          grad += p.c1[a][o + S] * (v - cj);
+        }
+        // adjoint-ring contributions of the strips j belongs to on this axis
+        for (int side = 0; side < 2; ++side) {
+          const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
+          if (!in) continue;
+          const int F = 2 * a + side;
+          Real* src = aring + ring_at(p, slot_n, j.pe, F, strip_elem(p, F, j.l, S));
+          acc += static_cast<double>(*src);
+          *src = Real(0);
+        }
+      }
     }
-    const double u0 = level_value<Real>(q, q.n, j.x, j.y, j.z, j.pe, 0, j.l);
-    const int gc[3] = {j.x, j.y, j.z};
-    const int ext[3] = {p.nx, p.ny, p.nz};
-    for (int a = 0; a < p.ndim; ++a) {
-      const int b = edge_of(p, a);
-      for (int o = -S; o <= S; ++o) {
-        if (o == 0) continue;
-        acc -= p.kad[a][o + S] * mu;
-        // transposed interior tap: from i = j - o (same PE) to j
-        const int ia = j.l[a] - o;
-        if (ia >= 0 && ia < b) {
-          int c[3] = {gc[0], gc[1], gc[2]};
-          c[a] = gc[a] - o;
-          acc += p.kad[a][o + S] * mu_at<Real>(q, gindex(p, c[0], c[1], c[2]));
-        }
-        // forward AT Laplacian of the stored levels at j (alpha derivative)
-        const int ta = j.l[a] + o;
-        int c[3] = {gc[0], gc[1], gc[2]};
-        c[a] = (gc[a] + o + ext[a]) % ext[a];
-        double v;
-        if (ta >= 0 && ta < b) {
-          v = level_value<Real>(q, q.n, c[0], c[1], c[2], j.pe, 0, j.l);
-        } else {
-          // the forward halo value of this tap, combined once per step
-          const int side = ta < 0 ? 0 : 1;
-          const int f = 2 * a + side;
-          int ls[3] = {j.l[0], j.l[1], j.l[2]};
-          ls[a] = side ? ta - b : ta + b;
-          v = static_cast<double>(static_cast<const Real*>(q.hbuf)[static_cast<int64_t>(j.pe) * p.pe_block +
-                                                                  p.face_off[f] + strip_elem(p, f ^ 1, ls, S)]);
-        }
-        lap += p.c2[a][o + S] * (v - u0);
-      }
-      // adjoint-ring contributions of the strips j belongs to on this axis
-      for (int side = 0; side < 2; ++side) {
-        const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
-        if (!in) continue;
-        const int F = 2 * a + side;
-        Real* src = aring + ring_at(p, slot_n, j.pe, F, strip_elem(p, F, j.l, S));
-        acc += static_cast<double>(*src);
-        *src = Real(0);
-      }
-    }
-    lam0[g] = static_cast<Real>(acc);
+    // D_j mu_j with D_j = -sum K (- G_j for Burgers)
+    acc += (-sumk - (q.burgers ? grad : 0.0)) * mu;
+    out[g] = static_cast<Real>(acc);
     da += mu * lap;
   }
   // fixed-order block reduction of the alpha-gradient part

@@ -8,21 +8,27 @@ namespace atfd {
 
 constexpr int kAdjBlocks = 1024;   // fixed grid of the lambda kernel: its alpha partials
 
+// One stage of the reversed step n (see adjoint.hip): mu = m0 y0 + m1 y1,
+// out = b0 x0 + b1 x1 + (transposed stage) + drained adjoint ring.
 struct AdjParams {
-  StepParams sp;                   // the forward problem (taps kad, c2; delays; ring layout)
+  StepParams sp;                   // the forward problem (taps, delays, ring layout)
   int64_t n;                       // the step being reversed (n -> n + 1)
   int64_t npts;
-  double dt, beta0, beta1;         // mu^n = dt (beta0 lambda^{n+1} + beta1 lambda^{n+2})
-  const void* lam1;                // lambda^{n+1}
-  const void* lam2;                // lambda^{n+2}
-  void* lam0;                      // lambda^n (output)
-  void* mu;                        // mu^n (written by the first kernel of the step)
-  void* hbuf;                      // forward halo values of step n [pe][face strips]
-  void* aring;                     // adjoint ring, forward ring layout, anslots slots
-  int anslots;
-  const void* levels;              // forward levels seg_start .. seg_start + len, npts apart
+  int burgers;                     // Burgers right-hand side (taps depend on the stage field)
+  const void* y0;
+  const void* y1;
+  double m0, m1;
+  void* mu;                        // dJ/dF of this stage (written by the first kernel)
+  const void* x0;
+  const void* x1;
+  double b0, b1;
+  void* out;                       // the stage's adjoint field
+  const void* levels;              // stored levels of the stage field from seg_start, npts apart
   int64_t seg_start;
-  const void* ring0;               // the forward ring at step seg_start
+  const void* ring0;               // that field's ring at step seg_start
+  void* hbuf;                      // forward halo values of this stage [pe][face strips]
+  void* aring;                     // adjoint ring of the stage field, anslots slots
+  int anslots;
   double* partial;                 // [kAdjBlocks] alpha-gradient partial sums
 };
 

@@ -602,14 +602,18 @@ const char* at_last_error(const at_ctx* c) {
 
 namespace {
 
-// Scratch layout of at_adjoint: nck + 1 checkpoints, the levels of one
-// segment (contiguous fields), three lambda fields, the adjoint ring, the
-// forward ring at the segment start, alpha partial sums.
+// Scratch layout of at_adjoint: nck + 1 checkpoints; the levels of one
+// segment (contiguous fields: u^seg .. u^{seg+every}, and for RK2 the
+// predictors u*^seg .. u*^{seg+every-1}); the adjoint fields (lambda x3,
+// sigma, mu); the forward halo buffer; the adjoint ring (two for RK2); the
+// forward rings at the segment start; alpha partial sums.
 struct AdjLayout {
-  size_t ck = 0, off_levels = 0, off_lam[3] = {0, 0, 0}, off_mu = 0, off_hbuf = 0, off_aring = 0, off_ring0 = 0;
+  size_t ck = 0, off_levels = 0, off_slevels = 0, off_lam[3] = {0, 0, 0}, off_sigma = 0, off_mu = 0;
+  size_t off_hbuf = 0, off_aring = 0, off_bring = 0, off_ring0 = 0, off_sring0 = 0;
   size_t off_partial = 0, off_out = 0, total = 0, aring_bytes = 0;
   int64_t nck = 0;
   int anslots = 0;
+  bool rk2 = false;
 };
 
 AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
@@ -618,6 +622,7 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   at_checkpoint_size(c, &ck);
   a.ck = align_up(ck);
   a.nck = (nsteps + every - 1) / every;
+  a.rk2 = c->prob.integrator == AT_RK2;
   size_t off = a.ck * static_cast<size_t>(a.nck + 1);
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -625,14 +630,19 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
     return o;
   };
   const Layout& l = c->lay;
+  const size_t w = c->g.f64 ? 8 : 4;
   a.off_levels = take(l.field_bytes * static_cast<size_t>(every + 1));
+  if (a.rk2) a.off_slevels = take(l.field_bytes * static_cast<size_t>(every));
   for (int i = 0; i < 3; ++i) a.off_lam[i] = take(l.field_bytes);
+  if (a.rk2) a.off_sigma = take(l.field_bytes);
   a.off_mu = take(l.field_bytes);
-  a.off_hbuf = take(static_cast<size_t>(c->g.npe) * l.pe_block * (c->g.f64 ? 8 : 4));
+  a.off_hbuf = take(static_cast<size_t>(c->g.npe) * l.pe_block * w);
   a.anslots = c->delay.mode == AT_SYNC ? 1 : l.nslots;
-  a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * (c->g.f64 ? 8 : 4);
+  a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * w;
   a.off_aring = take(a.aring_bytes);
+  if (a.rk2) a.off_bring = take(a.aring_bytes);
   a.off_ring0 = take(l.ring_bytes);
+  if (a.rk2) a.off_sring0 = take(l.ring_bytes);
   a.off_partial = take(kAdjBlocks * sizeof(double));
   a.off_out = take(sizeof(double));
   a.total = off;
@@ -642,9 +652,7 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
 at_status adj_check(at_ctx* c, int64_t nsteps, int32_t every) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
   if (nsteps < 1 || every < 1) return fail(c, AT_EINVAL, "nsteps and the checkpoint interval must be >= 1");
-  if (c->prob.equation != AT_ADVDIFF) return fail(c, AT_EINVAL, "the adjoint covers advection-diffusion");
-  if (c->prob.integrator != AT_EULER && c->prob.integrator != AT_AB2)
-    return fail(c, AT_EINVAL, "the adjoint covers Euler and AB2");
+  if (c->prob.integrator == AT_AB3) return fail(c, AT_EINVAL, "the adjoint covers Euler, AB2 and RK2");
   if (c->delay.mode == AT_DELAY_HOST && nsteps > c->delay.host_nsteps)
     return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
   if (c->g.npts >= (int64_t(1) << 31)) return fail(c, AT_EINVAL, "the adjoint covers fields below 2^31 points");
@@ -686,28 +694,38 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
   }
   st = at_save(c, sc + a.ck * a.nck);
   if (st != AT_OK) return st;
-  // reverse sweep: lambda^N = seed
+  // reverse sweep from lambda^N = seed
   unsigned char* lam[3] = {sc + a.off_lam[0], sc + a.off_lam[1], sc + a.off_lam[2]};
   int i1 = 0, i2 = 1, i0 = 2;   // roles: lambda^{n+1}, lambda^{n+2}, lambda^n
   HIP_TRY(c, hipMemcpyAsync(lam[i1], seed_dev, l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(lam[i2], 0, l.field_bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(sc + a.off_aring, 0, a.aring_bytes, c->stream));
+  if (a.rk2) HIP_TRY(c, hipMemsetAsync(sc + a.off_bring, 0, a.aring_bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(sc + a.off_partial, 0, kAdjBlocks * sizeof(double), c->stream));
   unsigned char* levels = sc + a.off_levels;
+  unsigned char* slevels = a.rk2 ? sc + a.off_slevels : nullptr;
+  const double dt = c->prob.dt;
   for (int64_t s = a.nck - 1; s >= 0; --s) {
     st = at_load(c, sc + a.ck * s);
     if (st != AT_OK) return st;
     const int64_t seg = s * every;
     const int64_t len = std::min<int64_t>(every, N - seg);
     HIP_TRY(c, hipMemcpyAsync(levels, c->sp.ubuf[c->n & 1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (l.ring_bytes)
+    if (l.ring_bytes) {
       HIP_TRY(c, hipMemcpyAsync(sc + a.off_ring0, c->sp.ring, l.ring_bytes, hipMemcpyDeviceToDevice, c->stream));
+      if (a.rk2)
+        HIP_TRY(c, hipMemcpyAsync(sc + a.off_sring0, c->sp.sring, l.ring_bytes, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    }
     for (int64_t j = 1; j <= len; ++j) {
       st = enqueue_step(c, c->stream);
       if (st != AT_OK) return st;
       c->n += 1;
       HIP_TRY(c, hipMemcpyAsync(levels + l.field_bytes * j, c->sp.ubuf[c->n & 1], l.field_bytes,
                                 hipMemcpyDeviceToDevice, c->stream));
+      if (a.rk2)
+        HIP_TRY(c, hipMemcpyAsync(slevels + l.field_bytes * (j - 1), c->sp.ustar, l.field_bytes,
+                                  hipMemcpyDeviceToDevice, c->stream));
     }
     for (int64_t n = seg + len - 1; n >= seg; --n) {
       AdjParams q;
@@ -715,21 +733,44 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       q.sp = c->sp;
       q.n = n;
       q.npts = c->g.npts;
-      q.dt = c->prob.dt;
-      const bool ab2 = c->prob.integrator == AT_AB2;
-      q.beta0 = (ab2 && n > 0) ? 1.5 : 1.0;
-      q.beta1 = (ab2 && n + 1 <= N - 1) ? -0.5 : 0.0;
-      q.lam1 = lam[i1];
-      q.lam2 = lam[i2];
-      q.lam0 = lam[i0];
+      q.burgers = c->prob.equation == AT_BURGERS;
       q.mu = sc + a.off_mu;
       q.hbuf = sc + a.off_hbuf;
-      q.aring = sc + a.off_aring;
       q.anslots = a.anslots;
-      q.levels = levels;
       q.seg_start = seg;
-      q.ring0 = sc + a.off_ring0;
       q.partial = reinterpret_cast<double*>(sc + a.off_partial);
+      if (a.rk2) {
+        // stage 2: sigma = dJ/du*^n from mu = dt/2 lambda^{n+1}
+        AdjParams q2 = q;
+        q2.y0 = lam[i1];
+        q2.m0 = 0.5 * dt;
+        q2.x0 = lam[i1];
+        q2.b0 = 0.5;
+        q2.out = sc + a.off_sigma;
+        q2.levels = slevels;
+        q2.ring0 = sc + a.off_sring0;
+        q2.aring = sc + a.off_bring;
+        HIP_TRY(c, launch_adj_step(q2, c->g.f64, c->stream));
+        // stage 1: lambda^n from mu = dt sigma
+        q.y0 = sc + a.off_sigma;
+        q.m0 = dt;
+        q.x0 = lam[i1];
+        q.b0 = 0.5;
+        q.x1 = sc + a.off_sigma;
+        q.b1 = 1.0;
+      } else {
+        const bool ab2 = c->prob.integrator == AT_AB2;
+        q.y0 = lam[i1];
+        q.m0 = dt * ((ab2 && n > 0) ? 1.5 : 1.0);
+        q.y1 = lam[i2];
+        q.m1 = (ab2 && n + 1 <= N - 1) ? -0.5 * dt : 0.0;
+        q.x0 = lam[i1];
+        q.b0 = 1.0;
+      }
+      q.out = lam[i0];
+      q.levels = levels;
+      q.ring0 = sc + a.off_ring0;
+      q.aring = sc + a.off_aring;
       HIP_TRY(c, launch_adj_step(q, c->g.f64, c->stream));
       const int t = i2;
       i2 = i1;
@@ -749,4 +790,3 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
 }
 
 }  // extern "C"
-

@@ -64,3 +64,28 @@ def test_gradient_matches_directional_differences(ndim, n, pe, order, integ):
     ja = float((seed * forward(prob, dm, u0, 0.1 + ea, steps)).sum())
     jb = float((seed * forward(prob, dm, u0, 0.1 - ea, steps)).sum())
     assert ga == pytest.approx((ja - jb) / (2 * ea), rel=1e-6)
+
+
+def test_burgers_rk2_gradient_matches_directional_differences():
+    """Nonlinear case (viscous Burgers, Heun RK2 with the predictor's own
+    history): central differences with eps = 1e-6 carry an O(eps^2) error."""
+    dx = 2 * math.pi / 48
+    prob = Problem(ndim=1, n=(48,), pe=(4,), dt=0.01 * dx * dx / 0.05, order=4, equation="burgers",
+                   alpha=0.05, integrator="rk2")
+    dm = DelayModel(L=3, mode="rng", seed=9)
+    rs = np.random.default_rng(4)
+    u0 = torch.from_numpy(0.5 * np.sin(np.arange(48) * dx) + 0.1 * rs.standard_normal(48)).reshape(1, 1, 48)
+    seed = torch.from_numpy(rs.standard_normal((1, 1, 48)))
+    steps = 12
+    gu, ga = gradients(prob, dm, u0, 0.05, steps, seed)
+    for _ in range(3):
+        d = torch.from_numpy(rs.standard_normal((1, 1, 48)))
+        eps = 1e-6
+        up = forward(prob, dm, u0 + eps * d, 0.05, steps)
+        um = forward(prob, dm, u0 - eps * d, 0.05, steps)
+        fd = float((seed * (up - um)).sum()) / (2 * eps)
+        assert float((gu * d).sum()) == pytest.approx(fd, rel=1e-7)
+    ea = 1e-6
+    ja = float((seed * forward(prob, dm, u0, 0.05 + ea, steps)).sum())
+    jb = float((seed * forward(prob, dm, u0, 0.05 - ea, steps)).sum())
+    assert ga == pytest.approx((ja - jb) / (2 * ea), rel=1e-6)

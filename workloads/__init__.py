@@ -119,7 +119,7 @@ def burgers_spectrum_field(n, ndim, seed=2, kpeak=4.0, urms=0.5):
         amp = np.where(kmag > 0, np.sqrt(espec / np.maximum(kmag, 1e-30) ** (ndim - 1)), 0.0)
     ph = rs.uniform(0.0, TWO_PI, size=amp.shape)
     spec = amp * np.exp(1j * ph)
-    u = np.fft.irfftn(spec, s=shape)
+    u = np.fft.irfftn(spec, s=shape, axes=tuple(range(ndim)))
     u = u * (urms / np.sqrt((u * u).mean()))
     u3 = u.reshape((1,) * (3 - ndim) + u.shape)   # (nz, ny, nx)
     return np.ascontiguousarray(u3)
