@@ -62,13 +62,13 @@ __device__ inline int64_t gindex(const StepParams& p, int x, int y, int z) {
 __device__ inline int edge_of(const StepParams& p, int a) { return a == 0 ? p.bx : a == 1 ? p.by : p.bz; }
 
 // Element of the strip of face F = 2a + side of a PE for the point with PE
-// coordinates l (which must lie in that strip): x faces [z][d][y], y faces
+// coordinates l (which must lie in that strip): x faces [z][y][d], y faces
 // [z][d][x], z faces [d][y][x], with depth d counted from the PE's low side.
 __device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, int S) {
   const int a = F >> 1;
   const int b = edge_of(p, a);
   const int d = (F & 1) ? l[a] - (b - S) : l[a];
-  if (a == 0) return (static_cast<int64_t>(l[2]) * S + d) * p.by + l[1];
+  if (a == 0) return (static_cast<int64_t>(l[2]) * p.by + l[1]) * S + d;
   if (a == 1) return (static_cast<int64_t>(l[2]) * S + d) * p.bx + l[0];
   return (static_cast<int64_t>(d) * p.by + l[1]) * p.bx + l[0];
 }
@@ -152,8 +152,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
     int l[3] = {0, 0, 0};
     int d;
     if (a == 0) {
-      l[1] = static_cast<int>(e % p.by);
-      d = static_cast<int>((e / p.by) % S);
+      d = static_cast<int>(e % S);
+      l[1] = static_cast<int>((e / S) % p.by);
       l[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
     } else if (a == 1) {
       l[0] = static_cast<int>(e % p.bx);
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
     int ls[3] = {0, 0, 0};
     int d;
     if (a == 0) {
-      ls[1] = static_cast<int>(e % p.by);
-      d = static_cast<int>((e / p.by) % S);
+      d = static_cast<int>(e % S);
+      ls[1] = static_cast<int>((e / S) % p.by);
       ls[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
     } else if (a == 1) {
       ls[0] = static_cast<int>(e % p.bx);

@@ -99,12 +99,12 @@ struct Sweep {
         const int x = i % bx, y = i / bx;
         P[(DIM >= 2 ? y + S : 0) * px_stride + x + S] = centre[gidx(x0 + x, y0 + y, gz)];
       }
-      // x halos: [side][d][y], producer strip [z][d][y]
+      // x halos: producer strip [z][y][d]
       for (int h = tid; h < 2 * S * by; h += nt) {
-        const int side = h / (S * by), r = h % (S * by), d = r / by, y = r % by;
+        const int side = h / (S * by), r = h % (S * by), d = r % S, y = r / S;
         const int xl = side ? bx + d : d - S;
         const int gx = (x0 + xl + p.nx) % p.nx;
-        const int64_t q = (static_cast<int64_t>(zz) * S + d) * by + y;
+        const int64_t q = (static_cast<int64_t>(zz) * by + y) * S + d;
         P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, q, gx, y0 + y, gz);
       }
       if (DIM >= 2) {
@@ -236,8 +236,8 @@ struct Sweep {
     Real* R = static_cast<Real*>(rk1 ? p.sring : p.ring);
     const int slot = static_cast<int>((rk1 ? n : n + 1) % p.nslots);
     const int bx = p.bx, by = p.by, bz = p.bz;
-    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * S + x) * by + y)] = v;
-    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * S + x - (bx - S)) * by + y)] = v;
+    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * by + y) * S + x)] = v;
+    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * by + y) * S + x - (bx - S))] = v;
     if (DIM >= 2) {
       if (y < S) R[ring_off(slot, pid, 2, (static_cast<int64_t>(z) * S + y) * bx + x)] = v;
       if (y >= by - S) R[ring_off(slot, pid, 3, (static_cast<int64_t>(z) * S + y - (by - S)) * bx + x)] = v;
@@ -336,8 +336,8 @@ __global__ __launch_bounds__(kThreads) void publish_all_kernel(StepParams p) {
     int face[6];
     int64_t q[6];
     int nf = 0;
-    if (x < S) { face[nf] = 0; q[nf++] = (static_cast<int64_t>(z) * S + x) * p.by + y; }
-    if (x >= p.bx - S) { face[nf] = 1; q[nf++] = (static_cast<int64_t>(z) * S + x - (p.bx - S)) * p.by + y; }
+    if (x < S) { face[nf] = 0; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x; }
+    if (x >= p.bx - S) { face[nf] = 1; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * S + x - (p.bx - S); }
     if (DIM >= 2 && y < S) { face[nf] = 2; q[nf++] = (static_cast<int64_t>(z) * S + y) * p.bx + x; }
     if (DIM >= 2 && y >= p.by - S) { face[nf] = 3; q[nf++] = (static_cast<int64_t>(z) * S + y - (p.by - S)) * p.bx + x; }
     if (DIM == 3 && z < S) { face[nf] = 4; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * p.bx + x; }

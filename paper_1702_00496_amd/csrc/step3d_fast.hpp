@@ -18,7 +18,7 @@
 //    neighbour enters as (v - u0), which keeps float rounding relative to the
 //    O(dx) differences instead of the O(1/dx^2) taps; each axis accumulates
 //    into its own partial sum (three independent FMA chains per point).
-// Halo items are quads (x faces are stored [z][d][y], y faces [z][d][x]); the
+// Halo items are quads (x faces are stored [z][y][d], y faces [z][d][x]); the
 // ring slot and weight of every live delayed level of a face sit in LDS, and
 // a level with zero weight re-reads level n-k with weight 0 so that no read
 // sits behind a branch.
@@ -92,6 +92,20 @@ __device__ inline Vec<Real, V> zerov() {
 #pragma unroll
   for (int i = 0; i < V; ++i) r.v[i] = Real(0);
   return r;
+}
+
+// Store a run of N consecutive values (N = s <= 3; s = 2 as one 8- or
+// 16-byte vector store: its offset is even).
+template <typename Real, int N>
+__device__ inline void st_run(Real* p, const Real* w) {
+  if constexpr (N == 2 && sizeof(Real) == 4) {
+    *reinterpret_cast<float2*>(p) = make_float2(w[0], w[1]);
+  } else if constexpr (N == 2) {
+    *reinterpret_cast<double2*>(p) = make_double2(w[0], w[1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = w[i];
+  }
 }
 
 __device__ inline int neighbour_pe(const StepParams& p, int pid, int f) {
@@ -222,10 +236,12 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   };
 
   // Halo items, all quads so that every thread issues the same reads:
-  // x items (side, depth d, rows yq..yq+3; producer strip [z][d][y]) and y
-  // items (side, depth d, columns xq..xq+3; strip [z][d][x]). Each wave owns a
-  // contiguous share of the items in its low lanes; other lanes alias item 0
-  // (their reads hit the same lines and are discarded).
+  // x items (side and four consecutive values of the producer strip [z][y][d],
+  // i.e. rows and depths (e / S, e % S); the synchronous arm reads rows
+  // yq..yq+3 at one depth of the neighbour's field instead) and y items (side,
+  // depth d, columns xq..xq+3; strip [z][d][x]). Each wave owns a contiguous
+  // share of the items in its low lanes; other lanes alias item 0 (their reads
+  // hit the same lines and are discarded).
   constexpr int QPR = kB / 4;
   constexpr int NHX = 2 * S * QPR;
   constexpr int NH = 2 * NHX;
@@ -236,23 +252,34 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   const bool is_h = lane < NHW;
   const int hid = is_h ? (tid >> 6) * NHW + lane : 0;
   Src hs;
-  int hpos, lstride, estride;       // LDS position / stride of the 4 values, element stride (SYNC)
+  int hp[4];                        // LDS positions of the 4 values
+  int estride;                      // element stride of the synchronous arm's reads
   if (hid < NHX) {
-    const int side = hid / (S * QPR), r = hid % (S * QPR), d = r / QPR, yq = 4 * (r % QPR);
-    const int xl = side ? kB + d : d - S;
-    const int gx = (x0 + xl + p.nx) % p.nx;
-    hpos = (yq + S) * kRS + kHO + xl;
-    lstride = kRS;
-    estride = p.nx;
-    hs = make_src(side, static_cast<int64_t>(d) * kB + yq, static_cast<int64_t>(S) * kB,
-                  (static_cast<int64_t>(z0) * p.ny + y0 + yq) * p.nx + gx);
+    const int side = hid / (S * QPR), r = hid % (S * QPR);
+    if (kSync) {
+      const int d = r / QPR, yq = 4 * (r % QPR);
+      const int xl = side ? kB + d : d - S;
+      const int gx = (x0 + xl + p.nx) % p.nx;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hp[i] = (yq + i + S) * kRS + kHO + xl;
+      estride = p.nx;
+      hs = make_src(side, 0, 0, (static_cast<int64_t>(z0) * p.ny + y0 + yq) * p.nx + gx);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = 4 * r + i, y = e / S, d = e - (e / S) * S;
+        hp[i] = (y + S) * kRS + kHO + (side ? kB + d : d - S);
+      }
+      estride = 1;
+      hs = make_src(side, static_cast<int64_t>(4) * r, static_cast<int64_t>(S) * kB, 0);
+    }
   } else {
     const int h = hid - NHX;
     const int side = h / (S * QPR), r = h % (S * QPR), d = r / QPR, xq = 4 * (r % QPR);
     const int yl = side ? kB + d : d - S;
     const int gy = (y0 + yl + p.ny) % p.ny;
-    hpos = (yl + S) * kRS + kHO + xq;
-    lstride = 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hp[i] = (yl + S) * kRS + kHO + xq + i;
     estride = 1;
     hs = make_src(2 + side, static_cast<int64_t>(d) * kB + xq, static_cast<int64_t>(S) * kB,
                   (static_cast<int64_t>(z0) * p.ny + gy) * p.nx + x0 + xq);
@@ -345,7 +372,7 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
       if (is_h) {
         const Q hv = combine_levels<Real, 4, TT>(hs.w, HR[j], kSync);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Lp[hpos + i * lstride] = hv.v[i];
+        for (int i = 0; i < 4; ++i) Lp[hp[i]] = hv.v[i];
       }
       // refill the slot with what iteration z + D consumes
       if (z + D < bz) {
@@ -422,17 +449,34 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
       if (KIND == kAb2 || KIND == kAb3) stv<Real, V>(fout, g, fq);
       if (!kSync) {
         // publish the new edge values into the ring slot of their level;
-        // x faces: strip [z][d][y]
+        // x faces: strip [z][y][d], one run of s values per row
+        const int64_t xrow = (static_cast<int64_t>(z) * kB + y) * S;
+        if constexpr (V == 4) {
+          // the first quad of a row holds the low-face depths, the last one
+          // the high-face depths: one store of s values for both faces
+          const bool lo = vi == 0, hi = vi == VPR - 1;
+          if (lo || hi) {
+            Real w[S];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          if (x + e < S)
-            pstrip[p.face_off[0] + (static_cast<int64_t>(z) * S + x + e) * kB + y] = un.v[e];
-          if (x + e >= kB - S)
-            pstrip[p.face_off[1] + (static_cast<int64_t>(z) * S + x + e - (kB - S)) * kB + y] = un.v[e];
+            for (int d = 0; d < S; ++d) w[d] = hi ? un.v[V - S + d] : un.v[d];
+            // (select between the two uniform offsets: an index that varies
+            // per lane would turn the kernel-argument read into a memory load)
+            const int64_t fo = hi ? p.face_off[1] : p.face_off[0];
+            st_run<Real, S>(pstrip + fo + xrow, w);
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            if (x + e < S) pstrip[p.face_off[0] + xrow + x + e] = un.v[e];
+            if (x + e >= kB - S) pstrip[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
+          }
         }
-        if (y < S) stv<Real, V>(pstrip + p.face_off[2], static_cast<uint32_t>((z * S + y) * kB + x), un);
-        if (y >= kB - S)
-          stv<Real, V>(pstrip + p.face_off[3], static_cast<uint32_t>((z * S + y - (kB - S)) * kB + x), un);
+        // y faces: strip [z][d][x]; rows 0..s-1 and kB-s..kB-1, one store
+        if (y < S || y >= kB - S) {
+          const int64_t fo = y < S ? p.face_off[2] : p.face_off[3];
+          const int d = y < S ? y : y - (kB - S);
+          stv<Real, V>(pstrip + fo, static_cast<uint32_t>((z * S + d) * kB + x), un);
+        }
         if (z < S) stv<Real, V>(pstrip + p.face_off[4], static_cast<uint32_t>((z * kB + y) * kB + x), un);
         if (z >= bz - S)
           stv<Real, V>(pstrip + p.face_off[5], static_cast<uint32_t>(((z - (bz - S)) * kB + y) * kB + x), un);
