@@ -73,8 +73,13 @@ __device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, i
   return (static_cast<int64_t>(d) * p.by + l[1]) * p.bx + l[0];
 }
 
+// Offset of face F's strip inside one PE's pe_block values (the order used by
+// the per-PE thread numbering and the halo buffer; the ring itself stores the
+// faces of all PEs plane by plane).
+__device__ inline int64_t pe_face_off(const StepParams& p, int F) { return p.face_off[F] / p.npe; }
+
 __device__ inline int64_t ring_at(const StepParams& p, int slot, int pe, int F, int64_t e) {
-  return (static_cast<int64_t>(slot) * p.npe + pe) * p.pe_block + p.face_off[F] + e;
+  return ring_index_q(p, slot, pe, F, e);
 }
 
 __device__ inline int nbr_pe(const StepParams& p, int pid, int f) {
@@ -145,8 +150,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
     const int pe = static_cast<int>(t / p.pe_block);
     const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
     int F = 0;
-    while (F + 1 < 2 * p.ndim && r >= p.face_off[F + 1]) ++F;
-    const int64_t e = r - p.face_off[F];
+    while (F + 1 < 2 * p.ndim && r >= pe_face_off(p, F + 1)) ++F;
+    const int64_t e = r - pe_face_off(p, F);
     const int a = F >> 1;
     // decode the PE coordinates of strip element e
     int l[3] = {0, 0, 0};
@@ -215,7 +220,7 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y
 // The forward halo values of step n, for the alpha-derivative: for every
 // consumer PE, face f and element e of the producer strip it reads, the AT
 // combination of the stored levels (the synchronous scheme: level n).
-// hbuf[pe * pe_block + face_off[f] + e].
+// hbuf[pe * pe_block + (per-PE offset of face f) + e].
 template <typename Real>
 __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
   const StepParams& p = q.sp;
@@ -228,8 +233,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
     const int pe = static_cast<int>(t / p.pe_block);
     const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
     int f = 0;
-    while (f + 1 < 2 * p.ndim && r >= p.face_off[f + 1]) ++f;
-    const int64_t e = r - p.face_off[f];
+    while (f + 1 < 2 * p.ndim && r >= pe_face_off(p, f + 1)) ++f;
+    const int64_t e = r - pe_face_off(p, f);
     const int a = f >> 1, pf = f ^ 1;
     int ls[3] = {0, 0, 0};
     int d;
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
             const int f = 2 * a + side;
             int ls[3] = {j.l[0], j.l[1], j.l[2]};
             ls[a] = side ? ta - b : ta + b;
-            v = static_cast<double>(hb[static_cast<int64_t>(j.pe) * p.pe_block + p.face_off[f] +
+            v = static_cast<double>(hb[static_cast<int64_t>(j.pe) * p.pe_block + pe_face_off(p, f) +
                                        strip_elem(p, f ^ 1, ls, S)]);
           }
           lap += p.c2[a][o + S] * (v - cj);

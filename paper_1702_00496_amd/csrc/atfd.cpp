@@ -35,6 +35,7 @@ struct Layout {
   int nslots = 0;
   int64_t pe_block = 0;
   int64_t face_off[6] = {0, 0, 0, 0, 0, 0};
+  int64_t face_chunk[6] = {1, 1, 1, 1, 1, 1};
   int nfbuf = 0;
   bool star = false;
 };
@@ -161,20 +162,26 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
   for (int i = 0; i < l.nfbuf; ++i) l.off_f[i] = take(l.field_bytes);
   l.star = p->integrator == AT_RK2;
   if (l.star) l.off_ustar = take(l.field_bytes);
-  // face strips of one PE: faces 2a, 2a+1 hold s * (product of the other edges)
+  // face strips: faces 2a, 2a+1 of a PE hold s * (product of the other
+  // edges) values, as planes of face_chunk values (x, y faces: one plane per
+  // z-plane; z faces: one per depth); a slot stores every face's planes of
+  // all PEs side by side (ring_index)
   const int s = g.s;
-  int64_t fo = 0;
+  int64_t fo = 0, pe_block = 0;
   for (int a = 0; a < 3; ++a) {
     int64_t area = 1;
     for (int c = 0; c < 3; ++c)
       if (c != a) area *= g.b[c];
     const int64_t sz = a < g.ndim ? s * area : 0;
-    l.face_off[2 * a] = fo;
-    fo += sz;
-    l.face_off[2 * a + 1] = fo;
-    fo += sz;
+    const int64_t chunk = a == 2 ? static_cast<int64_t>(g.b[0]) * g.b[1] : static_cast<int64_t>(s) * g.b[1 - a];
+    for (int side = 0; side < 2; ++side) {
+      l.face_off[2 * a + side] = fo;
+      l.face_chunk[2 * a + side] = chunk > 0 ? chunk : 1;
+      fo += sz * g.npe;
+      pe_block += sz;
+    }
   }
-  l.pe_block = fo;
+  l.pe_block = pe_block;
   if (d->mode != AT_SYNC) {
     l.nslots = d->L + g.T;
     l.ring_bytes = static_cast<size_t>(l.nslots) * g.npe * l.pe_block * w;
@@ -242,7 +249,10 @@ void fill_params(at_ctx* c) {
   p.sring = (l.nslots && l.star) ? ws + l.off_sring : nullptr;
   p.nslots = l.nslots;
   p.pe_block = l.pe_block;
-  for (int f = 0; f < 6; ++f) p.face_off[f] = l.face_off[f];
+  for (int f = 0; f < 6; ++f) {
+    p.face_off[f] = l.face_off[f];
+    p.face_chunk[f] = l.face_chunk[f];
+  }
   p.counter = reinterpret_cast<int64_t*>(ws + l.off_counter);
   p.advance = 1;
 }

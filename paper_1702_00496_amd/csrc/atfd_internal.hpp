@@ -121,16 +121,37 @@ struct StepParams {
   void* ubuf[2];               // ping-pong solution, u^n in ubuf[n & 1]
   void* fbuf[2];               // f history (AB2: fbuf[0]; AB3: f^n -> fbuf[n & 1])
   void* ustar;                 // RK2 predictor
-  void* ring;                  // u levels: [nslots][npe][pe_block]
+  void* ring;                  // u levels: slot, then face, then plane, then PE (see ring_index)
   void* sring;                 // RK2 predictor levels
   int nslots;
-  int64_t pe_block;            // elements of all face strips of one PE
-  int64_t face_off[6];         // strip offset of face 2*axis+side within a PE block
+  int64_t pe_block;            // elements of all face strips of one PE (a slot holds npe of them)
+  int64_t face_off[6];         // offset of face 2*axis+side's strips (all PEs) within a slot
+  int64_t face_chunk[6];       // elements of one plane of one PE's strip of that face
   int64_t* counter;            // [0] = step n, [1] = finished workgroups
   int advance;                 // this launch ends the step: bump the counter
   int depth;                   // 3-D 32x32 path schedule: planes in flight D (1, 2, 4) with 4
                                // points per thread, or 8 + D with 2 points per thread
 };
+
+// Ring layout. The strip of face f of a PE is a stack of planes (x and y
+// faces: one per z-plane of the PE, [y][d] and [d][x] inside; z faces: one per
+// depth d, [y][x] inside) of face_chunk[f] elements. A slot stores, face by
+// face and plane by plane, the planes of all PEs side by side:
+//   [slot][face][plane][pe][chunk].
+// Workgroups sweep their PEs' z-planes in step, so the strips that all of them
+// publish or read at one moment form one contiguous run of memory.
+__host__ __device__ inline int64_t ring_index(const StepParams& p, int slot, int pe, int f, int64_t plane,
+                                              int64_t r) {
+  return static_cast<int64_t>(slot) * p.npe * p.pe_block + p.face_off[f] +
+         (plane * p.npe + pe) * p.face_chunk[f] + r;
+}
+
+// Same, for element q of the PE's strip counted plane after plane.
+__host__ __device__ inline int64_t ring_index_q(const StepParams& p, int slot, int pe, int f, int64_t q) {
+  const int64_t c = p.face_chunk[f];
+  const int64_t plane = q / c;
+  return ring_index(p, slot, pe, f, plane, q - plane * c);
+}
 
 struct NormParams {
   int nx, ny, nz, bx, by, bz, ndim, s;

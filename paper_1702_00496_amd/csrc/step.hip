@@ -70,7 +70,7 @@ struct Sweep {
 
   // Offset of element q of face `face` of PE `pe` in ring slot `slot`.
   __device__ int64_t ring_off(int slot, int pe, int face, int64_t q) const {
-    return (static_cast<int64_t>(slot) * p.npe + pe) * p.pe_block + p.face_off[face] + q;
+    return ring_index_q(p, slot, pe, face, q);
   }
 
   // Halo value across face f = 2*axis + side, element q of the producer strip.
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void publish_all_kernel(StepParams p) {
     const Real v = u[(static_cast<int64_t>(z0 + z) * p.ny + y0 + y) * p.nx + x0 + x];
     for (int j = 0; j < nf; ++j)
       for (int sl = 0; sl < p.nslots; ++sl) {
-        const int64_t off = (static_cast<int64_t>(sl) * p.npe + pid) * p.pe_block + p.face_off[face[j]] + q[j];
+        const int64_t off = ring_index_q(p, sl, pid, face[j], q[j]);
         R[off] = v;
         if (SR) SR[off] = v;
       }

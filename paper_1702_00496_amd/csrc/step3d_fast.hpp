@@ -225,13 +225,21 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
       r.stride = zstride;
       return r;
     }
-    const Real* strip = ring + static_cast<int64_t>(s_nbr[f]) * p.pe_block + p.face_off[f ^ 1] + q0;
+    // producer face f ^ 1 of the neighbour (uniform offsets selected, not
+    // indexed per lane)
+    const int pf = f ^ 1;
+    const int64_t foff = pf == 0 ? p.face_off[0] : pf == 1 ? p.face_off[1] : pf == 2 ? p.face_off[2]
+                       : pf == 3 ? p.face_off[3] : pf == 4 ? p.face_off[4] : p.face_off[5];
+    const int64_t chunk = pf < 4 ? p.face_chunk[0] : p.face_chunk[4];
+    const Real* strip = ring + foff + static_cast<int64_t>(s_nbr[f]) * chunk + q0;
 #pragma unroll
     for (int m = 0; m < TT; ++m) {
       r.lvl[m] = strip + s_slot[f * kMaxT + m] * slot_stride;
       r.w[m] = s_w[f * kMaxT + m];
     }
-    r.stride = qstride;
+    // the next plane of the same strip is npe chunks further (ring_index)
+    r.stride = static_cast<int64_t>(p.npe) * chunk;
+    (void)qstride;
     return r;
   };
 
@@ -341,7 +349,12 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   Real* unext = static_cast<Real*>(KIND == kRk1 ? p.ustar : p.ubuf[(n + 1) & 1]);
   Real* pub = static_cast<Real*>(KIND == kRk1 ? p.sring : p.ring);
   const int pslot = static_cast<int>((KIND == kRk1 ? n : n + 1) % (p.nslots > 0 ? p.nslots : 1));
-  Real* pstrip = kSync ? nullptr : pub + (static_cast<int64_t>(pslot) * p.npe + pid) * p.pe_block;
+  // this PE's strips in the ring slot of the new level (ring_index): plane
+  // z of an x or y face at face_off + (z npe + pid) chunk, depth d of a z
+  // face at face_off + (d npe + pid) chunk
+  Real* pslotp = kSync ? nullptr : pub + static_cast<int64_t>(pslot) * p.npe * p.pe_block;
+  const int64_t cxy = p.face_chunk[0];             // s * 32 (x and y faces)
+  const int64_t cz = p.face_chunk[4];              // 32 * 32 (z faces)
 
   // z queue (planes z-S .. z+S) and the rotating prefetch slots
   VR qz[2 * S + 1];
@@ -449,8 +462,9 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
       if (KIND == kAb2 || KIND == kAb3) stv<Real, V>(fout, g, fq);
       if (!kSync) {
         // publish the new edge values into the ring slot of their level;
-        // x faces: strip [z][y][d], one run of s values per row
-        const int64_t xrow = (static_cast<int64_t>(z) * kB + y) * S;
+        // x faces: plane [y][d], one run of s values per row
+        const int64_t xyplane = (static_cast<int64_t>(z) * p.npe + pid) * cxy;
+        const int64_t xrow = xyplane + static_cast<int64_t>(y) * S;
         if constexpr (V == 4) {
           // the first quad of a row holds the low-face depths, the last one
           // the high-face depths: one store of s values for both faces
@@ -462,24 +476,28 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
             // (select between the two uniform offsets: an index that varies
             // per lane would turn the kernel-argument read into a memory load)
             const int64_t fo = hi ? p.face_off[1] : p.face_off[0];
-            st_run<Real, S>(pstrip + fo + xrow, w);
+            st_run<Real, S>(pslotp + fo + xrow, w);
           }
         } else {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            if (x + e < S) pstrip[p.face_off[0] + xrow + x + e] = un.v[e];
-            if (x + e >= kB - S) pstrip[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
+            if (x + e < S) pslotp[p.face_off[0] + xrow + x + e] = un.v[e];
+            if (x + e >= kB - S) pslotp[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
           }
         }
-        // y faces: strip [z][d][x]; rows 0..s-1 and kB-s..kB-1, one store
+        // y faces: plane [d][x]; rows 0..s-1 and kB-s..kB-1, one store
         if (y < S || y >= kB - S) {
           const int64_t fo = y < S ? p.face_off[2] : p.face_off[3];
           const int d = y < S ? y : y - (kB - S);
-          stv<Real, V>(pstrip + fo, static_cast<uint32_t>((z * S + d) * kB + x), un);
+          stv<Real, V>(pslotp + fo + xyplane, static_cast<uint32_t>(d * kB + x), un);
         }
-        if (z < S) stv<Real, V>(pstrip + p.face_off[4], static_cast<uint32_t>((z * kB + y) * kB + x), un);
+        // z faces: depth plane [y][x]
+        if (z < S)
+          stv<Real, V>(pslotp + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * cz,
+                       static_cast<uint32_t>(y * kB + x), un);
         if (z >= bz - S)
-          stv<Real, V>(pstrip + p.face_off[5], static_cast<uint32_t>(((z - (bz - S)) * kB + y) * kB + x), un);
+          stv<Real, V>(pslotp + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * cz,
+                       static_cast<uint32_t>(y * kB + x), un);
       }
 #pragma unroll
       for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];
