@@ -156,8 +156,13 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
     off = align_up(off + bytes);
     return o;
   };
+  // Every delay mode except the synchronous arm reads neighbours only through
+  // the ring, and each sweep reads a point's own level-n values before it
+  // writes them: the solution is updated in place (one buffer; a smaller
+  // working set stays in the Infinity Cache). The synchronous arm reads the
+  // neighbours' level-n values directly and keeps two buffers.
   l.off_u[0] = take(l.field_bytes);
-  l.off_u[1] = take(l.field_bytes);
+  l.off_u[1] = d->mode == AT_SYNC ? take(l.field_bytes) : l.off_u[0];
   l.nfbuf = p->integrator == AT_AB2 ? 1 : p->integrator == AT_AB3 ? 2 : 0;
   for (int i = 0; i < l.nfbuf; ++i) l.off_f[i] = take(l.field_bytes);
   l.star = p->integrator == AT_RK2;

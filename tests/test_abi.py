@@ -73,14 +73,15 @@ def test_workspace_size_accounts_for_fields_and_rings():
     st, nb = _size(L, lib, p, d)
     assert st == L.AT_OK
     npts = 64 ** 3
-    # two solution buffers + one AB2 history at 8 bytes, plus L+T ring slots of
-    # 6 faces * s * 32^2 per PE for 8 PEs
+    # one solution buffer (updated in place) + one AB2 history at 8 bytes,
+    # plus L+T ring slots of 6 faces * s * 32^2 per PE for 8 PEs
     ring = (4 + 3) * 8 * 6 * 2 * 32 * 32 * 8
-    assert nb >= 3 * npts * 8 + ring
-    assert nb < 3 * npts * 8 + ring + 4 * 2 ** 20
+    assert nb >= 2 * npts * 8 + ring
+    assert nb < 2 * npts * 8 + ring + 4 * 2 ** 20
+    # the synchronous arm: two solution buffers, no ring
     d.mode = L.MODES["sync"]
     st, nb2 = _size(L, lib, p, d)
-    assert st == L.AT_OK and nb2 < nb - ring + 2 ** 20
+    assert st == L.AT_OK and 3 * npts * 8 <= nb2 < 3 * npts * 8 + 4 * 2 ** 20
 
 
 @pytest.mark.parametrize("kw,dkw", [
