@@ -138,8 +138,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "at_step3d_fast_256cube_traffic.md
 
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, per arm; None where the kernel sources changed since it was taken
-    or the workload differs."""
+    summary, per schedule variant and arm; empty where the kernel sources
+    changed since it was taken or the workload differs."""
     import hashlib
     if args.n != 256 or args.b != 32 or not os.path.exists(TRAFFIC_FILE):
         return {}
@@ -154,7 +154,7 @@ def measured_traffic():
     meta = json.loads(line[len("bench-traffic: "):])
     if meta.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
         return {}
-    return {arm: (r["traffic_bytes"], meta.get("variant")) for arm, r in meta["arms"].items()}
+    return {int(v): arms for v, arms in meta["variants"].items()}
 
 
 def cpu_baseline():
@@ -296,8 +296,7 @@ def time_adjoint():
 
 traffic = measured_traffic()
 for arm, r in arms.items():
-    t = traffic.get(arm)
-    r["traffic_bytes"] = t[0] if t and t[1] == r["depth"] else None
+    r["traffic_bytes"] = traffic.get(r["depth"], {}).get(arm)
 head_arm = "f32" if "f32" in arms else next(iter(arms))
 head = arms[head_arm]
 copy_gbs = copy_bandwidth()
