@@ -266,18 +266,32 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
   }
 }
 
+// Ring index of the strip value of face F at PE coordinates l (in that strip),
+// without the division of ring_index_q: x faces plane z, [y][d]; y faces plane
+// z, [d][x]; z faces plane d, [y][x].
+__device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int F, const int* l, int S) {
+  const int a = F >> 1;
+  const int b = edge_of(p, a);
+  const int d = (F & 1) ? l[a] - (b - S) : l[a];
+  if (a == 0) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(l[1]) * S + d);
+  if (a == 1) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(d) * p.bx + l[0]);
+  return ring_index(p, slot, pe, F, d, static_cast<int64_t>(l[1]) * p.bx + l[0]);
+}
+
 // The stage adjoint out = b0 x0 + b1 x1 + D mu + transposed taps + the adjoint
 // ring slot of level n (drained and cleared here), plus this stage's part of
-// dJ/dalpha.
-template <typename Real>
+// dJ/dalpha. Branch-free per point: every lane issues the same loads, a tap
+// that leaves the PE selects the address of its halo value (or of a value it
+// then multiplies by zero), so PE-edge points cost what interior points cost.
+template <typename Real, int DIM, int S>
 __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
   const StepParams& p = q.sp;
-  const int S = p.s;
   Real* out = static_cast<Real*>(q.out);
   const Real* x0 = static_cast<const Real*>(q.x0);
   const Real* x1 = static_cast<const Real*>(q.x1);
   const Real* C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
   const Real* M = static_cast<const Real*>(q.mu);
+  const Real* hb = static_cast<const Real*>(q.hbuf);
   Real* aring = static_cast<Real*>(q.aring);
   const int slot_n = static_cast<int>(q.n % q.anslots);
   const int64_t st[3] = {1, p.nx, static_cast<int64_t>(p.nx) * p.ny};
@@ -290,67 +304,44 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
     double acc = q.b0 * static_cast<double>(x0[g]);
     if (q.b1 != 0.0) acc += q.b1 * static_cast<double>(x1[g]);
     double lap = 0.0, grad = 0.0, sumk = 0.0;
-    bool inner = true;
-    for (int a = 0; a < p.ndim; ++a) inner = inner && j.l[a] >= S && j.l[a] < edge_of(p, a) - S;
-    if (inner) {
-      // every tap of j and every tap reaching j stays inside the PE: level n
-      // only, no wrap, no adjoint-ring entry
-      for (int a = 0; a < p.ndim; ++a) {
-        for (int o = -S; o <= S; ++o) {
-          if (o == 0) continue;
-          const double v = static_cast<double>(C[g + o * st[a]]) - cj;
-          lap += p.c2[a][o + S] * v;
-          grad += p.c1[a][o + S] * v;
-          sumk += tap_k(q, a, o, cj);
-          const int64_t gi = g - o * st[a];
-          acc += tap_k(q, a, o, q.burgers ? static_cast<double>(C[gi]) : 0.0) * static_cast<double>(M[gi]);
-        }
+    const Real* hpe = hb + static_cast<int64_t>(j.pe) * p.pe_block;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int b = edge_of(p, a);
+#pragma unroll
+      for (int o = -S; o <= S; ++o) {
+        if (o == 0) continue;
+        sumk += tap_k(q, a, o, cj);
+        // transposed interior tap: from i = j - o when i lies in the PE
+        const int ia = j.l[a] - o;
+        const bool tin = ia >= 0 && ia < b;
+        const int64_t gi = tin ? g - o * st[a] : g;
+        const double mi = static_cast<double>(M[gi]);
+        const double ci = q.burgers ? static_cast<double>(C[gi]) : 0.0;
+        acc += tin ? tap_k(q, a, o, ci) * mi : 0.0;
+        // forward stencil of the stage field at j: inside the PE from the
+        // field, across a face from the stage's combined halo values
+        const int ta = j.l[a] + o;
+        const bool fin = ta >= 0 && ta < b;
+        const int side = ta < 0 ? 0 : 1;
+        int ls[3] = {j.l[0], j.l[1], j.l[2]};
+        ls[a] = fin ? (side ? b - S : 0) : (side ? ta - b : ta + b);
+        const int f = 2 * a + side;
+        const Real* pv = fin ? C + (g + o * st[a]) : hpe + q.pfo[f] + strip_elem(p, f ^ 1, ls, S);
+        const double v = static_cast<double>(*pv) - cj;
+        lap += p.c2[a][o + S] * v;
+        grad += p.c1[a][o + S] * v;
       }
-    } else {
-      const int gc[3] = {j.x, j.y, j.z};
-      const int ext[3] = {p.nx, p.ny, p.nz};
-      const Real* hb = static_cast<const Real*>(q.hbuf);
-      for (int a = 0; a < p.ndim; ++a) {
-        const int b = edge_of(p, a);
-        for (int o = -S; o <= S; ++o) {
-          if (o == 0) continue;
-          sumk += tap_k(q, a, o, cj);
-          // transposed interior tap: from i = j - o (same PE) to j
-          const int ia = j.l[a] - o;
-          if (ia >= 0 && ia < b) {
-            int c[3] = {gc[0], gc[1], gc[2]};
-            c[a] = gc[a] - o;
-            const int64_t gi = gindex(p, c[0], c[1], c[2]);
-            acc += tap_k(q, a, o, q.burgers ? static_cast<double>(C[gi]) : 0.0) * static_cast<double>(M[gi]);
-          }
-          // forward stencil of the stage field at j (Laplacian and gradient)
-          const int ta = j.l[a] + o;
-          double v;
-          if (ta >= 0 && ta < b) {
-            int c[3] = {gc[0], gc[1], gc[2]};
-            c[a] = (gc[a] + o + ext[a]) % ext[a];
-            v = static_cast<double>(C[gindex(p, c[0], c[1], c[2])]);
-          } else {
-            // the forward halo value of this tap, combined once per stage
-            const int side = ta < 0 ? 0 : 1;
-            const int f = 2 * a + side;
-            int ls[3] = {j.l[0], j.l[1], j.l[2]};
-            ls[a] = side ? ta - b : ta + b;
-            v = static_cast<double>(hb[static_cast<int64_t>(j.pe) * p.pe_block + pe_face_off(p, f) +
-                                       strip_elem(p, f ^ 1, ls, S)]);
-          }
-          lap += p.c2[a][o + S] * (v - cj);
-          grad += p.c1[a][o + S] * (v - cj);
-        }
-        // adjoint-ring contributions of the strips j belongs to on this axis
-        for (int side = 0; side < 2; ++side) {
-          const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
-          if (!in) continue;
-          const int F = 2 * a + side;
-          Real* src = aring + ring_at(p, slot_n, j.pe, F, strip_elem(p, F, j.l, S));
-          acc += static_cast<double>(*src);
-          *src = Real(0);
-        }
+      // adjoint-ring contributions of the strips j belongs to on this axis
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
+        int ls[3] = {j.l[0], j.l[1], j.l[2]};
+        if (!in) ls[a] = side ? b - S : 0;
+        Real* src = aring + ring_at_pt(p, slot_n, j.pe, 2 * a + side, ls, S);
+        const double r = static_cast<double>(*src);
+        acc += in ? r : 0.0;
+        if (in) *src = Real(0);
       }
     }
     // D_j mu_j with D_j = -sum K (- G_j for Burgers)
@@ -368,6 +359,23 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
     for (int w = 0; w < kAdjThreads / 64; ++w) s += part[w];
     q.partial[blockIdx.x] += s;
   }
+}
+
+template <typename Real>
+hipError_t launch_lambda(const AdjParams& q, int blocks, hipStream_t st) {
+  const int key = q.sp.ndim * 10 + q.sp.s;
+  switch (key) {
+#define ATFD_ADJ_CASE(D, S)                                                                         \
+  case D * 10 + S:                                                                                   \
+    hipLaunchKernelGGL((adj_lambda_kernel<Real, D, S>), dim3(blocks), dim3(kAdjThreads), 0, st, q); \
+    break;
+    ATFD_ADJ_CASE(1, 1) ATFD_ADJ_CASE(1, 2) ATFD_ADJ_CASE(1, 3)
+    ATFD_ADJ_CASE(2, 1) ATFD_ADJ_CASE(2, 2) ATFD_ADJ_CASE(2, 3)
+    ATFD_ADJ_CASE(3, 1) ATFD_ADJ_CASE(3, 2) ATFD_ADJ_CASE(3, 3)
+#undef ATFD_ADJ_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 __global__ void adj_sum_kernel(const double* partial, int count, double* out) {
@@ -394,12 +402,14 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
     hipLaunchKernelGGL(adj_mu_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_halo_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipLaunchKernelGGL(adj_lambda_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+    hipError_t e = launch_lambda<double>(q, lblocks, st);
+    if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(adj_mu_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_halo_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipLaunchKernelGGL(adj_lambda_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
+    hipError_t e = launch_lambda<float>(q, lblocks, st);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -27,6 +27,7 @@ struct AdjParams {
   int64_t seg_start;
   const void* ring0;               // that field's ring at step seg_start
   void* hbuf;                      // forward halo values of this stage [pe][face strips]
+  int64_t pfo[6];                  // offset of face f's strip inside one PE's pe_block values
   void* aring;                     // adjoint ring of the stage field, anslots slots
   int anslots;
   double* partial;                 // [kAdjBlocks] alpha-gradient partial sums

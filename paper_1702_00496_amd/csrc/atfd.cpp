@@ -754,6 +754,7 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       q.anslots = a.anslots;
       q.seg_start = seg;
       q.partial = reinterpret_cast<double*>(sc + a.off_partial);
+      for (int f = 0; f < 6; ++f) q.pfo[f] = c->lay.face_off[f] / c->g.npe;
       if (a.rk2) {
         // stage 2: sigma = dJ/du*^n from mu = dt/2 lambda^{n+1}
         AdjParams q2 = q;
