@@ -13,7 +13,8 @@ constexpr int kMaxL = 8;
 constexpr int kMaxT = 4;
 constexpr int kMaxS = 3;
 constexpr int kMaxModes = 16;
-constexpr int kThreads = 256;          // workgroup size of the sweep kernels
+constexpr int kThreads = 256;          // workgroup size of the helper kernels
+constexpr int kMaxSweepThreads = 1024; // largest workgroup of the generic sweep
 constexpr size_t kLdsLimit = 160 * 1024;
 
 // ---------------------------------------------------------------- generator

@@ -271,7 +271,7 @@ __device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n)
 }
 
 template <typename Real, int DIM, int S>
-__global__ __launch_bounds__(kThreads) void at_step_kernel(StepParams p) {
+__global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
   __shared__ double s_w[6 * kMaxT];
@@ -380,10 +380,21 @@ size_t lds_bytes_t(const StepParams& p) {
   return nsl * plane * sizeof(Real);
 }
 
+// Workgroup size of the generic sweep: about four points of a plane per
+// thread (a 64 x 64 PE plane gets 1024 threads, a 32 x 32 one 256), so that
+// large 2-D PEs, one workgroup each, still fill a compute unit with waves.
+int sweep_threads(const StepParams& p) {
+  const int64_t pts = static_cast<int64_t>(p.bx) * (p.ndim >= 2 ? p.by : 1);
+  int64_t t = (pts / 4 + 63) / 64 * 64;
+  if (t < 64) t = 64;
+  if (t > kMaxSweepThreads) t = kMaxSweepThreads;
+  return static_cast<int>(t);
+}
+
 template <typename Real, int DIM, int S>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
   const size_t lds = lds_bytes_t<Real, DIM, S>(p);
-  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S>), dim3(p.npe), dim3(kThreads), lds, st, p);
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S>), dim3(p.npe), dim3(sweep_threads(p)), lds, st, p);
   return hipGetLastError();
 }
 
