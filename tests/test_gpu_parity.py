@@ -21,7 +21,8 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
 def _dt(case, r_alpha):
-    dx = 2 * math.pi / min(v for v in case["n"][: case["ndim"]])
+    # diffusive CFL on the finest axis
+    dx = 2 * math.pi / max(v for v in case["n"][: case["ndim"]])
     return r_alpha * dx * dx / case.get("alpha", 0.1)
 
 
@@ -48,6 +49,16 @@ CASES = {
     "3d_fast_o4_ab2_bz16": dict(ndim=3, n=(64, 64, 48), pe=(2, 2, 3), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), L=4, steps=12, ra=0.02),
     "3d_fast_o4_ab2_sync": dict(ndim=3, n=(64, 64, 32), pe=(2, 2, 1), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), mode="sync", steps=12, ra=0.02),
     "3d_o2_euler_sync": dict(ndim=3, n=(32, 32, 32), pe=(2, 2, 2), order=2, integrator="euler", c=(1.0, 0.5, 0.25), mode="sync", steps=20, ra=0.05),
+    # degenerate and extreme cases: the smallest PE edge b = 2s on every axis,
+    # L = 1 (every delay 0), one PE per axis (a PE is its own neighbour), the
+    # largest L and T, the 32 x 32 path with the thinnest PE (bz = 2s)
+    "1d_o4_min_edge": dict(ndim=1, n=(16,), pe=(4,), order=4, integrator="ab2", c=(1.0,), L=3, steps=30, ra=0.02),
+    "2d_o6_min_edge": dict(ndim=2, n=(18, 12), pe=(3, 2), order=6, integrator="euler", c=(1.0, -1.0), L=2, steps=20, ra=0.005),
+    "3d_o2_min_edge": dict(ndim=3, n=(8, 6, 4), pe=(4, 3, 2), order=2, integrator="euler", c=(0.5, 1.0, -1.0), L=3, steps=20, ra=0.05),
+    "1d_o2_L1": dict(ndim=1, n=(64,), pe=(4,), order=2, integrator="euler", c=(1.0,), L=1, steps=50, ra=0.1),
+    "2d_o4_one_pe_per_axis": dict(ndim=2, n=(24, 20), pe=(1, 1), order=4, integrator="ab2", c=(1.0, 0.5), L=4, steps=30, ra=0.02),
+    "1d_o6_L8_T4_rk2": dict(ndim=1, n=(96,), pe=(4,), order=6, integrator="rk2", c=(1.0,), L=8, steps=60, ra=0.002),
+    "3d_fast_o4_ab2_bz4": dict(ndim=3, n=(64, 64, 8), pe=(2, 2, 2), order=4, integrator="ab2", c=(1.0, -0.5, 0.5), L=4, steps=12, ra=0.02),
 }
 
 
@@ -106,6 +117,23 @@ def test_zero_delays_equal_synchronous_bitwise(name, precision):
         s.step(case["steps"])
         out[mode] = s.state()
     assert torch.equal(out["zero"], out["sync"])
+
+
+def test_zero_steps_and_repeated_state_are_no_ops():
+    case = _case("1d_o4_ab2_ragged")
+    u0 = torch.from_numpy(initial_field(case))
+    s = solver_for(case, "f64")
+    s.set_state(u0)
+    s.step(0)
+    assert s.n_step == 0
+    assert torch.equal(s.state().cpu(), u0.reshape(s.shape))
+    s.step(7)
+    a = s.state()
+    s.set_state(u0)                       # back to step 0: the same 7 steps again
+    s.step(3)
+    s.step(0)
+    s.step(4)
+    assert torch.equal(s.state(), a)
 
 
 def test_host_delay_table():
