@@ -73,13 +73,58 @@ __device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, i
   return (static_cast<int64_t>(d) * p.by + l[1]) * p.bx + l[0];
 }
 
-// Offset of face F's strip inside one PE's pe_block values (the order used by
-// the per-PE thread numbering and the halo buffer; the ring itself stores the
-// faces of all PEs plane by plane).
-__device__ inline int64_t pe_face_off(const StepParams& p, int F) { return p.face_off[F] / p.npe; }
+// Ring index of the strip value of face F at PE coordinates l (in that strip):
+// x faces plane z, [y][d]; y faces plane z, [d][x]; z faces plane d, [y][x].
+__device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int F, const int* l, int S) {
+  const int a = F >> 1;
+  const int b = edge_of(p, a);
+  const int d = (F & 1) ? l[a] - (b - S) : l[a];
+  if (a == 0) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(l[1]) * S + d);
+  if (a == 1) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(d) * p.bx + l[0]);
+  return ring_index(p, slot, pe, F, d, static_cast<int64_t>(l[1]) * p.bx + l[0]);
+}
 
-__device__ inline int64_t ring_at(const StepParams& p, int slot, int pe, int F, int64_t e) {
-  return ring_index_q(p, slot, pe, F, e);
+// Strip value t of the per-PE numbering used by the scatter and halo kernels
+// and the halo buffer: PE pe, face F (its strip starts at pfo[F] inside the
+// PE's pe_block values), depth d from the strip's low side and the other PE
+// coordinates in l (l[F >> 1] = 0). 32-bit: the host keeps npe * pe_block
+// below 2^31.
+struct StripPt {
+  int pe, F, d;
+  int l[3];
+};
+
+__device__ inline StripPt strip_point(const AdjParams& q, int t) {
+  const StepParams& p = q.sp;
+  const int S = p.s, blk = static_cast<int>(p.pe_block);
+  StripPt s;
+  s.pe = t / blk;
+  const int r = t - s.pe * blk;
+  int F = 0, off = 0;
+#pragma unroll
+  for (int f = 1; f < 6; ++f) {
+    const bool past = f < 2 * p.ndim && r >= static_cast<int>(q.pfo[f]);
+    F += past ? 1 : 0;
+    off = past ? static_cast<int>(q.pfo[f]) : off;
+  }
+  s.F = F;
+  const int e = r - off;
+  const int a = F >> 1;
+  s.l[0] = s.l[1] = s.l[2] = 0;
+  if (a == 0) {
+    s.d = e % S;
+    s.l[1] = (e / S) % p.by;
+    s.l[2] = e / (p.by * S);
+  } else if (a == 1) {
+    s.l[0] = e % p.bx;
+    s.d = (e / p.bx) % S;
+    s.l[2] = e / (p.bx * S);
+  } else {
+    s.l[0] = e % p.bx;
+    s.l[1] = (e / p.bx) % p.by;
+    s.d = e / (p.bx * p.by);
+  }
+  return s;
 }
 
 __device__ inline int nbr_pe(const StepParams& p, int pid, int f) {
@@ -105,9 +150,14 @@ __device__ inline int adj_delay(const StepParams& p, int pid, int f, int64_t n) 
 
 __device__ inline int adj_levels(const StepParams& p) { return p.mode == AT_SYNC ? 1 : p.T; }
 
+// mu = dJ/dF of this stage at point g: m0 y0 + m1 y1, formed where it is
+// used. Without a second field (m1 = 0) y1 falls back to y0, so both loads
+// are unconditional and the m1 term is an exact zero for finite y0.
 template <typename Real>
 __device__ inline double mu_at(const AdjParams& q, int64_t g) {
-  return static_cast<double>(static_cast<const Real*>(q.mu)[g]);
+  const Real* y0 = static_cast<const Real*>(q.y0);
+  const Real* y1 = static_cast<const Real*>(q.m1 != 0.0 ? q.y1 : q.y0);
+  return q.m0 * static_cast<double>(y0[g]) + q.m1 * static_cast<double>(y1[g]);
 }
 
 template <typename Real>
@@ -122,20 +172,6 @@ __device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
   return p.kad[a][o + p.s];
 }
 
-// mu = m0 y0 + m1 y1 (dJ/dF of this stage), stored once per stage for both
-// sweeps to gather.
-template <typename Real>
-__global__ __launch_bounds__(kAdjThreads) void adj_mu_kernel(AdjParams q) {
-  const Real* y0 = static_cast<const Real*>(q.y0);
-  const Real* y1 = static_cast<const Real*>(q.y1);
-  Real* mu = static_cast<Real*>(q.mu);
-  for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
-       g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double b = q.m1 != 0.0 ? q.m1 * static_cast<double>(y1[g]) : 0.0;
-    mu[g] = static_cast<Real>(q.m0 * static_cast<double>(y0[g]) + b);
-  }
-}
-
 // Scatter of step n (gather form): every strip value e of face F of PE q
 // collects the transposed taps of the consumer PE across F, weighted by the
 // consumer's level weights, into the adjoint ring slots of levels n-k-m.
@@ -143,32 +179,12 @@ template <typename Real>
 __global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
   const StepParams& p = q.sp;
   const int S = p.s;
-  const int64_t total = static_cast<int64_t>(p.npe) * p.pe_block;
+  const int total = p.npe * static_cast<int>(p.pe_block);
   Real* aring = static_cast<Real*>(q.aring);
-  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
-       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int pe = static_cast<int>(t / p.pe_block);
-    const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
-    int F = 0;
-    while (F + 1 < 2 * p.ndim && r >= pe_face_off(p, F + 1)) ++F;
-    const int64_t e = r - pe_face_off(p, F);
-    const int a = F >> 1;
-    // decode the PE coordinates of strip element e
-    int l[3] = {0, 0, 0};
-    int d;
-    if (a == 0) {
-      d = static_cast<int>(e % S);
-      l[1] = static_cast<int>((e / S) % p.by);
-      l[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
-    } else if (a == 1) {
-      l[0] = static_cast<int>(e % p.bx);
-      d = static_cast<int>((e / p.bx) % S);
-      l[2] = static_cast<int>(e / (static_cast<int64_t>(p.bx) * S));
-    } else {
-      l[0] = static_cast<int>(e % p.bx);
-      l[1] = static_cast<int>((e / p.bx) % p.by);
-      d = static_cast<int>(e / (static_cast<int64_t>(p.bx) * p.by));
-    }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const StripPt sp = strip_point(q, t);
+    const int pe = sp.pe, F = sp.F, d = sp.d, a = F >> 1;
+    const int* l = sp.l;
     const int b = edge_of(p, a);
     // the consumer across F reads this strip through its opposite face
     const int cons = nbr_pe(p, pe, F);
@@ -177,25 +193,40 @@ __global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
     const int jp = (F & 1) ? d - S : b + d;
     const int cq[3] = {cons % p.px, (cons / p.px) % p.py, cons / (p.px * p.py)};
     const int org[3] = {cq[0] * p.bx, cq[1] * p.by, cq[2] * p.bz};
+    // taps from consumer points outside the consumer PE are dropped by a
+    // select after unconditional loads from a clamped (in-PE) point, so that
+    // every load of the element is in flight together
     double g = 0.0;
     for (int o = -S; o <= S; ++o) {
       if (o == 0) continue;
       const int ia = jp - o;
-      if (ia < 0 || ia >= b) continue;
+      const bool valid = ia >= 0 && ia < b;
       int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
-      c[a] = org[a] + ia;
+      c[a] = org[a] + min(max(ia, 0), b - 1);
       const int64_t gi = gindex(p, c[0], c[1], c[2]);
-      g += tap_k(q, a, o, q.burgers ? centre_at<Real>(q, gi) : 0.0) * mu_at<Real>(q, gi);
+      const double t = tap_k(q, a, o, centre_at<Real>(q, gi)) * mu_at<Real>(q, gi);
+      g += valid ? t : 0.0;
     }
     const int k = adj_delay(p, cons, cf, q.n);
     double w[kMaxT];
     const int T = adj_levels(p);
     level_weights(k, T, w);
-    for (int m = 0; m < T; ++m) {
-      if (w[m] == 0.0) continue;
-      const int slot = static_cast<int>((q.n - k - m) % q.anslots);
-      Real* dst = aring + ring_at(p, slot, pe, F, e);
-      *dst = static_cast<Real>(static_cast<double>(*dst) + w[m] * g);
+    int lsF[3] = {l[0], l[1], l[2]};   // the strip value's PE coordinates
+    lsF[a] = (F & 1) ? b - S + d : d;
+    Real* dst[kMaxT];
+    double old[kMaxT];
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) {
+      if (m >= T) break;
+      const int64_t l = q.n - k - m;   // negative only where w[m] = 0
+      const int slot = static_cast<int>((l < 0 ? 0 : l) % q.anslots);
+      dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
+      old[m] = static_cast<double>(*dst[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) {
+      if (m >= T) break;
+      if (w[m] != 0.0) *dst[m] = static_cast<Real>(old[m] + w[m] * g);
     }
   }
 }
@@ -208,13 +239,14 @@ template <typename Real>
 __device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y, int z, int src, int pf,
                                      const int* ls) {
   const StepParams& p = q.sp;
-  if (l >= q.seg_start) {
-    const Real* U = static_cast<const Real*>(q.levels) + (l - q.seg_start) * q.npts;
-    return static_cast<double>(U[gindex(p, x, y, z)]);
-  }
+  // both candidates are loaded (from in-range addresses) and one is selected
+  const bool stored = l >= q.seg_start;
+  const Real* U = static_cast<const Real*>(q.levels) + (stored ? l - q.seg_start : 0) * q.npts;
+  const double a = static_cast<double>(U[gindex(p, x, y, z)]);
   const Real* R0 = static_cast<const Real*>(q.ring0);
-  const int slot = static_cast<int>(l % p.nslots);
-  return static_cast<double>(R0[ring_at(p, slot, src, pf, strip_elem(p, pf, ls, p.s))]);
+  const int slot = static_cast<int>((l < 0 ? 0 : l) % p.nslots);
+  const double b = static_cast<double>(R0[ring_at_pt(p, slot, src, pf, ls, p.s)]);
+  return stored ? a : b;
 }
 
 // The forward halo values of step n, for the alpha-derivative: for every
@@ -226,31 +258,12 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
   const StepParams& p = q.sp;
   const int S = p.s;
   const int T = adj_levels(p);
-  const int64_t total = static_cast<int64_t>(p.npe) * p.pe_block;
+  const int total = p.npe * static_cast<int>(p.pe_block);
   Real* hb = static_cast<Real*>(q.hbuf);
-  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
-       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int pe = static_cast<int>(t / p.pe_block);
-    const int64_t r = t - static_cast<int64_t>(pe) * p.pe_block;
-    int f = 0;
-    while (f + 1 < 2 * p.ndim && r >= pe_face_off(p, f + 1)) ++f;
-    const int64_t e = r - pe_face_off(p, f);
-    const int a = f >> 1, pf = f ^ 1;
-    int ls[3] = {0, 0, 0};
-    int d;
-    if (a == 0) {
-      d = static_cast<int>(e % S);
-      ls[1] = static_cast<int>((e / S) % p.by);
-      ls[2] = static_cast<int>(e / (static_cast<int64_t>(p.by) * S));
-    } else if (a == 1) {
-      ls[0] = static_cast<int>(e % p.bx);
-      d = static_cast<int>((e / p.bx) % S);
-      ls[2] = static_cast<int>(e / (static_cast<int64_t>(p.bx) * S));
-    } else {
-      ls[0] = static_cast<int>(e % p.bx);
-      ls[1] = static_cast<int>((e / p.bx) % p.by);
-      d = static_cast<int>(e / (static_cast<int64_t>(p.bx) * p.by));
-    }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const StripPt sp = strip_point(q, t);
+    const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
+    int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
     const int b = edge_of(p, a);
     ls[a] = (pf & 1) ? b - S + d : d;
     const int src = nbr_pe(p, pe, f);
@@ -259,23 +272,22 @@ __global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
     const int k = adj_delay(p, pe, f, q.n);
     double w[kMaxT];
     level_weights(k, T, w);
+    if (p.mode == AT_SYNC) {   // level n, always stored
+      hb[t] = static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
+      continue;
+    }
+    // all kMaxT levels are loaded unconditionally (a level m >= T repeats
+    // level T - 1 and is dropped below), so the loads overlap
+    double lv[kMaxT];
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m)
+      lv[m] = level_value<Real>(q, q.n - k - min(m, T - 1), gx, gy, gz, src, pf, ls);
     double v = 0.0;
-    for (int m = 0; m < T; ++m)
-      if (w[m] != 0.0) v += w[m] * level_value<Real>(q, q.n - k - m, gx, gy, gz, src, pf, ls);
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m)
+      if (m < T && w[m] != 0.0) v += w[m] * lv[m];
     hb[t] = static_cast<Real>(v);
   }
-}
-
-// Ring index of the strip value of face F at PE coordinates l (in that strip),
-// without the division of ring_index_q: x faces plane z, [y][d]; y faces plane
-// z, [d][x]; z faces plane d, [y][x].
-__device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int F, const int* l, int S) {
-  const int a = F >> 1;
-  const int b = edge_of(p, a);
-  const int d = (F & 1) ? l[a] - (b - S) : l[a];
-  if (a == 0) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(l[1]) * S + d);
-  if (a == 1) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(d) * p.bx + l[0]);
-  return ring_index(p, slot, pe, F, d, static_cast<int64_t>(l[1]) * p.bx + l[0]);
 }
 
 // The stage adjoint out = b0 x0 + b1 x1 + D mu + transposed taps + the adjoint
@@ -286,25 +298,29 @@ __device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int 
 template <typename Real, int DIM, int S>
 __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
   const StepParams& p = q.sp;
-  Real* out = static_cast<Real*>(q.out);
-  const Real* x0 = static_cast<const Real*>(q.x0);
-  const Real* x1 = static_cast<const Real*>(q.x1);
-  const Real* C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
-  const Real* M = static_cast<const Real*>(q.mu);
-  const Real* hb = static_cast<const Real*>(q.hbuf);
-  Real* aring = static_cast<Real*>(q.aring);
+  Real* __restrict__ out = static_cast<Real*>(q.out);
+  const Real* __restrict__ x0 = static_cast<const Real*>(q.x0);
+  // with b1 = 0, x1 falls back to x0 (an exact zero term for finite x0)
+  const Real* __restrict__ x1 = static_cast<const Real*>(q.b1 != 0.0 ? q.x1 : q.x0);
+  const Real* __restrict__ C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
+  const Real* __restrict__ hb = static_cast<const Real*>(q.hbuf);
+  Real* __restrict__ aring = static_cast<Real*>(q.aring);
   const int slot_n = static_cast<int>(q.n % q.anslots);
   const int64_t st[3] = {1, p.nx, static_cast<int64_t>(p.nx) * p.ny};
   double da = 0.0;
   for (int64_t g = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; g < q.npts;
        g += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const Pt j = point_of(p, g);
-    const double mu = static_cast<double>(M[g]);
+    const double mu = mu_at<Real>(q, g);
     const double cj = static_cast<double>(C[g]);
-    double acc = q.b0 * static_cast<double>(x0[g]);
-    if (q.b1 != 0.0) acc += q.b1 * static_cast<double>(x1[g]);
+    const double v1 = static_cast<double>(x1[g]);
+    double acc = q.b0 * static_cast<double>(x0[g]) + q.b1 * v1;
     double lap = 0.0, grad = 0.0, sumk = 0.0;
     const Real* hpe = hb + static_cast<int64_t>(j.pe) * p.pe_block;
+    // adjoint-ring entries of the strips j belongs to: every load of the
+    // point is issued before the entries are cleared at the end
+    Real* rsrc[2 * DIM];
+    bool rin[2 * DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const int b = edge_of(p, a);
@@ -316,8 +332,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
         const int ia = j.l[a] - o;
         const bool tin = ia >= 0 && ia < b;
         const int64_t gi = tin ? g - o * st[a] : g;
-        const double mi = static_cast<double>(M[gi]);
-        const double ci = q.burgers ? static_cast<double>(C[gi]) : 0.0;
+        const double mi = mu_at<Real>(q, gi);
+        const double ci = static_cast<double>(C[gi]);   // used by the Burgers taps only
         acc += tin ? tap_k(q, a, o, ci) * mi : 0.0;
         // forward stencil of the stage field at j: inside the PE from the
         // field, across a face from the stage's combined halo values
@@ -327,12 +343,12 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
         int ls[3] = {j.l[0], j.l[1], j.l[2]};
         ls[a] = fin ? (side ? b - S : 0) : (side ? ta - b : ta + b);
         const int f = 2 * a + side;
-        const Real* pv = fin ? C + (g + o * st[a]) : hpe + q.pfo[f] + strip_elem(p, f ^ 1, ls, S);
+        const int64_t pfo = side ? q.pfo[2 * a + 1] : q.pfo[2 * a];   // uniform values, no indexed load
+        const Real* pv = fin ? C + (g + o * st[a]) : hpe + pfo + strip_elem(p, f ^ 1, ls, S);
         const double v = static_cast<double>(*pv) - cj;
         lap += p.c2[a][o + S] * v;
         grad += p.c1[a][o + S] * v;
       }
-      // adjoint-ring contributions of the strips j belongs to on this axis
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const bool in = side ? j.l[a] >= b - S : j.l[a] < S;
@@ -341,9 +357,13 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
         Real* src = aring + ring_at_pt(p, slot_n, j.pe, 2 * a + side, ls, S);
         const double r = static_cast<double>(*src);
         acc += in ? r : 0.0;
-        if (in) *src = Real(0);
+        rsrc[2 * a + side] = src;
+        rin[2 * a + side] = in;
       }
     }
+#pragma unroll
+    for (int f = 0; f < 2 * DIM; ++f)
+      if (rin[f]) *rsrc[f] = Real(0);
     // D_j mu_j with D_j = -sum K (- G_j for Burgers)
     acc += (-sumk - (q.burgers ? grad : 0.0)) * mu;
     out[g] = static_cast<Real>(acc);
@@ -399,13 +419,11 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
   const int lblocks = adj_blocks(q.npts);
   if (f64) {
-    hipLaunchKernelGGL(adj_mu_kernel<double>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_halo_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = launch_lambda<double>(q, lblocks, st);
     if (e != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(adj_mu_kernel<float>, dim3(lblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_halo_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipLaunchKernelGGL(adj_scatter_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = launch_lambda<float>(q, lblocks, st);

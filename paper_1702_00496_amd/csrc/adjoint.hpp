@@ -18,7 +18,6 @@ struct AdjParams {
   const void* y0;
   const void* y1;
   double m0, m1;
-  void* mu;                        // dJ/dF of this stage (written by the first kernel)
   const void* x0;
   const void* x1;
   double b0, b1;

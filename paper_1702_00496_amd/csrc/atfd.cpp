@@ -620,10 +620,10 @@ namespace {
 // Scratch layout of at_adjoint: nck + 1 checkpoints; the levels of one
 // segment (contiguous fields: u^seg .. u^{seg+every}, and for RK2 the
 // predictors u*^seg .. u*^{seg+every-1}); the adjoint fields (lambda x3,
-// sigma, mu); the forward halo buffer; the adjoint ring (two for RK2); the
+// sigma); the forward halo buffer; the adjoint ring (two for RK2); the
 // forward rings at the segment start; alpha partial sums.
 struct AdjLayout {
-  size_t ck = 0, off_levels = 0, off_slevels = 0, off_lam[3] = {0, 0, 0}, off_sigma = 0, off_mu = 0;
+  size_t ck = 0, off_levels = 0, off_slevels = 0, off_lam[3] = {0, 0, 0}, off_sigma = 0;
   size_t off_hbuf = 0, off_aring = 0, off_bring = 0, off_ring0 = 0, off_sring0 = 0;
   size_t off_partial = 0, off_out = 0, total = 0, aring_bytes = 0;
   int64_t nck = 0;
@@ -650,7 +650,6 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   if (a.rk2) a.off_slevels = take(l.field_bytes * static_cast<size_t>(every));
   for (int i = 0; i < 3; ++i) a.off_lam[i] = take(l.field_bytes);
   if (a.rk2) a.off_sigma = take(l.field_bytes);
-  a.off_mu = take(l.field_bytes);
   a.off_hbuf = take(static_cast<size_t>(c->g.npe) * l.pe_block * w);
   a.anslots = c->delay.mode == AT_SYNC ? 1 : l.nslots;
   a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * w;
@@ -670,7 +669,8 @@ at_status adj_check(at_ctx* c, int64_t nsteps, int32_t every) {
   if (c->prob.integrator == AT_AB3) return fail(c, AT_EINVAL, "the adjoint covers Euler, AB2 and RK2");
   if (c->delay.mode == AT_DELAY_HOST && nsteps > c->delay.host_nsteps)
     return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
-  if (c->g.npts >= (int64_t(1) << 31)) return fail(c, AT_EINVAL, "the adjoint covers fields below 2^31 points");
+  if (c->g.npts >= (int64_t(1) << 31) || c->g.npe * c->lay.pe_block >= (int64_t(1) << 31))
+    return fail(c, AT_EINVAL, "the adjoint covers fields and strip sets below 2^31 values");
   return AT_OK;
 }
 
@@ -749,7 +749,6 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       q.n = n;
       q.npts = c->g.npts;
       q.burgers = c->prob.equation == AT_BURGERS;
-      q.mu = sc + a.off_mu;
       q.hbuf = sc + a.off_hbuf;
       q.anslots = a.anslots;
       q.seg_start = seg;

@@ -265,26 +265,68 @@ __global__ __launch_bounds__(256) void ens_publish_all_kernel(EnsParams p) {
   }
 }
 
+// One workgroup per member. The exact solution at point i = 1024 q + j is
+// sum_m Im(lo_m[j] hi_m[q]) with lo_m[j] = exp(i kappa_m dx j) and
+// hi_m[q] = A_m e^{-alpha kappa_m^2 t} exp(i (kappa_m dx 1024 q + phi_m -
+// kappa_m c t)), both tabulated in LDS, so a point costs two multiply-adds per
+// mode instead of a sine.
+constexpr int kEnsNormThreads = 1024;
+constexpr int kEnsNormTable = 60 * 1024;   // LDS bytes for the two tables
+
 template <typename Real>
-__global__ __launch_bounds__(256) void ens_norms_kernel(EnsNormParams p) {
+__global__ __launch_bounds__(kEnsNormThreads) void ens_norms_kernel(EnsNormParams p) {
+  extern __shared__ double2 etab[];   // lo[m][1024], then hi[m][nq]
+  __shared__ double dec[kMaxModes], sh[kMaxModes];
   const EnsMember& M = p.mem[blockIdx.x];
-  const Real* u = static_cast<const Real*>(p.u);
+  const Real* u = static_cast<const Real*>(p.u) + M.off;
   const double t = static_cast<double>(p.nstep) * M.dt;
   const double dx = M.length / static_cast<double>(M.n);
-  double decay[kMaxModes];
-  for (int m = 0; m < p.nmodes; ++m) decay[m] = p.amp[m] * exp(-M.alpha * double(p.kap[m]) * p.kap[m] * t);
-  const double* ph = p.phase + static_cast<int64_t>(blockIdx.x) * p.nmodes;
+  const int nm = p.nmodes;
+  const double* ph = p.phase + static_cast<int64_t>(blockIdx.x) * nm;
+  if (static_cast<int>(threadIdx.x) < nm) {
+    const int m = threadIdx.x;
+    dec[m] = p.amp[m] * exp(-M.alpha * double(p.kap[m]) * p.kap[m] * t);
+    sh[m] = ph[m] - double(p.kap[m]) * M.c * t;
+  }
+  __syncthreads();
+  const int n = static_cast<int>(M.n);   // members are validated below 2^31 points
+  const int nq = (n + kEnsNormThreads - 1) / kEnsNormThreads;
+  const bool table = nm > 0 && static_cast<size_t>(nm) * (kEnsNormThreads + nq) * sizeof(double2) <=
+                                   static_cast<size_t>(kEnsNormTable);
+  double2* lo = etab;
+  double2* hi = etab + nm * kEnsNormThreads;
+  if (table) {
+    for (int i = threadIdx.x; i < nm * (kEnsNormThreads + nq); i += blockDim.x) {
+      double arg, scale = 1.0;
+      if (i < nm * kEnsNormThreads) {
+        arg = double(p.kap[i / kEnsNormThreads]) * dx * (i % kEnsNormThreads);
+      } else {
+        const int r = i - nm * kEnsNormThreads, m = r / nq, q = r % nq;
+        arg = double(p.kap[m]) * dx * (static_cast<double>(q) * kEnsNormThreads) + sh[m];
+        scale = dec[m];
+      }
+      double sv, cv;
+      sincos(arg, &sv, &cv);
+      etab[i] = make_double2(scale * cv, scale * sv);
+    }
+    __syncthreads();
+  }
   double s1 = 0.0, s2 = 0.0, mx = 0.0, bad = 0.0;
-  for (int64_t i = threadIdx.x; i < M.n; i += blockDim.x) {
-    double ref;
-    if (p.nmodes > 0) {
-      ref = 0.0;
-      const double x = static_cast<double>(i) * dx;
-      for (int m = 0; m < p.nmodes; ++m) ref += decay[m] * sin(double(p.kap[m]) * (x - M.c * t) + ph[m]);
+  for (int q = 0; q < nq; ++q) {
+    const int j = threadIdx.x, i = q * kEnsNormThreads + j;
+    if (i >= n) break;
+    double ref = 0.0;
+    if (table) {
+      for (int m = 0; m < nm; ++m) {
+        const double2 a = lo[m * kEnsNormThreads + j], b = hi[m * nq + q];
+        ref += a.y * b.x + a.x * b.y;
+      }
+    } else if (nm > 0) {
+      for (int m = 0; m < nm; ++m) ref += dec[m] * sin(double(p.kap[m]) * dx * i + sh[m]);
     } else {
       ref = p.ref[M.off + i];
     }
-    const double e = static_cast<double>(u[M.off + i]) - ref;
+    const double e = static_cast<double>(u[i]) - ref;
     if (!isfinite(e)) {
       bad += 1.0;
       continue;
@@ -300,7 +342,7 @@ __global__ __launch_bounds__(256) void ens_norms_kernel(EnsNormParams p) {
     mx = fmax(mx, __shfl_down(mx, off, 64));
     bad += __shfl_down(bad, off, 64);
   }
-  __shared__ double part[4][4];
+  __shared__ double part[kEnsNormThreads / 64][4];
   const int wave = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
     part[wave][0] = s1;
@@ -342,9 +384,9 @@ hipError_t launch_ens_publish_all(const EnsParams& p, bool f64, int count, hipSt
 
 hipError_t launch_ens_norms(const EnsNormParams& p, bool f64, int count, hipStream_t st) {
   if (f64)
-    hipLaunchKernelGGL(ens_norms_kernel<double>, dim3(count), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(ens_norms_kernel<double>, dim3(count), dim3(kEnsNormThreads), kEnsNormTable, st, p);
   else
-    hipLaunchKernelGGL(ens_norms_kernel<float>, dim3(count), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(ens_norms_kernel<float>, dim3(count), dim3(kEnsNormThreads), kEnsNormTable, st, p);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ __device__ inline int slot_of(int zz) {
 template <typename Real, int DIM, int S>
 struct Sweep {
   static constexpr int NSL = DIM == 3 ? 2 * S + 2 : 1;
+  static constexpr int kBatch = 4;   // points per thread whose loads are issued together
 
   const StepParams& p;
   Real* lds;
@@ -68,23 +69,34 @@ struct Sweep {
     return (static_cast<int64_t>(z) * p.ny + y) * p.nx + x;
   }
 
-  // Offset of element q of face `face` of PE `pe` in ring slot `slot`.
-  __device__ int64_t ring_off(int slot, int pe, int face, int64_t q) const {
-    return ring_index_q(p, slot, pe, face, q);
+  // Offset of element r of plane `plane` of face `face`'s strip of PE `pe`
+  // in ring slot `slot` (x and y strips: plane z; z strips: plane d).
+  __device__ int64_t ring_off(int slot, int pe, int face, int plane, int r) const {
+    return ring_index(p, slot, pe, face, plane, r);
   }
 
-  // Halo value across face f = 2*axis + side, element q of the producer strip.
+  // Halo value across face f = 2*axis + side, element r of plane `plane` of
+  // the producer strip.
   // AT: sum over the T delayed levels, in double. SYNC: the neighbour's
   // level-n value at global position (gx, gy, gz).
-  __device__ Real halo(int f, int64_t q, int gx, int gy, int gz) const {
+  __device__ Real halo(int f, int plane, int r, int gx, int gy, int gz) const {
     if (p.mode == AT_SYNC) return centre[gidx(gx, gy, gz)];
     const int pf = f ^ 1;   // producer face: the opposite side
     const int nb = nbr[f];
-    double acc = 0.0;
-    for (int m = 0; m < p.T; ++m) {
+    // every level is loaded from an in-range slot so that the T loads are in
+    // flight together; a level of weight zero (k = 0: exact synchronous
+    // value) is then dropped by the select
+    Real v[kMaxT];
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) {
       const int sl = lev_slot[f * kMaxT + m];
-      if (sl < 0) continue;   // zero weight (k = 0): exact synchronous value
-      acc += w[f * kMaxT + m] * static_cast<double>(ring_rd[ring_off(sl, nb, pf, q)]);
+      if (m < p.T) v[m] = ring_rd[ring_off(sl < 0 ? 0 : sl, nb, pf, plane, r)];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) {
+      const int sl = lev_slot[f * kMaxT + m];
+      if (m < p.T && sl >= 0) acc += w[f * kMaxT + m] * static_cast<double>(v[m]);
     }
     return static_cast<Real>(acc);
   }
@@ -95,26 +107,37 @@ struct Sweep {
     const int bx = p.bx, by = p.by, bz = p.bz;
     if (zz >= 0 && zz < bz) {
       const int gz = z0 + zz;
-      for (int i = tid; i < bx * by; i += nt) {
-        const int x = i % bx, y = i / bx;
-        P[(DIM >= 2 ? y + S : 0) * px_stride + x + S] = centre[gidx(x0 + x, y0 + y, gz)];
+      // kBatch loads per thread are issued before any LDS write, from
+      // clamped (in-range) addresses
+      const int np = bx * by;
+      for (int i0 = tid; i0 < np; i0 += kBatch * nt) {
+        Real v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          const int i = min(i0 + k * nt, np - 1);
+          v[k] = centre[gidx(x0 + i % bx, y0 + i / bx, gz)];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          const int i = i0 + k * nt;
+          if (i < np) P[(DIM >= 2 ? i / bx + S : 0) * px_stride + i % bx + S] = v[k];
+        }
       }
-      // x halos: producer strip [z][y][d]
-      for (int h = tid; h < 2 * S * by; h += nt) {
-        const int side = h / (S * by), r = h % (S * by), d = r % S, y = r / S;
-        const int xl = side ? bx + d : d - S;
-        const int gx = (x0 + xl + p.nx) % p.nx;
-        const int64_t q = (static_cast<int64_t>(zz) * by + y) * S + d;
-        P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, q, gx, y0 + y, gz);
-      }
-      if (DIM >= 2) {
-        // y halos: producer strip [z][d][x]
-        for (int h = tid; h < 2 * S * bx; h += nt) {
-          const int side = h / (S * bx), r = h % (S * bx), d = r / bx, x = r % bx;
+      // x halos (producer strip [z][y][d]) and y halos (producer strip
+      // [z][d][x]) in one pass, so that their loads overlap
+      const int nxh = 2 * S * by, nh = nxh + (DIM >= 2 ? 2 * S * bx : 0);
+      for (int h = tid; h < nh; h += nt) {
+        if (h < nxh) {
+          const int side = h / (S * by), r = h % (S * by), d = r % S, y = r / S;
+          const int xl = side ? bx + d : d - S;
+          const int gx = (x0 + xl + p.nx) % p.nx;
+          P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, zz, y * S + d, gx, y0 + y, gz);
+        } else {
+          const int hy = h - nxh;
+          const int side = hy / (S * bx), r = hy % (S * bx), d = r / bx, x = r % bx;
           const int yl = side ? by + d : d - S;
           const int gy = (y0 + yl + p.ny) % p.ny;
-          const int64_t q = (static_cast<int64_t>(zz) * S + d) * bx + x;
-          P[(yl + S) * px_stride + x + S] = halo(2 + side, q, x0 + x, gy, gz);
+          P[(yl + S) * px_stride + x + S] = halo(2 + side, zz, d * bx + x, x0 + x, gy, gz);
         }
       }
     } else {
@@ -124,8 +147,7 @@ struct Sweep {
       const int gz = (z0 + zz + p.nz) % p.nz;
       for (int i = tid; i < bx * by; i += nt) {
         const int x = i % bx, y = i / bx;
-        const int64_t q = (static_cast<int64_t>(d) * by + y) * bx + x;
-        P[(y + S) * px_stride + x + S] = halo(4 + side, q, x0 + x, y0 + y, gz);
+        P[(y + S) * px_stride + x + S] = halo(4 + side, d, y * bx + x, x0 + x, y0 + y, gz);
       }
     }
   }
@@ -146,86 +168,101 @@ struct Sweep {
     const Real vx = static_cast<Real>(p.vel[0]), vy = static_cast<Real>(p.vel[1]),
                vz = static_cast<Real>(p.vel[2]);
     const int gz = z0 + z;
-    for (int i = tid; i < bx * by; i += nt) {
-      const int x = i % bx, y = i / bx;
-      const int ly = DIM >= 2 ? y + S : 0;
-      const int c_at = ly * px_stride + x + S;
-      const Real u0 = C[c_at];
-      // difference form: the taps of each derivative sum to zero, so each
-      // neighbour enters as (v - u0), which keeps float rounding small
-      Real g1 = 0, g2 = 0;
-      {
-        Real d1 = 0, d2 = 0;
+    const int np = bx * by;
+    // the previous-level values the update reads (f^{n-1}, f^{n-2} or u^n)
+    // are loaded for kBatch points before any of them is computed
+    const bool rk2 = p.stage == kStageRk2;
+    const bool ab = p.stage != kStageRk1 && p.stage != kStageRk2 && p.integrator != AT_EULER && n > 0;
+    const bool ab3 = ab && p.integrator == AT_AB3 && n >= 2;
+    const Real* pre_a = static_cast<const Real*>(
+        rk2 ? p.ubuf[n & 1] : (ab3 ? p.fbuf[(n - 1) & 1] : p.fbuf[0]));
+    const Real* pre_b = static_cast<const Real*>(p.fbuf[n & 1]);
+    for (int i0 = tid; i0 < np; i0 += kBatch * nt) {
+      Real pa[kBatch], pb[kBatch];
 #pragma unroll
-        for (int o = -S; o <= S; ++o) {
-          if (o == 0) continue;
-          const Real v = C[c_at + o] - u0;
-          d1 += c1[0][o + S] * v;
-          d2 += c2[0][o + S] * v;
-        }
-        g1 = p.equation == AT_ADVDIFF ? vx * d1 : d1;
-        g2 = d2;
+      for (int k = 0; k < kBatch; ++k) {
+        const int i = min(i0 + k * nt, np - 1);
+        const int64_t g = gidx(x0 + i % bx, y0 + i / bx, gz);
+        pa[k] = (rk2 || ab) ? pre_a[g] : Real(0);
+        pb[k] = ab3 ? pre_b[g] : Real(0);
       }
-      if (DIM >= 2) {
-        Real d1 = 0, d2 = 0;
 #pragma unroll
-        for (int o = -S; o <= S; ++o) {
-          if (o == 0) continue;
-          const Real v = C[c_at + o * px_stride] - u0;
-          d1 += c1[1][o + S] * v;
-          d2 += c2[1][o + S] * v;
-        }
-        g1 += p.equation == AT_ADVDIFF ? vy * d1 : d1;
-        g2 += d2;
-      }
-      if (DIM == 3) {
-        Real d1 = 0, d2 = 0;
+      for (int k = 0; k < kBatch; ++k) {
+        const int i = i0 + k * nt;
+        if (i >= np) break;
+        const int x = i % bx, y = i / bx;
+        const int ly = DIM >= 2 ? y + S : 0;
+        const int c_at = ly * px_stride + x + S;
+        const Real u0 = C[c_at];
+        // difference form: the taps of each derivative sum to zero, so each
+        // neighbour enters as (v - u0), which keeps float rounding small
+        Real g1 = 0, g2 = 0;
+        {
+          Real d1 = 0, d2 = 0;
 #pragma unroll
-        for (int o = -S; o <= S; ++o) {
-          if (o == 0) continue;
-          const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at] - u0;
-          d1 += c1[2][o + S] * v;
-          d2 += c2[2][o + S] * v;
-        }
-        g1 += p.equation == AT_ADVDIFF ? vz * d1 : d1;
-        g2 += d2;
-      }
-      const Real f = p.equation == AT_ADVDIFF ? alpha * g2 - g1 : alpha * g2 - u0 * g1;
-      const int64_t g = gidx(x0 + x, y0 + y, gz);
-      Real un;
-      if (p.stage == kStageRk1) {
-        un = u0 + dt * f;
-        static_cast<Real*>(p.ustar)[g] = un;
-      } else if (p.stage == kStageRk2) {
-        const Real uold = static_cast<const Real*>(p.ubuf[n & 1])[g];
-        un = Real(0.5) * (uold + u0) + (Real(0.5) * dt) * f;
-        static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
-      } else {
-        if (p.integrator == AT_EULER || n == 0) {
-          un = u0 + dt * f;
-          if (p.integrator == AT_AB2) static_cast<Real*>(p.fbuf[0])[g] = f;
-          if (p.integrator == AT_AB3) static_cast<Real*>(p.fbuf[0])[g] = f;
-        } else if (p.integrator == AT_AB2 || n == 1) {
-          // AB3 at n = 1 takes an AB2 step; f^{n-1} is in fbuf[0] either way
-          Real* fb = static_cast<Real*>(p.fbuf[0]);
-          const Real fo = fb[g];
-          un = u0 + dt * (Real(1.5) * f - Real(0.5) * fo);
-          if (p.integrator == AT_AB2) {
-            fb[g] = f;
-          } else {
-            static_cast<Real*>(p.fbuf[1])[g] = f;   // f^1 -> fbuf[1]
+          for (int o = -S; o <= S; ++o) {
+            if (o == 0) continue;
+            const Real v = C[c_at + o] - u0;
+            d1 += c1[0][o + S] * v;
+            d2 += c2[0][o + S] * v;
           }
-        } else {
-          // AB3, n >= 2: f^{n-1} in fbuf[(n-1)&1], f^{n-2} in fbuf[n&1]
-          Real* fm1 = static_cast<Real*>(p.fbuf[(n - 1) & 1]);
-          Real* fm2 = static_cast<Real*>(p.fbuf[n & 1]);
-          const Real a1 = fm1[g], a2 = fm2[g];
-          un = u0 + dt * ((Real(23) * f - Real(16) * a1 + Real(5) * a2) / Real(12));
-          fm2[g] = f;
+          g1 = p.equation == AT_ADVDIFF ? vx * d1 : d1;
+          g2 = d2;
         }
-        static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
+        if (DIM >= 2) {
+          Real d1 = 0, d2 = 0;
+#pragma unroll
+          for (int o = -S; o <= S; ++o) {
+            if (o == 0) continue;
+            const Real v = C[c_at + o * px_stride] - u0;
+            d1 += c1[1][o + S] * v;
+            d2 += c2[1][o + S] * v;
+          }
+          g1 += p.equation == AT_ADVDIFF ? vy * d1 : d1;
+          g2 += d2;
+        }
+        if (DIM == 3) {
+          Real d1 = 0, d2 = 0;
+#pragma unroll
+          for (int o = -S; o <= S; ++o) {
+            if (o == 0) continue;
+            const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at] - u0;
+            d1 += c1[2][o + S] * v;
+            d2 += c2[2][o + S] * v;
+          }
+          g1 += p.equation == AT_ADVDIFF ? vz * d1 : d1;
+          g2 += d2;
+        }
+        const Real f = p.equation == AT_ADVDIFF ? alpha * g2 - g1 : alpha * g2 - u0 * g1;
+        const int64_t g = gidx(x0 + x, y0 + y, gz);
+        Real un;
+        if (p.stage == kStageRk1) {
+          un = u0 + dt * f;
+          static_cast<Real*>(p.ustar)[g] = un;
+        } else if (rk2) {
+          un = Real(0.5) * (pa[k] + u0) + (Real(0.5) * dt) * f;
+          static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
+        } else {
+          if (!ab) {
+            un = u0 + dt * f;
+            if (p.integrator == AT_AB2 || p.integrator == AT_AB3) static_cast<Real*>(p.fbuf[0])[g] = f;
+          } else if (!ab3) {
+            // AB2, or AB3 at n = 1 (an AB2 step); f^{n-1} is in fbuf[0] either way
+            un = u0 + dt * (Real(1.5) * f - Real(0.5) * pa[k]);
+            if (p.integrator == AT_AB2) {
+              static_cast<Real*>(p.fbuf[0])[g] = f;
+            } else {
+              static_cast<Real*>(p.fbuf[1])[g] = f;   // f^1 -> fbuf[1]
+            }
+          } else {
+            // AB3, n >= 2: f^{n-1} in fbuf[(n-1)&1], f^{n-2} in fbuf[n&1]
+            un = u0 + dt * ((Real(23) * f - Real(16) * pa[k] + Real(5) * pb[k]) / Real(12));
+            static_cast<Real*>(p.fbuf[n & 1])[g] = f;
+          }
+          static_cast<Real*>(p.ubuf[(n + 1) & 1])[g] = un;
+        }
+        if (p.mode != AT_SYNC) publish(x, y, z, un);
       }
-      if (p.mode != AT_SYNC) publish(x, y, z, un);
     }
   }
 
@@ -236,15 +273,15 @@ struct Sweep {
     Real* R = static_cast<Real*>(rk1 ? p.sring : p.ring);
     const int slot = static_cast<int>((rk1 ? n : n + 1) % p.nslots);
     const int bx = p.bx, by = p.by, bz = p.bz;
-    if (x < S) R[ring_off(slot, pid, 0, (static_cast<int64_t>(z) * by + y) * S + x)] = v;
-    if (x >= bx - S) R[ring_off(slot, pid, 1, (static_cast<int64_t>(z) * by + y) * S + x - (bx - S))] = v;
+    if (x < S) R[ring_off(slot, pid, 0, z, y * S + x)] = v;
+    if (x >= bx - S) R[ring_off(slot, pid, 1, z, y * S + x - (bx - S))] = v;
     if (DIM >= 2) {
-      if (y < S) R[ring_off(slot, pid, 2, (static_cast<int64_t>(z) * S + y) * bx + x)] = v;
-      if (y >= by - S) R[ring_off(slot, pid, 3, (static_cast<int64_t>(z) * S + y - (by - S)) * bx + x)] = v;
+      if (y < S) R[ring_off(slot, pid, 2, z, y * bx + x)] = v;
+      if (y >= by - S) R[ring_off(slot, pid, 3, z, (y - (by - S)) * bx + x)] = v;
     }
     if (DIM == 3) {
-      if (z < S) R[ring_off(slot, pid, 4, (static_cast<int64_t>(z) * by + y) * bx + x)] = v;
-      if (z >= bz - S) R[ring_off(slot, pid, 5, (static_cast<int64_t>(z - (bz - S)) * by + y) * bx + x)] = v;
+      if (z < S) R[ring_off(slot, pid, 4, z, y * bx + x)] = v;
+      if (z >= bz - S) R[ring_off(slot, pid, 5, z - (bz - S), y * bx + x)] = v;
     }
   }
 };
