@@ -16,7 +16,7 @@
 //   out_j = (base terms) + D_j mu_j + sum_{o: j-o in the PE of j} K_{j-o,a,o} mu_{j-o} + A^n_j,
 // where A^l gathers, at the edge strips that neighbours read, K_{i,a,o} c_m(k)
 // mu_i of every later step with n - k - m = l: an adjoint ring of the forward
-// ring's shape, filled by the scatter kernel (in gather form: one thread per
+// ring's shape, filled by the strip kernel (in gather form: one thread per
 // strip value) and drained when the sweep reaches level l. The
 // alpha-gradient adds <mu, dF/dalpha> = <mu, AT Laplacian of c>.
 //
@@ -84,7 +84,7 @@ __device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int 
   return ring_index(p, slot, pe, F, d, static_cast<int64_t>(l[1]) * p.bx + l[0]);
 }
 
-// Strip value t of the per-PE numbering used by the scatter and halo kernels
+// Strip value t of the per-PE numbering used by the strip kernel
 // and the halo buffer: PE pe, face F (its strip starts at pfo[F] inside the
 // PE's pe_block values), depth d from the strip's low side and the other PE
 // coordinates in l (l[F >> 1] = 0). 32-bit: the host keeps npe * pe_block
@@ -176,58 +176,54 @@ __device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
 // collects the transposed taps of the consumer PE across F, weighted by the
 // consumer's level weights, into the adjoint ring slots of levels n-k-m.
 template <typename Real>
-__global__ __launch_bounds__(kAdjThreads) void adj_scatter_kernel(AdjParams q) {
+__device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
   const StepParams& p = q.sp;
   const int S = p.s;
-  const int total = p.npe * static_cast<int>(p.pe_block);
   Real* aring = static_cast<Real*>(q.aring);
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-    const StripPt sp = strip_point(q, t);
-    const int pe = sp.pe, F = sp.F, d = sp.d, a = F >> 1;
-    const int* l = sp.l;
-    const int b = edge_of(p, a);
-    // the consumer across F reads this strip through its opposite face
-    const int cons = nbr_pe(p, pe, F);
-    const int cf = F ^ 1;
-    // coordinate of the strip value in the consumer's frame
-    const int jp = (F & 1) ? d - S : b + d;
-    const int cq[3] = {cons % p.px, (cons / p.px) % p.py, cons / (p.px * p.py)};
-    const int org[3] = {cq[0] * p.bx, cq[1] * p.by, cq[2] * p.bz};
-    // taps from consumer points outside the consumer PE are dropped by a
-    // select after unconditional loads from a clamped (in-PE) point, so that
-    // every load of the element is in flight together
-    double g = 0.0;
-    for (int o = -S; o <= S; ++o) {
-      if (o == 0) continue;
-      const int ia = jp - o;
-      const bool valid = ia >= 0 && ia < b;
-      int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
-      c[a] = org[a] + min(max(ia, 0), b - 1);
-      const int64_t gi = gindex(p, c[0], c[1], c[2]);
-      const double t = tap_k(q, a, o, centre_at<Real>(q, gi)) * mu_at<Real>(q, gi);
-      g += valid ? t : 0.0;
-    }
-    const int k = adj_delay(p, cons, cf, q.n);
-    double w[kMaxT];
-    const int T = adj_levels(p);
-    level_weights(k, T, w);
-    int lsF[3] = {l[0], l[1], l[2]};   // the strip value's PE coordinates
-    lsF[a] = (F & 1) ? b - S + d : d;
-    Real* dst[kMaxT];
-    double old[kMaxT];
+  const int pe = sp.pe, F = sp.F, d = sp.d, a = F >> 1;
+  const int* l = sp.l;
+  const int b = edge_of(p, a);
+  // the consumer across F reads this strip through its opposite face
+  const int cons = nbr_pe(p, pe, F);
+  const int cf = F ^ 1;
+  // coordinate of the strip value in the consumer's frame
+  const int jp = (F & 1) ? d - S : b + d;
+  const int cq[3] = {cons % p.px, (cons / p.px) % p.py, cons / (p.px * p.py)};
+  const int org[3] = {cq[0] * p.bx, cq[1] * p.by, cq[2] * p.bz};
+  // taps from consumer points outside the consumer PE are dropped by a
+  // select after unconditional loads from a clamped (in-PE) point, so that
+  // every load of the element is in flight together
+  double g = 0.0;
+  for (int o = -S; o <= S; ++o) {
+    if (o == 0) continue;
+    const int ia = jp - o;
+    const bool valid = ia >= 0 && ia < b;
+    int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
+    c[a] = org[a] + min(max(ia, 0), b - 1);
+    const int64_t gi = gindex(p, c[0], c[1], c[2]);
+    const double t = tap_k(q, a, o, centre_at<Real>(q, gi)) * mu_at<Real>(q, gi);
+    g += valid ? t : 0.0;
+  }
+  const int k = adj_delay(p, cons, cf, q.n);
+  double w[kMaxT];
+  const int T = adj_levels(p);
+  level_weights(k, T, w);
+  int lsF[3] = {l[0], l[1], l[2]};   // the strip value's PE coordinates
+  lsF[a] = (F & 1) ? b - S + d : d;
+  Real* dst[kMaxT];
+  double old[kMaxT];
 #pragma unroll
-    for (int m = 0; m < kMaxT; ++m) {
-      if (m >= T) break;
-      const int64_t l = q.n - k - m;   // negative only where w[m] = 0
-      const int slot = static_cast<int>((l < 0 ? 0 : l) % q.anslots);
-      dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
-      old[m] = static_cast<double>(*dst[m]);
-    }
+  for (int m = 0; m < kMaxT; ++m) {
+    if (m >= T) break;
+    const int64_t l = q.n - k - m;   // negative only where w[m] = 0
+    const int slot = static_cast<int>((l < 0 ? 0 : l) % q.anslots);
+    dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
+    old[m] = static_cast<double>(*dst[m]);
+  }
 #pragma unroll
-    for (int m = 0; m < kMaxT; ++m) {
-      if (m >= T) break;
-      if (w[m] != 0.0) *dst[m] = static_cast<Real>(old[m] + w[m] * g);
-    }
+  for (int m = 0; m < kMaxT; ++m) {
+    if (m >= T) break;
+    if (w[m] != 0.0) *dst[m] = static_cast<Real>(old[m] + w[m] * g);
   }
 }
 
@@ -254,39 +250,47 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y
 // combination of the stored levels (the synchronous scheme: level n).
 // hbuf[pe * pe_block + (per-PE offset of face f) + e].
 template <typename Real>
-__global__ __launch_bounds__(kAdjThreads) void adj_halo_kernel(AdjParams q) {
+__device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp) {
   const StepParams& p = q.sp;
   const int S = p.s;
   const int T = adj_levels(p);
-  const int total = p.npe * static_cast<int>(p.pe_block);
   Real* hb = static_cast<Real*>(q.hbuf);
+  const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
+  int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
+  const int b = edge_of(p, a);
+  ls[a] = (pf & 1) ? b - S + d : d;
+  const int src = nbr_pe(p, pe, f);
+  const int sq[3] = {src % p.px, (src / p.px) % p.py, src / (p.px * p.py)};
+  const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
+  const int k = adj_delay(p, pe, f, q.n);
+  double w[kMaxT];
+  level_weights(k, T, w);
+  if (p.mode == AT_SYNC) {   // level n, always stored
+    hb[t] = static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
+    return;
+  }
+  // all kMaxT levels are loaded unconditionally (a level m >= T repeats
+  // level T - 1 and is dropped below), so the loads overlap
+  double lv[kMaxT];
+#pragma unroll
+  for (int m = 0; m < kMaxT; ++m)
+    lv[m] = level_value<Real>(q, q.n - k - min(m, T - 1), gx, gy, gz, src, pf, ls);
+  double v = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxT; ++m)
+    if (m < T && w[m] != 0.0) v += w[m] * lv[m];
+  hb[t] = static_cast<Real>(v);
+}
+
+// One thread per strip value t: its forward halo value (consumer view) and its
+// adjoint-ring scatter (producer view) share the decode of t.
+template <typename Real>
+__global__ __launch_bounds__(kAdjThreads) void adj_strip_kernel(AdjParams q) {
+  const int total = q.sp.npe * static_cast<int>(q.sp.pe_block);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
     const StripPt sp = strip_point(q, t);
-    const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
-    int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
-    const int b = edge_of(p, a);
-    ls[a] = (pf & 1) ? b - S + d : d;
-    const int src = nbr_pe(p, pe, f);
-    const int sq[3] = {src % p.px, (src / p.px) % p.py, src / (p.px * p.py)};
-    const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
-    const int k = adj_delay(p, pe, f, q.n);
-    double w[kMaxT];
-    level_weights(k, T, w);
-    if (p.mode == AT_SYNC) {   // level n, always stored
-      hb[t] = static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
-      continue;
-    }
-    // all kMaxT levels are loaded unconditionally (a level m >= T repeats
-    // level T - 1 and is dropped below), so the loads overlap
-    double lv[kMaxT];
-#pragma unroll
-    for (int m = 0; m < kMaxT; ++m)
-      lv[m] = level_value<Real>(q, q.n - k - min(m, T - 1), gx, gy, gz, src, pf, ls);
-    double v = 0.0;
-#pragma unroll
-    for (int m = 0; m < kMaxT; ++m)
-      if (m < T && w[m] != 0.0) v += w[m] * lv[m];
-    hb[t] = static_cast<Real>(v);
+    halo_elem<Real>(q, t, sp);
+    scatter_elem<Real>(q, sp);
   }
 }
 
@@ -398,12 +402,14 @@ hipError_t launch_lambda(const AdjParams& q, int blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void adj_sum_kernel(const double* partial, int count, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < count; ++i) s += partial[i];
-    out[0] = s;
-  }
+// One wave: lane l adds partials l, l + 64, ... in order, then a fixed
+// butterfly combines the lanes.
+__global__ __launch_bounds__(64) void adj_sum_kernel(const double* partial, int count, double* out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < count; i += 64) s += partial[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (threadIdx.x == 0) out[0] = s;
 }
 
 }  // namespace
@@ -419,13 +425,11 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
   const int lblocks = adj_blocks(q.npts);
   if (f64) {
-    hipLaunchKernelGGL(adj_halo_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipLaunchKernelGGL(adj_scatter_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_strip_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = launch_lambda<double>(q, lblocks, st);
     if (e != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(adj_halo_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipLaunchKernelGGL(adj_scatter_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    hipLaunchKernelGGL(adj_strip_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = launch_lambda<float>(q, lblocks, st);
     if (e != hipSuccess) return e;
   }

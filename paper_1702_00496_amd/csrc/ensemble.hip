@@ -54,15 +54,25 @@ __device__ inline void ens_member_halos(const EnsMember& M, const Real* __restri
       // the left neighbour's right strip (face 1) or the right neighbour's
       // left strip (face 0)
       const Real* strip = ring + M.ring_off + (static_cast<int64_t>(q) * 2 + (side ? 0 : 1)) * S;
+      // all kMaxT levels are read (a level beyond T, or before t = 0, reads
+      // an in-range slot that a zero weight then drops), so the reads of the
+      // face are in flight together
+      Real raw[kMaxT][S];
+#pragma unroll
+      for (int m = 0; m < kMaxT; ++m) {
+        const int64_t l = n - k - min(m, M.T - 1);
+        const Real* lv = strip + static_cast<int>((l < 0 ? 0 : l) % M.nslots) * slot_stride;
+#pragma unroll
+        for (int d = 0; d < S; ++d) raw[m][d] = lv[d];
+      }
       double acc[S];
 #pragma unroll
       for (int d = 0; d < S; ++d) acc[d] = 0.0;
-      for (int m = 0; m < M.T; ++m) {
-        const double w = M.wt[k][m];
-        if (w == 0.0) continue;   // never touches a level before t = 0
-        const Real* lv = strip + static_cast<int>((n - k - m) % M.nslots) * slot_stride;
 #pragma unroll
-        for (int d = 0; d < S; ++d) acc[d] += w * static_cast<double>(lv[d]);
+      for (int m = 0; m < kMaxT; ++m) {
+        const double w = m < M.T ? M.wt[k][m] : 0.0;
+#pragma unroll
+        for (int d = 0; d < S; ++d) acc[d] += w != 0.0 ? w * static_cast<double>(raw[m][d]) : 0.0;
       }
 #pragma unroll
       for (int d = 0; d < S; ++d) v[d] = static_cast<Real>(acc[d]);
@@ -134,7 +144,10 @@ __device__ inline EnsChunk<Real, S, V> ens_chunk_load(const EnsMember& M, const 
     const Real* ar = pr < M.b ? u + k.g0 + V - 1 + o : hr + (pr - M.b);
     k.w[S + V - 1 + o] = *ar;
   }
-  if (M.integrator == AT_AB2) ens_load<Real, V>(f + k.g0, k.fo);
+  // f^{n-1}, read for every member (a non-AB2 member reads its own u^n; the
+  // update weights it by an exact zero, as it does f at n = 0, which
+  // at_ens_set_state zeroes), so that the load does not sit behind a branch
+  ens_load<Real, V>((M.integrator == AT_AB2 ? f : u) + k.g0, k.fo);
   return k;
 }
 
@@ -143,6 +156,10 @@ template <typename Real, int S, int V>
 __device__ inline void ens_chunk_finish(const EnsMember& M, const EnsChunk<Real, S, V>& k, Real* __restrict__ un,
                                         Real* __restrict__ f, Real* __restrict__ ring, int64_t n) {
   const Real dt = static_cast<Real>(M.dt);
+  // AB2 after its first step: u + dt (3/2 f^n - 1/2 f^{n-1}); Euler (and the
+  // first AB2 step): u + dt f^n, with an exact zero weight on f^{n-1}
+  const bool ab2 = M.integrator == AT_AB2 && n > 0;
+  const Real b1 = ab2 ? Real(1.5) : Real(1), b2 = ab2 ? Real(-0.5) : Real(0);
   Real r[V], acc[V];
 #pragma unroll
   for (int e = 0; e < V; ++e) {
@@ -156,10 +173,7 @@ __device__ inline void ens_chunk_finish(const EnsMember& M, const EnsChunk<Real,
       a += ens_tap<Real>(M, S + o) * (k.w[S + e + o] - u0);
     }
     acc[e] = a;
-    if (M.integrator == AT_AB2 && n > 0)
-      r[e] = u0 + dt * (Real(1.5) * a - Real(0.5) * k.fo[e]);
-    else
-      r[e] = u0 + dt * a;
+    r[e] = u0 + dt * (b1 * a + b2 * k.fo[e]);
   }
   ens_store<Real, V>(un + k.g0, r);
   if (M.integrator == AT_AB2) ens_store<Real, V>(f + k.g0, acc);
@@ -203,17 +217,19 @@ __device__ inline void ens_member_sweep_s(const EnsMember& M, const Real* u, Rea
                                           const Real* hb, int64_t n) {
   // as many chunks in flight as the 128 registers of a 1024-thread
   // workgroup hold without spilling
-  constexpr int U = (sizeof(Real) == 4 && S <= 2) ? 4 : 2;
+  constexpr int U = sizeof(Real) == 4 ? (S <= 2 ? 4 : 2) : (S <= 2 ? 2 : 1);
   if (M.vec)
     ens_member_sweep<Real, S, 4, U>(M, u, un, f, ring, hb, n);
   else
     ens_member_sweep<Real, S, 1, sizeof(Real) == 4 ? 4 : 2>(M, u, un, f, ring, hb, n);
 }
 
+// Members whose descriptors a workgroup holds in LDS at a time.
+constexpr int kEnsLdsMembers = 24;
+
+// All steps of `count` members whose descriptors are in LDS.
 template <typename Real>
-__global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) {
-  const int m0 = p.bin_start[blockIdx.x], m1 = p.bin_start[blockIdx.x + 1];
-  const int64_t n0 = p.counter[0];
+__device__ inline void ens_run(const EnsParams& p, int64_t n0, const EnsMember* mem, int count) {
   Real* f = static_cast<Real*>(p.f);
   Real* ring = static_cast<Real*>(p.ring);
   Real* hb = static_cast<Real*>(p.hbuf);
@@ -221,8 +237,8 @@ __global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) 
     const int64_t n = n0 + st;
     const Real* u = static_cast<const Real*>(p.u[n & 1]);
     Real* un = static_cast<Real*>(p.u[(n + 1) & 1]);
-    for (int mi = m0; mi < m1; ++mi) {
-      const EnsMember& M = p.mem[p.order[mi]];
+    for (int i = 0; i < count; ++i) {
+      const EnsMember& M = mem[i];
       switch (M.s) {
         case 1: ens_member_halos<Real, 1>(M, u, ring, hb, n); break;
         case 2: ens_member_halos<Real, 2>(M, u, ring, hb, n); break;
@@ -231,8 +247,8 @@ __global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) 
     }
     // halo values complete before the sweep reads them
     __syncthreads();
-    for (int mi = m0; mi < m1; ++mi) {
-      const EnsMember& M = p.mem[p.order[mi]];
+    for (int i = 0; i < count; ++i) {
+      const EnsMember& M = mem[i];
       switch (M.s) {
         case 1: ens_member_sweep_s<Real, 1>(M, u, un, f, ring, hb, n); break;
         case 2: ens_member_sweep_s<Real, 2>(M, u, un, f, ring, hb, n); break;
@@ -242,6 +258,29 @@ __global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) 
     // every member's level n+1 (field and ring) is complete, and the halo
     // values are consumed, before step n+1 starts
     __syncthreads();
+  }
+}
+
+// One workgroup per bin of members. Members are independent problems, so a
+// bin larger than the LDS descriptor cache runs all steps for one batch of
+// members, then for the next.
+template <typename Real>
+__global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) {
+  __shared__ EnsMember s_mem[kEnsLdsMembers];
+  constexpr int kWords = sizeof(EnsMember) / sizeof(uint32_t);
+  static_assert(sizeof(EnsMember) % sizeof(uint32_t) == 0, "descriptors are copied as words");
+  const int m0 = p.bin_start[blockIdx.x], m1 = p.bin_start[blockIdx.x + 1];
+  const int64_t n0 = p.counter[0];
+  for (int b0 = m0; b0 < m1; b0 += kEnsLdsMembers) {
+    const int count = min(kEnsLdsMembers, m1 - b0);
+    __syncthreads();   // the previous batch is done with the descriptors
+    uint32_t* dst = reinterpret_cast<uint32_t*>(s_mem);
+    for (int i = threadIdx.x; i < count * kWords; i += blockDim.x) {
+      const int j = i / kWords;
+      dst[i] = reinterpret_cast<const uint32_t*>(p.mem + p.order[b0 + j])[i - j * kWords];
+    }
+    __syncthreads();
+    ens_run<Real>(p, n0, s_mem, count);
   }
   if (threadIdx.x == 0) advance_counter(p.counter, n0 + p.nsteps - 1);
 }

@@ -274,6 +274,9 @@ at_status at_ens_set_state(at_ens* e, const void* u0_dev) {
   if (!e || !u0_dev) return efail(e, AT_EINVAL, "null argument");
   ENS_TRY(e, hipMemcpyAsync(e->ep.u[0], u0_dev, e->field_bytes, hipMemcpyDeviceToDevice, e->stream));
   ENS_TRY(e, hipMemsetAsync(e->ep.counter, 0, 2 * sizeof(int64_t), e->stream));
+  // the sweep reads f^{n-1} at every step and weights it by an exact zero at
+  // n = 0 (and for Euler members): it must hold finite values from the start
+  if (e->ep.f) ENS_TRY(e, hipMemsetAsync(e->ep.f, 0, e->field_bytes, e->stream));
   if (e->ring_elems) ENS_TRY(e, launch_ens_publish_all(e->ep, e->f64, e->count, e->stream));
   e->n = 0;
   e->state_set = true;

@@ -31,6 +31,9 @@ __device__ inline int slot_of(int zz) {
   return DIM == 3 ? (zz + S) % (2 * S + 2) : 0;
 }
 
+// Parts of an LDS plane: the PE's own values and the x/y halo frame.
+constexpr int kPlaneCentre = 1, kPlaneHalos = 2;
+
 template <typename Real, int DIM, int S>
 struct Sweep {
   static constexpr int NSL = DIM == 3 ? 2 * S + 2 : 1;
@@ -101,7 +104,7 @@ struct Sweep {
     return static_cast<Real>(acc);
   }
 
-  __device__ void load_plane(int zz) {
+  __device__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
     Real* P = lds + slot_of<DIM, S>(zz) * plane;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
@@ -109,7 +112,7 @@ struct Sweep {
       const int gz = z0 + zz;
       // kBatch loads per thread are issued before any LDS write, from
       // clamped (in-range) addresses
-      const int np = bx * by;
+      const int np = (parts & kPlaneCentre) ? bx * by : 0;
       for (int i0 = tid; i0 < np; i0 += kBatch * nt) {
         Real v[kBatch];
 #pragma unroll
@@ -125,7 +128,7 @@ struct Sweep {
       }
       // x halos (producer strip [z][y][d]) and y halos (producer strip
       // [z][d][x]) in one pass, so that their loads overlap
-      const int nxh = 2 * S * by, nh = nxh + (DIM >= 2 ? 2 * S * bx : 0);
+      const int nxh = 2 * S * by, nh = (parts & kPlaneHalos) ? nxh + (DIM >= 2 ? 2 * S * bx : 0) : 0;
       for (int h = tid; h < nh; h += nt) {
         if (h < nxh) {
           const int side = h / (S * by), r = h % (S * by), d = r % S, y = r / S;
@@ -318,7 +321,9 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
   const int64_t n = p.counter[0];
   const int pid = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid < 2 * DIM) {
+  // neighbours, delays and level weights of the 2 * DIM faces
+  auto faces = [&]() {
+    if (tid >= 2 * DIM) return;
     const int f = tid;
     s_nbr[f] = neighbour(p, pid, f);
     if (p.mode != AT_SYNC) {
@@ -331,11 +336,12 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
         s_slot[f * kMaxT + m] = live ? static_cast<int>((n - k - m) % p.nslots) : -1;
       }
     }
-  }
-  __syncthreads();
+  };
 
   Sweep<Real, DIM, S> sw(p, lds, n, s_w, s_slot, s_nbr);
   if (DIM == 3) {
+    faces();
+    __syncthreads();
     for (int zz = -S; zz < S; ++zz) sw.load_plane(zz);
     for (int z = 0; z < p.bz; ++z) {
       sw.load_plane(z + S);
@@ -343,7 +349,12 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
       sw.compute_plane(z);
     }
   } else {
-    sw.load_plane(0);
+    // the PE's own values do not depend on the delays: their loads are in
+    // flight while the first wave derives the face weights
+    sw.load_plane(0, kPlaneCentre);
+    faces();
+    __syncthreads();
+    sw.load_plane(0, kPlaneHalos);
     __syncthreads();
     sw.compute_plane(0);
   }
