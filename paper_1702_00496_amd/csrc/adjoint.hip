@@ -215,8 +215,8 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
 #pragma unroll
   for (int m = 0; m < kMaxT; ++m) {
     if (m >= T) break;
-    const int64_t l = q.n - k - m;   // negative only where w[m] = 0
-    const int slot = static_cast<int>((l < 0 ? 0 : l) % q.anslots);
+    // level n - k - m (before t = 0 only where w[m] = 0: any slot is read)
+    const int slot = slot_back(static_cast<int>(q.n % q.anslots), k + m, q.anslots);
     dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
     old[m] = static_cast<double>(*dst[m]);
   }
@@ -227,20 +227,20 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
   }
 }
 
-// Value of level l at global point (x, y, z), which lies in PE `src` at PE
-// coordinates ls: from the stored levels of the segment, or, for a level
-// before the segment, from the ring as it was at the segment's start (the
-// point is then an edge value of that ring, read through producer face pf).
+// Value of level l (ring slot `slot`) at global point (x, y, z), which lies in
+// PE `src` at PE coordinates ls: from the stored levels of the segment, or,
+// for a level before the segment, from the ring as it was at the segment's
+// start (the point is then an edge value of that ring, read through producer
+// face pf).
 template <typename Real>
-__device__ inline double level_value(const AdjParams& q, int64_t l, int x, int y, int z, int src, int pf,
-                                     const int* ls) {
+__device__ inline double level_value(const AdjParams& q, int64_t l, int slot, int x, int y, int z, int src,
+                                     int pf, const int* ls) {
   const StepParams& p = q.sp;
   // both candidates are loaded (from in-range addresses) and one is selected
   const bool stored = l >= q.seg_start;
   const Real* U = static_cast<const Real*>(q.levels) + (stored ? l - q.seg_start : 0) * q.npts;
   const double a = static_cast<double>(U[gindex(p, x, y, z)]);
   const Real* R0 = static_cast<const Real*>(q.ring0);
-  const int slot = static_cast<int>((l < 0 ? 0 : l) % p.nslots);
   const double b = static_cast<double>(R0[ring_at_pt(p, slot, src, pf, ls, p.s)]);
   return stored ? a : b;
 }
@@ -271,10 +271,12 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp) {
   }
   // all kMaxT levels are loaded unconditionally (a level m >= T repeats
   // level T - 1 and is dropped below), so the loads overlap
+  const int rn = static_cast<int>(q.n % p.nslots);
   double lv[kMaxT];
 #pragma unroll
   for (int m = 0; m < kMaxT; ++m)
-    lv[m] = level_value<Real>(q, q.n - k - min(m, T - 1), gx, gy, gz, src, pf, ls);
+    lv[m] = level_value<Real>(q, q.n - k - min(m, T - 1), slot_back(rn, k + min(m, T - 1), p.nslots), gx, gy,
+                              gz, src, pf, ls);
   double v = 0.0;
 #pragma unroll
   for (int m = 0; m < kMaxT; ++m)

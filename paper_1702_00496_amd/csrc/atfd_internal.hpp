@@ -43,6 +43,13 @@ __host__ __device__ inline int raw_delay(uint64_t key, int64_t n, uint32_t face,
   return k;
 }
 
+// Ring slot of level n - back from r0 = n mod nslots, for 0 <= back < nslots
+// (every delayed level k + m < L + T = nslots): no 64-bit division.
+__host__ __device__ inline int slot_back(int r0, int back, int nslots) {
+  const int s = r0 - back;
+  return s < 0 ? s + nslots : s;
+}
+
 // No level before t = 0 exists: the delay is clamped so that the oldest level
 // of the T-level combination, n - k - (T - 1), is not negative.
 __host__ __device__ inline int clamp_startup(int k, int64_t n, int T) {

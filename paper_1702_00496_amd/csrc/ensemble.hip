@@ -58,10 +58,10 @@ __device__ inline void ens_member_halos(const EnsMember& M, const Real* __restri
       // an in-range slot that a zero weight then drops), so the reads of the
       // face are in flight together
       Real raw[kMaxT][S];
+      const int r0 = static_cast<int>(n % M.nslots);
 #pragma unroll
       for (int m = 0; m < kMaxT; ++m) {
-        const int64_t l = n - k - min(m, M.T - 1);
-        const Real* lv = strip + static_cast<int>((l < 0 ? 0 : l) % M.nslots) * slot_stride;
+        const Real* lv = strip + slot_back(r0, k + min(m, M.T - 1), M.nslots) * slot_stride;
 #pragma unroll
         for (int d = 0; d < S; ++d) raw[m][d] = lv[d];
       }

@@ -73,9 +73,14 @@ struct Sweep {
   }
 
   // Offset of element r of plane `plane` of face `face`'s strip of PE `pe`
-  // in ring slot `slot` (x and y strips: plane z; z strips: plane d).
+  // in ring slot `slot` (x and y strips: plane z; z strips: plane d). The
+  // face may differ between lanes: its offset and chunk are selected from
+  // the uniform values rather than indexed.
   __device__ int64_t ring_off(int slot, int pe, int face, int plane, int r) const {
-    return ring_index(p, slot, pe, face, plane, r);
+    const int64_t fo = face == 0 ? p.face_off[0] : face == 1 ? p.face_off[1] : face == 2 ? p.face_off[2]
+                     : face == 3 ? p.face_off[3] : face == 4 ? p.face_off[4] : p.face_off[5];
+    const int64_t ch = face < 2 ? p.face_chunk[0] : face < 4 ? p.face_chunk[2] : p.face_chunk[4];
+    return static_cast<int64_t>(slot) * p.npe * p.pe_block + fo + (static_cast<int64_t>(plane) * p.npe + pe) * ch + r;
   }
 
   // Halo value across face f = 2*axis + side, element r of plane `plane` of
@@ -89,11 +94,13 @@ struct Sweep {
     // every level is loaded from an in-range slot so that the T loads are in
     // flight together; a level of weight zero (k = 0: exact synchronous
     // value) is then dropped by the select
+    const int64_t base = ring_off(0, nb, pf, plane, r);
+    const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
     Real v[kMaxT];
 #pragma unroll
     for (int m = 0; m < kMaxT; ++m) {
       const int sl = lev_slot[f * kMaxT + m];
-      if (m < p.T) v[m] = ring_rd[ring_off(sl < 0 ? 0 : sl, nb, pf, plane, r)];
+      v[m] = ring_rd[base + (m < p.T && sl > 0 ? sl : 0) * slot_stride];
     }
     double acc = 0.0;
 #pragma unroll
@@ -104,6 +111,26 @@ struct Sweep {
     return static_cast<Real>(acc);
   }
 
+  // Point i = tid + k nt of a bx * by plane as (x, y), stepped from k to k + 1
+  // without a division.
+  struct PlaneIter {
+    int x, y, dx, dy, bx;
+    __device__ PlaneIter(int tid, int nt, int bx_) : bx(bx_) {
+      x = tid % bx;
+      y = tid / bx;
+      dx = nt % bx;
+      dy = nt / bx;
+    }
+    __device__ void next() {
+      x += dx;
+      y += dy;
+      if (x >= bx) {
+        x -= bx;
+        ++y;
+      }
+    }
+  };
+
   __device__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
     Real* P = lds + slot_of<DIM, S>(zz) * plane;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -112,18 +139,22 @@ struct Sweep {
       const int gz = z0 + zz;
       // kBatch loads per thread are issued before any LDS write, from
       // clamped (in-range) addresses
-      const int np = (parts & kPlaneCentre) ? bx * by : 0;
-      for (int i0 = tid; i0 < np; i0 += kBatch * nt) {
-        Real v[kBatch];
+      if (parts & kPlaneCentre) {
+        const Real* cz = centre + gidx(x0, y0, gz);
+        PlaneIter it(tid, nt, bx);
+        while (it.y < by) {
+          Real v[kBatch];
+          int at[kBatch];
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-          const int i = min(i0 + k * nt, np - 1);
-          v[k] = centre[gidx(x0 + i % bx, y0 + i / bx, gz)];
-        }
+          for (int k = 0; k < kBatch; ++k) {
+            const bool in = it.y < by;
+            v[k] = cz[static_cast<int64_t>(in ? it.y : by - 1) * p.nx + (in ? it.x : bx - 1)];
+            at[k] = in ? (DIM >= 2 ? it.y + S : 0) * px_stride + it.x + S : -1;
+            it.next();
+          }
 #pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-          const int i = i0 + k * nt;
-          if (i < np) P[(DIM >= 2 ? i / bx + S : 0) * px_stride + i % bx + S] = v[k];
+          for (int k = 0; k < kBatch; ++k)
+            if (at[k] >= 0) P[at[k]] = v[k];
         }
       }
       // x halos (producer strip [z][y][d]) and y halos (producer strip
@@ -171,7 +202,7 @@ struct Sweep {
     const Real vx = static_cast<Real>(p.vel[0]), vy = static_cast<Real>(p.vel[1]),
                vz = static_cast<Real>(p.vel[2]);
     const int gz = z0 + z;
-    const int np = bx * by;
+    const int64_t gbase = gidx(x0, y0, gz);   // the plane's first point in the field
     // the previous-level values the update reads (f^{n-1}, f^{n-2} or u^n)
     // are loaded for kBatch points before any of them is computed
     const bool rk2 = p.stage == kStageRk2;
@@ -180,20 +211,25 @@ struct Sweep {
     const Real* pre_a = static_cast<const Real*>(
         rk2 ? p.ubuf[n & 1] : (ab3 ? p.fbuf[(n - 1) & 1] : p.fbuf[0]));
     const Real* pre_b = static_cast<const Real*>(p.fbuf[n & 1]);
-    for (int i0 = tid; i0 < np; i0 += kBatch * nt) {
+    set_publish_plane(z);
+    PlaneIter it(tid, nt, bx);
+    while (it.y < by) {
       Real pa[kBatch], pb[kBatch];
+      int px[kBatch], py[kBatch];
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
-        const int i = min(i0 + k * nt, np - 1);
-        const int64_t g = gidx(x0 + i % bx, y0 + i / bx, gz);
+        px[k] = it.x;
+        py[k] = it.y;
+        const bool in = it.y < by;
+        const int64_t g = gbase + static_cast<int64_t>(in ? it.y : by - 1) * p.nx + (in ? it.x : bx - 1);
         pa[k] = (rk2 || ab) ? pre_a[g] : Real(0);
         pb[k] = ab3 ? pre_b[g] : Real(0);
+        it.next();
       }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
-        const int i = i0 + k * nt;
-        if (i >= np) break;
-        const int x = i % bx, y = i / bx;
+        const int x = px[k], y = py[k];
+        if (y >= by) break;
         const int ly = DIM >= 2 ? y + S : 0;
         const int c_at = ly * px_stride + x + S;
         const Real u0 = C[c_at];
@@ -237,7 +273,7 @@ struct Sweep {
           g2 += d2;
         }
         const Real f = p.equation == AT_ADVDIFF ? alpha * g2 - g1 : alpha * g2 - u0 * g1;
-        const int64_t g = gidx(x0 + x, y0 + y, gz);
+        const int64_t g = gbase + static_cast<int64_t>(y) * p.nx + x;
         Real un;
         if (p.stage == kStageRk1) {
           un = u0 + dt * f;
@@ -269,22 +305,38 @@ struct Sweep {
     }
   }
 
-  // Write a new edge value into the ring slot of its level: u^{n+1} after a
-  // full step, u*^n after the first RK2 stage.
-  __device__ void publish(int x, int y, int z, Real v) const {
+  // This PE's x and y strips of plane z in the ring slot of the new level:
+  // u^{n+1} after a full step, u*^n after the first RK2 stage (z strips are
+  // addressed in publish, for the few planes that have them).
+  Real* slot_base;
+  Real* pub[4];
+  __device__ void set_publish_plane(int z) {
+    if (p.mode == AT_SYNC) return;
     const bool rk1 = p.stage == kStageRk1;
     Real* R = static_cast<Real*>(rk1 ? p.sring : p.ring);
     const int slot = static_cast<int>((rk1 ? n : n + 1) % p.nslots);
+    slot_base = R + static_cast<int64_t>(slot) * p.npe * p.pe_block;
+#pragma unroll
+    for (int f = 0; f < (DIM >= 2 ? 4 : 2); ++f)
+      pub[f] = slot_base + p.face_off[f] + (static_cast<int64_t>(z) * p.npe + pid) * p.face_chunk[f];
+  }
+
+  // Write a new edge value into the strips (of the plane set last) it lies in.
+  __device__ void publish(int x, int y, int z, Real v) const {
     const int bx = p.bx, by = p.by, bz = p.bz;
-    if (x < S) R[ring_off(slot, pid, 0, z, y * S + x)] = v;
-    if (x >= bx - S) R[ring_off(slot, pid, 1, z, y * S + x - (bx - S))] = v;
+    if (x < S) pub[0][y * S + x] = v;
+    if (x >= bx - S) pub[1][y * S + x - (bx - S)] = v;
     if (DIM >= 2) {
-      if (y < S) R[ring_off(slot, pid, 2, z, y * bx + x)] = v;
-      if (y >= by - S) R[ring_off(slot, pid, 3, z, (y - (by - S)) * bx + x)] = v;
+      if (y < S) pub[2][y * bx + x] = v;
+      if (y >= by - S) pub[3][(y - (by - S)) * bx + x] = v;
     }
     if (DIM == 3) {
-      if (z < S) R[ring_off(slot, pid, 4, z, y * bx + x)] = v;
-      if (z >= bz - S) R[ring_off(slot, pid, 5, z - (bz - S), y * bx + x)] = v;
+      // z strips: depth plane z (low face) or z - (bz - s) (high face)
+      if (z < S)
+        slot_base[p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * p.face_chunk[4] + y * bx + x] = v;
+      if (z >= bz - S)
+        slot_base[p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * p.face_chunk[5] +
+                  y * bx + x] = v;
     }
   }
 };
@@ -328,12 +380,13 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     s_nbr[f] = neighbour(p, pid, f);
     if (p.mode != AT_SYNC) {
       const int k = face_delay(p, pid, f, n);
+      const int r0 = static_cast<int>(n % p.nslots);
       double w[kMaxT];
       level_weights(k, p.T, w);
       for (int m = 0; m < kMaxT; ++m) {
         const bool live = m < p.T && w[m] != 0.0;
         s_w[f * kMaxT + m] = live ? w[m] : 0.0;
-        s_slot[f * kMaxT + m] = live ? static_cast<int>((n - k - m) % p.nslots) : -1;
+        s_slot[f * kMaxT + m] = live ? slot_back(r0, k + m, p.nslots) : -1;
       }
     }
   };

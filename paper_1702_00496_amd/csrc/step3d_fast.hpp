@@ -192,11 +192,12 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
       // a level whose weight is zero re-reads level n-k (same lines, cache
       // hits) and is multiplied by an exact zero, so every read is issued
       // without a branch
-      const int s0 = static_cast<int>((n - k) % p.nslots);
+      const int r0 = static_cast<int>(n % p.nslots);
+      const int s0 = slot_back(r0, k, p.nslots);
       for (int m = 0; m < kMaxT; ++m) {
         const bool live = m < TT && w[m] != 0.0;
         s_w[f * kMaxT + m] = live ? w[m] : 0.0;
-        s_slot[f * kMaxT + m] = live ? static_cast<int>((n - k - m) % p.nslots) : s0;
+        s_slot[f * kMaxT + m] = live ? slot_back(r0, k + m, p.nslots) : s0;
       }
     }
   }
