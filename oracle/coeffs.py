@@ -228,3 +228,42 @@ def n_time_levels(d, a, r):
     """T = ceil((d + a) / r): successive delayed levels needed to cancel the
     asynchrony terms u^{(0,q)}, q < (d + a) / r (eq. cond with p = 0)."""
     return -(-(d + a) // r)
+
+
+# Footprints of the space-expanded single-level AT schemes (Tables
+# atschemes-left/right, rows (2,1,2), (1,2,2)a, (2,2,2)a): at the point next to
+# a face, own points at level n on one side and buffer points at the single
+# delayed level n-k on the other. Left boundary: buffer at j < 0.
+_SPACE_FOOTPRINTS = {
+    # (d, scheme): (own offsets, buffer offsets, a) for the left boundary
+    (1, "space212"): ((1, 0), (-1, -2), 2),     # (1,2,2)a
+    (1, "space222"): ((1, 0), (-1, -2), 2),     # (1,2,2)a
+    (2, "space212"): ((1, 0), (-1, -2), 1),     # (2,1,2)
+    (2, "space222"): ((2, 1, 0), (-1, -2, -3), 2),   # (2,2,2)a
+}
+
+
+def space_expanded_at_stencil(d, scheme, side):
+    """Coefficients of a space-expanded AT scheme at the point next to a face.
+
+    Solves eq. cond (Sec. 3.1, r = 2) exactly for the scheme's footprint with
+    the buffer points at delay k. The solution does not depend on k >= 1 (the
+    rows with q > 0 scale by powers of k), and the paper uses the same
+    coefficients for every k, k = 0 included (Sec. 5.1: these schemes do not
+    reduce to the central difference at k = 0). Returns {(j, 'k' or 0): c}
+    with 'k' marking buffer points; side 'right' mirrors the footprint.
+    """
+    own, buf, a = _SPACE_FOOTPRINTS[(d, scheme)]
+    sgn = 1 if side == "left" else -1
+    sols = []
+    for k in (1, 2, 3):
+        st = [(sgn * j, 0) for j in own] + [(sgn * j, k) for j in buf]
+        status, c = derive_scheme(st, d, a, 2)
+        if status != "unique":
+            raise ValueError(f"space-expanded d={d} {scheme}: {status}")
+        sols.append([c[x] for x in st])
+    if sols[0] != sols[1] or sols[0] != sols[2]:
+        raise ValueError("space-expanded coefficients depend on k")
+    keys = [(sgn * j, 0) for j in own] + [(sgn * j, "k") for j in buf]
+    return dict(zip(keys, sols[0]))
+

@@ -21,6 +21,17 @@ What one step n -> n+1 computes:
    scheme of eq. general_deriv_async.
    Multi-dimensional problems apply this per axis with that axis' face delay
    (no mixed derivatives occur).
+   Space-expanded single-level family (Tables atschemes-left/right, rows
+   (2,1,2), (1,2,2)a, (2,2,2)a; Sec. 5.1 Cases 2 and 3), second-order CD
+   only: the point next to a face whose delay k is positive takes an
+   asymmetric stencil over own points at level n and 2 or 3 buffer points at
+   the one level n-k (oracle.coeffs.space_expanded_at_stencil). Reading:
+   these stencils are not the CD at k = 0 (Sec. 5.1 says so) and are used at
+   "communication delayed" buffer points (caption of the convergence figure
+   of Cases 2-5), so a face with k = 0 keeps the standard CD2; the paper's
+   delay-free curve then has the synchronous slope -2, as it reports.
+   Scheme "space212": first derivative (1,2,2)a, second (2,1,2);
+   "space222": (1,2,2)a and (2,2,2)a.
 3. Right-hand side (Sec. 5 eq. general): advection-diffusion
    f = -c . grad u + alpha lap u, viscous Burgers f = -u (sum_d du/dx_d) +
    alpha lap u.
@@ -103,8 +114,11 @@ class DelayModel:
     seed: int = 0
     weights: Optional[Sequence[int]] = None   # integer bin weights, None = uniform
     host: Optional[object] = None      # int array [nsteps, n_pe, ndim, 2] for mode "host"
+    scheme: str = "time"               # "time" | "space212" | "space222"
 
     def levels(self, order):
+        if self.scheme != "time":
+            return 1
         return self.T if self.T > 0 else order // 2 + 1
 
 
@@ -154,6 +168,19 @@ class Oracle:
         # c_m(k) for every delay value
         self.wtab = {k: [_fr(c) for c in coeffs.time_level_weights(k, self.T)]
                      for k in range(0, max(dm.L, 1))}
+        # space-expanded family: boundary stencils per derivative and side
+        self.space = None
+        if dm.scheme != "time":
+            if dm.scheme not in ("space212", "space222"):
+                raise ValueError(f"unknown scheme {dm.scheme}")
+            if prob.order != 2:
+                raise ValueError("the space-expanded schemes extend the second-order CD")
+            depth = 3 if dm.scheme == "space222" else 2
+            if any(prob.b[a] < depth for a in range(prob.ndim)):
+                raise ValueError(f"{dm.scheme} needs PE edges of at least {depth} points")
+            self.space = {(d, side): {key: _fr(c) for key, c in
+                                      coeffs.space_expanded_at_stencil(d, dm.scheme, side).items()}
+                          for d in (1, 2) for side in ("left", "right")}
         u0 = torch.as_tensor(u0, dtype=torch.float64)
         if tuple(u0.shape) != prob.shape:
             raise ValueError(f"u0 shape {tuple(u0.shape)} != {prob.shape}")
@@ -189,6 +216,8 @@ class Oracle:
 
         ``centre`` is the field at level n; ``hist`` holds the past levels of
         the same quantity (default: the solution history)."""
+        if self.space is not None and self.dm.mode != "sync":
+            return self._space_axis_derivative(centre, K, axis, 1 if taps is self.taps1 else 2, hist)
         prob = self.prob
         hist = self.hist if hist is None else hist
         dim = 2 - axis
@@ -224,6 +253,36 @@ class Oracle:
                         val = val + w[m] * st
                     acc = torch.where(mask, val, acc)
                 D = D.index_copy(dim, idx, acc)
+        return D
+
+    def _space_axis_derivative(self, centre, K, axis, d, hist=None):
+        """Space-expanded family: CD2 everywhere, the face-adjacent points
+        (ell = 0 and ell = b - 1) of a face with delay k > 0 replaced by the
+        asymmetric single-level stencil with buffer points at level n - k."""
+        prob = self.prob
+        hist = self.hist if hist is None else hist
+        taps = self.taps1 if d == 1 else self.taps2
+        dim = 2 - axis
+        N = prob.n[axis]
+        b = prob.b[axis]
+        D = torch.zeros_like(centre)
+        for o in (-1, 0, 1):
+            D = D + taps[o + 1] * torch.roll(centre, shifts=-o, dims=dim)
+        for side, ell, name in ((0, 0, "left"), (1, b - 1, "right")):
+            Kslab = self._slab_delays(K, axis, side)
+            idx = torch.arange(prob.pe[axis]) * b + ell
+            acc = D.index_select(dim, idx)          # k = 0: the standard CD2
+            for kd in range(1, self.dm.L):
+                mask = Kslab == kd
+                if not bool(mask.any()):
+                    continue
+                older = self.level(hist, self.n - kd)
+                val = torch.zeros_like(acc)
+                for (j, lev), c in self.space[(d, name)].items():
+                    src = older if lev == "k" else centre
+                    val = val + c * src.index_select(dim, (idx + j) % N)
+                acc = torch.where(mask, val, acc)
+            D = D.index_copy(dim, idx, acc)
         return D
 
     def rhs(self, centre, K, hist=None):
