@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -226,6 +226,61 @@ def time_burgers():
                          "200 steps, FP32 bulk / FP64 AT combination", arms=res)
 
 
+def time_space():
+    """The space-expanded single-level schemes against the time-expanded one on
+    a 3-D grid: 256^3, 8^3 PEs of 32^3, second-order CD, advection-diffusion,
+    Euler, L = 3 with p = {0.5, 0.3, 0.2} (the delay law of Sec. 5.1 Cases
+    2 and 3), FP32 bulk, 100 steps. Bytes per update (solution in place): u
+    read and written, halo reads h (p0 + (1 - p0) D) and the publish h D, with
+    h = 2 * 3 / 32 face columns per point and D buffer points per column: 3
+    for (1,2,2)a + (2,2,2)a, 2 for (1,2,2)a + (2,1,2); the time-expanded
+    (1,2,2)b + (2,2,2)b reads h (p0 + 2 (1 - p0)) values of its two levels and
+    publishes h."""
+    cfg3 = W.config_3d_advdiff(n=256, b=32)
+    n3 = cfg3["n"]
+    alpha = 0.1
+    dx = 2 * math.pi / n3[0]
+    dt = 0.05 * dx * dx / alpha
+    steps = 100
+    u3 = torch.from_numpy(W.eval_modes(cfg3["modes"], n3, 3))
+    p0 = 0.5
+    h = 2 * 3 / 32
+    res = {}
+    for scheme, depth in (("space222", 3), ("space212", 2), ("time", None)):
+        s = Solver(ndim=3, n=n3, pe=cfg3["pe"], dt=dt, order=2, c=(1.0, 1.0, 1.0), alpha=alpha,
+                   integrator="euler", precision="f32", L=3, weights=[5, 3, 2], seed=cfg3["seed"], scheme=scheme)
+        s.set_state(u3)
+        s.step(5)
+        s.set_graph(20)
+        s.set_state(u3)
+        s.step(20)
+        s.set_state(u3)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nrm = s.norms(modes=cfg3["modes"])
+        if depth is None:
+            bpu = 4 * (2 + h * (p0 + (1 - p0) * 2) + h)
+        else:
+            bpu = 4 * (2 + h * (p0 + (1 - p0) * depth) + h * depth)
+        ups = n3[0] ** 3 * steps / (ms / 1e3)
+        res[scheme] = dict(ms_per_step=ms / steps, updates_per_s=ups, bytes_per_update=bpu,
+                           achieved_gbs=ups * bpu / 1e9, frac=ups * bpu / 1e9 / HBM_PEAK_GBS,
+                           l2_error=nrm["l2"], l2_error_boundary=nrm["l2_b"], l2_error_interior=nrm["l2_i"])
+        print(f"[bench] space-expanded {scheme}: {ms / steps:.4f} ms/step {ups:.3e} upd/s l2={nrm['l2']:.3e}",
+              file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return dict(workload="3-D advection-diffusion 256^3, 8^3 PEs of 32^3, 2nd-order CD, Euler, L=3 with "
+                         "p={0.5,0.3,0.2}, 100 FP32 steps: space-expanded (1,2,2)a+(2,2,2)a and (1,2,2)a+(2,1,2) "
+                         "against time-expanded (1,2,2)b+(2,2,2)b", arms=res)
+
+
 def time_ensemble():
     """512 independent 1-D members (N log-uniform in [1024, 65536], PE 64,
     orders 2/4, L in {2, 4, 8}), 2000 steps in one persistent launch, FP32."""
@@ -335,7 +390,8 @@ if "f32" in arms and "sync32" in arms:
                           "error_ratio": a["l2_error"] / b["l2_error"]}
 others = {}
 for w in [x for x in args.others.split(",") if x]:
-    others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint}[w]()
+    others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
+                 "space": time_space}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:

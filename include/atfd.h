@@ -72,6 +72,20 @@ enum { AT_F64 = 0, AT_F32_F64B = 1 };
  * traffic; the comparison arm "standard scheme"). */
 enum { AT_DELAY_RNG = 0, AT_DELAY_ZERO = 1, AT_DELAY_HOST = 2, AT_SYNC = 3 };
 
+/* AT family at the points next to a PE face (Tables atschemes-left/right).
+ * TIME: the time-expanded schemes, a combination of T delayed levels of the
+ * central difference (rows (1,2,2)b, (2,2,2)b, (1,4,2), (2,4,2), (2,6,2) and
+ * their order-6 first-derivative sibling); with k = 0 they are the CD.
+ * SPACE_212, SPACE_222: the space-expanded single-level schemes of the
+ * second-order CD (Sec. 5.1 Cases 2 and 3): one delayed level n-k of 2 or 3
+ * buffer points; first derivative (1,2,2)a, second derivative (2,1,2) or
+ * (2,2,2)a. They are not the CD at k = 0, and a face whose delay is 0 keeps
+ * the CD (they act at communication-delayed buffer points). The printed
+ * left-boundary (1,2,2)a carries a sign slip (its coefficients do not sum to
+ * zero); the library uses the mirror image of the right-boundary row, which
+ * is what the order conditions (Sec. 3.1 eq. cond) give. */
+enum { AT_SCHEME_TIME = 0, AT_SCHEME_SPACE_212 = 1, AT_SCHEME_SPACE_222 = 2 };
+
 typedef struct at_problem {
   int32_t ndim;        /* 1, 2 or 3                                              */
   int32_t pe[3];       /* PEs per axis (x, y, z); unused axes 1                  */
@@ -103,7 +117,10 @@ typedef struct at_delay {
   int32_t T;                 /* time levels in the AT combination; 0 = order/2+1;
                                 1 = standard scheme fed with delayed halos     */
   int32_t mode;              /* AT_DELAY_RNG | AT_DELAY_ZERO | AT_DELAY_HOST | AT_SYNC */
-  int32_t reserved;
+  int32_t scheme;            /* AT_SCHEME_TIME | AT_SCHEME_SPACE_212 | AT_SCHEME_SPACE_222;
+                                the space schemes need order 2, T = 0 or 1
+                                (one level), PE edges >= 2 (212) or >= 3 (222),
+                                and are not covered by at_adjoint            */
   uint64_t seed;             /* generator key                                   */
   const uint32_t* weights;   /* host, L integer bin weights (p_j ~ weights[j]);
                                 NULL = uniform                                  */
@@ -199,7 +216,8 @@ const char* at_last_error(const at_ctx* ctx);
 
 /* ------------------------------------------------------------------------
  * Discrete adjoint of the AT step (advection-diffusion or viscous Burgers;
- * Euler, AB2 or Heun RK2; every delay mode; AB3 is not covered). This is not
+ * Euler, AB2 or Heun RK2; every delay mode of the time-expanded schemes; AB3
+ * and the space-expanded schemes are not covered: AT_EINVAL). This is not
  * in the paper: it is the exact transpose of the linearised discrete map that
  * at_step applies, so that gradients of a function J(u^N) of the field after
  * N steps can be taken with respect to the initial field and the diffusivity

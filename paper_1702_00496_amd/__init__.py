@@ -37,7 +37,7 @@ class Solver:
 
     def __init__(self, ndim, n, pe, dt, order=2, equation="advdiff", c=(0.0, 0.0, 0.0), alpha=0.0,
                  integrator="euler", precision="f64", length=2.0 * math.pi, L=1, T=0, mode="rng",
-                 seed=0, weights=None, host_delays=None, device="cuda"):
+                 seed=0, weights=None, host_delays=None, device="cuda", scheme="time"):
         L_ = _lib.load()
         n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
         pe = tuple(int(v) for v in pe) + (1,) * (3 - len(pe))
@@ -63,6 +63,7 @@ class Solver:
         dl.L = L
         dl.T = T
         dl.mode = _lib.MODES[mode]
+        dl.scheme = _lib.SCHEMES[scheme]
         dl.seed = seed
         self._keep = []
         if weights is not None:

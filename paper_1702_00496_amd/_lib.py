@@ -16,6 +16,7 @@ EQUATIONS = {"advdiff": 0, "burgers": 1}
 INTEGRATORS = {"euler": 0, "ab2": 1, "ab3": 2, "rk2": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
 MODES = {"rng": 0, "zero": 1, "host": 2, "sync": 3}
+SCHEMES = {"time": 0, "space212": 1, "space222": 2}
 
 
 class AtProblem(ctypes.Structure):
@@ -39,7 +40,7 @@ class AtDelay(ctypes.Structure):
         ("L", ctypes.c_int32),
         ("T", ctypes.c_int32),
         ("mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("weights", ctypes.POINTER(ctypes.c_uint32)),
         ("host_delays", ctypes.POINTER(ctypes.c_int8)),

@@ -44,6 +44,7 @@ constexpr int64_t kDelayScratch = 1 << 16;   // bytes for at_get_delays chunks
 
 struct Geometry {
   int ndim, s, T;
+  int scheme, sd;     // AT family and face-strip depth (s, or 2 / 3 for the space-expanded schemes)
   int64_t n[3];
   int pe[3], b[3];
   int64_t npts;
@@ -105,7 +106,15 @@ at_status validate(const at_problem* p, const at_delay* d, Geometry* g) {
   if (d->mode < AT_DELAY_RNG || d->mode > AT_SYNC) return fail(nullptr, AT_EINVAL, "unknown delay mode");
   g->ndim = p->ndim;
   g->s = p->order / 2;
-  g->T = d->T == 0 ? p->order / 2 + 1 : d->T;
+  if (d->scheme < AT_SCHEME_TIME || d->scheme > AT_SCHEME_SPACE_222)
+    return fail(nullptr, AT_EINVAL, "unknown AT scheme");
+  g->scheme = d->scheme;
+  if (d->scheme != AT_SCHEME_TIME) {
+    if (p->order != 2) return fail(nullptr, AT_EINVAL, "the space-expanded schemes need order 2");
+    if (d->T != 0 && d->T != 1) return fail(nullptr, AT_EINVAL, "the space-expanded schemes use one level (T = 1)");
+  }
+  g->T = d->scheme != AT_SCHEME_TIME ? 1 : d->T == 0 ? p->order / 2 + 1 : d->T;
+  g->sd = d->scheme == AT_SCHEME_SPACE_212 ? 2 : d->scheme == AT_SCHEME_SPACE_222 ? 3 : g->s;
   g->f64 = p->precision == AT_F64;
   if (d->mode != AT_SYNC) {
     if (d->L < 1 || d->L > kMaxL) return fail(nullptr, AT_EINVAL, "L must be 1..%d", kMaxL);
@@ -126,6 +135,8 @@ at_status validate(const at_problem* p, const at_delay* d, Geometry* g) {
     g->b[a] = static_cast<int>(p->n[a] / p->pe[a]);
     if (a < p->ndim && g->b[a] < 2 * g->s)
       return fail(nullptr, AT_EINVAL, "axis %d: PE edge %d < 2s = %d", a, g->b[a], 2 * g->s);
+    if (a < p->ndim && g->b[a] < g->sd)
+      return fail(nullptr, AT_EINVAL, "axis %d: PE edge %d below the strip depth %d", a, g->b[a], g->sd);
     g->npts *= p->n[a];
     g->npe *= p->pe[a];
   }
@@ -167,11 +178,12 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
   for (int i = 0; i < l.nfbuf; ++i) l.off_f[i] = take(l.field_bytes);
   l.star = p->integrator == AT_RK2;
   if (l.star) l.off_ustar = take(l.field_bytes);
-  // face strips: faces 2a, 2a+1 of a PE hold s * (product of the other
-  // edges) values, as planes of face_chunk values (x, y faces: one plane per
-  // z-plane; z faces: one per depth); a slot stores every face's planes of
-  // all PEs side by side (ring_index)
-  const int s = g.s;
+  // face strips: faces 2a, 2a+1 of a PE hold sd * (product of the other
+  // edges) values (sd = s, or the 2 or 3 buffer points of the
+  // space-expanded stencils), as planes of face_chunk values (x, y faces:
+  // one plane per z-plane; z faces: one per depth); a slot stores every
+  // face's planes of all PEs side by side (ring_index)
+  const int s = g.sd;
   int64_t fo = 0, pe_block = 0;
   for (int a = 0; a < 3; ++a) {
     int64_t area = 1;
@@ -215,6 +227,8 @@ void fill_params(at_ctx* c) {
   p.ndim = g.ndim;
   p.npe = g.npe;
   p.s = g.s;
+  p.scheme = g.scheme;
+  p.sd = g.sd;
   for (int a = 0; a < 3; ++a) {
     double t1[2 * kMaxS + 1] = {0}, t2[2 * kMaxS + 1] = {0};
     cd_taps(1, c->prob.order, t1);
@@ -229,6 +243,15 @@ void fill_params(at_ctx* c) {
       p.c1f[a][o] = static_cast<float>(p.c1[a][o]);
       p.d2af[a][o] = static_cast<float>(p.d2a[a][o]);
       p.kadf[a][o] = static_cast<float>(p.kad[a][o]);
+    }
+    double l1[2 * kMaxS + 1] = {0}, l2[2 * kMaxS + 1] = {0};
+    if (g.scheme != AT_SCHEME_TIME) {
+      space_taps(1, g.scheme, l1);
+      space_taps(2, g.scheme, l2);
+    }
+    for (int o = 0; o <= 2 * kMaxS; ++o) {
+      p.sl1[a][o] = l1[o] / dx;
+      p.sl2[a][o] = l2[o] / (dx * dx);
     }
   }
   p.depth = fast3d_default_depth(g.f64);
@@ -358,7 +381,7 @@ at_status at_set_state(at_ctx* c, const void* u0_dev) {
   if (!c || !u0_dev) return fail(c, AT_EINVAL, "null argument");
   HIP_TRY(c, hipMemcpyAsync(c->sp.ubuf[0], u0_dev, c->lay.field_bytes, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, launch_set_counter(c->sp.counter, 0, c->stream));
-  if (c->delay.mode != AT_SYNC) HIP_TRY(c, launch_publish_all(c->sp, c->g.f64, c->g.s, c->stream));
+  if (c->delay.mode != AT_SYNC) HIP_TRY(c, launch_publish_all(c->sp, c->g.f64, c->g.sd, c->stream));
   c->n = 0;
   c->state_set = true;
   return AT_OK;
@@ -667,6 +690,8 @@ at_status adj_check(at_ctx* c, int64_t nsteps, int32_t every) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
   if (nsteps < 1 || every < 1) return fail(c, AT_EINVAL, "nsteps and the checkpoint interval must be >= 1");
   if (c->prob.integrator == AT_AB3) return fail(c, AT_EINVAL, "the adjoint covers Euler, AB2 and RK2");
+  if (c->delay.scheme != AT_SCHEME_TIME)
+    return fail(c, AT_EINVAL, "the adjoint covers the time-expanded schemes");
   if (c->delay.mode == AT_DELAY_HOST && nsteps > c->delay.host_nsteps)
     return fail(c, AT_EINVAL, "host delay table covers %lld steps", (long long)c->delay.host_nsteps);
   if (c->g.npts >= (int64_t(1) << 31) || c->g.npe * c->lay.pe_block >= (int64_t(1) << 31))

@@ -109,6 +109,12 @@ struct StepParams {
   int ndim;
   int npe;
   int s;                       // stencil half-width (order / 2)
+  int scheme;                  // AT_SCHEME_TIME | AT_SCHEME_SPACE_212 | AT_SCHEME_SPACE_222
+  int sd;                      // depth of the face strips (s; 2 or 3 for the space-expanded schemes)
+  // space-expanded schemes: taps of the point next to a low face, o = -3..3,
+  // / dx and / dx^2 per axis (first derivative (1,2,2)a, second (2,1,2) or
+  // (2,2,2)a); the high-face taps are the mirror images
+  double sl1[3][2 * kMaxS + 1], sl2[3][2 * kMaxS + 1];
   // scheme
   double c1[3][2 * kMaxS + 1]; // first-derivative taps / dx (per axis)
   double c2[3][2 * kMaxS + 1]; // second-derivative taps / dx^2

@@ -46,4 +46,23 @@ inline bool cd_taps(int d, int order, double* t) {
   return true;
 }
 
+// Taps of the space-expanded single-level schemes at the point next to a low
+// face, o = -3..3 (Tables atschemes-left/right; the right-boundary rows are
+// the mirror images): first derivative (1,2,2)a, second derivative (2,1,2)
+// (scheme 1) or (2,2,2)a (scheme 2). Offsets o < 0 are the buffer points at
+// the delayed level. The printed left (1,2,2)a row has -U_{i-1} where the
+// order conditions, and the mirror of the right row, give +U_{i-1}.
+inline bool space_taps(int d, int scheme, double* t) {
+  static const double d1_122a[7] = {0.0, -0.25, 0.25, -0.75, 0.75, 0.0, 0.0};
+  static const double d2_212[7] = {0.0, 0.5, -0.5, -0.5, 0.5, 0.0, 0.0};
+  static const double d2_222a[7] = {1.0 / 3, -2.0 / 3, 1.0 / 3, 2.0 / 3, -4.0 / 3, 2.0 / 3, 0.0};
+  const double* src = nullptr;
+  if (d == 1 && (scheme == 1 || scheme == 2)) src = d1_122a;
+  if (d == 2 && scheme == 1) src = d2_212;
+  if (d == 2 && scheme == 2) src = d2_222a;
+  if (!src) return false;
+  for (int i = 0; i < 7; ++i) t[i] = src[i];
+  return true;
+}
+
 }  // namespace atfd

@@ -34,9 +34,20 @@ __device__ inline int slot_of(int zz) {
 // Parts of an LDS plane: the PE's own values and the x/y halo frame.
 constexpr int kPlaneCentre = 1, kPlaneHalos = 2;
 
-template <typename Real, int DIM, int S>
+// SP: 0 = time-expanded AT (or the standard scheme); 1, 2 = the
+// space-expanded single-level schemes with the second derivative (2,1,2) or
+// (2,2,2)a and the first (1,2,2)a (second-order CD only). SD = depth of the
+// face strips and of the LDS halo frame: s, or the 2 or 3 buffer points the
+// space-expanded stencils reach.
+template <int S, int SP>
+constexpr int strip_depth() {
+  return SP == 0 ? S : SP == 1 ? 2 : 3;
+}
+
+template <typename Real, int DIM, int S, int SP>
 struct Sweep {
-  static constexpr int NSL = DIM == 3 ? 2 * S + 2 : 1;
+  static constexpr int SD = strip_depth<S, SP>();
+  static constexpr int NSL = DIM == 3 ? 2 * SD + 2 : 1;
   static constexpr int kBatch = 4;   // points per thread whose loads are issued together
 
   const StepParams& p;
@@ -50,10 +61,11 @@ struct Sweep {
   const double* w;          // [6][kMaxT]
   const int* lev_slot;      // [6][kMaxT] ring slot of level n-k-m, -1 if weight 0
   const int* nbr;           // [6] neighbour PE of face
+  const int* kpos;          // [6] face delay k > 0 (space-expanded stencils apply)
 
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
-                   const int* ls_, const int* nb_)
-      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_) {
+                   const int* ls_, const int* nb_, const int* kp_)
+      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_) {
     pid = blockIdx.x;
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
@@ -61,8 +73,8 @@ struct Sweep {
     x0 = qx * p.bx;
     y0 = qy * p.by;
     z0 = qz * p.bz;
-    px_stride = p.bx + 2 * S;
-    plane = (DIM >= 2 ? p.by + 2 * S : 1) * px_stride;
+    px_stride = p.bx + 2 * SD;
+    plane = (DIM >= 2 ? p.by + 2 * SD : 1) * px_stride;
     const bool rk2 = p.stage == kStageRk2;
     centre = static_cast<const Real*>(rk2 ? p.ustar : p.ubuf[n & 1]);
     ring_rd = static_cast<const Real*>(rk2 ? p.sring : p.ring);
@@ -132,7 +144,7 @@ struct Sweep {
   };
 
   __device__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
-    Real* P = lds + slot_of<DIM, S>(zz) * plane;
+    Real* P = lds + slot_of<DIM, SD>(zz) * plane;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
     if (zz >= 0 && zz < bz) {
@@ -149,7 +161,7 @@ struct Sweep {
           for (int k = 0; k < kBatch; ++k) {
             const bool in = it.y < by;
             v[k] = cz[static_cast<int64_t>(in ? it.y : by - 1) * p.nx + (in ? it.x : bx - 1)];
-            at[k] = in ? (DIM >= 2 ? it.y + S : 0) * px_stride + it.x + S : -1;
+            at[k] = in ? (DIM >= 2 ? it.y + SD : 0) * px_stride + it.x + SD : -1;
             it.next();
           }
 #pragma unroll
@@ -159,29 +171,29 @@ struct Sweep {
       }
       // x halos (producer strip [z][y][d]) and y halos (producer strip
       // [z][d][x]) in one pass, so that their loads overlap
-      const int nxh = 2 * S * by, nh = (parts & kPlaneHalos) ? nxh + (DIM >= 2 ? 2 * S * bx : 0) : 0;
+      const int nxh = 2 * SD * by, nh = (parts & kPlaneHalos) ? nxh + (DIM >= 2 ? 2 * SD * bx : 0) : 0;
       for (int h = tid; h < nh; h += nt) {
         if (h < nxh) {
-          const int side = h / (S * by), r = h % (S * by), d = r % S, y = r / S;
-          const int xl = side ? bx + d : d - S;
+          const int side = h / (SD * by), r = h % (SD * by), d = r % SD, y = r / SD;
+          const int xl = side ? bx + d : d - SD;
           const int gx = (x0 + xl + p.nx) % p.nx;
-          P[(DIM >= 2 ? y + S : 0) * px_stride + xl + S] = halo(side, zz, y * S + d, gx, y0 + y, gz);
+          P[(DIM >= 2 ? y + SD : 0) * px_stride + xl + SD] = halo(side, zz, y * SD + d, gx, y0 + y, gz);
         } else {
           const int hy = h - nxh;
-          const int side = hy / (S * bx), r = hy % (S * bx), d = r / bx, x = r % bx;
-          const int yl = side ? by + d : d - S;
+          const int side = hy / (SD * bx), r = hy % (SD * bx), d = r / bx, x = r % bx;
+          const int yl = side ? by + d : d - SD;
           const int gy = (y0 + yl + p.ny) % p.ny;
-          P[(yl + S) * px_stride + x + S] = halo(2 + side, zz, d * bx + x, x0 + x, gy, gz);
+          P[(yl + SD) * px_stride + x + SD] = halo(2 + side, zz, d * bx + x, x0 + x, gy, gz);
         }
       }
     } else {
       // z halo plane: producer strip [d][y][x]
       const int side = zz < 0 ? 0 : 1;
-      const int d = side ? zz - bz : zz + S;
+      const int d = side ? zz - bz : zz + SD;
       const int gz = (z0 + zz + p.nz) % p.nz;
       for (int i = tid; i < bx * by; i += nt) {
         const int x = i % bx, y = i / bx;
-        P[(y + S) * px_stride + x + S] = halo(4 + side, d, y * bx + x, x0 + x, y0 + y, gz);
+        P[(y + SD) * px_stride + x + SD] = halo(4 + side, d, y * bx + x, x0 + x, y0 + y, gz);
       }
     }
   }
@@ -189,7 +201,7 @@ struct Sweep {
   __device__ void compute_plane(int z) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
-    const Real* C = lds + slot_of<DIM, S>(z) * plane;
+    const Real* C = lds + slot_of<DIM, SD>(z) * plane;
     Real c1[3][2 * S + 1], c2[3][2 * S + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -197,6 +209,16 @@ struct Sweep {
       for (int o = 0; o <= 2 * S; ++o) {
         c1[a][o] = static_cast<Real>(p.c1[a][o]);
         c2[a][o] = static_cast<Real>(p.c2[a][o]);
+      }
+    // space-expanded schemes: taps at a point next to a low face (o = -SD..SD);
+    // the high-face stencils are their mirror images
+    Real l1[3][2 * SD + 1], l2[3][2 * SD + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = -SD; o <= SD; ++o) {
+        l1[a][o + SD] = SP != 0 ? static_cast<Real>(p.sl1[a][o + kMaxS]) : Real(0);
+        l2[a][o + SD] = SP != 0 ? static_cast<Real>(p.sl2[a][o + kMaxS]) : Real(0);
       }
     const Real dt = static_cast<Real>(p.dt), alpha = static_cast<Real>(p.alpha);
     const Real vx = static_cast<Real>(p.vel[0]), vy = static_cast<Real>(p.vel[1]),
@@ -230,47 +252,76 @@ struct Sweep {
       for (int k = 0; k < kBatch; ++k) {
         const int x = px[k], y = py[k];
         if (y >= by) break;
-        const int ly = DIM >= 2 ? y + S : 0;
-        const int c_at = ly * px_stride + x + S;
+        const int ly = DIM >= 2 ? y + SD : 0;
+        const int c_at = ly * px_stride + x + SD;
         const Real u0 = C[c_at];
         // difference form: the taps of each derivative sum to zero, so each
         // neighbour enters as (v - u0), which keeps float rounding small
         Real g1 = 0, g2 = 0;
-        {
-          Real d1 = 0, d2 = 0;
+        if constexpr (SP != 0) {
+          // per axis: the standard taps, or at the point next to a face whose
+          // delay is positive the space-expanded stencil over the own points
+          // and the 2 or 3 buffer points of level n - k in the halo frame
+          const Real vel[3] = {vx, vy, vz};
+          const bool at_lo[3] = {x == 0, y == 0, z == 0};
+          const bool at_hi[3] = {x == bx - 1, y == by - 1, z == bz - 1};
 #pragma unroll
-          for (int o = -S; o <= S; ++o) {
-            if (o == 0) continue;
-            const Real v = C[c_at + o] - u0;
-            d1 += c1[0][o + S] * v;
-            d2 += c2[0][o + S] * v;
-          }
-          g1 = p.equation == AT_ADVDIFF ? vx * d1 : d1;
-          g2 = d2;
-        }
-        if (DIM >= 2) {
-          Real d1 = 0, d2 = 0;
+          for (int a = 0; a < DIM; ++a) {
+            const bool lo = at_lo[a] && kpos[2 * a] != 0, hi = at_hi[a] && kpos[2 * a + 1] != 0;
+            Real d1 = 0, d2 = 0;
 #pragma unroll
-          for (int o = -S; o <= S; ++o) {
-            if (o == 0) continue;
-            const Real v = C[c_at + o * px_stride] - u0;
-            d1 += c1[1][o + S] * v;
-            d2 += c2[1][o + S] * v;
+            for (int o = -SD; o <= SD; ++o) {
+              if (o == 0) continue;
+              const Real nv = a == 0 ? C[c_at + o] : a == 1 ? C[c_at + o * px_stride]
+                                                     : lds[slot_of<DIM, SD>(z + o) * plane + c_at];
+              const Real v = nv - u0;
+              const Real s1 = (o >= -S && o <= S) ? c1[a][o + S] : Real(0);
+              const Real s2 = (o >= -S && o <= S) ? c2[a][o + S] : Real(0);
+              const Real t1 = lo ? l1[a][o + SD] : hi ? -l1[a][SD - o] : s1;
+              const Real t2 = lo ? l2[a][o + SD] : hi ? l2[a][SD - o] : s2;
+              d1 += t1 * v;
+              d2 += t2 * v;
+            }
+            g1 += p.equation == AT_ADVDIFF ? vel[a] * d1 : d1;
+            g2 += d2;
           }
-          g1 += p.equation == AT_ADVDIFF ? vy * d1 : d1;
-          g2 += d2;
-        }
-        if (DIM == 3) {
-          Real d1 = 0, d2 = 0;
+        } else {
+          {
+            Real d1 = 0, d2 = 0;
 #pragma unroll
-          for (int o = -S; o <= S; ++o) {
-            if (o == 0) continue;
-            const Real v = lds[slot_of<DIM, S>(z + o) * plane + c_at] - u0;
-            d1 += c1[2][o + S] * v;
-            d2 += c2[2][o + S] * v;
+            for (int o = -S; o <= S; ++o) {
+              if (o == 0) continue;
+              const Real v = C[c_at + o] - u0;
+              d1 += c1[0][o + S] * v;
+              d2 += c2[0][o + S] * v;
+            }
+            g1 = p.equation == AT_ADVDIFF ? vx * d1 : d1;
+            g2 = d2;
           }
-          g1 += p.equation == AT_ADVDIFF ? vz * d1 : d1;
-          g2 += d2;
+          if (DIM >= 2) {
+            Real d1 = 0, d2 = 0;
+#pragma unroll
+            for (int o = -S; o <= S; ++o) {
+              if (o == 0) continue;
+              const Real v = C[c_at + o * px_stride] - u0;
+              d1 += c1[1][o + S] * v;
+              d2 += c2[1][o + S] * v;
+            }
+            g1 += p.equation == AT_ADVDIFF ? vy * d1 : d1;
+            g2 += d2;
+          }
+          if (DIM == 3) {
+            Real d1 = 0, d2 = 0;
+#pragma unroll
+            for (int o = -S; o <= S; ++o) {
+              if (o == 0) continue;
+              const Real v = lds[slot_of<DIM, SD>(z + o) * plane + c_at] - u0;
+              d1 += c1[2][o + S] * v;
+              d2 += c2[2][o + S] * v;
+            }
+            g1 += p.equation == AT_ADVDIFF ? vz * d1 : d1;
+            g2 += d2;
+          }
         }
         const Real f = p.equation == AT_ADVDIFF ? alpha * g2 - g1 : alpha * g2 - u0 * g1;
         const int64_t g = gbase + static_cast<int64_t>(y) * p.nx + x;
@@ -324,18 +375,18 @@ struct Sweep {
   // Write a new edge value into the strips (of the plane set last) it lies in.
   __device__ void publish(int x, int y, int z, Real v) const {
     const int bx = p.bx, by = p.by, bz = p.bz;
-    if (x < S) pub[0][y * S + x] = v;
-    if (x >= bx - S) pub[1][y * S + x - (bx - S)] = v;
+    if (x < SD) pub[0][y * SD + x] = v;
+    if (x >= bx - SD) pub[1][y * SD + x - (bx - SD)] = v;
     if (DIM >= 2) {
-      if (y < S) pub[2][y * bx + x] = v;
-      if (y >= by - S) pub[3][(y - (by - S)) * bx + x] = v;
+      if (y < SD) pub[2][y * bx + x] = v;
+      if (y >= by - SD) pub[3][(y - (by - SD)) * bx + x] = v;
     }
     if (DIM == 3) {
       // z strips: depth plane z (low face) or z - (bz - s) (high face)
-      if (z < S)
+      if (z < SD)
         slot_base[p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * p.face_chunk[4] + y * bx + x] = v;
-      if (z >= bz - S)
-        slot_base[p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * p.face_chunk[5] +
+      if (z >= bz - SD)
+        slot_base[p.face_off[5] + (static_cast<int64_t>(z - (bz - SD)) * p.npe + pid) * p.face_chunk[5] +
                   y * bx + x] = v;
     }
   }
@@ -362,13 +413,15 @@ __device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n)
   return clamp_startup(k, n, p.T);
 }
 
-template <typename Real, int DIM, int S>
+template <typename Real, int DIM, int S, int SP>
 __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p) {
+  constexpr int SD = strip_depth<S, SP>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
   __shared__ double s_w[6 * kMaxT];
   __shared__ int s_slot[6 * kMaxT];
   __shared__ int s_nbr[6];
+  __shared__ int s_kpos[6];
 
   const int64_t n = p.counter[0];
   const int pid = blockIdx.x;
@@ -378,8 +431,10 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     if (tid >= 2 * DIM) return;
     const int f = tid;
     s_nbr[f] = neighbour(p, pid, f);
+    s_kpos[f] = 0;
     if (p.mode != AT_SYNC) {
       const int k = face_delay(p, pid, f, n);
+      s_kpos[f] = k > 0;
       const int r0 = static_cast<int>(n % p.nslots);
       double w[kMaxT];
       level_weights(k, p.T, w);
@@ -391,13 +446,13 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     }
   };
 
-  Sweep<Real, DIM, S> sw(p, lds, n, s_w, s_slot, s_nbr);
+  Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos);
   if (DIM == 3) {
     faces();
     __syncthreads();
-    for (int zz = -S; zz < S; ++zz) sw.load_plane(zz);
+    for (int zz = -SD; zz < SD; ++zz) sw.load_plane(zz);
     for (int z = 0; z < p.bz; ++z) {
-      sw.load_plane(z + S);
+      sw.load_plane(z + SD);
       __syncthreads();
       sw.compute_plane(z);
     }
@@ -474,10 +529,11 @@ __global__ void delays_kernel(StepParams p, int64_t n0, int64_t count, int8_t* o
   }
 }
 
-template <typename Real, int DIM, int S>
+template <typename Real, int DIM, int S, int SP>
 size_t lds_bytes_t(const StepParams& p) {
-  const int nsl = DIM == 3 ? 2 * S + 2 : 1;
-  const size_t plane = static_cast<size_t>(DIM >= 2 ? p.by + 2 * S : 1) * (p.bx + 2 * S);
+  constexpr int SD = strip_depth<S, SP>();
+  const int nsl = DIM == 3 ? 2 * SD + 2 : 1;
+  const size_t plane = static_cast<size_t>(DIM >= 2 ? p.by + 2 * SD : 1) * (p.bx + 2 * SD);
   return nsl * plane * sizeof(Real);
 }
 
@@ -492,10 +548,10 @@ int sweep_threads(const StepParams& p) {
   return static_cast<int>(t);
 }
 
-template <typename Real, int DIM, int S>
+template <typename Real, int DIM, int S, int SP>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
-  const size_t lds = lds_bytes_t<Real, DIM, S>(p);
-  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S>), dim3(p.npe), dim3(sweep_threads(p)), lds, st, p);
+  const size_t lds = lds_bytes_t<Real, DIM, S, SP>(p);
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(p.npe), dim3(sweep_threads(p)), lds, st, p);
   return hipGetLastError();
 }
 
@@ -505,12 +561,18 @@ hipError_t launch_pub_t(const StepParams& p, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Sweep launches by half-width s (and the space-expanded scheme, s = 1);
+// publish_all launches by strip depth s.
 template <typename Real, int DIM>
 hipError_t dispatch_s(const StepParams& p, int s, hipStream_t st, bool pub) {
+  if (!pub && p.scheme != AT_SCHEME_TIME) {
+    if (s != 1) return hipErrorInvalidValue;
+    return p.scheme == AT_SCHEME_SPACE_212 ? launch_t<Real, DIM, 1, 1>(p, st) : launch_t<Real, DIM, 1, 2>(p, st);
+  }
   switch (s) {
-    case 1: return pub ? launch_pub_t<Real, DIM, 1>(p, st) : launch_t<Real, DIM, 1>(p, st);
-    case 2: return pub ? launch_pub_t<Real, DIM, 2>(p, st) : launch_t<Real, DIM, 2>(p, st);
-    case 3: return pub ? launch_pub_t<Real, DIM, 3>(p, st) : launch_t<Real, DIM, 3>(p, st);
+    case 1: return pub ? launch_pub_t<Real, DIM, 1>(p, st) : launch_t<Real, DIM, 1, 0>(p, st);
+    case 2: return pub ? launch_pub_t<Real, DIM, 2>(p, st) : launch_t<Real, DIM, 2, 0>(p, st);
+    case 3: return pub ? launch_pub_t<Real, DIM, 3>(p, st) : launch_t<Real, DIM, 3, 0>(p, st);
   }
   return hipErrorInvalidValue;
 }
@@ -525,18 +587,24 @@ hipError_t dispatch_dim(const StepParams& p, int s, hipStream_t st, bool pub) {
   return hipErrorInvalidValue;
 }
 
+template <typename Real, int DIM>
+size_t lds_s(const StepParams& p, int s) {
+  if (p.scheme == AT_SCHEME_SPACE_212) return lds_bytes_t<Real, DIM, 1, 1>(p);
+  if (p.scheme == AT_SCHEME_SPACE_222) return lds_bytes_t<Real, DIM, 1, 2>(p);
+  switch (s) {
+    case 1: return lds_bytes_t<Real, DIM, 1, 0>(p);
+    case 2: return lds_bytes_t<Real, DIM, 2, 0>(p);
+    case 3: return lds_bytes_t<Real, DIM, 3, 0>(p);
+  }
+  return ~size_t(0);
+}
+
 template <typename Real>
 size_t lds_dim(const StepParams& p, int s) {
-  switch (p.ndim * 4 + s) {
-    case 5: return lds_bytes_t<Real, 1, 1>(p);
-    case 6: return lds_bytes_t<Real, 1, 2>(p);
-    case 7: return lds_bytes_t<Real, 1, 3>(p);
-    case 9: return lds_bytes_t<Real, 2, 1>(p);
-    case 10: return lds_bytes_t<Real, 2, 2>(p);
-    case 11: return lds_bytes_t<Real, 2, 3>(p);
-    case 13: return lds_bytes_t<Real, 3, 1>(p);
-    case 14: return lds_bytes_t<Real, 3, 2>(p);
-    case 15: return lds_bytes_t<Real, 3, 3>(p);
+  switch (p.ndim) {
+    case 1: return lds_s<Real, 1>(p, s);
+    case 2: return lds_s<Real, 2>(p, s);
+    case 3: return lds_s<Real, 3>(p, s);
   }
   return ~size_t(0);
 }

@@ -13,7 +13,7 @@ bool fast3d_applies(const StepParams& p, bool f64) {
   (void)f64;
   // time-expanded AT (T = s + 1) or the synchronous arm; other T take the
   // generic kernel
-  const bool levels_ok = p.mode == AT_SYNC || p.T == p.s + 1;
+  const bool levels_ok = p.mode == AT_SYNC || (p.scheme == AT_SCHEME_TIME && p.T == p.s + 1);
   return p.ndim == 3 && p.bx == fast3d::kB && p.by == fast3d::kB && levels_ok &&
          fast3d_valid_variant(p.depth) && p.bz % (p.depth & 7) == 0;
 }

@@ -13,7 +13,7 @@ def oracle_for(case, u0):
                    alpha=case.get("alpha", 0.1), integrator=case.get("integrator", "euler"))
     dm = DelayModel(L=case.get("L", 3), T=case.get("T", 0), mode=case.get("mode", "rng"),
                     seed=case.get("seed", 0), weights=case.get("weights"),
-                    host=case.get("host"))
+                    host=case.get("host"), scheme=case.get("scheme", "time"))
     return Oracle(prob, dm, torch.as_tensor(u0, dtype=torch.float64))
 
 
@@ -25,7 +25,7 @@ def solver_for(case, precision="f64"):
                   alpha=case.get("alpha", 0.1), integrator=case.get("integrator", "euler"),
                   precision=precision, L=case.get("L", 3), T=case.get("T", 0),
                   mode=case.get("mode", "rng"), seed=case.get("seed", 0),
-                  weights=case.get("weights"),
+                  weights=case.get("weights"), scheme=case.get("scheme", "time"),
                   host_delays=None if host is None else np.asarray(host, dtype=np.int8))
 
 

@@ -58,6 +58,7 @@ def _delay(mod, **kw):
     d.L = kw.get("L", 4)
     d.T = kw.get("T", 0)
     d.mode = mod.MODES[kw.get("mode", "rng")]
+    d.scheme = mod.SCHEMES[kw.get("scheme", "time")]
     return d
 
 
@@ -100,6 +101,39 @@ def test_invalid_arguments_are_rejected(kw, dkw):
     st, _ = _size(L, lib, _prob(L, **kw), _delay(L, **dkw))
     assert st == L.AT_EINVAL
     assert lib.at_last_error(None)
+
+
+def test_space_expanded_schemes_size_rings_by_strip_depth_and_validate():
+    """The space-expanded schemes keep one level (T = 1: L + 1 ring slots) of
+    2 ((2,1,2)) or 3 ((2,2,2)a) buffer points per face."""
+    L, lib = _lib()
+    p = _prob(L, ndim=1, n=(64, 1, 1), pe=(8, 1, 1), order=2, integrator="euler")
+    npts = 64
+    sizes = {}
+    for scheme in ("time", "space212", "space222"):
+        st, nb = _size(L, lib, p, _delay(L, L=3, scheme=scheme))
+        assert st == L.AT_OK, scheme
+        sizes[scheme] = nb
+    # ring bytes: slots x PEs x (2 faces x depth) x 8 B, solution in place
+    ring = {"time": (3 + 2) * 8 * 2 * 1 * 8, "space212": (3 + 1) * 8 * 2 * 2 * 8,
+            "space222": (3 + 1) * 8 * 2 * 3 * 8}
+    for scheme, nb in sizes.items():
+        assert npts * 8 + ring[scheme] <= nb < npts * 8 + ring[scheme] + 4 * 2 ** 20
+    assert sizes["space222"] - sizes["space212"] <= 4096 + ring["space222"]
+    bad = [
+        (dict(ndim=1, n=(64, 1, 1), pe=(8, 1, 1), order=4), dict(scheme="space222")),    # order 4
+        (dict(ndim=1, n=(16, 1, 1), pe=(8, 1, 1), order=2), dict(scheme="space222")),    # PE edge 2 < 3
+        (dict(ndim=1, n=(64, 1, 1), pe=(8, 1, 1), order=2), dict(scheme="space212", T=3)),
+    ]
+    for kw, dkw in bad:
+        st, _ = _size(L, lib, _prob(L, **kw), _delay(L, L=3, **dkw))
+        assert st == L.AT_EINVAL, (kw, dkw)
+    d = _delay(L, L=3)
+    d.scheme = 3
+    st, _ = _size(L, lib, p, d)
+    assert st == L.AT_EINVAL
+    st, _ = _size(L, lib, _prob(L, ndim=1, n=(16, 1, 1), pe=(8, 1, 1), order=2), _delay(L, L=3, scheme="space212"))
+    assert st == L.AT_OK
 
 
 def test_host_delay_table_is_validated():

@@ -59,6 +59,18 @@ CASES = {
     "2d_o4_one_pe_per_axis": dict(ndim=2, n=(24, 20), pe=(1, 1), order=4, integrator="ab2", c=(1.0, 0.5), L=4, steps=30, ra=0.02),
     "1d_o6_L8_T4_rk2": dict(ndim=1, n=(96,), pe=(4,), order=6, integrator="rk2", c=(1.0,), L=8, steps=60, ra=0.002),
     "3d_fast_o4_ab2_bz4": dict(ndim=3, n=(64, 64, 8), pe=(2, 2, 2), order=4, integrator="ab2", c=(1.0, -0.5, 0.5), L=4, steps=12, ra=0.02),
+    # space-expanded single-level schemes (second-order CD): Case 2 (diffusion,
+    # (2,1,2)) and Case 3 (advection-diffusion, (1,2,2)a + (2,2,2)a) with the
+    # paper's p = {0.5, 0.3, 0.2}, then other integrators, shapes and the
+    # thinnest PEs the stencils allow (b = 2 for (2,1,2), 3 for (2,2,2)a)
+    "1d_o2_space212_case2": dict(ndim=1, n=(128,), pe=(16,), order=2, integrator="euler", c=(0.0,), L=3, weights=[5, 3, 2], scheme="space212", steps=200, ra=0.05),
+    "1d_o2_space222_case3": dict(ndim=1, n=(128,), pe=(16,), order=2, integrator="euler", c=(1.0,), L=3, weights=[5, 3, 2], scheme="space222", steps=200, ra=0.05),
+    "1d_o2_space222_ab2_min_edge": dict(ndim=1, n=(24,), pe=(8,), order=2, integrator="ab2", c=(1.0,), L=4, scheme="space222", steps=60, ra=0.05),
+    "1d_o2_space212_min_edge": dict(ndim=1, n=(16,), pe=(8,), order=2, integrator="euler", c=(0.5,), L=3, scheme="space212", steps=60, ra=0.05),
+    "2d_o2_space212_ragged": dict(ndim=2, n=(40, 36), pe=(4, 3), order=2, integrator="euler", c=(1.0, -0.5), L=3, scheme="space212", steps=40, ra=0.05),
+    "2d_o2_space222_rk2": dict(ndim=2, n=(30, 24), pe=(3, 4), order=2, integrator="rk2", c=(1.0, 0.5), L=4, scheme="space222", steps=30, ra=0.05),
+    "3d_o2_space222_ab2": dict(ndim=3, n=(24, 20, 18), pe=(2, 2, 3), order=2, integrator="ab2", c=(1.0, 1.0, -0.5), L=3, scheme="space222", steps=16, ra=0.05),
+    "3d_o2_space212_burgers": dict(ndim=3, n=(20, 20, 20), pe=(2, 2, 2), order=2, integrator="ab2", equation="burgers", alpha=0.05, L=4, scheme="space212", steps=12, ra=0.02),
 }
 
 
@@ -91,7 +103,8 @@ def test_field_parity(name, precision):
     assert err <= TOL[precision], (name, precision, err)
 
 
-@pytest.mark.parametrize("name", ["1d_o2_euler_L3", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers"])
+@pytest.mark.parametrize("name", ["1d_o2_euler_L3", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
+                                  "1d_o2_space222_case3"])
 def test_delays_bit_exact(name):
     case = _case(name)
     s = solver_for(case, "f64")
@@ -104,7 +117,8 @@ def test_delays_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
-                                  "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16"])
+                                  "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16", "1d_o2_space222_case3",
+                                  "2d_o2_space212_ragged", "3d_o2_space222_ab2"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
@@ -231,6 +245,32 @@ def test_full_size_3d_workload_first_steps():
         d = s.delays(0, steps)
         for n in range(steps):
             assert np.array_equal(d[n], o.delays[n].numpy().reshape(d[n].shape))
+
+
+@pytest.mark.parametrize("scheme", ["space222", "space212"])
+def test_full_size_space_expanded_workload_first_steps(scheme):
+    """The benchmark's space-expanded workload (256^3, 8^3 PEs of 32^3,
+    second-order CD, Euler, L = 3 with p = {0.5, 0.3, 0.2}) in its graph
+    launch configuration: the first 4 steps against the oracle, FP32 bulk."""
+    cfg = W.config_3d_advdiff(n=256, b=32)
+    dx = 2 * math.pi / 256
+    case = dict(ndim=3, n=cfg["n"], pe=cfg["pe"], order=2, integrator="euler", c=(1.0, 1.0, 1.0), alpha=0.1,
+                dt=0.05 * dx * dx / 0.1, L=3, weights=[5, 3, 2], seed=cfg["seed"], scheme=scheme)
+    steps = 4
+    u0 = torch.from_numpy(W.eval_modes(cfg["modes"], cfg["n"], 3))
+    _say(f"[parity] full-size {scheme} oracle run")
+    o = oracle_for(case, u0)
+    o.run(steps)
+    s = solver_for(case, "f32")
+    s.set_graph(2)
+    s.set_state(u0.cuda())
+    s.step(steps)
+    err = rel_l2(s.state().cpu(), o.u)
+    _say(f"[parity] full size {scheme} f32: rel L2 {err:.3e}")
+    assert err <= TOL["f32"], err
+    d = s.delays(0, steps)
+    for n in range(steps):
+        assert np.array_equal(d[n], o.delays[n].numpy().reshape(d[n].shape))
 
 
 def test_full_size_3d_workload_full_run_properties():
