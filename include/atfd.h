@@ -164,7 +164,9 @@ at_status at_set_graph(at_ctx* ctx, int32_t chunk);
  * (1, 2 or 4) with 4 points per thread and 256 threads per PE, or 8 + D with
  * 2 points per thread and 512 threads per PE; 0 = the library default. Every
  * variant computes bit-identical results; only speed differs. Other shapes
- * ignore it. */
+ * ignore it. The space-expanded schemes have variants 1 and 2 on this path;
+ * with another variant they run on the generic sweep (same scheme, results
+ * equal to rounding, not bitwise), and at_autotune times only 1 and 2. */
 at_status at_set_tuning(at_ctx* ctx, int32_t depth);
 at_status at_get_tuning(const at_ctx* ctx, int32_t* depth);
 

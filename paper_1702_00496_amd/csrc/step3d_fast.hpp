@@ -156,9 +156,16 @@ __device__ inline Vec<Real, W> combine_levels(const double* w, const Vec<Real, W
   return r;
 }
 
-template <typename Real, int S, int V, int D, int KIND, int EQ, int TT>
+// SP = 0: time-expanded AT (TT = T levels) or the synchronous arm (TT = 1).
+// SP = 1, 2: the space-expanded single-level schemes of the second-order CD
+// (first derivative (1,2,2)a, second (2,1,2) or (2,2,2)a), TT = 1, S = the
+// strip depth (2 or 3): the CD2 stencil everywhere plus, at a point next to a
+// face whose delay is positive, the difference between that scheme's stencil
+// and the CD2 one over the S buffer points of level n-k and the own points.
+template <typename Real, int S, int V, int D, int KIND, int EQ, int TT, int SP = 0>
 __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams p) {
   static_assert(S <= kHO, "the x halo must fit left of column kHO");
+  static_assert(SP == 0 || TT == 1, "the space-expanded schemes combine one level");
   static_assert(TT >= 1 && TT <= kMaxT, "levels per halo value");
   using VR = Vec<Real, V>;
   using Q = Vec<Real, 4>;
@@ -166,12 +173,14 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   constexpr int VPR = kB / V;             // vectors per row
   constexpr int ROWS = kB + 2 * S;
   constexpr bool kHist = KIND == kAb2 || KIND == kAb3 || KIND == kRk2;
-  constexpr bool kSync = TT == 1;         // synchronous arm: neighbours' u^n directly
+  constexpr bool kSync = TT == 1 && SP == 0;   // synchronous arm: neighbours' u^n directly
+  constexpr int SS = SP != 0 ? 1 : S;     // half-width of the bulk central difference
   __shared__ __align__(16) Real buf[2][ROWS * kRS];
   __shared__ __align__(16) Real zhi_lds[S * kB * kB];   // planes bz .. bz+S-1
   __shared__ double s_w[6 * kMaxT];
   __shared__ int s_slot[6 * kMaxT];
   __shared__ int s_nbr[6];
+  __shared__ int s_kpos[6];               // face delay k > 0 (space-expanded stencils apply)
 
   const int tid = threadIdx.x;
   const int vi = tid % VPR, y = tid / VPR;
@@ -185,8 +194,10 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   if (tid < 6) {
     const int f = tid;
     s_nbr[f] = neighbour_pe(p, pid, f);
+    s_kpos[f] = 0;
     if (!kSync) {
       const int k = face_delay_fast(p, pid, f, n);
+      s_kpos[f] = k > 0;
       double w[kMaxT];
       level_weights(k, TT, w);
       // a level whose weight is zero re-reads level n-k (same lines, cache
@@ -374,6 +385,23 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
     for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(j, m);
   }
 
+  // space-expanded schemes: low-face taps minus the CD2 taps, o = -S..S
+  Real dl1[3][2 * S + 1], dl2[3][2 * S + 1];
+  const Real alpha_r = static_cast<Real>(p.alpha);
+  const Real vel[3] = {static_cast<Real>(p.vel[0]), static_cast<Real>(p.vel[1]), static_cast<Real>(p.vel[2])};
+  if constexpr (SP != 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = -S; o <= S; ++o) {
+        const bool in_cd = o >= -1 && o <= 1;
+        dl1[a][o + S] = static_cast<Real>(p.sl1[a][o + kMaxS] - (in_cd ? p.c1[a][o + 1] : 0.0));
+        dl2[a][o + S] = static_cast<Real>(p.sl2[a][o + kMaxS] - (in_cd ? p.c2[a][o + 1] : 0.0));
+      }
+  }
+  const bool kpos0 = SP != 0 && s_kpos[0], kpos1 = SP != 0 && s_kpos[1], kpos2 = SP != 0 && s_kpos[2],
+             kpos3 = SP != 0 && s_kpos[3], kpos4 = SP != 0 && s_kpos[4], kpos5 = SP != 0 && s_kpos[5];
+
   const int c_at = (y + S) * kRS + kHO + x;     // LDS index of this thread's first point
   for (int zb = 0; zb < bz; zb += D) {
 #pragma unroll
@@ -417,31 +445,57 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
           // partial sum per axis
           Real ax = 0, ay = 0, az = 0;
 #pragma unroll
-          for (int o = 1; o <= S; ++o) {
-            ax += Taps<Real>::kad(p, 0, S - o) * (row[S + e - o] - u0);
-            ay += Taps<Real>::kad(p, 1, S - o) * (ym[o - 1].v[e] - u0);
-            az += Taps<Real>::kad(p, 2, S - o) * (qz[S - o].v[e] - u0);
-            ax += Taps<Real>::kad(p, 0, S + o) * (row[S + e + o] - u0);
-            ay += Taps<Real>::kad(p, 1, S + o) * (yp[o - 1].v[e] - u0);
-            az += Taps<Real>::kad(p, 2, S + o) * (qz[S + o].v[e] - u0);
+          for (int o = 1; o <= SS; ++o) {
+            ax += Taps<Real>::kad(p, 0, SS - o) * (row[S + e - o] - u0);
+            ay += Taps<Real>::kad(p, 1, SS - o) * (ym[o - 1].v[e] - u0);
+            az += Taps<Real>::kad(p, 2, SS - o) * (qz[S - o].v[e] - u0);
+            ax += Taps<Real>::kad(p, 0, SS + o) * (row[S + e + o] - u0);
+            ay += Taps<Real>::kad(p, 1, SS + o) * (yp[o - 1].v[e] - u0);
+            az += Taps<Real>::kad(p, 2, SS + o) * (qz[S + o].v[e] - u0);
           }
           fval = (ax + ay) + az;
         } else {
           // f = alpha lap u - u (sum_d du/dx_d)
           Real lx = 0, ly = 0, lz = 0, gx = 0, gy = 0, gz = 0;
 #pragma unroll
-          for (int o = 1; o <= S; ++o) {
+          for (int o = 1; o <= SS; ++o) {
             const Real xm = row[S + e - o] - u0, xp = row[S + e + o] - u0;
             const Real ymv = ym[o - 1].v[e] - u0, ypv = yp[o - 1].v[e] - u0;
             const Real zm = qz[S - o].v[e] - u0, zp = qz[S + o].v[e] - u0;
-            lx += Taps<Real>::d2a(p, 0, S - o) * xm + Taps<Real>::d2a(p, 0, S + o) * xp;
-            ly += Taps<Real>::d2a(p, 1, S - o) * ymv + Taps<Real>::d2a(p, 1, S + o) * ypv;
-            lz += Taps<Real>::d2a(p, 2, S - o) * zm + Taps<Real>::d2a(p, 2, S + o) * zp;
-            gx += Taps<Real>::d1(p, 0, S - o) * xm + Taps<Real>::d1(p, 0, S + o) * xp;
-            gy += Taps<Real>::d1(p, 1, S - o) * ymv + Taps<Real>::d1(p, 1, S + o) * ypv;
-            gz += Taps<Real>::d1(p, 2, S - o) * zm + Taps<Real>::d1(p, 2, S + o) * zp;
+            lx += Taps<Real>::d2a(p, 0, SS - o) * xm + Taps<Real>::d2a(p, 0, SS + o) * xp;
+            ly += Taps<Real>::d2a(p, 1, SS - o) * ymv + Taps<Real>::d2a(p, 1, SS + o) * ypv;
+            lz += Taps<Real>::d2a(p, 2, SS - o) * zm + Taps<Real>::d2a(p, 2, SS + o) * zp;
+            gx += Taps<Real>::d1(p, 0, SS - o) * xm + Taps<Real>::d1(p, 0, SS + o) * xp;
+            gy += Taps<Real>::d1(p, 1, SS - o) * ymv + Taps<Real>::d1(p, 1, SS + o) * ypv;
+            gz += Taps<Real>::d1(p, 2, SS - o) * zm + Taps<Real>::d1(p, 2, SS + o) * zp;
           }
           fval = ((lx + ly) + lz) - u0 * ((gx + gy) + gz);
+        }
+        if constexpr (SP != 0) {
+          // space-expanded stencils at points next to a face with k > 0: the
+          // difference to the CD2 taps, over o = -S..S (the high face mirrors
+          // the low-face taps: first derivative odd, second even)
+          Real c1s = 0, c2s = 0, adv = 0;
+          auto add_axis = [&](int a, bool lo, bool hi, auto val) {
+            if (!(lo || hi)) return;
+            Real t1 = 0, t2 = 0;
+#pragma unroll
+            for (int o = -S; o <= S; ++o) {
+              if (o == 0) continue;
+              const Real v = val(o) - u0;
+              t1 += (lo ? dl1[a][o + S] : -dl1[a][S - o]) * v;
+              t2 += (lo ? dl2[a][o + S] : dl2[a][S - o]) * v;
+            }
+            c1s += EQ == AT_ADVDIFF ? Real(0) : t1;
+            adv += EQ == AT_ADVDIFF ? vel[a] * t1 : Real(0);
+            c2s += t2;
+          };
+          add_axis(0, e == 0 && x == 0 && kpos0, e == V - 1 && x + e == kB - 1 && kpos1,
+                   [&](int o) { return row[S + e + o]; });
+          add_axis(1, y == 0 && kpos2, y == kB - 1 && kpos3,
+                   [&](int o) { return o < 0 ? ym[-o - 1].v[e] : yp[o - 1].v[e]; });
+          add_axis(2, z == 0 && kpos4, z == bz - 1 && kpos5, [&](int o) { return qz[S + o].v[e]; });
+          fval += EQ == AT_ADVDIFF ? alpha_r * c2s - adv : alpha_r * c2s - u0 * c1s;
         }
         fq.v[e] = fval;
         Real r;
@@ -512,14 +566,14 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   }
 }
 
-template <typename Real, int S, int V, int D, int KIND, int TT>
+template <typename Real, int S, int V, int D, int KIND, int TT, int SP = 0>
 hipError_t launch_eq(const StepParams& p, hipStream_t st) {
   constexpr int NT = kB * kB / V;
   if (p.equation == AT_ADVDIFF)
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_ADVDIFF, TT>), dim3(p.npe),
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_ADVDIFF, TT, SP>), dim3(p.npe),
                        dim3(NT), 0, st, p);
   else
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_BURGERS, TT>), dim3(p.npe),
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_BURGERS, TT, SP>), dim3(p.npe),
                        dim3(NT), 0, st, p);
   return hipGetLastError();
 }
@@ -561,6 +615,32 @@ hipError_t launch_fast_t(const StepParams& p, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+// The space-expanded schemes (one level, strips S = 2 or 3 deep): schedule
+// variants 1 and 2 (V = 4, D = 1 or 2).
+template <typename Real, int S, int SP, int D>
+hipError_t launch_space_d(const StepParams& p, hipStream_t st) {
+  if (p.stage == kStageRk1) return launch_eq<Real, S, 4, D, kRk1, 1, SP>(p, st);
+  if (p.stage == kStageRk2) return launch_eq<Real, S, 4, D, kRk2, 1, SP>(p, st);
+  switch (p.integrator) {
+    case AT_EULER: return launch_eq<Real, S, 4, D, kEuler, 1, SP>(p, st);
+    case AT_AB2: return launch_eq<Real, S, 4, D, kAb2, 1, SP>(p, st);
+    case AT_AB3: return launch_eq<Real, S, 4, D, kAb3, 1, SP>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+hipError_t launch_space_t(const StepParams& p, hipStream_t st) {
+  const int key = p.scheme * 10 + p.depth;
+  switch (key) {
+    case 11: return launch_space_d<Real, 2, 1, 1>(p, st);
+    case 12: return launch_space_d<Real, 2, 1, 2>(p, st);
+    case 21: return launch_space_d<Real, 3, 2, 1>(p, st);
+    case 22: return launch_space_d<Real, 3, 2, 2>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace fast3d
 
 // one instantiation per translation unit (fast3d_*.hip), built in parallel
@@ -570,5 +650,7 @@ hipError_t launch_fast3d_f32_s3(const StepParams& p, hipStream_t st);
 hipError_t launch_fast3d_f64_s1(const StepParams& p, hipStream_t st);
 hipError_t launch_fast3d_f64_s2(const StepParams& p, hipStream_t st);
 hipError_t launch_fast3d_f64_s3(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_space_f32(const StepParams& p, hipStream_t st);
+hipError_t launch_fast3d_space_f64(const StepParams& p, hipStream_t st);
 
 }  // namespace atfd

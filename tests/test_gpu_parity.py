@@ -71,6 +71,11 @@ CASES = {
     "2d_o2_space222_rk2": dict(ndim=2, n=(30, 24), pe=(3, 4), order=2, integrator="rk2", c=(1.0, 0.5), L=4, scheme="space222", steps=30, ra=0.05),
     "3d_o2_space222_ab2": dict(ndim=3, n=(24, 20, 18), pe=(2, 2, 3), order=2, integrator="ab2", c=(1.0, 1.0, -0.5), L=3, scheme="space222", steps=16, ra=0.05),
     "3d_o2_space212_burgers": dict(ndim=3, n=(20, 20, 20), pe=(2, 2, 2), order=2, integrator="ab2", equation="burgers", alpha=0.05, L=4, scheme="space212", steps=12, ra=0.02),
+    # 32 x 32 cross-sections: the space-expanded schemes on the 3-D fast path
+    "3d_fast_o2_space222": dict(ndim=3, n=(64, 64, 32), pe=(2, 2, 2), order=2, integrator="euler", c=(1.0, -0.5, 0.5), L=3, weights=[5, 3, 2], scheme="space222", steps=14, ra=0.05),
+    "3d_fast_o2_space212_ab2": dict(ndim=3, n=(64, 32, 64), pe=(2, 1, 2), order=2, integrator="ab2", c=(0.5, 1.0, -1.0), L=4, scheme="space212", steps=14, ra=0.05),
+    "3d_fast_o2_space222_rk2_burgers": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="rk2", equation="burgers", alpha=0.05, L=3, scheme="space222", steps=10, ra=0.02),
+    "3d_fast_o2_space222_ab3_bz6": dict(ndim=3, n=(32, 64, 12), pe=(1, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=4, scheme="space222", steps=12, ra=0.02),
 }
 
 
@@ -118,7 +123,7 @@ def test_delays_bit_exact(name):
 
 @pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
                                   "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16", "1d_o2_space222_case3",
-                                  "2d_o2_space212_ragged", "3d_o2_space222_ab2"])
+                                  "2d_o2_space212_ragged", "3d_o2_space222_ab2", "3d_fast_o2_space222"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
