@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint,space",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space,study",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -281,6 +281,32 @@ def time_space():
                          "against time-expanded (1,2,2)b+(2,2,2)b", arms=res)
 
 
+def time_study():
+    """The moment-law study of Sec. 5.2 on the ensemble kernel: the Case 1
+    scheme (order 2, T = 2, Euler), N = 1024 with 16 PEs, p_k = 1/L for
+    L = 2..6, 256 delay histories per L plus a synchronous member (1281
+    members in one launch), r_alpha = 0.1, t = 0.1 (2653 steps), FP64."""
+    from paper_1702_00496_amd import studies
+    kw = dict(order=2, Ls=(2, 3, 4, 5, 6), realizations=256, n=1024, pe=16, r_alpha=0.1, t_final=0.1,
+              precision="f64")
+    studies.moment_study(**dict(kw, realizations=4, t_final=0.01))     # build and warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = studies.moment_study(**kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    npts = 1024 * len(res["members"])
+    ratios = [r["ratio"] for r in res["per_L"].values()]
+    print(f"[bench] moment study: {ms:.1f} ms for {len(res['members'])} members x {res['steps']} steps, "
+          f"async/law {min(ratios):.3e}..{max(ratios):.3e}", file=sys.stderr, flush=True)
+    return dict(workload="moment-law study (Sec. 5.2): order 2, T=2, Euler, N=1024 / 16 PEs, L=2..6 uniform, "
+                         "256 histories per L + 1 synchronous member, FP64, set-up + run + norms",
+                ms=ms, members=len(res["members"]), steps=res["steps"],
+                updates_per_s=npts * res["steps"] / (ms / 1e3),
+                per_L={str(L): dict(E=r["E"], E_sync=r["E_sync"], asynchronous=r["asynchronous"], law=r["law"],
+                                    ratio=r["ratio"]) for L, r in res["per_L"].items()})
+
+
 def time_ensemble():
     """512 independent 1-D members (N log-uniform in [1024, 65536], PE 64,
     orders 2/4, L in {2, 4, 8}), 2000 steps in one persistent launch, FP32."""
@@ -391,7 +417,7 @@ if "f32" in arms and "sync32" in arms:
 others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
-                 "space": time_space}[w]()
+                 "space": time_space, "study": time_study}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:

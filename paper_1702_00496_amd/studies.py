@@ -1,0 +1,148 @@
+"""Delay-statistics studies run on the ensemble kernel (Sec. 5.2).
+
+Every realisation of a study is one member of a single ``Ensemble`` launch: a
+periodic 1-D advection-diffusion problem (Sec. 5 eq. general) with the
+initial sine series of Sec. 5.1 (eq. IC), its own delay generator key and the
+delay law of its configuration. The average overall error <E> (Sec. 4) is the
+mean over realisations of each member's space-averaged |E| against the exact
+solution (Sec. 5.1 eq. ana_sol), computed in double on the device.
+
+- ``moment_study``: <E> against L (or any delay law) for a time-expanded
+  scheme with T levels, and the asynchronous part (<E> - <E>_s) / <E>_s
+  relative to a synchronous member, next to the law of Sec. 5.2 eq.
+  aveE_scaling_gen_kmom: <E> - <E>_s ~ E[k (k+1) ... (k+T-1)], i.e.
+  <k^2> + <k> for T = 2 and <k^3> + 3<k^2> + 2<k> for T = 3 (with p_k = 1/L:
+  L^2 - 1 and L^3 + 2L^2 - L - 2, eq. aveE_scaling_gen_L).
+- ``pe_scaling_study``: <E> against the number of PEs P at fixed N (strong
+  scaling) or at fixed N/P (weak scaling), eq. aveE_scaling_gen2
+  (<E> ~ P dx^{a+1} sum gamma_m <k^m>).
+
+Only argument marshalling and averaging happen here; the steps and the error
+norms run in the library's kernels.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import Ensemble
+
+# Sec. 5.1 configuration of the 1-D experiments: kappa = {3, 4, 5},
+# A = {2.0, 0.5, 1.5}
+DEFAULT_MODES = ((3, 2.0), (4, 0.5), (5, 1.5))
+
+
+def delay_law(L, T, weights=None):
+    """E[k (k+1) ... (k+T-1)] for k drawn with bin weights (uniform if None)."""
+    w = [1.0] * L if weights is None else [float(v) for v in weights]
+    tot = sum(w)
+    out = 0.0
+    for k in range(L):
+        term = 1.0
+        for m in range(T):
+            term *= k + m
+        out += w[k] / tot * term
+    return out
+
+
+def _member_key(seed, tag, r):
+    """Distinct 64-bit generator keys per (study seed, configuration, realisation)."""
+    x = (seed * 0x9E3779B97F4A7C15 + tag * 0xBF58476D1CE4E5B9 + r * 0x94D049BB133111EB) & (2 ** 64 - 1)
+    return x ^ (x >> 29)
+
+
+def _initial_fields(members, modes):
+    out = []
+    for m in members:
+        x = np.arange(m["n"], dtype=np.float64) * (2 * math.pi / m["n"])
+        out.append(sum(a * np.sin(k * x) for k, a in modes))
+    return torch.from_numpy(np.concatenate(out))
+
+
+def run_members(members, steps, modes=DEFAULT_MODES, precision="f64", device="cuda", sync_ref=False):
+    """Advance the members together for ``steps`` steps; per-member mean |E|,
+    rms E and max |E| against the exact solution at t = steps * dt. With
+    ``sync_ref`` the first member must be synchronous and every member of the
+    same size is also measured against its final field (the asynchronous
+    perturbation |u - u_s|): returns (exact norms, norms against u_s)."""
+    ens = Ensemble(members, precision=precision, device=device)
+    ens.set_state(_initial_fields(members, modes))
+    ens.run(steps)
+    kap = [k for k, _ in modes]
+    amp = [a for _, a in modes]
+    nrm = ens.norms(kap, amp, np.zeros((len(members), len(modes))))
+    if not sync_ref:
+        ens.close()
+        return nrm
+    parts = ens.split(ens.state().to(torch.float64))
+    ref = torch.cat([parts[0] if m["n"] == members[0]["n"] else p for m, p in zip(members, parts)])
+    rel = ens.norms(ref=ref)
+    ens.close()
+    return nrm, rel
+
+
+def _dt(n, alpha, r_alpha):
+    dx = 2 * math.pi / n
+    return r_alpha * dx * dx / alpha
+
+
+def moment_study(order=2, Ls=(2, 3, 4, 5, 6), realizations=64, n=128, pe=16, r_alpha=0.1, t_final=0.5,
+                 c=1.0, alpha=0.1, weights=None, seed=0, precision="f64", device="cuda"):
+    """<E> of the time-expanded scheme of ``order`` (T = order/2 + 1; Euler
+    for order 2, AB2 for order 4) for every L in ``Ls`` (``weights``: one bin
+    weight list per L, or None for p_k = 1/L), with ``realizations`` delay
+    histories each and one synchronous member. Returns a dict with the
+    members, and per L: E, E_sync, async = (E - E_sync) / E_sync, law =
+    E[k (k+1) ... (k+T-1)] and the ratio async / law."""
+    T = order // 2 + 1
+    integ = "euler" if order == 2 else "ab2"
+    dt = _dt(n, alpha, r_alpha)
+    steps = int(round(t_final / dt))
+    base = dict(n=n, pe=pe, order=order, integrator=integ, c=c, alpha=alpha, dt=dt)
+    members = [dict(base, L=1, mode="sync", seed=0)]
+    for i, L in enumerate(Ls):
+        w = None if weights is None else weights[i]
+        for r in range(realizations):
+            members.append(dict(base, L=L, mode="rng", seed=_member_key(seed, L, r), weights=w))
+    nrm = run_members(members, steps, precision=precision, device=device)
+    es = float(nrm[0, 0])
+    rows = {}
+    for i, L in enumerate(Ls):
+        e = float(np.mean(nrm[1 + i * realizations: 1 + (i + 1) * realizations, 0]))
+        law = delay_law(L, T, None if weights is None else weights[i])
+        a = (e - es) / es
+        rows[L] = dict(E=e, E_sync=es, asynchronous=a, law=law, ratio=a / law if law else float("nan"))
+    return dict(order=order, T=T, steps=steps, dt=dt, members=members, per_L=rows)
+
+
+def pe_scaling_study(order=2, configs=((512, 2), (512, 4), (512, 8), (512, 16), (512, 32)), L=3,
+                     weights=(2, 5, 3), realizations=16, r_alpha=0.1, t_final=0.2, c=1.0, alpha=0.1,
+                     seed=0, precision="f64", device="cuda"):
+    """<E> for every (N, P) in ``configs`` (strong scaling: N fixed; weak:
+    N/P fixed), with ``realizations`` delay histories each and one
+    synchronous member per configuration; dt = r_alpha dx^2 / alpha per N and
+    the same final time. Returns per (N, P): E, E_sync, E - E_sync and
+    asynchronous = the mean over histories of mean |u - u_s| (the
+    perturbation the delays cause, free of cancellation against the
+    synchronous error)."""
+    integ = "euler" if order == 2 else "ab2"
+    members = []
+    index = []
+    for j, (n, p) in enumerate(configs):
+        dt = _dt(n, alpha, r_alpha)
+        base = dict(n=n, pe=p, order=order, integrator=integ, c=c, alpha=alpha, dt=dt)
+        index.append((len(members), int(round(t_final / dt))))
+        members.append(dict(base, L=1, mode="sync", seed=0))
+        for r in range(realizations):
+            members.append(dict(base, L=L, mode="rng", seed=_member_key(seed, 1000 + j, r), weights=list(weights)))
+    # members of different N need different step counts: one launch per configuration
+    rows = {}
+    for j, (n, p) in enumerate(configs):
+        start, steps = index[j]
+        group = members[start: start + 1 + realizations]
+        nrm, rel = run_members(group, steps, precision=precision, device=device, sync_ref=True)
+        es = float(nrm[0, 0])
+        e = float(np.mean(nrm[1:, 0]))
+        rows[(n, p)] = dict(E=e, E_sync=es, difference=e - es, asynchronous=float(np.mean(rel[1:, 0])),
+                            steps=steps)
+    return dict(order=order, members=members, per_config=rows)

@@ -1,0 +1,81 @@
+"""The delay-statistics studies on the ensemble kernel (Sec. 5.2): the
+averaged errors against the FP64 oracle run member by member, and the
+scaling laws the paper reports (eq. aveE_scaling_gen_kmom / _L: the
+asynchronous error part follows E[k (k+1) ... (k+T-1)]; eq.
+aveE_scaling_gen2: it grows linearly with P at fixed N)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.solver import DelayModel, Oracle, Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_mean_error(m, steps, modes):
+    prob = Problem(ndim=1, n=(m["n"],), pe=(m["pe"],), dt=m["dt"], order=m["order"], c=(m["c"],),
+                   alpha=m["alpha"], integrator=m["integrator"])
+    x = torch.arange(m["n"], dtype=torch.float64) * (2 * math.pi / m["n"])
+    u0 = sum(a * torch.sin(k * x) for k, a in modes).reshape(prob.shape)
+    o = Oracle(prob, DelayModel(L=m["L"], mode=m["mode"], seed=m["seed"], weights=m.get("weights")), u0)
+    o.run(steps)
+    t = steps * m["dt"]
+    exact = sum(a * math.exp(-m["alpha"] * k * k * t) * torch.sin(k * (x - m["c"] * t)) for k, a in modes)
+    return float((o.u.reshape(-1) - exact).abs().mean())
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_moment_study_matches_the_oracle(order):
+    from paper_1702_00496_amd import studies
+    res = studies.moment_study(order=order, Ls=(1, 2, 3), realizations=3, n=64, pe=8,
+                               r_alpha=0.1 if order == 2 else 0.02, t_final=0.05, precision="f64")
+    steps = res["steps"]
+    mem = res["members"]
+    es = _oracle_mean_error(mem[0], steps, studies.DEFAULT_MODES)
+    for i, L in enumerate((1, 2, 3)):
+        group = mem[1 + 3 * i: 4 + 3 * i]
+        e = np.mean([_oracle_mean_error(m, steps, studies.DEFAULT_MODES) for m in group])
+        row = res["per_L"][L]
+        _say(f"[study] order {order} L={L}: GPU {row['E']:.12e} oracle {e:.12e}")
+        assert abs(row["E"] - e) <= 1e-10 * e
+        assert abs(row["E_sync"] - es) <= 1e-10 * es
+    # L = 1: every delay 0, the scheme is the CD: no asynchronous error
+    assert abs(res["per_L"][1]["asynchronous"]) < 1e-12
+
+
+def test_asynchronous_error_follows_the_moment_law():
+    """Case 1 scheme ((1,2,2)b/(2,2,2)b, T = 2), p_k = 1/L: (<E> - <E>_s) / <E>_s
+    proportional to L^2 - 1 (ratio to the law within a factor 2 over L = 2..6)."""
+    from paper_1702_00496_amd import studies
+    res = studies.moment_study(order=2, Ls=(2, 3, 4, 5, 6), realizations=64, n=128, pe=16, r_alpha=0.1,
+                               t_final=0.5, precision="f64")
+    ratios = [res["per_L"][L]["ratio"] for L in (2, 3, 4, 5, 6)]
+    _say("[study] async / law:", ", ".join(f"{r:.3e}" for r in ratios))
+    assert all(r > 0 for r in ratios)
+    assert max(ratios) / min(ratios) < 2.0
+    # the asynchronous part grows with L as the law does (monotone)
+    asy = [res["per_L"][L]["asynchronous"] for L in (2, 3, 4, 5, 6)]
+    assert all(b > a for a, b in zip(asy, asy[1:]))
+
+
+def test_strong_scaling_error_grows_linearly_with_pe_count():
+    """Case 1 at N = 512, L = 3, p_k = {0.2, 0.5, 0.3} (the delay law of the
+    strong-scaling figure): the asynchronous perturbation mean |u - u_s| grows
+    about linearly with P."""
+    from paper_1702_00496_amd import studies
+    cfg = ((512, 2), (512, 4), (512, 8), (512, 16), (512, 32))
+    res = studies.pe_scaling_study(order=2, configs=cfg, L=3, weights=(2, 5, 3), realizations=16,
+                                   r_alpha=0.1, t_final=0.2, precision="f64")
+    asy = [res["per_config"][c]["asynchronous"] for c in cfg]
+    _say("[study] strong scaling async:", ", ".join(f"{a:.3e}" for a in asy))
+    assert all(b > a > 0 for a, b in zip(asy, asy[1:]))
+    slope = np.polyfit(np.log([p for _, p in cfg]), np.log(asy), 1)[0]
+    assert 0.6 < slope < 1.4, slope
