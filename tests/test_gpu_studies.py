@@ -53,17 +53,35 @@ def test_moment_study_matches_the_oracle(order):
 
 def test_asynchronous_error_follows_the_moment_law():
     """Case 1 scheme ((1,2,2)b/(2,2,2)b, T = 2), p_k = 1/L: (<E> - <E>_s) / <E>_s
-    proportional to L^2 - 1 (ratio to the law within a factor 2 over L = 2..6)."""
+    proportional to L^2 - 1 (reading G6; ratio to the law within a factor 2
+    over L = 2..6), and the perturbation mean |u - u_s| within 5 %."""
     from paper_1702_00496_amd import studies
     res = studies.moment_study(order=2, Ls=(2, 3, 4, 5, 6), realizations=64, n=128, pe=16, r_alpha=0.1,
                                t_final=0.5, precision="f64")
     ratios = [res["per_L"][L]["ratio"] for L in (2, 3, 4, 5, 6)]
+    pert = [res["per_L"][L]["perturbation_ratio"] for L in (2, 3, 4, 5, 6)]
     _say("[study] async / law:", ", ".join(f"{r:.3e}" for r in ratios))
+    _say("[study] perturbation / law:", ", ".join(f"{r:.3e}" for r in pert))
     assert all(r > 0 for r in ratios)
     assert max(ratios) / min(ratios) < 2.0
+    # the delay perturbation mean |u - u_s| follows the law to 1 % (measured)
+    assert max(pert) / min(pert) < 1.05
     # the asynchronous part grows with L as the law does (monotone)
     asy = [res["per_L"][L]["asynchronous"] for L in (2, 3, 4, 5, 6)]
     assert all(b > a for a, b in zip(asy, asy[1:]))
+
+
+def test_three_level_perturbation_follows_the_moment_law():
+    """Case 4 scheme ((1,4,2)/(2,4,2), T = 3, AB2), p_k = 1/L: the asynchronous
+    perturbation mean |u - u_s| is proportional to L^3 + 2L^2 - L - 2 (reading
+    G5 of eq. aveE_scaling_gen_L; within 10 % over L = 2..5)."""
+    from paper_1702_00496_amd import studies
+    res = studies.moment_study(order=4, Ls=(2, 3, 4, 5), realizations=64, n=128, pe=16, r_alpha=0.005,
+                               t_final=0.2, precision="f64")
+    ratios = [res["per_L"][L]["perturbation_ratio"] for L in (2, 3, 4, 5)]
+    _say("[study] order 4 perturbation / law:", ", ".join(f"{r:.3e}" for r in ratios))
+    assert all(r > 0 for r in ratios)
+    assert max(ratios) / min(ratios) < 1.1
 
 
 def test_strong_scaling_error_grows_linearly_with_pe_count():
