@@ -299,12 +299,22 @@ def time_study():
     ratios = [r["ratio"] for r in res["per_L"].values()]
     print(f"[bench] moment study: {ms:.1f} ms for {len(res['members'])} members x {res['steps']} steps, "
           f"async/law {min(ratios):.3e}..{max(ratios):.3e}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    conv = studies.convergence_study(case="case6", Ns=(32, 64, 128, 256), precision="f64")
+    torch.cuda.synchronize()
+    ms6 = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] Case 6 convergence study: {ms6:.1f} ms, slopes "
+          f"{[round(r['slopes'][-1], 2) for r in conv['per_law'].values()]}", file=sys.stderr, flush=True)
     return dict(workload="moment-law study (Sec. 5.2): order 2, T=2, Euler, N=1024 / 16 PEs, L=2..6 uniform, "
                          "256 histories per L + 1 synchronous member, FP64, set-up + run + norms",
                 ms=ms, members=len(res["members"]), steps=res["steps"],
                 updates_per_s=npts * res["steps"] / (ms / 1e3),
                 per_L={str(L): dict(E=r["E"], E_sync=r["E_sync"], asynchronous=r["asynchronous"], law=r["law"],
-                                    ratio=r["ratio"]) for L, r in res["per_L"].items()})
+                                    ratio=r["ratio"], perturbation=r["perturbation"],
+                                    perturbation_ratio=r["perturbation_ratio"]) for L, r in res["per_L"].items()},
+                case6_convergence=dict(ms=ms6, Ns=conv["Ns"],
+                                       per_law={str(w): dict(E=r["E"], slopes=r["slopes"])
+                                                for w, r in conv["per_law"].items()}))
 
 
 def time_ensemble():

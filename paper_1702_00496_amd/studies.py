@@ -152,3 +152,97 @@ def pe_scaling_study(order=2, configs=((512, 2), (512, 4), (512, 8), (512, 16), 
         rows[(n, p)] = dict(E=e, E_sync=es, difference=e - es, asynchronous=float(np.mean(rel[1:, 0])),
                             steps=steps)
     return dict(order=order, members=members, per_config=rows)
+
+
+# ---------------------------------------------------------------- Cases 5, 6
+def cole_hopf(x, t, amp, nu, nterms=None):
+    """Exact solution of u_t + u u_x = nu u_xx on the periodic [0, 2 pi) with
+    u(x, 0) = amp sin x (Cole-Hopf): with a = amp / (2 nu),
+    theta = I_0(a) + 2 sum_n I_n(a) e^{-nu n^2 t} cos(n x) and
+    u = -2 nu theta_x / theta (Bessel functions scaled by e^{-a}; the scale
+    cancels in the ratio)."""
+    from scipy.special import ive
+    a = amp / (2.0 * nu)
+    if nterms is None:
+        nterms = int(max(40, 6 * a + 40))
+    x = np.asarray(x, dtype=np.float64)
+    theta = np.full_like(x, ive(0, a))
+    dtheta = np.zeros_like(x)
+    for n in range(1, nterms + 1):
+        c = 2.0 * ive(n, a) * math.exp(-nu * n * n * t)
+        theta += c * np.cos(n * x)
+        dtheta -= c * n * np.sin(n * x)
+    return -2.0 * nu * dtheta / theta
+
+
+def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, weights, mode, seed, precision):
+    from . import Solver
+    s = Solver(ndim=1, n=(n,), pe=(pe,), dt=dt, order=order, equation=equation, c=(c,), alpha=alpha,
+               integrator=integrator, precision=precision, L=L, mode=mode, seed=seed, weights=weights)
+    s.set_graph(64)
+    s.set_state(torch.as_tensor(u0).reshape(1, 1, n))
+    s.step(steps)
+    out = s.state().double().cpu().numpy().reshape(-1)
+    s.close()
+    return out
+
+
+CASE_CONFIGS = {
+    # Sec. 5.1 table of cases: Case 5 = diffusion, AB3, CD6 with (2,6,2) (T = 4);
+    # Case 6 = viscous Burgers, AB2, CD4 with (1,4,2)/(2,4,2) (T = 3)
+    "case5": dict(order=6, integrator="ab3", equation="advdiff", c=0.0, alpha=0.1, r_alpha=0.01, t_final=0.1),
+    "case6": dict(order=4, integrator="ab2", equation="burgers", c=0.0, alpha=0.1, r_alpha=0.02, t_final=0.5,
+                  amp=1.0),
+}
+
+
+def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
+                      weight_sets=((1, 0, 0), (7, 2, 1), (4, 4, 2), (3, 5, 2)), realizations=2, seed=0,
+                      precision="f64"):
+    """<E> against N for Case 5 (exact: the decaying sine series of Sec. 5.1)
+    or Case 6 (exact: Cole-Hopf for u0 = amp sin x), for every delay law in
+    ``weight_sets`` (bin weights of k = 0, 1, 2; (1, 0, 0) is delay-free),
+    dt = r_alpha dx^2 / alpha at a fixed final time. Returns per weight set
+    the errors against N, their slopes, and the final fields (for moments)."""
+    cfg = CASE_CONFIGS[case]
+    out = {}
+    for w in weight_sets:
+        errs, fields = [], []
+        for n in Ns:
+            dx = 2 * math.pi / n
+            steps = int(math.ceil(cfg["t_final"] / (cfg["r_alpha"] * dx * dx / cfg["alpha"])))
+            dt = cfg["t_final"] / steps
+            x = np.arange(n, dtype=np.float64) * dx
+            if case == "case5":
+                u0 = sum(a * np.sin(k * x) for k, a in DEFAULT_MODES)
+                exact = sum(a * math.exp(-cfg["alpha"] * k * k * cfg["t_final"]) * np.sin(k * x)
+                            for k, a in DEFAULT_MODES)
+            else:
+                u0 = cfg["amp"] * np.sin(x)
+                exact = cole_hopf(x, cfg["t_final"], cfg["amp"], cfg["alpha"])
+            e_r, f_r = [], []
+            for r in range(realizations if sum(w[1:]) else 1):
+                u = _gpu_run(n, pe, cfg["order"], cfg["integrator"], cfg["equation"], cfg["c"], cfg["alpha"], dt,
+                             steps, u0, L, list(w), "rng", _member_key(seed, n, r), precision)
+                e_r.append(float(np.mean(np.abs(u - exact))))
+                f_r.append(u)
+            errs.append(float(np.mean(e_r)))
+            fields.append(f_r)
+        slopes = [math.log(errs[i + 1] / errs[i]) / math.log(Ns[i + 1] / Ns[i]) for i in range(len(Ns) - 1)]
+        out[tuple(w)] = dict(E=errs, slopes=slopes, fields=fields)
+    return dict(case=case, Ns=list(Ns), per_law=out)
+
+
+def central_moments(u, dx):
+    """Normalised central moments of u and of du/dx (spectral derivative of
+    the periodic field): <(u - <u>)^2>, <(u - <u>)^3> / m2^{3/2},
+    <(u - <u>)^4> / m2^2, for u and for du/dx (Sec. 5.2, Case 6 moments)."""
+    n = u.size
+    k = np.fft.rfftfreq(n, d=dx / (2 * math.pi))
+    du = np.fft.irfft(1j * k * np.fft.rfft(u), n)
+
+    def mom(v):
+        d = v - v.mean()
+        m2 = float(np.mean(d * d))
+        return m2, float(np.mean(d ** 3)) / m2 ** 1.5, float(np.mean(d ** 4)) / m2 ** 2
+    return dict(u=mom(u), dudx=mom(du))

@@ -97,3 +97,67 @@ def test_strong_scaling_error_grows_linearly_with_pe_count():
     assert all(b > a > 0 for a, b in zip(asy, asy[1:]))
     slope = np.polyfit(np.log([p for _, p in cfg]), np.log(asy), 1)[0]
     assert 0.6 < slope < 1.4, slope
+
+
+@pytest.mark.parametrize("case", ["case5", "case6"])
+def test_convergence_study_fields_match_the_oracle(case):
+    from paper_1702_00496_amd import studies
+    cfg = studies.CASE_CONFIGS[case]
+    w = (4, 4, 2)
+    res = studies.convergence_study(case=case, Ns=(32,), weight_sets=(w,), realizations=1, precision="f64")
+    got = res["per_law"][w]["fields"][0][0]
+    n = 32
+    dx = 2 * math.pi / n
+    steps = int(math.ceil(cfg["t_final"] / (cfg["r_alpha"] * dx * dx / cfg["alpha"])))
+    dt = cfg["t_final"] / steps
+    x = torch.arange(n, dtype=torch.float64) * dx
+    if case == "case5":
+        u0 = sum(a * torch.sin(k * x) for k, a in studies.DEFAULT_MODES)
+    else:
+        u0 = cfg["amp"] * torch.sin(x)
+    prob = Problem(ndim=1, n=(n,), pe=(4,), dt=dt, order=cfg["order"], equation=cfg["equation"], c=(cfg["c"],),
+                   alpha=cfg["alpha"], integrator=cfg["integrator"])
+    o = Oracle(prob, DelayModel(L=3, mode="rng", seed=studies._member_key(0, n, 0), weights=list(w)),
+               u0.reshape(prob.shape))
+    o.run(steps)
+    want = o.u.reshape(-1).numpy()
+    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    _say(f"[study] {case} N=32 field rel L2 vs oracle {err:.3e}")
+    assert err < 1e-12
+
+
+def test_cases_5_and_6_converge_at_the_scheme_order_for_every_delay_law():
+    """Sec. 5.1 figure of Cases 2-5 part (d) (Case 5: (2,6,2), AB3, slope -6)
+    and the Burgers convergence figure (Case 6: (1,4,2)/(2,4,2), AB2, slope -4
+    against the exact Cole-Hopf solution), for p = {1,0,0}, {0.7,0.2,0.1},
+    {0.4,0.4,0.2}, {0.3,0.5,0.2}; asynchrony barely changes the error."""
+    from paper_1702_00496_amd import studies
+    for case, Ns, lo, hi in (("case5", (32, 64, 128), -7.2, -4.8), ("case6", (32, 64, 128, 256), -4.6, -3.4)):
+        res = studies.convergence_study(case=case, Ns=Ns, precision="f64")
+        base = res["per_law"][(1, 0, 0)]["E"]
+        for w, row in res["per_law"].items():
+            _say(f"[study] {case} p={w}: E {', '.join(f'{e:.3e}' for e in row['E'])} "
+                 f"slopes {', '.join(f'{s:.2f}' for s in row['slopes'])}")
+            assert lo < row["slopes"][-1] < hi, (case, w, row["slopes"])
+            assert row["E"][-1] < 1.5 * base[-1], (case, w)
+
+
+def test_case6_gradient_moments_converge_by_n256():
+    """Sec. 5.2 (velocity and velocity-gradient moments, Case 6): at N = 256
+    the second to fourth normalised central moments of u and du/dx agree with
+    those of the exact solution on a fine grid, with and without delays."""
+    from paper_1702_00496_amd import studies
+    cfg = studies.CASE_CONFIGS["case6"]
+    res = studies.convergence_study(case="case6", Ns=(64, 256), weight_sets=((1, 0, 0), (3, 5, 2)),
+                                    realizations=2, precision="f64")
+    xf = np.arange(4096) * (2 * math.pi / 4096)
+    ref = studies.central_moments(studies.cole_hopf(xf, cfg["t_final"], cfg["amp"], cfg["alpha"]),
+                                  2 * math.pi / 4096)
+    for w, row in res["per_law"].items():
+        for fields, n in zip(row["fields"], (64, 256)):
+            m = studies.central_moments(fields[0], 2 * math.pi / n)
+            dev = max(abs(m[q][i] - ref[q][i]) / abs(ref[q][i]) for q in ("u", "dudx") for i in range(3)
+                      if abs(ref[q][i]) > 1e-8)
+            _say(f"[study] case6 p={w} N={n}: moments {m} max rel dev {dev:.2e}")
+            if n == 256:
+                assert dev < 1e-4, (w, m, ref)
