@@ -110,7 +110,7 @@ def test_adjoint_is_independent_of_the_checkpoint_interval():
 def test_adjoint_rejects_unsupported_problems():
     from paper_1702_00496_amd import ATError
     case = _case("1d_o2_euler_L3")
-    for bad in (dict(integrator="ab3"),):
+    for bad in (dict(integrator="ab3"), dict(scheme="space222")):
         c = dict(case, **bad)
         s = solver_for(c, "f64")
         s.set_state(torch.from_numpy(initial_field(c)))

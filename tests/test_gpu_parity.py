@@ -189,8 +189,9 @@ def test_first_configuration_full_run():
         assert abs(got[k] - want[k]) <= 1e-9 * want[k], (k, got[k], want[k])
 
 
-def test_checkpoint_resume_bitwise():
-    case = _case("3d_o4_ab2_ragged")
+@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_fast_o2_space222", "2d_o2_space212_ragged"])
+def test_checkpoint_resume_bitwise(name):
+    case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
     a = solver_for(case, "f64")
     a.set_state(u0)
@@ -206,7 +207,8 @@ def test_checkpoint_resume_bitwise():
     assert torch.equal(b.state(), ref)
 
 
-@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3", "3d_fast_o6_rk2_burgers"])
+@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3", "3d_fast_o6_rk2_burgers",
+                                  "3d_fast_o2_space222_rk2_burgers", "1d_o2_space222_case3"])
 def test_graph_replay_equals_plain_launches(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
