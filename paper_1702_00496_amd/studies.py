@@ -175,10 +175,12 @@ def cole_hopf(x, t, amp, nu, nterms=None):
     return -2.0 * nu * dtheta / theta
 
 
-def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, weights, mode, seed, precision):
+def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, weights, mode, seed, precision,
+             scheme="time"):
     from . import Solver
     s = Solver(ndim=1, n=(n,), pe=(pe,), dt=dt, order=order, equation=equation, c=(c,), alpha=alpha,
-               integrator=integrator, precision=precision, L=L, mode=mode, seed=seed, weights=weights)
+               integrator=integrator, precision=precision, L=L, mode=mode, seed=seed, weights=weights,
+               scheme=scheme)
     s.set_graph(64)
     s.set_state(torch.as_tensor(u0).reshape(1, 1, n))
     s.step(steps)
@@ -188,8 +190,16 @@ def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, wei
 
 
 CASE_CONFIGS = {
-    # Sec. 5.1 table of cases: Case 5 = diffusion, AB3, CD6 with (2,6,2) (T = 4);
-    # Case 6 = viscous Burgers, AB2, CD4 with (1,4,2)/(2,4,2) (T = 3)
+    # Sec. 5.1 table of cases: Case 2 = diffusion, Euler, CD2 with the
+    # space-expanded (2,1,2); Case 3 = advection-diffusion, Euler, CD2 with
+    # (1,2,2)a/(2,2,2)a; Case 4 = advection-diffusion, AB2, CD4 with
+    # (1,4,2)/(2,4,2) (T = 3); Case 5 = diffusion, AB3, CD6 with (2,6,2)
+    # (T = 4); Case 6 = viscous Burgers, AB2, CD4 with (1,4,2)/(2,4,2)
+    "case2": dict(order=2, integrator="euler", equation="advdiff", c=0.0, alpha=0.1, r_alpha=0.05, t_final=0.05,
+                  scheme="space212"),
+    "case3": dict(order=2, integrator="euler", equation="advdiff", c=1.0, alpha=0.1, r_alpha=0.05, t_final=0.05,
+                  scheme="space222"),
+    "case4": dict(order=4, integrator="ab2", equation="advdiff", c=1.0, alpha=0.1, r_alpha=0.02, t_final=0.05),
     "case5": dict(order=6, integrator="ab3", equation="advdiff", c=0.0, alpha=0.1, r_alpha=0.01, t_final=0.1),
     "case6": dict(order=4, integrator="ab2", equation="burgers", c=0.0, alpha=0.1, r_alpha=0.02, t_final=0.5,
                   amp=1.0),
@@ -199,8 +209,8 @@ CASE_CONFIGS = {
 def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
                       weight_sets=((1, 0, 0), (7, 2, 1), (4, 4, 2), (3, 5, 2)), realizations=2, seed=0,
                       precision="f64"):
-    """<E> against N for Case 5 (exact: the decaying sine series of Sec. 5.1)
-    or Case 6 (exact: Cole-Hopf for u0 = amp sin x), for every delay law in
+    """<E> against N for Cases 2-5 (exact: the decaying advected sine series of
+    Sec. 5.1) or Case 6 (exact: Cole-Hopf for u0 = amp sin x), for every delay law in
     ``weight_sets`` (bin weights of k = 0, 1, 2; (1, 0, 0) is delay-free),
     dt = r_alpha dx^2 / alpha at a fixed final time. Returns per weight set
     the errors against N, their slopes, and the final fields (for moments)."""
@@ -213,9 +223,10 @@ def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
             steps = int(math.ceil(cfg["t_final"] / (cfg["r_alpha"] * dx * dx / cfg["alpha"])))
             dt = cfg["t_final"] / steps
             x = np.arange(n, dtype=np.float64) * dx
-            if case == "case5":
+            if case != "case6":
                 u0 = sum(a * np.sin(k * x) for k, a in DEFAULT_MODES)
-                exact = sum(a * math.exp(-cfg["alpha"] * k * k * cfg["t_final"]) * np.sin(k * x)
+                t = cfg["t_final"]
+                exact = sum(a * math.exp(-cfg["alpha"] * k * k * t) * np.sin(k * (x - cfg["c"] * t))
                             for k, a in DEFAULT_MODES)
             else:
                 u0 = cfg["amp"] * np.sin(x)
@@ -223,7 +234,8 @@ def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
             e_r, f_r = [], []
             for r in range(realizations if sum(w[1:]) else 1):
                 u = _gpu_run(n, pe, cfg["order"], cfg["integrator"], cfg["equation"], cfg["c"], cfg["alpha"], dt,
-                             steps, u0, L, list(w), "rng", _member_key(seed, n, r), precision)
+                             steps, u0, L, list(w), "rng", _member_key(seed, n, r), precision,
+                             cfg.get("scheme", "time"))
                 e_r.append(float(np.mean(np.abs(u - exact))))
                 f_r.append(u)
             errs.append(float(np.mean(e_r)))

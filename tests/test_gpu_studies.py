@@ -142,6 +142,28 @@ def test_cases_5_and_6_converge_at_the_scheme_order_for_every_delay_law():
             assert row["E"][-1] < 1.5 * base[-1], (case, w)
 
 
+def test_cases_2_to_4_converge_at_second_and_fourth_order_with_delays():
+    """Sec. 5.1 figure of Cases 2-5, parts (a)-(c): Case 2 ((2,1,2), first
+    order at the buffer points) and Case 3 ((1,2,2)a/(2,2,2)a) converge
+    asymptotically at slope -2 with 16 PEs, Case 4 ((1,4,2)/(2,4,2)) at -4; the
+    error grows with the amount of asynchrony (p = {0.7,0.2,0.1} ->
+    {0.3,0.5,0.2})."""
+    from paper_1702_00496_amd import studies
+    sets = ((1, 0, 0), (7, 2, 1), (4, 4, 2), (3, 5, 2))
+    for case, Ns, pe, lo, hi in (("case2", (64, 128, 256, 512), 16, -2.9, -1.7),
+                                 ("case3", (64, 128, 256, 512), 16, -2.9, -1.7),
+                                 ("case4", (64, 128, 256), 16, -4.8, -3.4)):
+        res = studies.convergence_study(case=case, Ns=Ns, pe=pe, weight_sets=sets, precision="f64")
+        for w in sets:
+            row = res["per_law"][w]
+            _say(f"[study] {case} p={w}: E {', '.join(f'{e:.3e}' for e in row['E'])} "
+                 f"slopes {', '.join(f'{s:.2f}' for s in row['slopes'])}")
+            assert lo < row["slopes"][-1] < hi, (case, w, row["slopes"])
+        if case != "case4":
+            e = [res["per_law"][w]["E"][0] for w in sets]
+            assert e[0] < e[1] < e[3], (case, e)
+
+
 def test_case6_gradient_moments_converge_by_n256():
     """Sec. 5.2 (velocity and velocity-gradient moments, Case 6): at N = 256
     the second to fourth normalised central moments of u and du/dx agree with
