@@ -321,6 +321,58 @@ at_status at_ens_destroy(at_ens* ens);
 /* Text of the last failure of `ens`, or of the calling thread for NULL. */
 const char* at_ens_last_error(const at_ens* ens);
 
+/* ------------------------------------------------------------------------
+ * Scheme derivation (host only, exact arithmetic; no device work, no
+ * context, callable without a GPU).
+ *
+ * A stencil is n pairs (j[i], l[i]): the scheme uses u_{i+j}^{n-l} (Sec. 3.2
+ * eq. general_deriv_at2). The order conditions of Sec. 3.1 eq. cond are
+ * imposed for every Taylor term u^{(p,q)} with p + r q < d + a (dt ~ dx^r),
+ * and the system is classified by the rank test of the Sec. 3.1 derivation
+ * recipe. Coefficients are exact reduced fractions num[i] / den[i] (den > 0)
+ * of the dimensionless scheme: d^d u/dx^d ~ sum_i c_i u_{i+j[i]}^{n-l[i]} / dx^d.
+ */
+enum { AT_DERIVE_UNIQUE = 0,    /* rank(A) = rank(A|b) = n: one scheme          */
+       AT_DERIVE_NONE = 1,      /* rank(A) < rank(A|b): the stencil has none    */
+       AT_DERIVE_INFINITE = 2   /* rank(A) = rank(A|b) < n: a family            */
+};
+
+typedef struct at_derivation {
+  int32_t status;      /* AT_DERIVE_*                                           */
+  int32_t order;       /* accuracy a whose conditions were imposed             */
+  int32_t n_cond;      /* equations (terms with p + r q < d + a)               */
+  int32_t n_unknown;   /* stencil entries                                      */
+  int32_t rank_a;      /* rank(A)                                              */
+  int32_t rank_ab;     /* rank(A|b)                                            */
+} at_derivation;
+
+/* Derive the scheme of derivative order d (1..4) and accuracy a (1..12) for
+ * dt ~ dx^r (r 1..4) on the stencil (j[n], l[n]) (host arrays, 1 <= n <= 48,
+ * |j| <= 32, 0 <= l <= 64, no repeated pair). Writes num[n], den[n] and
+ * *info. UNIQUE: the scheme. INFINITE: one member of the family (the free
+ * unknowns set to zero). NONE: all zero. AT_EINVAL for out-of-range
+ * arguments or when exact 128-bit arithmetic would overflow (never rounds). */
+at_status at_derive_scheme(int32_t d, int32_t a, int32_t r, int32_t n, const int32_t* j, const int32_t* l,
+                           int64_t* num, int64_t* den, at_derivation* info);
+
+/* Search for the smallest AT scheme of a fixed interior layout (step 2 of the
+ * Sec. 3.1 recipe, done systematically): interior points j = -s_min..0 at
+ * level n (j = 0 only if with_centre), buffer points j = 1..s_max each at the
+ * T successive levels n-k .. n-k-T+1 (the uniform-delay layout of Sec. 3.2 eq.
+ * cond-async2 for T = 1, the time-expanded one for T > 1). s_max grows from 1
+ * to max_extent; a stencil whose system has a family of solutions takes
+ * further conditions (a + 1, a + 2, ...) while the family persists and, if
+ * that leaves no scheme, is reduced by one buffer entry (oldest level of the
+ * farthest point first) (both routes of recipe step 3); the first unique
+ * scheme with a nonzero buffer coefficient is returned
+ * (*n_out entries of j_out, l_out, num, den, at most `cap`; info->order is the
+ * accuracy reached). side = -1 mirrors it to a buffer on the left
+ * (j -> -j, coefficients times (-1)^d). *n_out = 0 and info->status =
+ * AT_DERIVE_NONE when none exists up to max_extent (1..32). */
+at_status at_search_scheme(int32_t d, int32_t a, int32_t r, int32_t s_min, int32_t with_centre, int32_t k,
+                           int32_t T, int32_t side, int32_t max_extent, int32_t cap, int32_t* n_out,
+                           int32_t* j_out, int32_t* l_out, int64_t* num, int64_t* den, at_derivation* info);
+
 #ifdef __cplusplus
 }
 #endif

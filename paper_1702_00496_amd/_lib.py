@@ -66,11 +66,19 @@ class AtEnsMember(ctypes.Structure):
     ]
 
 
+class AtDerivation(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in ("status", "order", "n_cond", "n_unknown", "rank_a", "rank_ab")]
+
+
+DERIVE_STATUS = {0: "unique", 1: "none", 2: "infinite"}
+
 P = ctypes.c_void_p
 I32 = ctypes.c_int32
 I64 = ctypes.c_int64
 SZ = ctypes.c_size_t
 DP = ctypes.POINTER(ctypes.c_double)
+IP = ctypes.POINTER(ctypes.c_int32)
+LP = ctypes.POINTER(ctypes.c_int64)
 
 # name -> (restype, argtypes); the complete exported surface of include/atfd.h
 SIGNATURES = {
@@ -104,6 +112,9 @@ SIGNATURES = {
     "at_ens_norms": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),
     "at_ens_destroy": (I32, [P]),
     "at_ens_last_error": (ctypes.c_char_p, [P]),
+    "at_derive_scheme": (I32, [I32, I32, I32, I32, IP, IP, LP, LP, ctypes.POINTER(AtDerivation)]),
+    "at_search_scheme": (I32, [I32, I32, I32, I32, I32, I32, I32, I32, I32, I32, IP, IP, IP, LP, LP,
+                               ctypes.POINTER(AtDerivation)]),
 }
 
 _lib = None
