@@ -114,10 +114,10 @@ class DelayModel:
     seed: int = 0
     weights: Optional[Sequence[int]] = None   # integer bin weights, None = uniform
     host: Optional[object] = None      # int array [nsteps, n_pe, ndim, 2] for mode "host"
-    scheme: str = "time"               # "time" | "space212" | "space222"
+    scheme: str = "time"               # "time" | "space212" | "space222" | "nonuniform212"
 
     def levels(self, order):
-        if self.scheme != "time":
+        if self.scheme != "time":   # single-level families
             return 1
         return self.T if self.T > 0 else order // 2 + 1
 
@@ -145,6 +145,40 @@ def delay_table(prob: Problem, dm: DelayModel, n: int, key: Optional[int] = None
     return K
 
 
+def point_delay_table(prob: Problem, dm: DelayModel, n: int, key: Optional[int] = None):
+    """Delay of the second buffer point of every face at step n (non-uniform
+    scheme): LongTensor [n_pe, ndim, 2]. The first buffer point takes the face
+    delay of ``delay_table``; the second its own draw from the same generator
+    with the face index shifted by the number of faces, n_pe * 2 * ndim."""
+    K = torch.zeros((prob.n_pe, prob.ndim, 2), dtype=torch.long)
+    if dm.mode in ("zero", "sync"):
+        return K
+    if dm.mode != "rng":
+        raise ValueError("per-point delays come from the generator (mode rng) or are zero")
+    thr = rng.thresholds(dm.L, dm.weights)
+    k0 = dm.seed if key is None else key
+    nfaces = prob.n_pe * 2 * prob.ndim
+    for p in range(prob.n_pe):
+        for a in range(prob.ndim):
+            for sd in range(2):
+                face = p * 2 * prob.ndim + 2 * a + sd
+                K[p, a, sd] = rng.clamp_startup(rng.raw_delay(k0, n, nfaces + face, thr), n, 1)
+    return K
+
+
+def nonuniform_delays(k1, k2):
+    """Delays (k1, k2) of the nearest and second buffer point as the
+    non-uniform scheme uses them. Sec. 3.4 Example 1: eq. ex1-0 is singular
+    where 3 k1 = k2 and is to be avoided by altering a delay; with k1 >= 1 the
+    nearest point takes the next older level, k1 + 1 (always stored, and then
+    3 k1 - k2 = 3). Both zero: the point is synchronous (None: the CD2 is used)."""
+    if k1 == 0 and k2 == 0:
+        return None
+    if 3 * k1 == k2:
+        k1 += 1
+    return k1, k2
+
+
 def _fr(x):
     return float(Fraction(x))
 
@@ -170,7 +204,16 @@ class Oracle:
                      for k in range(0, max(dm.L, 1))}
         # space-expanded family: boundary stencils per derivative and side
         self.space = None
-        if dm.scheme != "time":
+        self.nonuniform = None
+        if dm.scheme == "nonuniform212":
+            if prob.order != 2:
+                raise ValueError("the non-uniform-delay scheme extends the second-order CD")
+            if any(prob.b[a] < 2 for a in range(prob.ndim)):
+                raise ValueError("nonuniform212 needs PE edges of at least 2 points")
+            if dm.mode == "host":
+                raise ValueError("nonuniform212 draws its per-point delays from the generator")
+            self.nonuniform = {}     # (k1, k2) -> {d: {j: c}} at a right face, from eq. cond
+        elif dm.scheme != "time":
             if dm.scheme not in ("space212", "space222"):
                 raise ValueError(f"unknown scheme {dm.scheme}")
             if prob.order != 2:
@@ -216,6 +259,8 @@ class Oracle:
 
         ``centre`` is the field at level n; ``hist`` holds the past levels of
         the same quantity (default: the solution history)."""
+        if self.nonuniform is not None and self.dm.mode != "sync":
+            return self._nonuniform_axis_derivative(centre, K, axis, 1 if taps is self.taps1 else 2, hist)
         if self.space is not None and self.dm.mode != "sync":
             return self._space_axis_derivative(centre, K, axis, 1 if taps is self.taps1 else 2, hist)
         prob = self.prob
@@ -285,6 +330,60 @@ class Oracle:
             D = D.index_copy(dim, idx, acc)
         return D
 
+    def _nonuniform_taps(self, k1, k2, d):
+        """Right-face stencil {j: (level delay, c)} of the non-uniform scheme
+        at the point i next to the face: points i-1, i at level n, i+1 at
+        n-k1, i+2 at n-k2. d = 1: eq. cond with a = 2, r = 2 (Sec. 3.4 Example
+        1, eq. ex1-0); d = 2: the same footprint with a = 1, r = 2 (the
+        non-uniform form of the (2,1,2) row)."""
+        key = (k1, k2)
+        if key not in self.nonuniform:
+            st = [(-1, 0), (0, 0), (1, k1), (2, k2)]
+            tabs = {}
+            for dd, a in ((1, 2), (2, 1)):
+                status, c = coeffs.derive_scheme(st, dd, a, 2)
+                if status != "unique":
+                    raise AssertionError(f"non-uniform stencil {st} has no unique scheme")
+                tabs[dd] = {j: (lev, _fr(c[(j, lev)])) for j, lev in st}
+            self.nonuniform[key] = tabs
+        return self.nonuniform[key][d]
+
+    def _nonuniform_axis_derivative(self, centre, K, axis, d, hist=None):
+        """Non-uniform-delay scheme: CD2 everywhere; at the face-adjacent
+        points (ell = 0 and b - 1) the four-point stencil whose two buffer
+        points carry their own delays (k1 nearest, k2 next). The left face is
+        the mirror image (j -> -j, coefficients times (-1)^d)."""
+        prob = self.prob
+        hist = self.hist if hist is None else hist
+        taps = self.taps1 if d == 1 else self.taps2
+        dim = 2 - axis
+        N = prob.n[axis]
+        b = prob.b[axis]
+        D = torch.zeros_like(centre)
+        for o in (-1, 0, 1):
+            D = D + taps[o + 1] * torch.roll(centre, shifts=-o, dims=dim)
+        sgn_left = -1.0 if d == 1 else 1.0
+        for side, ell in ((0, 0), (1, b - 1)):
+            K1 = self._slab_delays(K, axis, side)
+            K2 = self._slab_delays(self.K2, axis, side)
+            idx = torch.arange(prob.pe[axis]) * b + ell
+            acc = D.index_select(dim, idx)          # both delays 0: the standard CD2
+            pairs = sorted(set(zip(K1.flatten().tolist(), K2.flatten().tolist())))
+            for k1, k2 in pairs:
+                kk = nonuniform_delays(k1, k2)
+                if kk is None:
+                    continue
+                mask = (K1 == k1) & (K2 == k2)
+                val = torch.zeros_like(acc)
+                for j, (lev, c) in self._nonuniform_taps(kk[0], kk[1], d).items():
+                    src = self.level(hist, self.n - lev) if lev > 0 else centre
+                    jj = j if side == 1 else -j
+                    cc = c if side == 1 else sgn_left * c
+                    val = val + cc * src.index_select(dim, (idx + jj) % N)
+                acc = torch.where(mask, val, acc)
+            D = D.index_copy(dim, idx, acc)
+        return D
+
     def rhs(self, centre, K, hist=None):
         """f = -c . grad u + alpha lap u, or -u sum_d u_{x_d} + alpha lap u."""
         prob = self.prob
@@ -315,6 +414,8 @@ class Oracle:
         n = self.n
         K = delay_table(prob, self.dm, n, self.key)
         self.delays.append(K)
+        if self.nonuniform is not None:
+            self.K2 = point_delay_table(prob, self.dm, n, self.key)
         u = self.hist[n]
         dt = prob.dt
         integ = prob.integrator
