@@ -83,8 +83,19 @@ enum { AT_DELAY_RNG = 0, AT_DELAY_ZERO = 1, AT_DELAY_HOST = 2, AT_SYNC = 3 };
  * the CD (they act at communication-delayed buffer points). The printed
  * left-boundary (1,2,2)a carries a sign slip (its coefficients do not sum to
  * zero); the library uses the mirror image of the right-boundary row, which
- * is what the order conditions (Sec. 3.1 eq. cond) give. */
-enum { AT_SCHEME_TIME = 0, AT_SCHEME_SPACE_212 = 1, AT_SCHEME_SPACE_222 = 2 };
+ * is what the order conditions (Sec. 3.1 eq. cond) give.
+ * NONUNIFORM_212: the non-uniform-delay class (Sec. 3.4 Example 1): the two
+ * buffer points next to a face carry their own delays, k1 (nearest, the
+ * face's draw) and k2 (a second draw, see the generator below). First
+ * derivative eq. ex1-0, ((k2 - 4k1), 3k1, -k2, k1) / (2 (3k1 - k2)) at
+ * (i-1, i, i+1 @ n-k1, i+2 @ n-k2); second derivative the same footprint
+ * solved from eq. cond at the accuracy of the (2,1,2) row:
+ * ((2k1 - k2), (2k2 - 3k1), -k2, k1) / (3k1 - k2). Both reduce to (1,2,2)a
+ * and (2,1,2) when k1 = k2. On the singular set 3k1 = k2 (k1 >= 1) the
+ * nearest point takes the next older level k1 + 1 (the paper prescribes
+ * altering a delay there); with k1 = k2 = 0 the point keeps the CD2. Left
+ * faces use the mirror image. Order 2, T = 0 or 1, no host delay tables. */
+enum { AT_SCHEME_TIME = 0, AT_SCHEME_SPACE_212 = 1, AT_SCHEME_SPACE_222 = 2, AT_SCHEME_NONUNIFORM_212 = 3 };
 
 typedef struct at_problem {
   int32_t ndim;        /* 1, 2 or 3                                              */
@@ -110,17 +121,20 @@ typedef struct at_problem {
  *   k~   = first j with u53 < THR[j],  THR[j] = floor(2^53 * W_j / W_{L-1})
  *          with W_j the running sum of the integer bin weights,
  *   k    = min(k~, max(0, n - T + 1))   (no level before t = 0 is touched).
- * Every buffer point of one face uses the same k (uniform-delay class).
+ * Every buffer point of one face uses the same k (uniform-delay class),
+ * except under AT_SCHEME_NONUNIFORM_212, whose second buffer point draws its
+ * own k with face + P * 2 * ndim in place of face (P = number of PEs).
  */
 typedef struct at_delay {
   int32_t L;                 /* maximum delay levels, k in [0, L-1]; 1..8       */
   int32_t T;                 /* time levels in the AT combination; 0 = order/2+1;
                                 1 = standard scheme fed with delayed halos     */
   int32_t mode;              /* AT_DELAY_RNG | AT_DELAY_ZERO | AT_DELAY_HOST | AT_SYNC */
-  int32_t scheme;            /* AT_SCHEME_TIME | AT_SCHEME_SPACE_212 | AT_SCHEME_SPACE_222;
-                                the space schemes need order 2, T = 0 or 1
-                                (one level), PE edges >= 2 (212) or >= 3 (222),
-                                and are not covered by at_adjoint            */
+  int32_t scheme;            /* AT_SCHEME_TIME | AT_SCHEME_SPACE_212 | AT_SCHEME_SPACE_222
+                                | AT_SCHEME_NONUNIFORM_212; the single-level
+                                schemes need order 2, T = 0 or 1, PE edges
+                                >= 2 (212) or >= 3 (222), and are not covered
+                                by at_adjoint                                 */
   uint64_t seed;             /* generator key                                   */
   const uint32_t* weights;   /* host, L integer bin weights (p_j ~ weights[j]);
                                 NULL = uniform                                  */

@@ -16,7 +16,7 @@ EQUATIONS = {"advdiff": 0, "burgers": 1}
 INTEGRATORS = {"euler": 0, "ab2": 1, "ab3": 2, "rk2": 3}
 PRECISIONS = {"f64": 0, "f32": 1}
 MODES = {"rng": 0, "zero": 1, "host": 2, "sync": 3}
-SCHEMES = {"time": 0, "space212": 1, "space222": 2}
+SCHEMES = {"time": 0, "space212": 1, "space222": 2, "nonuniform212": 3}
 
 
 class AtProblem(ctypes.Structure):

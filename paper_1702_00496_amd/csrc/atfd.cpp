@@ -106,15 +106,17 @@ at_status validate(const at_problem* p, const at_delay* d, Geometry* g) {
   if (d->mode < AT_DELAY_RNG || d->mode > AT_SYNC) return fail(nullptr, AT_EINVAL, "unknown delay mode");
   g->ndim = p->ndim;
   g->s = p->order / 2;
-  if (d->scheme < AT_SCHEME_TIME || d->scheme > AT_SCHEME_SPACE_222)
+  if (d->scheme < AT_SCHEME_TIME || d->scheme > AT_SCHEME_NONUNIFORM_212)
     return fail(nullptr, AT_EINVAL, "unknown AT scheme");
   g->scheme = d->scheme;
   if (d->scheme != AT_SCHEME_TIME) {
-    if (p->order != 2) return fail(nullptr, AT_EINVAL, "the space-expanded schemes need order 2");
-    if (d->T != 0 && d->T != 1) return fail(nullptr, AT_EINVAL, "the space-expanded schemes use one level (T = 1)");
+    if (p->order != 2) return fail(nullptr, AT_EINVAL, "the single-level AT schemes need order 2");
+    if (d->T != 0 && d->T != 1) return fail(nullptr, AT_EINVAL, "the single-level AT schemes use one level (T = 1)");
   }
+  if (d->scheme == AT_SCHEME_NONUNIFORM_212 && d->mode == AT_DELAY_HOST)
+    return fail(nullptr, AT_EINVAL, "the non-uniform-delay scheme draws its per-point delays (no host table)");
   g->T = d->scheme != AT_SCHEME_TIME ? 1 : d->T == 0 ? p->order / 2 + 1 : d->T;
-  g->sd = d->scheme == AT_SCHEME_SPACE_212 ? 2 : d->scheme == AT_SCHEME_SPACE_222 ? 3 : g->s;
+  g->sd = d->scheme == AT_SCHEME_SPACE_222 ? 3 : d->scheme != AT_SCHEME_TIME ? 2 : g->s;
   g->f64 = p->precision == AT_F64;
   if (d->mode != AT_SYNC) {
     if (d->L < 1 || d->L > kMaxL) return fail(nullptr, AT_EINVAL, "L must be 1..%d", kMaxL);
@@ -252,6 +254,12 @@ void fill_params(at_ctx* c) {
     for (int o = 0; o <= 2 * kMaxS; ++o) {
       p.sl1[a][o] = l1[o] / dx;
       p.sl2[a][o] = l2[o] / (dx * dx);
+    }
+    if (g.scheme == AT_SCHEME_NONUNIFORM_212) {
+      // the sweep derives this scheme's taps from the step's delays; the
+      // tables carry only the axis scales, in their centre entry
+      p.sl1[a][kMaxS] = 1.0 / dx;
+      p.sl2[a][kMaxS] = 1.0 / (dx * dx);
     }
   }
   p.depth = fast3d_default_depth(g.f64);

@@ -36,13 +36,17 @@ constexpr int kPlaneCentre = 1, kPlaneHalos = 2;
 
 // SP: 0 = time-expanded AT (or the standard scheme); 1, 2 = the
 // space-expanded single-level schemes with the second derivative (2,1,2) or
-// (2,2,2)a and the first (1,2,2)a (second-order CD only). SD = depth of the
-// face strips and of the LDS halo frame: s, or the 2 or 3 buffer points the
-// space-expanded stencils reach.
+// (2,2,2)a and the first (1,2,2)a (second-order CD only); 3 = the
+// non-uniform-delay scheme (Sec. 3.4 Example 1) whose two buffer points carry
+// their own delays. SD = depth of the face strips and of the LDS halo frame:
+// s, or the 2 or 3 buffer points the single-level stencils reach.
 template <int S, int SP>
 constexpr int strip_depth() {
-  return SP == 0 ? S : SP == 1 ? 2 : 3;
+  return SP == 0 ? S : SP == 2 ? 3 : 2;
 }
+
+// Per-face taps of the non-uniform scheme, [face][derivative][o + 2]
+constexpr int kNuTaps = 10;
 
 template <typename Real, int DIM, int S, int SP>
 struct Sweep {
@@ -62,10 +66,11 @@ struct Sweep {
   const int* lev_slot;      // [6][kMaxT] ring slot of level n-k-m, -1 if weight 0
   const int* nbr;           // [6] neighbour PE of face
   const int* kpos;          // [6] face delay k > 0 (space-expanded stencils apply)
+  const double* nut;        // [6][kNuTaps] non-uniform taps (SP = 3)
 
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
-                   const int* ls_, const int* nb_, const int* kp_)
-      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_) {
+                   const int* ls_, const int* nb_, const int* kp_, const double* nu_)
+      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
     pid = blockIdx.x;
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
@@ -96,13 +101,15 @@ struct Sweep {
   }
 
   // Halo value across face f = 2*axis + side, element r of plane `plane` of
-  // the producer strip.
+  // the producer strip; m = the buffer point's distance from the face - 1.
   // AT: sum over the T delayed levels, in double. SYNC: the neighbour's
-  // level-n value at global position (gx, gy, gz).
-  __device__ Real halo(int f, int plane, int r, int gx, int gy, int gz) const {
+  // level-n value at global position (gx, gy, gz). Non-uniform scheme: the
+  // single level of buffer point m.
+  __device__ Real halo(int f, int plane, int r, int m, int gx, int gy, int gz) const {
     if (p.mode == AT_SYNC) return centre[gidx(gx, gy, gz)];
     const int pf = f ^ 1;   // producer face: the opposite side
     const int nb = nbr[f];
+    if constexpr (SP == 3) return ring_rd[ring_off(lev_slot[f * kMaxT + m], nb, pf, plane, r)];
     // every level is loaded from an in-range slot so that the T loads are in
     // flight together; a level of weight zero (k = 0: exact synchronous
     // value) is then dropped by the select
@@ -177,13 +184,14 @@ struct Sweep {
           const int side = h / (SD * by), r = h % (SD * by), d = r % SD, y = r / SD;
           const int xl = side ? bx + d : d - SD;
           const int gx = (x0 + xl + p.nx) % p.nx;
-          P[(DIM >= 2 ? y + SD : 0) * px_stride + xl + SD] = halo(side, zz, y * SD + d, gx, y0 + y, gz);
+          P[(DIM >= 2 ? y + SD : 0) * px_stride + xl + SD] =
+              halo(side, zz, y * SD + d, side ? d : SD - 1 - d, gx, y0 + y, gz);
         } else {
           const int hy = h - nxh;
           const int side = hy / (SD * bx), r = hy % (SD * bx), d = r / bx, x = r % bx;
           const int yl = side ? by + d : d - SD;
           const int gy = (y0 + yl + p.ny) % p.ny;
-          P[(yl + SD) * px_stride + x + SD] = halo(2 + side, zz, d * bx + x, x0 + x, gy, gz);
+          P[(yl + SD) * px_stride + x + SD] = halo(2 + side, zz, d * bx + x, side ? d : SD - 1 - d, x0 + x, gy, gz);
         }
       }
     } else {
@@ -193,7 +201,7 @@ struct Sweep {
       const int gz = (z0 + zz + p.nz) % p.nz;
       for (int i = tid; i < bx * by; i += nt) {
         const int x = i % bx, y = i / bx;
-        P[(y + SD) * px_stride + x + SD] = halo(4 + side, d, y * bx + x, x0 + x, y0 + y, gz);
+        P[(y + SD) * px_stride + x + SD] = halo(4 + side, d, y * bx + x, side ? d : SD - 1 - d, x0 + x, y0 + y, gz);
       }
     }
   }
@@ -258,7 +266,34 @@ struct Sweep {
         // difference form: the taps of each derivative sum to zero, so each
         // neighbour enters as (v - u0), which keeps float rounding small
         Real g1 = 0, g2 = 0;
-        if constexpr (SP != 0) {
+        if constexpr (SP == 3) {
+          // per axis the CD2; at the point next to a face whose delays are
+          // not both zero, the four-point stencil with the face's taps
+          const Real vel[3] = {vx, vy, vz};
+          const bool at_lo[3] = {x == 0, y == 0, z == 0};
+          const bool at_hi[3] = {x == bx - 1, y == by - 1, z == bz - 1};
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            auto nb = [&](int o) -> Real {
+              return a == 0 ? C[c_at + o] : a == 1 ? C[c_at + o * px_stride]
+                                          : lds[slot_of<DIM, SD>(z + o) * plane + c_at];
+            };
+            const Real vm = nb(-1) - u0, vp = nb(1) - u0;
+            Real d1 = c1[a][0] * vm + c1[a][2] * vp;
+            Real d2 = c2[a][0] * vm + c2[a][2] * vp;
+            const int f = 2 * a + (at_hi[a] ? 1 : 0);
+            if ((at_lo[a] || at_hi[a]) && kpos[f] != 0) {
+              const double* t = nut + f * kNuTaps;
+              const Real v2m = nb(-2) - u0, v2p = nb(2) - u0;
+              d1 = static_cast<Real>(t[0]) * v2m + static_cast<Real>(t[1]) * vm + static_cast<Real>(t[3]) * vp +
+                   static_cast<Real>(t[4]) * v2p;
+              d2 = static_cast<Real>(t[5]) * v2m + static_cast<Real>(t[6]) * vm + static_cast<Real>(t[8]) * vp +
+                   static_cast<Real>(t[9]) * v2p;
+            }
+            g1 += p.equation == AT_ADVDIFF ? vel[a] * d1 : d1;
+            g2 += d2;
+          }
+        } else if constexpr (SP != 0) {
           // per axis: the standard taps, or at the point next to a face whose
           // delay is positive the space-expanded stencil over the own points
           // and the 2 or 3 buffer points of level n - k in the halo frame
@@ -413,6 +448,46 @@ __device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n)
   return clamp_startup(k, n, p.T);
 }
 
+// Non-uniform-delay scheme, face f of PE pid at step n (Sec. 3.4 Example 1):
+// delays k1 (nearest buffer point: the face's draw) and k2 (second point: a
+// draw with the face index shifted by the number of faces), both clamped as
+// any delay. On the singular set 3 k1 = k2 (k1 >= 1) the nearest point takes
+// the next older level k1 + 1, which the ring still holds. Writes the use
+// flag, the two ring slots and the taps by offset o = -2..2 of both
+// derivatives, scaled by 1/dx and 1/dx^2: at a high face, for points (i-1,
+// i+1, i+2) the first derivative ((k2 - 4k1), -k2, k1) / (2 (3k1 - k2)) and
+// the second ((2k1 - k2), -k2, k1) / (3k1 - k2) (the centre tap is implied:
+// each row sums to zero); a low face takes the mirror image.
+__device__ inline void nonuniform_face(const StepParams& p, int pid, int f, int64_t n, int* kpos, int* slot,
+                                       double* nu) {
+  int k1 = face_delay(p, pid, f, n);
+  int k2 = 0;
+  if (p.mode == AT_DELAY_RNG) {
+    const uint32_t nfaces = static_cast<uint32_t>(p.npe * 2 * p.ndim);
+    k2 = clamp_startup(raw_delay(p.key, n, nfaces + static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L),
+                       n, p.T);
+  }
+  const bool use = k1 != 0 || k2 != 0;
+  if (use && 3 * k1 == k2) ++k1;
+  kpos[f] = use;
+  const int r0 = static_cast<int>(n % p.nslots);
+  slot[f * kMaxT + 0] = slot_back(r0, k1, p.nslots);
+  slot[f * kMaxT + 1] = slot_back(r0, k2, p.nslots);
+  const int a = f >> 1;
+  const double den = use ? static_cast<double>(3 * k1 - k2) : 1.0;
+  // taps at j = -1, +1, +2 of a high face
+  const double t1[3] = {(k2 - 4 * k1) / (2.0 * den), -k2 / (2.0 * den), k1 / (2.0 * den)};
+  const double t2[3] = {(2 * k1 - k2) / den, -k2 / den, k1 / den};
+  const int jj[3] = {-1, 1, 2};
+  const bool hi = f & 1;
+  for (int i = 0; i < kNuTaps; ++i) nu[f * kNuTaps + i] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const int o = hi ? jj[i] : -jj[i];
+    nu[f * kNuTaps + o + 2] = (hi ? t1[i] : -t1[i]) * p.sl1[a][kMaxS];
+    nu[f * kNuTaps + 5 + o + 2] = t2[i] * p.sl2[a][kMaxS];
+  }
+}
+
 template <typename Real, int DIM, int S, int SP>
 __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p) {
   constexpr int SD = strip_depth<S, SP>();
@@ -422,6 +497,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
   __shared__ int s_slot[6 * kMaxT];
   __shared__ int s_nbr[6];
   __shared__ int s_kpos[6];
+  __shared__ double s_nu[SP == 3 ? 6 * kNuTaps : 1];
 
   const int64_t n = p.counter[0];
   const int pid = blockIdx.x;
@@ -432,6 +508,10 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     const int f = tid;
     s_nbr[f] = neighbour(p, pid, f);
     s_kpos[f] = 0;
+    if constexpr (SP == 3) {
+      if (p.mode != AT_SYNC) nonuniform_face(p, pid, f, n, s_kpos, s_slot, s_nu);
+      return;
+    }
     if (p.mode != AT_SYNC) {
       const int k = face_delay(p, pid, f, n);
       s_kpos[f] = k > 0;
@@ -446,7 +526,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     }
   };
 
-  Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos);
+  Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nu);
   if (DIM == 3) {
     faces();
     __syncthreads();
@@ -567,6 +647,7 @@ template <typename Real, int DIM>
 hipError_t dispatch_s(const StepParams& p, int s, hipStream_t st, bool pub) {
   if (!pub && p.scheme != AT_SCHEME_TIME) {
     if (s != 1) return hipErrorInvalidValue;
+    if (p.scheme == AT_SCHEME_NONUNIFORM_212) return launch_t<Real, DIM, 1, 3>(p, st);
     return p.scheme == AT_SCHEME_SPACE_212 ? launch_t<Real, DIM, 1, 1>(p, st) : launch_t<Real, DIM, 1, 2>(p, st);
   }
   switch (s) {
@@ -591,6 +672,7 @@ template <typename Real, int DIM>
 size_t lds_s(const StepParams& p, int s) {
   if (p.scheme == AT_SCHEME_SPACE_212) return lds_bytes_t<Real, DIM, 1, 1>(p);
   if (p.scheme == AT_SCHEME_SPACE_222) return lds_bytes_t<Real, DIM, 1, 2>(p);
+  if (p.scheme == AT_SCHEME_NONUNIFORM_212) return lds_bytes_t<Real, DIM, 1, 3>(p);
   switch (s) {
     case 1: return lds_bytes_t<Real, DIM, 1, 0>(p);
     case 2: return lds_bytes_t<Real, DIM, 2, 0>(p);

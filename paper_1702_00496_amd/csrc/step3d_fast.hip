@@ -11,9 +11,12 @@ bool fast3d_valid_variant(int v) { return v == 1 || v == 2 || v == 4 || v == 9 |
 
 bool fast3d_applies(const StepParams& p, bool f64) {
   (void)f64;
+  // the non-uniform-delay scheme runs the generic sweep in every mode, so
+  // that its zero-delay and synchronous arms share one kernel
+  if (p.scheme == AT_SCHEME_NONUNIFORM_212) return false;
   // time-expanded AT (T = s + 1), the space-expanded schemes (schedule
   // variants 1 and 2) or the synchronous arm; other T take the generic kernel
-  const bool space = p.mode != AT_SYNC && p.scheme != AT_SCHEME_TIME;
+  const bool space = p.mode != AT_SYNC && (p.scheme == AT_SCHEME_SPACE_212 || p.scheme == AT_SCHEME_SPACE_222);
   const bool levels_ok = p.mode == AT_SYNC || (p.scheme == AT_SCHEME_TIME && p.T == p.s + 1) ||
                          (space && p.T == 1 && (p.depth == 1 || p.depth == 2));
   return p.ndim == 3 && p.bx == fast3d::kB && p.by == fast3d::kB && levels_ok &&
@@ -21,6 +24,7 @@ bool fast3d_applies(const StepParams& p, bool f64) {
 }
 
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st) {
+  if (p.mode != AT_SYNC && p.scheme == AT_SCHEME_NONUNIFORM_212) return hipErrorInvalidValue;
   if (p.mode != AT_SYNC && p.scheme != AT_SCHEME_TIME)
     return f64 ? launch_fast3d_space_f64(p, st) : launch_fast3d_space_f32(p, st);
   if (f64) {

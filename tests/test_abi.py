@@ -129,11 +129,25 @@ def test_space_expanded_schemes_size_rings_by_strip_depth_and_validate():
         st, _ = _size(L, lib, _prob(L, **kw), _delay(L, L=3, **dkw))
         assert st == L.AT_EINVAL, (kw, dkw)
     d = _delay(L, L=3)
-    d.scheme = 3
+    d.scheme = 4
     st, _ = _size(L, lib, p, d)
     assert st == L.AT_EINVAL
     st, _ = _size(L, lib, _prob(L, ndim=1, n=(16, 1, 1), pe=(8, 1, 1), order=2), _delay(L, L=3, scheme="space212"))
     assert st == L.AT_OK
+
+
+def test_nonuniform_scheme_sizes_two_deep_strips_and_validates():
+    """The non-uniform-delay scheme keeps one level of 2 buffer points per face
+    (the space212 ring) and takes no host delay table."""
+    L, lib = _lib()
+    p = _prob(L, ndim=1, n=(64, 1, 1), pe=(8, 1, 1), order=2, integrator="euler")
+    st, a = _size(L, lib, p, _delay(L, L=3, scheme="space212"))
+    st2, b = _size(L, lib, p, _delay(L, L=3, scheme="nonuniform212"))
+    assert st == st2 == L.AT_OK and a == b
+    st, _ = _size(L, lib, _prob(L, ndim=1, n=(64, 1, 1), pe=(8, 1, 1), order=4), _delay(L, L=3, scheme="nonuniform212"))
+    assert st == L.AT_EINVAL
+    st, _ = _size(L, lib, p, _delay(L, L=3, scheme="nonuniform212", T=2))
+    assert st == L.AT_EINVAL
 
 
 def test_host_delay_table_is_validated():

@@ -76,6 +76,13 @@ CASES = {
     "3d_fast_o2_space212_ab2": dict(ndim=3, n=(64, 32, 64), pe=(2, 1, 2), order=2, integrator="ab2", c=(0.5, 1.0, -1.0), L=4, scheme="space212", steps=14, ra=0.05),
     "3d_fast_o2_space222_rk2_burgers": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="rk2", equation="burgers", alpha=0.05, L=3, scheme="space222", steps=10, ra=0.02),
     "3d_fast_o2_space222_ab3_bz6": dict(ndim=3, n=(32, 64, 12), pe=(1, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=4, scheme="space222", steps=12, ra=0.02),
+    # non-uniform delays at the two buffer points (Sec. 3.4 Example 1); L = 8
+    # and L = 5 with uniform bins reach the singular set 3 k1 = k2 many times
+    "1d_o2_nonuniform_case2": dict(ndim=1, n=(128,), pe=(16,), order=2, integrator="euler", c=(0.0,), L=8, scheme="nonuniform212", steps=200, ra=0.05),
+    "1d_o2_nonuniform_ab2_min_edge": dict(ndim=1, n=(16,), pe=(8,), order=2, integrator="ab2", c=(1.0,), L=4, scheme="nonuniform212", steps=60, ra=0.05),
+    "2d_o2_nonuniform_rk2_ragged": dict(ndim=2, n=(40, 36), pe=(4, 3), order=2, integrator="rk2", c=(1.0, -0.5), L=6, scheme="nonuniform212", steps=30, ra=0.05),
+    "3d_o2_nonuniform_burgers": dict(ndim=3, n=(20, 20, 20), pe=(2, 2, 2), order=2, integrator="ab2", equation="burgers", alpha=0.05, L=4, scheme="nonuniform212", steps=12, ra=0.02),
+    "3d_o2_nonuniform_32x32_ab3": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=5, scheme="nonuniform212", steps=12, ra=0.02),
 }
 
 
@@ -109,7 +116,7 @@ def test_field_parity(name, precision):
 
 
 @pytest.mark.parametrize("name", ["1d_o2_euler_L3", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
-                                  "1d_o2_space222_case3"])
+                                  "1d_o2_space222_case3", "2d_o2_nonuniform_rk2_ragged"])
 def test_delays_bit_exact(name):
     case = _case(name)
     s = solver_for(case, "f64")
@@ -123,7 +130,8 @@ def test_delays_bit_exact(name):
 
 @pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
                                   "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16", "1d_o2_space222_case3",
-                                  "2d_o2_space212_ragged", "3d_o2_space222_ab2", "3d_fast_o2_space222"])
+                                  "2d_o2_space212_ragged", "3d_o2_space222_ab2", "3d_fast_o2_space222",
+                                  "1d_o2_nonuniform_case2", "3d_o2_nonuniform_32x32_ab3"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
@@ -136,6 +144,32 @@ def test_zero_delays_equal_synchronous_bitwise(name, precision):
         s.step(case["steps"])
         out[mode] = s.state()
     assert torch.equal(out["zero"], out["sync"])
+
+
+@pytest.mark.parametrize("name", ["1d_o2_nonuniform_case2", "3d_o2_nonuniform_32x32_ab3"])
+def test_nonuniform_cases_reach_the_singular_set(name):
+    """The non-uniform parity cases draw (k1, k2) on the singular set 3 k1 = k2
+    with k1 >= 1 (handled by the older level k1 + 1) and pairs with k1 != k2;
+    their field parity is test_field_parity."""
+    from oracle.solver import point_delay_table
+    case = _case(name)
+    o = oracle_for(case, initial_field(case))
+    sing = unequal = 0
+    for n in range(case["steps"]):
+        K1 = delay_table(o.prob, o.dm, n)
+        K2 = point_delay_table(o.prob, o.dm, n)
+        sing += int(((3 * K1 == K2) & (K1 >= 1)).sum())
+        unequal += int((K1 != K2).sum())
+    assert sing >= 3 and unequal > 10 * sing, (sing, unequal)
+
+
+def test_nonuniform_scheme_rejects_host_tables_and_other_orders():
+    from paper_1702_00496_amd import ATError
+    case = _case("1d_o2_nonuniform_ab2_min_edge")
+    with pytest.raises(ATError, match="per-point"):
+        solver_for(dict(case, mode="host", host=np.zeros((4, 8, 1, 2), dtype=np.int8)))
+    with pytest.raises(ATError, match="order 2"):
+        solver_for(dict(case, order=4, n=(32,), pe=(4,)))
 
 
 def test_zero_steps_and_repeated_state_are_no_ops():
@@ -189,7 +223,8 @@ def test_first_configuration_full_run():
         assert abs(got[k] - want[k]) <= 1e-9 * want[k], (k, got[k], want[k])
 
 
-@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_fast_o2_space222", "2d_o2_space212_ragged"])
+@pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_fast_o2_space222", "2d_o2_space212_ragged",
+                                  "2d_o2_nonuniform_rk2_ragged"])
 def test_checkpoint_resume_bitwise(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
@@ -208,7 +243,8 @@ def test_checkpoint_resume_bitwise(name):
 
 
 @pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3", "3d_fast_o6_rk2_burgers",
-                                  "3d_fast_o2_space222_rk2_burgers", "1d_o2_space222_case3"])
+                                  "3d_fast_o2_space222_rk2_burgers", "1d_o2_space222_case3",
+                                  "3d_o2_nonuniform_32x32_ab3"])
 def test_graph_replay_equals_plain_launches(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
@@ -222,6 +258,7 @@ def test_graph_replay_equals_plain_launches(name):
         b.step(7)
         torch.cuda.synchronize()
         _ = b.state().sum().item()
+    assert torch.isfinite(a.state()).all()
     assert torch.equal(a.state(), b.state())
 
 
