@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint,space,study",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -281,6 +281,54 @@ def time_space():
                          "against time-expanded (1,2,2)b+(2,2,2)b", arms=res)
 
 
+def time_nonuniform():
+    """The non-uniform-delay scheme (Sec. 3.4 Example 1: own delays at the two
+    buffer points next to a face) against the uniform-delay (1,2,2)a/(2,1,2)
+    pair and the time-expanded (1,2,2)b/(2,2,2)b (T = 2) on one kernel, the
+    generic sweep: 2-D 4096^2, 64 x 64 PEs of 64^2, second-order CD,
+    advection-diffusion, Euler, L = 4 with uniform delays, FP32 bulk, 100
+    steps. Bytes per update (solution in place): u read and written, plus per
+    face column (h = 4 / 64 per point) the halo values the sweep loads and the
+    strip it publishes: 2 + 2 for the single-level pair and the non-uniform
+    scheme (2-deep strips, one level each), T + 1 for the time-expanded one."""
+    n2 = (4096, 4096)
+    pe = (64, 64)
+    alpha = 0.1
+    dx = 2 * math.pi / n2[0]
+    dt = 0.05 * dx * dx / alpha
+    steps = 100
+    modes = W.make_modes([(1, 2, 0), (3, 1, 0), (2, 5, 0)], [1.0, 0.5, 0.25], seed=5)
+    u2 = torch.from_numpy(W.eval_modes(modes, n2 + (1,), 2))
+    h = 4 / 64
+    res = {}
+    for scheme, per_col in (("nonuniform212", 4), ("space212", 4), ("time", 3)):
+        s = Solver(ndim=2, n=n2, pe=pe, dt=dt, order=2, c=(1.0, 0.5), alpha=alpha, integrator="euler",
+                   precision="f32", L=4, seed=17, scheme=scheme)
+        s.set_state(u2)
+        s.step(5)
+        s.set_graph(20)
+        s.set_state(u2)
+        s.step(20)
+        s.set_state(u2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nrm = s.norms(modes=modes)
+        bpu = 4 * (2 + h * per_col)
+        ups = n2[0] * n2[1] * steps / (ms / 1e3)
+        res[scheme] = dict(ms_per_step=ms / steps, updates_per_s=ups, bytes_per_update=bpu,
+                           achieved_gbs=ups * bpu / 1e9, frac=ups * bpu / 1e9 / HBM_PEAK_GBS,
+                           l2_error=nrm["l2"], l2_error_boundary=nrm["l2_b"])
+    res["config"] = {"n": list(n2), "pe": list(pe), "order": 2, "integrator": "euler", "L": 4,
+                     "weights": "uniform", "precision": "f32", "steps": steps, "kernel": "generic sweep"}
+    return res
+
+
 def time_study():
     """The moment-law study of Sec. 5.2 on the ensemble kernel: the Case 1
     scheme (order 2, T = 2, Euler), N = 1024 with 16 PEs, p_k = 1/L for
@@ -427,7 +475,7 @@ if "f32" in arms and "sync32" in arms:
 others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
-                 "space": time_space, "study": time_study}[w]()
+                 "space": time_space, "study": time_study, "nonuniform": time_nonuniform}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:
