@@ -59,7 +59,7 @@ def search_scheme(d, a, r, s_min, k, T=1, with_centre=True, side="right", max_ex
     num = (ctypes.c_int64 * cap)()
     den = (ctypes.c_int64 * cap)()
     info = _lib.AtDerivation()
-    sd = {"right": 1, "left": -1}[side]
+    sd = {"right": 1, "left": -1}.get(side, 0)    # anything else: the library rejects it
     _lib.check(lib.at_search_scheme(d, a, r, s_min, 1 if with_centre else 0, k, T, sd, max_extent, cap,
                                     ctypes.byref(n_out), js, ls, num, den, ctypes.byref(info)))
     out = _info_dict(info)

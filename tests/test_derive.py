@@ -214,3 +214,31 @@ def test_derivation_rejects_bad_arguments_and_overflow():
         derive.derive_scheme([(0, 0), (40, 0)], 1, 2, 2)
     with pytest.raises(ATError, match="overflow|64-bit"):
         derive.derive_scheme([(j, (j * 37) % 65) for j in range(-32, 8)], 4, 12, 1)
+
+
+def test_search_rejects_bad_arguments_and_reports_no_scheme():
+    derive = _derive()
+    from paper_1702_00496_amd import ATError
+    with pytest.raises(ATError, match="side"):
+        derive.search_scheme(1, 2, 2, s_min=1, k=1, side="up")
+    with pytest.raises(ATError, match="levels"):
+        derive.search_scheme(1, 2, 2, s_min=1, k=-1)
+    with pytest.raises(ATError, match="s_min"):
+        derive.search_scheme(1, 2, 2, s_min=40, k=1)
+    with pytest.raises(ATError, match="max_extent"):
+        derive.search_scheme(1, 2, 2, s_min=1, k=1, max_extent=0)
+    # order 12 first derivative with one interior point and one buffer point
+    # per extent: the buffer alone never satisfies the conditions up to 2 points
+    found, info = derive.search_scheme(1, 12, 1, s_min=0, k=1, with_centre=False, max_extent=2)
+    assert found is None and info["status"] == "none"
+
+
+def test_search_left_side_is_the_mirror_image():
+    """side='left' puts the buffer at j < 0: j -> -j, coefficients times (-1)^d,
+    and the mirrored stencil is again the oracle's unique solution."""
+    derive = _derive()
+    for d, a in ((1, 2), (2, 2), (2, 4)):
+        right, _ = derive.search_scheme(d, a, 2, s_min=a // 2, k=2, T=coeffs.n_time_levels(d, a, 2))
+        left, _ = derive.search_scheme(d, a, 2, s_min=a // 2, k=2, T=coeffs.n_time_levels(d, a, 2), side="left")
+        assert left == {(-j, l): (-1) ** d * c for (j, l), c in right.items()}
+        assert coeffs.derive_scheme(sorted(left), d, a, 2) == ("unique", left)

@@ -82,6 +82,8 @@ CASES = {
     "1d_o2_nonuniform_ab2_min_edge": dict(ndim=1, n=(16,), pe=(8,), order=2, integrator="ab2", c=(1.0,), L=4, scheme="nonuniform212", steps=60, ra=0.05),
     "2d_o2_nonuniform_rk2_ragged": dict(ndim=2, n=(40, 36), pe=(4, 3), order=2, integrator="rk2", c=(1.0, -0.5), L=6, scheme="nonuniform212", steps=30, ra=0.05),
     "3d_o2_nonuniform_burgers": dict(ndim=3, n=(20, 20, 20), pe=(2, 2, 2), order=2, integrator="ab2", equation="burgers", alpha=0.05, L=4, scheme="nonuniform212", steps=12, ra=0.02),
+    "1d_o2_nonuniform_single_pe_L5": dict(ndim=1, n=(32,), pe=(1,), order=2, integrator="ab2", c=(1.0,), L=5, weights=[1, 1, 1, 3, 3], scheme="nonuniform212", steps=80, ra=0.05),
+    "2d_o2_nonuniform_pe1x5_ab3": dict(ndim=2, n=(24, 40), pe=(1, 5), order=2, integrator="ab3", c=(0.5, 1.0), L=8, scheme="nonuniform212", steps=40, ra=0.02),
     "3d_o2_nonuniform_32x32_ab3": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=5, scheme="nonuniform212", steps=12, ra=0.02),
 }
 
@@ -161,6 +163,20 @@ def test_nonuniform_cases_reach_the_singular_set(name):
         sing += int(((3 * K1 == K2) & (K1 >= 1)).sum())
         unequal += int((K1 != K2).sum())
     assert sing >= 3 and unequal > 10 * sing, (sing, unequal)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_nonuniform_with_one_delay_level_is_the_synchronous_scheme(precision):
+    """L = 1: every delay is 0, so no face takes the four-point stencil."""
+    case = dict(_case("2d_o2_nonuniform_rk2_ragged"), L=1)
+    u0 = torch.from_numpy(initial_field(case))
+    out = {}
+    for mode in ("rng", "sync"):
+        s = solver_for(dict(case, mode=mode), precision)
+        s.set_state(u0)
+        s.step(case["steps"])
+        out[mode] = s.state()
+    assert torch.equal(out["rng"], out["sync"])
 
 
 def test_nonuniform_scheme_rejects_host_tables_and_other_orders():
