@@ -620,15 +620,18 @@ size_t lds_bytes_t(const StepParams& p) {
 // Workgroup size of the generic sweep: about four points of a plane per
 // thread. A 3-D PE walks its planes with a barrier per plane, so it keeps up
 // to 1024 threads (a 48 x 48 plane: 576). A 1-D or 2-D PE is a single plane
-// loaded and computed once: there at most 256 threads (16 points each for a
-// 64 x 64 PE) let several workgroups share a compute unit, one loading while
-// another computes (4096^2 in 64^2 PEs: 78 us per step against 139 us with
-// 1024 threads, whose one workgroup per CU serialises the phases).
+// loaded and computed once: when there are PEs enough for four workgroups per
+// compute unit (256 CUs), at most 256 threads (16 points each for a 64 x 64
+// PE) let several workgroups share a CU, one loading while another computes
+// (4096^2 in 4096 PEs of 64^2: 78 us per step against 139 us with 1024
+// threads, whose one workgroup per CU serialises the phases); with fewer PEs
+// the larger groups keep the CUs filled (1024^2 in 256 PEs of 64^2: 14 us
+// with 1024 threads, 20 us with 256).
 int sweep_threads(const StepParams& p) {
   const int64_t pts = static_cast<int64_t>(p.bx) * (p.ndim >= 2 ? p.by : 1);
   int64_t t = (pts / 4 + 63) / 64 * 64;
   if (t < 64) t = 64;
-  const int64_t cap = p.ndim == 3 ? kMaxSweepThreads : 256;
+  const int64_t cap = (p.ndim == 3 || p.npe < 4 * 256) ? kMaxSweepThreads : 256;
   if (t > cap) t = cap;
   return static_cast<int>(t);
 }
