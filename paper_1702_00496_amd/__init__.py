@@ -11,7 +11,7 @@ import math
 import numpy as np
 import torch
 
-from . import _lib
+from . import _lib, tuning
 from ._lib import ATError, AtDelay, AtEnsMember, AtProblem, check
 
 __all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS"]
@@ -76,6 +76,9 @@ class Solver:
             dl.host_delays = hd.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
             dl.host_nsteps = hd.shape[0]
         self._prob, self._delay = prob, dl
+        self._spec = dict(ndim=ndim, edges=tuple(n[a] // pe[a] for a in range(3)), order=order, T=T,
+                          scheme=scheme, precision=precision, integrator=integrator, equation=equation,
+                          mode=mode)
         nbytes = ctypes.c_size_t(0)
         check(L_.at_workspace_size(ctypes.byref(prob), ctypes.byref(dl), ctypes.byref(nbytes)))
         self.workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.device)
@@ -119,15 +122,34 @@ class Solver:
         check(self._lib.at_get_tuning(self._ctx, ctypes.byref(v)), self._ctx)
         return v.value
 
-    def autotune(self, nsteps=10):
+    def tuning_key(self):
+        """Cache key of this problem class on the current device."""
+        props = torch.cuda.get_device_properties(self.device)
+        return tuning.make_key(getattr(props, "gcnArchName", props.name), props.multi_processor_count,
+                               **self._spec)
+
+    def autotune(self, nsteps=10, cache=None):
         """Time every schedule candidate on the current state (restored
-        afterwards) and keep the fastest. Returns (depth, {depth: ms/step})."""
+        afterwards) and keep the fastest. Returns (depth, {depth: ms/step}).
+
+        ``cache``: path of a JSON tuning cache (``tuning.default_path()`` for
+        the per-user one). A stored entry for this problem class is applied
+        without timing (its recorded times are returned); otherwise the
+        result is timed and stored."""
+        if cache is not None:
+            ent = tuning.lookup(cache, self.tuning_key())
+            if ent is not None:
+                self.set_tuning(ent["variant"])
+                return ent["variant"], {int(k): v for k, v in ent.get("ms", {}).items()}
         scratch = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device=self.device)
         best = ctypes.c_int32(0)
         ms = (ctypes.c_double * 6)()
         check(self._lib.at_autotune(self._ctx, _as_ptr(scratch), scratch.numel(), int(nsteps),
                                     ctypes.byref(best), ms), self._ctx)
-        return best.value, {d: ms[i] for i, d in enumerate(VARIANTS) if ms[i] >= 0}
+        times = {d: ms[i] for i, d in enumerate(VARIANTS) if ms[i] >= 0}
+        if cache is not None:
+            tuning.store(cache, self.tuning_key(), best.value, times)
+        return best.value, times
 
     def state(self):
         out = torch.empty(self.shape, dtype=self.dtype, device=self.device)

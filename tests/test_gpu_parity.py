@@ -380,6 +380,28 @@ def test_schedule_depths_bit_identical_and_autotune_restores_state(precision):
     assert torch.equal(s.state(), outs[0])
 
 
+def test_autotune_cache_stores_then_applies_without_timing(tmp_path):
+    """The first autotune of a problem class times the candidates and stores
+    the winner; a second context of the same class (other data, other seed)
+    takes it from the cache; another class misses."""
+    from paper_1702_00496_amd import tuning
+    case = _case("3d_fast_o4_ab2_bz16")
+    path = str(tmp_path / "tuning.json")
+    u0 = torch.from_numpy(initial_field(case))
+    a = solver_for(case, "f32")
+    a.set_state(u0)
+    best, ms = a.autotune(nsteps=3, cache=path)
+    ent = tuning.lookup(path, a.tuning_key())
+    assert ent is not None and ent["variant"] == best and len(ent["ms"]) == len(ms)
+    b = solver_for(dict(case, seed=99), "f32")
+    b.set_state(2 * u0)
+    assert b.tuning_key() == a.tuning_key()
+    best2, ms2 = b.autotune(nsteps=3, cache=path)
+    assert best2 == best and b.tuning() == best and ms2 == ms
+    c = solver_for(case, "f64")
+    assert c.tuning_key() != a.tuning_key() and tuning.lookup(path, c.tuning_key()) is None
+
+
 def test_full_size_burgers_workload_properties():
     """512^3 viscous Burgers (16^3 PEs of 32^3, sixth order, T = 4, L = 8, Heun
     RK2) in the benchmark's launch configuration, 8 steps (delays up to 5
