@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform,matched",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -329,6 +329,66 @@ def time_nonuniform():
     return res
 
 
+def _run_family_point(cfg, mode, steps, precision="f64", graph=50):
+    nd = cfg["ndim"]
+    s = Solver(ndim=nd, n=cfg["n"][:nd], pe=cfg["pe"][:nd], dt=cfg["dt"], order=cfg["order"], c=cfg["c"][:nd],
+               alpha=cfg["alpha"], integrator=cfg["integrator"], precision=precision, L=cfg["L"],
+               seed=cfg["seed"], mode=mode)
+    u = torch.from_numpy(W.eval_modes(cfg["modes"], cfg["n"], nd))
+    s.set_graph(graph)
+    s.set_state(u)
+    s.step(graph)                       # capture outside the timing
+    s.set_state(u)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return ms, s.norms(modes=cfg["modes"])["l2"]
+
+
+def time_matched():
+    """Standard scheme against AT at matched error (FP64): for the 1-D
+    (N = 256, 8 PEs, order 2, Euler, L = 3, 1000 steps) and the 3-D (256^3,
+    PEs of 32^3, order 4, AB2, L = 4, 500 steps) workloads, N is swept at
+    fixed diffusive CFL and final time (steps scale with N^2). log E against
+    log N and log time against log N are fitted by least squares for the AT
+    arm; N* is where the AT error equals the synchronous error at the
+    reference N, and the reported ratio is AT's time at N* over the
+    synchronous time at the reference N (the intrinsic cost of AT on one GPU,
+    where the synchronous scheme waits for nothing)."""
+    fams = {
+        "1d_order2": (W.config_1d_advdiff, 256, 1000, (128, 256, 512, 1024), lambda n: dict(n=n, pe=8)),
+        "3d_order4": (W.config_3d_advdiff, 256, 500, (128, 192, 256, 320), lambda n: dict(n=n, b=32)),
+    }
+    res = {}
+    for name, (make_cfg, n_ref, steps_ref, ns, kw) in fams.items():
+        t_final = make_cfg(**kw(n_ref))["dt"] * steps_ref
+        rows = []
+        for n in ns:
+            cfg = make_cfg(**kw(n))
+            steps = int(round(steps_ref * (n / n_ref) ** 2))
+            cfg["dt"] = t_final / steps
+            at_ms, at_e = _run_family_point(cfg, "rng", steps)
+            sy_ms, sy_e = _run_family_point(cfg, "sync", steps)
+            rows.append(dict(n=n, steps=steps, at_ms=at_ms, sync_ms=sy_ms, at_l2=at_e, sync_l2=sy_e))
+        ln = np.log([r["n"] for r in rows])
+        fit_e = np.polyfit(ln, np.log([r["at_l2"] for r in rows]), 1)
+        fit_t = np.polyfit(ln, np.log([r["at_ms"] for r in rows]), 1)
+        ref = next(r for r in rows if r["n"] == n_ref)
+        n_star = float(np.exp((np.log(ref["sync_l2"]) - fit_e[1]) / fit_e[0]))
+        t_star = float(np.exp(np.polyval(fit_t, np.log(n_star))))
+        res[name] = dict(rows=rows, t_final=t_final, at_error_slope=float(fit_e[0]),
+                         sync_error_slope=float(np.polyfit(ln, np.log([r["sync_l2"] for r in rows]), 1)[0]),
+                         at_time_slope=float(fit_t[0]), n_ref=n_ref, sync_l2_at_n_ref=ref["sync_l2"],
+                         n_star=n_star, at_ms_at_n_star=t_star, sync_ms_at_n_ref=ref["sync_ms"],
+                         time_to_solution_ratio=t_star / ref["sync_ms"])
+    return res
+
+
 def time_study():
     """The moment-law study of Sec. 5.2 on the ensemble kernel: the Case 1
     scheme (order 2, T = 2, Euler), N = 1024 with 16 PEs, p_k = 1/L for
@@ -475,7 +535,8 @@ if "f32" in arms and "sync32" in arms:
 others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
-                 "space": time_space, "study": time_study, "nonuniform": time_nonuniform}[w]()
+                 "space": time_space, "study": time_study, "nonuniform": time_nonuniform,
+                 "matched": time_matched}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:
