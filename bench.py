@@ -168,8 +168,14 @@ def cpu_baseline():
     t0 = time.perf_counter()
     o.run(args.cpu_steps)
     dt_ = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return dict(value=npts * args.cpu_steps / dt_, unit="grid-pt updates/s",
-                cores=torch.get_num_threads(), kind="oracle",
+                cores=torch.get_num_threads(), cpu_model=model, kind="oracle",
                 sample=f"first {args.cpu_steps} of {cfg['steps']} steps of the {N}^3 workload, FP64, "
                        f"{dt_:.1f} s")
 
