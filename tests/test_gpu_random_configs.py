@@ -1,0 +1,66 @@
+"""Seeded random configurations against the oracle: dimension, ragged PE
+shapes, order, scheme family, T, L and bin weights, integrator, equation,
+delay mode and precision drawn together, so that combinations no hand-picked
+case covers are still checked to the usual bar (relative L2 <= 1e-12 FP64,
+<= 1e-5 FP32). Every configuration is one the library's validation accepts."""
+import math
+import random
+
+import numpy as np
+import pytest
+import torch
+
+from tests._cases import initial_field, oracle_for, rel_l2, solver_for
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def draw(seed):
+    rng = random.Random(seed)
+    ndim = rng.choice((1, 1, 2, 2, 3))
+    scheme = rng.choice(("time", "time", "time", "space212", "space222", "nonuniform212"))
+    order = 2 if scheme != "time" else rng.choice((2, 4, 6))
+    s = order // 2
+    depth = 3 if scheme == "space222" else (2 if scheme != "time" else s)
+    need = max(2 * s, depth)
+    n, pe = [], []
+    for a in range(ndim):
+        p = rng.choice((1, 2, 3, 4)) if ndim < 3 else rng.choice((1, 2, 3))
+        b = rng.randint(need, need + (9 if ndim == 1 else 5 if ndim == 2 else 3))
+        n.append(p * b)
+        pe.append(p)
+    equation = rng.choice(("advdiff", "advdiff", "burgers"))
+    integrator = rng.choice(("euler", "ab2", "ab3", "rk2"))
+    L = rng.randint(1, 6)
+    T = 0 if scheme != "time" else rng.choice((0, 0, 1))
+    weights = None if rng.random() < 0.5 else [rng.randint(1, 5) for _ in range(L)]
+    c = tuple(round(rng.uniform(-1, 1), 3) for _ in range(ndim))
+    alpha = 0.05 if equation == "burgers" else 0.1
+    dx = 2 * math.pi / max(n)
+    case = dict(ndim=ndim, n=tuple(n), pe=tuple(pe), order=order, integrator=integrator, equation=equation,
+                c=c, alpha=alpha, L=L, T=T, weights=weights, scheme=scheme, seed=rng.randint(0, 2 ** 31),
+                mode=rng.choice(("rng", "rng", "rng", "zero")), dt=min(0.005 * dx * dx / alpha, 0.02 * dx),
+                steps=rng.randint(5, 25), ic_seed=rng.randint(0, 100))
+    return case, rng.choice(("f64", "f32"))
+
+
+@pytest.mark.parametrize("seed", range(64))
+def test_random_configuration_matches_the_oracle(seed):
+    case, precision = draw(1000 + seed)
+    print(f"[random] seed {seed}: {case} {precision}", flush=True)
+    u0 = initial_field(case)
+    s = solver_for(case, precision)
+    s.set_state(torch.from_numpy(u0))
+    s.step(case["steps"])
+    got = s.state().double().cpu()
+    o = oracle_for(case, u0)
+    o.run(case["steps"])
+    assert torch.isfinite(got).all()
+    err = rel_l2(got, o.u)
+    assert err <= TOL[precision], (case, precision, err)
+    if case["mode"] == "rng":
+        d = s.delays(0, case["steps"])
+        for k in range(case["steps"]):
+            assert np.array_equal(d[k], o.delays[k].numpy().reshape(d[k].shape)), k
