@@ -103,6 +103,53 @@ def test_ensemble_matches_oracle_member_by_member(precision):
         off += m["n"]
 
 
+def _random_members(seed, count):
+    """Seeded heterogeneous members: PE edges from the minimum 2s up, one to
+    eight PEs, every order, both integrators, T from the default or 1..4, L
+    1..8, optional bin weights, every delay mode; diffusive and advective
+    time-step bounds keep each member from growing."""
+    import random
+    rng = random.Random(seed)
+    out = []
+    for i in range(count):
+        order = rng.choice((2, 4, 6))
+        s = order // 2
+        pe = rng.randint(1, 8)
+        n = pe * rng.randint(2 * s, 2 * s + 20)
+        T = rng.choice((0, 0, 0, 1, 2, 3, 4))
+        L = rng.randint(1, 3 if T > 2 else 8)
+        dx = 2 * math.pi / n
+        ra = {2: 0.05, 4: 0.01, 6: 0.004}[order]
+        m = dict(n=n, pe=pe, order=order, integrator=rng.choice(("euler", "ab2")), L=L, T=T,
+                 mode=rng.choice(("rng", "rng", "rng", "zero", "sync")), c=round(rng.uniform(-1, 1), 3),
+                 alpha=0.1, seed=rng.randint(0, 2 ** 40), length=2 * math.pi,
+                 dt=min(ra * dx * dx / 0.1, 0.05 * dx))
+        if rng.random() < 0.4:
+            m["weights"] = [rng.randint(1, 6) for _ in range(L)]
+        out.append(m)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_ensemble_random_members_match_oracle(precision):
+    members = _random_members(4242, 40)
+    ph = _phases(len(members), seed=5)
+    u0 = _u0(members, ph)
+    steps = 40
+    _say(f"[ens] random members {precision}: {len(members)} members, {steps} steps")
+    ens = _ensemble(members, precision)
+    ens.set_state(torch.from_numpy(u0))
+    ens.run(steps)
+    got = ens.split(ens.state().cpu())
+    off = 0
+    for i, m in enumerate(members):
+        o = _oracle(m, u0[off:off + m["n"]])
+        o.run(steps)
+        err = rel_l2(got[i], o.u.reshape(-1))
+        assert err <= TOL[precision], (i, m, err)
+        off += m["n"]
+
+
 def test_ensemble_zero_delays_equal_synchronous_bitwise():
     base = [dict(m, mode="zero") for m in MEMBERS]
     sync = [dict(m, mode="sync") for m in MEMBERS]
