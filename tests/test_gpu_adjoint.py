@@ -247,3 +247,40 @@ def test_adjoint_full_burgers_workload_against_finite_differences():
     _say(f"[adj]   nu: adjoint {ga:.9e}  fd {fda:.9e}   worst direction {worst:.2e}")
     assert worst <= 1e-3
     assert ga == pytest.approx(fda, rel=1e-3)
+
+
+def _random_case(seed):
+    """A seeded configuration the adjoint covers (time-expanded schemes;
+    Euler, AB2, Heun RK2; advection-diffusion or Burgers; every delay mode)."""
+    import random
+    rng = random.Random(seed)
+    ndim = rng.choice((1, 1, 2, 2, 3))
+    order = rng.choice((2, 4, 6))
+    s = order // 2
+    n, pe = [], []
+    for a in range(ndim):
+        p = rng.randint(1, 4) if ndim < 3 else rng.randint(1, 2)
+        n.append(p * rng.randint(2 * s, 2 * s + (10 if ndim == 1 else 4 if ndim == 2 else 2)))
+        pe.append(p)
+    equation = rng.choice(("advdiff", "advdiff", "burgers"))
+    alpha = 0.05 if equation == "burgers" else 0.1
+    dx = 2 * math.pi / max(n)
+    case = dict(ndim=ndim, n=tuple(n), pe=tuple(pe), order=order, integrator=rng.choice(("euler", "ab2", "rk2")),
+                equation=equation, c=tuple(round(rng.uniform(-1, 1), 3) for _ in range(ndim)), alpha=alpha,
+                L=rng.randint(1, 6), T=rng.choice((0, 0, 1)), mode=rng.choice(("rng", "rng", "zero", "sync")),
+                seed=rng.randint(0, 2 ** 31), steps=rng.randint(4, 20), every=rng.randint(2, 8),
+                dt=min(0.005 * dx * dx / alpha, 0.02 * dx), ic_seed=rng.randint(0, 100))
+    return case, rng.choice(("f64", "f32"))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_adjoint_random_configuration_matches_oracle_gradients(seed):
+    case, precision = _random_case(7000 + seed)
+    _say(f"[adj] random {seed}: {case} {precision}")
+    u0 = initial_field(case)
+    sd = _seed(case)
+    gu_o, ga_o = _oracle_grads(case, u0, sd)
+    s, gu, ga = _gpu_grads(case, u0, sd, precision)
+    tol = 1e-10 if precision == "f64" else 1e-4
+    assert rel_l2(gu, gu_o) <= tol, (case, precision, rel_l2(gu, gu_o))
+    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3), (case, precision, ga, ga_o)
