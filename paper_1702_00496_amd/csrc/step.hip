@@ -71,7 +71,7 @@ struct Sweep {
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
                    const int* ls_, const int* nb_, const int* kp_, const double* nu_)
       : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
-    pid = blockIdx.x;
+    pid = blockIdx.x % p.npe;   // workgroups beyond npe take further z-chunks of the PEs
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
     qz = pid / (p.px * p.py);
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
   __shared__ double s_nu[SP == 3 ? 6 * kNuTaps : 1];
 
   const int64_t n = p.counter[0];
-  const int pid = blockIdx.x;
+  const int pid = blockIdx.x % p.npe;
   const int tid = threadIdx.x;
   // neighbours, delays and level weights of the 2 * DIM faces
   auto faces = [&]() {
@@ -528,13 +528,21 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
 
   Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nu);
   if (DIM == 3) {
+    // workgroup blockIdx.x / npe sweeps z-chunk [zc0, zc1) of its PE; the
+    // SD planes on either side come from the PE (or across its z faces)
+    const int nch = gridDim.x / p.npe;
+    const int zper = (p.bz + nch - 1) / nch;
+    const int zc0 = static_cast<int>(blockIdx.x / p.npe) * zper;
+    const int zc1 = zc0 + zper < p.bz ? zc0 + zper : p.bz;
     faces();
     __syncthreads();
-    for (int zz = -SD; zz < SD; ++zz) sw.load_plane(zz);
-    for (int z = 0; z < p.bz; ++z) {
-      sw.load_plane(z + SD);
-      __syncthreads();
-      sw.compute_plane(z);
+    if (zc0 < zc1) {
+      for (int zz = zc0 - SD; zz < zc0 + SD; ++zz) sw.load_plane(zz);
+      for (int z = zc0; z < zc1; ++z) {
+        sw.load_plane(z + SD);
+        __syncthreads();
+        sw.compute_plane(z);
+      }
     }
   } else {
     // the PE's own values do not depend on the delays: their loads are in
@@ -636,10 +644,35 @@ int sweep_threads(const StepParams& p) {
   return static_cast<int>(t);
 }
 
+// Workgroups per PE of the generic sweep. A 3-D PE's planes are split into
+// z-chunks (each reloads the SD planes around it) when the PEs alone leave
+// compute units idle: as many chunks as fit in one round of resident
+// workgroups (256 CUs, each holding as many as its LDS and thread slots
+// allow, at most four), with at least 8 planes per chunk. Only where no
+// chunk overwrites planes another one reads: the new level goes to the other
+// solution buffer, or the stage writes the RK2 predictor / reads it (Heun).
+// 1-D and 2-D PEs are a single plane.
+int sweep_chunks(const StepParams& p, size_t lds, int threads) {
+  if (p.ndim != 3) return 1;
+  if (p.ubuf[0] == p.ubuf[1] && p.integrator != AT_RK2) return 1;
+  int per_cu = static_cast<int>((160 * 1024) / (lds > 0 ? lds : 1));
+  const int by_threads = 2048 / threads;
+  if (per_cu > by_threads) per_cu = by_threads;
+  if (per_cu > 4) per_cu = 4;
+  if (per_cu < 1) per_cu = 1;
+  const int want = 256 * per_cu / p.npe;
+  if (want <= 1) return 1;
+  int zper = (p.bz + want - 1) / want;
+  if (zper < 8) zper = 8;
+  return (p.bz + zper - 1) / zper;
+}
+
 template <typename Real, int DIM, int S, int SP>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
   const size_t lds = lds_bytes_t<Real, DIM, S, SP>(p);
-  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(p.npe), dim3(sweep_threads(p)), lds, st, p);
+  const int threads = sweep_threads(p);
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(p.npe * sweep_chunks(p, lds, threads)), dim3(threads),
+                     lds, st, p);
   return hipGetLastError();
 }
 

@@ -76,6 +76,10 @@ CASES = {
     "3d_fast_o2_space212_ab2": dict(ndim=3, n=(64, 32, 64), pe=(2, 1, 2), order=2, integrator="ab2", c=(0.5, 1.0, -1.0), L=4, scheme="space212", steps=14, ra=0.05),
     "3d_fast_o2_space222_rk2_burgers": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="rk2", equation="burgers", alpha=0.05, L=3, scheme="space222", steps=10, ra=0.02),
     "3d_fast_o2_space222_ab3_bz6": dict(ndim=3, n=(32, 64, 12), pe=(1, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=4, scheme="space222", steps=12, ra=0.02),
+    # deep PEs on the generic 3-D sweep: their planes are split into z-chunks
+    # of several workgroups (6 and 3 chunks), with two solution buffers for AB2
+    "3d_o4_ab2_chunked": dict(ndim=3, n=(40, 40, 48), pe=(2, 2, 1), order=4, integrator="ab2", c=(1.0, -0.5, 0.7), L=4, steps=10, ra=0.02),
+    "3d_o6_rk2_chunked": dict(ndim=3, n=(30, 30, 40), pe=(1, 1, 2), order=6, integrator="rk2", c=(0.5, 0.5, 1.0), L=3, steps=8, ra=0.004),
     # non-uniform delays at the two buffer points (Sec. 3.4 Example 1); L = 8
     # and L = 5 with uniform bins reach the singular set 3 k1 = k2 many times
     "1d_o2_nonuniform_case2": dict(ndim=1, n=(128,), pe=(16,), order=2, integrator="euler", c=(0.0,), L=8, scheme="nonuniform212", steps=200, ra=0.05),
@@ -133,7 +137,8 @@ def test_delays_bit_exact(name):
 @pytest.mark.parametrize("name", ["1d_o4_ab2_ragged", "2d_o4_ab2_ragged", "3d_o4_ab2_ragged", "3d_o6_rk2_burgers",
                                   "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16", "1d_o2_space222_case3",
                                   "2d_o2_space212_ragged", "3d_o2_space222_ab2", "3d_fast_o2_space222",
-                                  "1d_o2_nonuniform_case2", "3d_o2_nonuniform_32x32_ab3"])
+                                  "1d_o2_nonuniform_case2", "3d_o2_nonuniform_32x32_ab3", "3d_o4_ab2_chunked",
+                                  "3d_o6_rk2_chunked"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
@@ -240,7 +245,7 @@ def test_first_configuration_full_run():
 
 
 @pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_fast_o2_space222", "2d_o2_space212_ragged",
-                                  "2d_o2_nonuniform_rk2_ragged"])
+                                  "2d_o2_nonuniform_rk2_ragged", "3d_o4_ab2_chunked"])
 def test_checkpoint_resume_bitwise(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
@@ -260,7 +265,7 @@ def test_checkpoint_resume_bitwise(name):
 
 @pytest.mark.parametrize("name", ["3d_o4_ab2_ragged", "3d_o6_rk2_burgers", "1d_o2_euler_L3", "3d_fast_o6_rk2_burgers",
                                   "3d_fast_o2_space222_rk2_burgers", "1d_o2_space222_case3",
-                                  "3d_o2_nonuniform_32x32_ab3"])
+                                  "3d_o2_nonuniform_32x32_ab3", "3d_o6_rk2_chunked"])
 def test_graph_replay_equals_plain_launches(name):
     case = _case(name)
     u0 = torch.from_numpy(initial_field(case))
