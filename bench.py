@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform,matched",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform,matched,generic3d",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -335,6 +335,42 @@ def time_nonuniform():
     return res
 
 
+def time_generic3d():
+    """The generic 3-D sweep (PE edges other than 32: 192^3 in 4^3 PEs of 48^3,
+    fourth order, AB2, L = 4, FP32 bulk, 100 steps), AT and synchronous arms.
+    Its 64 PEs are split into z-chunks of several workgroups. Bytes per update
+    (two solution buffers): u read and written, f^{n-1} read and f^n written,
+    plus per face column (h = 2 * 3 * 2 / 48 per point) the T = 3 delayed halo
+    levels read and the strip published: 4 * (4 + 4 h) = 20 B (synchronous:
+    16 B)."""
+    cfg = W.config_3d_advdiff(n=192, b=48)
+    u = torch.from_numpy(W.eval_modes(cfg["modes"], cfg["n"], 3))
+    steps = 100
+    res = {}
+    for mode, bpu in (("rng", 20.0), ("sync", 16.0)):
+        s = Solver(ndim=3, n=cfg["n"], pe=cfg["pe"], dt=cfg["dt"], order=4, c=cfg["c"], alpha=cfg["alpha"],
+                   integrator="ab2", precision="f32", L=cfg["L"], seed=cfg["seed"], mode=mode)
+        s.set_graph(20)
+        s.set_state(u)
+        s.step(20)
+        s.set_state(u)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ups = 192 ** 3 * steps / (ms / 1e3)
+        res["at" if mode == "rng" else "sync"] = dict(
+            ms_per_step=ms / steps, updates_per_s=ups, bytes_per_update=bpu, achieved_gbs=ups * bpu / 1e9,
+            frac=ups * bpu / 1e9 / HBM_PEAK_GBS, l2_error=s.norms(modes=cfg["modes"])["l2"])
+    res["config"] = {"n": 192, "pe_edge": 48, "order": 4, "integrator": "ab2", "L": cfg["L"], "precision": "f32",
+                     "steps": steps, "kernel": "generic sweep, z-chunked"}
+    return res
+
+
 def _run_family_point(cfg, mode, steps, precision="f64", graph=50):
     nd = cfg["ndim"]
     s = Solver(ndim=nd, n=cfg["n"][:nd], pe=cfg["pe"][:nd], dt=cfg["dt"], order=cfg["order"], c=cfg["c"][:nd],
@@ -542,7 +578,7 @@ others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
                  "space": time_space, "study": time_study, "nonuniform": time_nonuniform,
-                 "matched": time_matched}[w]()
+                 "matched": time_matched, "generic3d": time_generic3d}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:
