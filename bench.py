@@ -35,7 +35,7 @@ p.add_argument("--arms", default="f32,f64,sync32", help="comma list of arms to t
 p.add_argument("--cpu-steps", type=int, default=10)
 p.add_argument("--no-autotune", action="store_true")
 p.add_argument("--variant", type=int, default=0, help="fixed schedule variant of the 3-D sweep (skips autotuning)")
-p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform,matched,generic3d",
+p.add_argument("--others", default="burgers,ensemble,adjoint,space,study,nonuniform,matched,generic3d,c1",
                help="other workloads timed after the headline (comma list; empty: none)")
 args = p.parse_args()
 
@@ -335,6 +335,45 @@ def time_nonuniform():
     return res
 
 
+def time_c1():
+    """The 1-D workload (N = 256, 8 PEs of 32, order 2, Euler, L = 3, 1000
+    steps, FP64) is a few KB: per-step launches (even replayed from HIP
+    graphs) cost far more than its arithmetic. Timed two ways: the context's
+    per-step sweep, and the same problem as a one-member ensemble, whose
+    persistent launch runs all steps in one workgroup; the two final fields
+    agree to rounding."""
+    from paper_1702_00496_amd import Ensemble
+    cfg = W.config_1d_advdiff()
+    steps = cfg["steps"]
+    u = torch.from_numpy(W.eval_modes(cfg["modes"], cfg["n"], 1))
+    ms, _ = _run_family_point(cfg, "rng", steps)
+    s = Solver(ndim=1, n=cfg["n"][:1], pe=cfg["pe"][:1], dt=cfg["dt"], order=2, c=cfg["c"][:1], alpha=cfg["alpha"],
+               integrator="euler", precision="f64", L=cfg["L"], seed=cfg["seed"])
+    s.set_state(u)
+    s.step(steps)
+    ref = s.state().double().reshape(-1).cpu()
+    m = dict(n=cfg["n"][0], pe=cfg["pe"][0], order=2, integrator="euler", L=cfg["L"], T=0, mode="rng",
+             c=cfg["c"][0], alpha=cfg["alpha"], dt=cfg["dt"], seed=cfg["seed"])
+    ens = Ensemble([m], precision="f64")
+    u1 = u.reshape(-1)
+    ens.set_state(u1)
+    ens.run(steps)                          # capture + warm-up
+    ens.set_state(u1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ens.run(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ems = e0.elapsed_time(e1)
+    got = ens.state().double().reshape(-1).cpu()
+    return dict(workload=f"1-D N = {cfg['n'][0]}, {cfg['pe'][0]} PEs, order 2, Euler, L = {cfg['L']}, "
+                         f"{steps} steps, FP64",
+                per_step_launch_ms=ms, persistent_ms=ems, speedup=ms / ems,
+                rel_l2_between=float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref)))
+
+
 def time_generic3d():
     """The generic 3-D sweep (PE edges other than 32: 192^3 in 4^3 PEs of 48^3,
     fourth order, AB2, L = 4, FP32 bulk, 100 steps), AT and synchronous arms.
@@ -578,7 +617,7 @@ others = {}
 for w in [x for x in args.others.split(",") if x]:
     others[w] = {"burgers": time_burgers, "ensemble": time_ensemble, "adjoint": time_adjoint,
                  "space": time_space, "study": time_study, "nonuniform": time_nonuniform,
-                 "matched": time_matched, "generic3d": time_generic3d}[w]()
+                 "matched": time_matched, "generic3d": time_generic3d, "c1": time_c1}[w]()
 if others:
     out["other_workloads"] = others
 if not args.no_cpu_baseline:
