@@ -151,8 +151,9 @@ const char* at_version(void);
 
 /* Bytes of device workspace at_create needs for this problem (256-B aligned
  * sub-buffers: the solution (one buffer updated in place, or two used by
- * step parity for the synchronous arm and for 3-D problems without a 32 x 32
- * PE cross-section, or with the non-uniform scheme, that do not use RK2),
+ * step parity for the synchronous arm and for 3-D problems of fewer than
+ * 1024 PEs without a 32 x 32 PE cross-section, or with the non-uniform
+ * scheme, that do not use RK2),
  * the integrator history, the RK2 predictor, the face rings of L+T slots,
  * delay tables, counters and reduction scratch). */
 at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_t* bytes);

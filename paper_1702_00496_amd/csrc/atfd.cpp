@@ -176,10 +176,12 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
   // neighbours' level-n values directly and keeps two buffers.
   l.off_u[0] = take(l.field_bytes);
   // Two buffers as well for a 3-D problem that only the generic sweep can
-  // take (no 32 x 32 cross-section, or the non-uniform-delay scheme) and
-  // whose new level is written over u^n (not RK2): that sweep splits a PE's
-  // planes over several workgroups, which read their neighbours' planes.
-  const bool generic3d = g.ndim == 3 && (g.b[0] != 32 || g.b[1] != 32 || g.scheme == AT_SCHEME_NONUNIFORM_212);
+  // take (no 32 x 32 cross-section, or the non-uniform-delay scheme), with
+  // fewer PEs than four workgroups per compute unit, and whose new level is
+  // written over u^n (not RK2): that sweep then splits a PE's planes over
+  // several workgroups, which read their neighbours' planes.
+  const bool generic3d = g.ndim == 3 && g.npe < 4 * 256 &&
+                         (g.b[0] != 32 || g.b[1] != 32 || g.scheme == AT_SCHEME_NONUNIFORM_212);
   const bool two = d->mode == AT_SYNC || (generic3d && p->integrator != AT_RK2);
   l.off_u[1] = two ? take(l.field_bytes) : l.off_u[0];
   l.nfbuf = p->integrator == AT_AB2 ? 1 : p->integrator == AT_AB3 ? 2 : 0;
