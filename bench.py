@@ -105,11 +105,23 @@ def time_arm(precision, mode):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     nrm = s.norms(modes=cfg["modes"])
+    # five more timed runs of the same K steps (after the reported one), for
+    # the spread between runs
+    repeats = []
+    for _ in range(5):
+        s.set_state(u0)
+        torch.cuda.synchronize()
+        e0.record()
+        s.step(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        repeats.append(e0.elapsed_time(e1) / args.steps)
     ups = npts * args.steps / (ms / 1e3)
     bpu = bytes_per_update(precision, mode)
     gbs = ups * bpu / 1e9
     return dict(precision=precision, mode=mode, depth=s.tuning(), autotune_ms=tuned[1] if tuned else None,
-                ms=ms, ms_per_step=ms / args.steps,
+                ms=ms, ms_per_step=ms / args.steps, repeat_ms_per_step=repeats,
+                median_ms_per_step=float(np.median([ms / args.steps] + repeats)),
                 updates_per_s=ups, bytes_per_update=bpu, achieved_gbs=gbs,
                 frac=gbs / HBM_PEAK_GBS, l2_error=nrm["l2"], linf_error=nrm["linf"])
 
