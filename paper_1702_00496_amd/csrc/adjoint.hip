@@ -201,7 +201,8 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
     int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
     c[a] = org[a] + min(max(ia, 0), b - 1);
     const int64_t gi = gindex(p, c[0], c[1], c[2]);
-    const double t = tap_k(q, a, o, centre_at<Real>(q, gi)) * mu_at<Real>(q, gi);
+    const double ci = q.burgers ? centre_at<Real>(q, gi) : 0.0;   // Burgers taps only
+    const double t = tap_k(q, a, o, ci) * mu_at<Real>(q, gi);
     g += valid ? t : 0.0;
   }
   const int k = adj_delay(p, cons, cf, q.n);
@@ -339,7 +340,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
         const bool tin = ia >= 0 && ia < b;
         const int64_t gi = tin ? g - o * st[a] : g;
         const double mi = mu_at<Real>(q, gi);
-        const double ci = static_cast<double>(C[gi]);   // used by the Burgers taps only
+        // the stage value at i enters the Burgers taps only (uniform branch)
+        const double ci = q.burgers ? static_cast<double>(C[gi]) : 0.0;
         acc += tin ? tap_k(q, a, o, ci) * mi : 0.0;
         // forward stencil of the stage field at j: inside the PE from the
         // field, across a face from the stage's combined halo values
