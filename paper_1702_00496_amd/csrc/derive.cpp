@@ -280,7 +280,12 @@ at_status at_search_scheme(int32_t d, int32_t a, int32_t r, int32_t s_min, int32
     bool determined = false;
     for (int a2 = a + 1; a2 <= kMaxOrder && !determined; ++a2) {
       Result r2;
-      if (at_status st = derive_checked(d, a2, r, n, jj.data(), ll.data(), r2)) return st;
+      // conditions beyond exact 128-bit range end the escalation (the
+      // reduction below may still find a scheme)
+      if (!derive(d, a2, r, n, jj.data(), ll.data(), r2)) break;
+      bool fits = true;
+      for (const Q& q : r2.c) fits = fits && fits_i64(q);
+      if (!fits) break;
       if (r2.status == AT_DERIVE_INFINITE) continue;
       determined = true;
       if (at_status st = accept(jj, ll, r2, a2, done)) return st;
