@@ -208,6 +208,13 @@ at_status at_get_step(const at_ctx* ctx, int64_t* n);
  * host_out[count][P][ndim][2] (int8). Synchronises the stream. */
 at_status at_get_delays(at_ctx* ctx, int64_t n0, int64_t count, int8_t* host_out);
 
+/* AT_SCHEME_NONUNIFORM_212 only (Sec. 3.4 Example 1): delays of the second
+ * buffer point of every face (the generator draw with face + P * 2 * ndim,
+ * after the start-up clamp, before the singular-set shift of k1), laid out as
+ * at_get_delays, whose table holds k1. AT_EINVAL for other schemes.
+ * Synchronises the stream. */
+at_status at_get_point_delays(at_ctx* ctx, int64_t n0, int64_t count, int8_t* host_out);
+
 /* Error norms of the current field (Sec. 4 averages; Sec. 5.1 error E = u -
  * u_a), accumulated in double with a fixed reduction order. Reference: the
  * decaying advected Fourier series of Sec. 5.1 eq. ana_sol with nmodes > 0

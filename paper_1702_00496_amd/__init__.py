@@ -169,6 +169,15 @@ class Solver:
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), self._ctx)
         return out
 
+    def point_delays(self, n0, count):
+        """Second-buffer-point delays of the non-uniform-delay scheme
+        (``at_get_point_delays``), shaped like ``delays``."""
+        npe = self.pe[0] * self.pe[1] * self.pe[2]
+        out = np.zeros((count, npe, self.ndim, 2), dtype=np.int8)
+        check(self._lib.at_get_point_delays(self._ctx, int(n0), int(count),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), self._ctx)
+        return out
+
     def norms(self, modes=None, ref=None):
         """Error norms vs Fourier modes [(kappa3, amp, phase)] or a float64 reference field."""
         out = (ctypes.c_double * 9)()

@@ -14,6 +14,7 @@
 
 #include "atfd_internal.hpp"
 #include "adjoint.hpp"
+#include "delays.hpp"
 #include "host_common.hpp"
 
 using namespace atfd;
@@ -538,6 +539,23 @@ at_status at_get_delays(at_ctx* c, int64_t n0, int64_t count, int8_t* host_out) 
   for (int64_t s = 0; s < count; s += chunk) {
     const int64_t m = count - s < chunk ? count - s : chunk;
     HIP_TRY(c, launch_delays(c->sp, n0 + s, m, scratch, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(host_out + s * per, scratch, m * per, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return AT_OK;
+}
+
+at_status at_get_point_delays(at_ctx* c, int64_t n0, int64_t count, int8_t* host_out) {
+  if (!c || !host_out || n0 < 0 || count < 0) return fail(c, AT_EINVAL, "bad arguments");
+  if (c->g.scheme != AT_SCHEME_NONUNIFORM_212)
+    return fail(c, AT_EINVAL, "only the non-uniform-delay scheme has per-point delays");
+  const int64_t per = static_cast<int64_t>(c->g.npe) * 2 * c->g.ndim;
+  if (per > kDelayScratch) return fail(c, AT_EINVAL, "too many faces for one step of scratch");
+  const int64_t chunk = kDelayScratch / per;
+  int8_t* scratch = reinterpret_cast<int8_t*>(c->ws + c->lay.off_delays);
+  for (int64_t s = 0; s < count; s += chunk) {
+    const int64_t m = count - s < chunk ? count - s : chunk;
+    HIP_TRY(c, launch_point_delays(c->sp, n0 + s, m, scratch, c->stream));
     HIP_TRY(c, hipMemcpyAsync(host_out + s * per, scratch, m * per, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }

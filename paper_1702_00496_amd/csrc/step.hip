@@ -19,6 +19,7 @@
 // per face and level).
 
 #include "atfd_internal.hpp"
+#include "delays.hpp"
 
 namespace atfd {
 namespace {
@@ -448,6 +449,16 @@ __device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n)
   return clamp_startup(k, n, p.T);
 }
 
+// Delay of the second buffer point of face f (non-uniform-delay scheme): a
+// draw of the generator with the face index shifted by the number of faces,
+// clamped like every delay; 0 unless the delays are drawn.
+__device__ inline int point_delay(const StepParams& p, int pid, int f, int64_t n) {
+  if (p.mode != AT_DELAY_RNG) return 0;
+  const uint32_t nfaces = static_cast<uint32_t>(p.npe * 2 * p.ndim);
+  return clamp_startup(raw_delay(p.key, n, nfaces + static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L), n,
+                       p.T);
+}
+
 // Non-uniform-delay scheme, face f of PE pid at step n (Sec. 3.4 Example 1):
 // delays k1 (nearest buffer point: the face's draw) and k2 (second point: a
 // draw with the face index shifted by the number of faces), both clamped as
@@ -461,12 +472,7 @@ __device__ inline int face_delay(const StepParams& p, int pid, int f, int64_t n)
 __device__ inline void nonuniform_face(const StepParams& p, int pid, int f, int64_t n, int* kpos, int* slot,
                                        double* nu) {
   int k1 = face_delay(p, pid, f, n);
-  int k2 = 0;
-  if (p.mode == AT_DELAY_RNG) {
-    const uint32_t nfaces = static_cast<uint32_t>(p.npe * 2 * p.ndim);
-    k2 = clamp_startup(raw_delay(p.key, n, nfaces + static_cast<uint32_t>(pid * 2 * p.ndim + f), p.thr, p.L),
-                       n, p.T);
-  }
+  const int k2 = point_delay(p, pid, f, n);
   const bool use = k1 != 0 || k2 != 0;
   if (use && 3 * k1 == k2) ++k1;
   kpos[f] = use;
@@ -617,6 +623,18 @@ __global__ void delays_kernel(StepParams p, int64_t n0, int64_t count, int8_t* o
   }
 }
 
+// Second-point delay table [count][npe][2*ndim] of steps n0.. (non-uniform scheme).
+__global__ void point_delays_kernel(StepParams p, int64_t n0, int64_t count, int8_t* out) {
+  const int64_t per = static_cast<int64_t>(p.npe) * 2 * p.ndim;
+  const int64_t total = count * per;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t n = n0 + i / per;
+    const int r = static_cast<int>(i % per);
+    out[i] = static_cast<int8_t>(point_delay(p, r / (2 * p.ndim), r % (2 * p.ndim), n));
+  }
+}
+
 template <typename Real, int DIM, int S, int SP>
 size_t lds_bytes_t(const StepParams& p) {
   constexpr int SD = strip_depth<S, SP>();
@@ -760,6 +778,15 @@ hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t*
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(delays_kernel, dim3(blocks), dim3(256), 0, st, p, n0, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_delays(const StepParams& p, int64_t n0, int64_t count, int8_t* out, hipStream_t st) {
+  const int64_t total = count * p.npe * 2 * p.ndim;
+  int blocks = static_cast<int>((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(point_delays_kernel, dim3(blocks), dim3(256), 0, st, p, n0, count, out);
   return hipGetLastError();
 }
 

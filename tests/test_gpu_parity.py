@@ -184,6 +184,25 @@ def test_nonuniform_with_one_delay_level_is_the_synchronous_scheme(precision):
     assert torch.equal(out["rng"], out["sync"])
 
 
+@pytest.mark.parametrize("name", ["2d_o2_nonuniform_rk2_ragged", "1d_o2_nonuniform_case2"])
+def test_nonuniform_point_delays_bit_exact(name):
+    """The device's second-point delays equal the generator's (the face
+    delays are test_delays_bit_exact); other schemes have none."""
+    from oracle.solver import point_delay_table
+    from paper_1702_00496_amd import ATError
+    case = _case(name)
+    s = solver_for(case, "f64")
+    steps = 60
+    got = s.point_delays(0, steps)
+    o = oracle_for(case, initial_field(case))
+    for n in range(steps):
+        want = point_delay_table(o.prob, o.dm, n).numpy()
+        assert np.array_equal(got[n], want.reshape(got[n].shape)), n
+    assert not np.array_equal(got, s.delays(0, steps))
+    with pytest.raises(ATError, match="per-point"):
+        solver_for(_case("1d_o2_space222_case3"), "f64").point_delays(0, 4)
+
+
 def test_nonuniform_scheme_rejects_host_tables_and_other_orders():
     from paper_1702_00496_amd import ATError
     case = _case("1d_o2_nonuniform_ab2_min_edge")
