@@ -318,9 +318,11 @@ at_status enqueue_step(at_ctx* c, hipStream_t st) {
   return AT_OK;
 }
 
+// Teardown calls below: a failure to release leaves nothing to recover, so
+// their status is deliberately discarded.
 void drop_graph(at_ctx* c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
   c->graph = nullptr;
 }
@@ -426,7 +428,7 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
       hipGraph_t gr = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
       if (st != AT_OK) {
-        if (gr) hipGraphDestroy(gr);
+        if (gr) (void)hipGraphDestroy(gr);
         return st;
       }
       if (e != hipSuccess) return fail(c, AT_EHIP, "graph capture: %s", hipGetErrorString(e));
@@ -502,8 +504,8 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
     }
     if (ms_out) ms_out[i] = ms;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   c->graph_chunk = keep_chunk;
   c->sp.depth = keep;
   at_status st2 = at_load(c, scratch_dev);
@@ -660,7 +662,7 @@ at_status at_load(at_ctx* c, const void* ckpt_dev) {
 at_status at_destroy(at_ctx* c) {
   if (!c) return AT_OK;
   drop_graph(c);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return AT_OK;
 }

@@ -196,9 +196,10 @@ at_status upload_schedule(at_ens* e) {
   return AT_OK;
 }
 
+// Releasing a graph that failed leaves nothing to recover: status discarded.
 void drop_graph(at_ens* e) {
-  if (e->graph_exec) hipGraphExecDestroy(e->graph_exec);
-  if (e->graph) hipGraphDestroy(e->graph);
+  if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
   e->graph_exec = nullptr;
   e->graph = nullptr;
   e->graph_nsteps = 0;
@@ -297,7 +298,7 @@ at_status at_ens_run(at_ens* e, int64_t nsteps) {
     hipGraph_t gr = nullptr;
     hipError_t ce = hipStreamEndCapture(e->cap_stream, &gr);
     if (le != hipSuccess || ce != hipSuccess) {
-      if (gr) hipGraphDestroy(gr);
+      if (gr) (void)hipGraphDestroy(gr);
       return efail(e, AT_EHIP, "ensemble graph capture: %s",
                    hipGetErrorString(le != hipSuccess ? le : ce));
     }
@@ -383,7 +384,7 @@ at_status at_ens_norms(at_ens* e, int32_t nmodes, const int32_t* kappa, const do
 at_status at_ens_destroy(at_ens* e) {
   if (!e) return AT_OK;
   drop_graph(e);
-  if (e->cap_stream) hipStreamDestroy(e->cap_stream);
+  if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
   delete e;
   return AT_OK;
 }
