@@ -176,10 +176,10 @@ def cole_hopf(x, t, amp, nu, nterms=None):
 
 
 def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, weights, mode, seed, precision,
-             scheme="time"):
+             scheme="time", T=0):
     from . import Solver
     s = Solver(ndim=1, n=(n,), pe=(pe,), dt=dt, order=order, equation=equation, c=(c,), alpha=alpha,
-               integrator=integrator, precision=precision, L=L, mode=mode, seed=seed, weights=weights,
+               integrator=integrator, precision=precision, L=L, T=T, mode=mode, seed=seed, weights=weights,
                scheme=scheme)
     s.set_graph(64)
     s.set_state(torch.as_tensor(u0).reshape(1, 1, n))
@@ -187,6 +187,54 @@ def _gpu_run(n, pe, order, integrator, equation, c, alpha, dt, steps, u0, L, wei
     out = s.state().double().cpu().numpy().reshape(-1)
     s.close()
     return out
+
+
+# The three arms of the Case 1 comparison (Sec. 5.2): the synchronous
+# standard scheme, the standard scheme fed with delayed halos (T = 1), and the
+# AT schemes (1,2,2)b/(2,2,2)b (T = 2).
+CASE1_ARMS = {"synchronous": ("sync", 0), "asynchronous_standard": ("rng", 1), "at": ("rng", 0)}
+
+
+def case1_study(n=128, pe=4, L=3, weights=(5, 3, 2), kappas=(2, 3, 5), amps=(1.0, 1.0, 1.0), c=1.0,
+                alpha=0.1, r_alpha=0.1, times=(0.005, 0.05), conv_ns=(64, 128, 256, 512), conv_time=0.05,
+                seed=3, precision="f64"):
+    """Case 1 of the Sec. 5.1 table (advection-diffusion, Euler, CD2 with
+    (1,2,2)b/(2,2,2)b) in the setting of the first experiment of Sec. 5.2:
+    N = 128, kappa = {2, 3, 5}, P = 4, delays with p = {0.5, 0.3, 0.2}. For
+    each time in ``times`` and each arm: mean |E|, max |E| at the points next
+    to PE faces and max |E| elsewhere, against the exact advected decaying
+    series (``per_time``); and the mean |E| at ``conv_time`` against N with
+    its slopes (``convergence``). Amplitudes and times are not stated in the
+    paper (readings)."""
+    modes = tuple(zip(kappas, amps))
+
+    def errors(n_, t):
+        dt = _dt(n_, alpha, r_alpha)
+        steps = max(1, int(round(t / dt)))
+        dt = t / steps
+        x = np.arange(n_) * (2 * math.pi / n_)
+        u0 = sum(a * np.sin(k * x) for k, a in modes)
+        exact = sum(a * math.exp(-alpha * k * k * t) * np.sin(k * (x - c * t)) for k, a in modes)
+        b = n_ // pe
+        face = (np.arange(n_) % b == 0) | (np.arange(n_) % b == b - 1)
+        out = {}
+        for arm, (mode, T) in CASE1_ARMS.items():
+            u = _gpu_run(n_, pe, 2, "euler", "advdiff", c, alpha, dt, steps, u0, L, list(weights), mode, seed,
+                         precision, T=T)
+            e = np.abs(u - exact)
+            out[arm] = dict(mean=float(e.mean()), face_max=float(e[face].max()), interior_max=float(e[~face].max()),
+                            steps=steps, dt=dt)
+        return out
+
+    per_time = {t: errors(n, t) for t in times}
+    conv = {arm: [] for arm in CASE1_ARMS}
+    for n_ in conv_ns:
+        r = errors(n_, conv_time)
+        for arm in CASE1_ARMS:
+            conv[arm].append(r[arm]["mean"])
+    slopes = {arm: [math.log(v[i + 1] / v[i]) / math.log(conv_ns[i + 1] / conv_ns[i]) for i in range(len(v) - 1)]
+              for arm, v in conv.items()}
+    return dict(per_time=per_time, convergence=dict(ns=list(conv_ns), mean=conv, slopes=slopes))
 
 
 CASE_CONFIGS = {

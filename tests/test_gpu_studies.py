@@ -183,3 +183,37 @@ def test_case6_gradient_moments_converge_by_n256():
             _say(f"[study] case6 p={w} N={n}: moments {m} max rel dev {dev:.2e}")
             if n == 256:
                 assert dev < 1e-4, (w, m, ref)
+
+
+def test_case1_asynchronous_standard_scheme_against_at():
+    """Sec. 5.2, first experiment (Case 1: AD, Euler, CD2 with (1,2,2)b/(2,2,2)b;
+    N = 128, kappa = {2, 3, 5}, P = 4, p = {0.5, 0.3, 0.2}): the standard scheme
+    fed with delayed halos has an error about an order of magnitude larger at
+    the points next to PE faces than the synchronous scheme, while the AT
+    schemes stay at the synchronous level; with N the asynchronous-standard
+    error falls towards first order, the others at second order. The GPU
+    field of the asynchronous-standard arm equals the oracle's."""
+    import math
+    from oracle import analytic
+    from oracle.solver import DelayModel, Oracle, Problem
+    from paper_1702_00496_amd import studies
+    res = studies.case1_study()
+    for t, r in res["per_time"].items():
+        sy, st, at = r["synchronous"], r["asynchronous_standard"], r["at"]
+        _say(f"[study] case1 t={t}: face max sync {sy['face_max']:.3e} async-std {st['face_max']:.3e} "
+             f"AT {at['face_max']:.3e}")
+        assert st["face_max"] > 8 * sy["face_max"], (t, r)
+        assert at["face_max"] < 1.1 * sy["face_max"], (t, r)
+    sl = res["convergence"]["slopes"]
+    _say(f"[study] case1 slopes {sl}")
+    assert -2.15 < sl["synchronous"][-1] < -1.85 and -2.15 < sl["at"][-1] < -1.85, sl
+    assert -1.45 < sl["asynchronous_standard"][-1] < -0.8, sl
+    # parity of one arm with the oracle (t = 0.005, N = 128)
+    r = res["per_time"][0.005]["asynchronous_standard"]
+    prob = Problem(ndim=1, n=(128,), pe=(4,), dt=r["dt"], order=2, c=(1.0,), alpha=0.1)
+    modes = [((k, 0, 0), 1.0, 0.0) for k in (2, 3, 5)]
+    o = Oracle(prob, DelayModel(L=3, T=1, mode="rng", seed=3, weights=[5, 3, 2]),
+               analytic.advected_modes(prob, modes, 0.0))
+    o.run(r["steps"])
+    e = (o.u - analytic.advected_modes(prob, modes, o.t)).abs().reshape(-1)
+    assert abs(float(e.mean()) - r["mean"]) <= 1e-12 * r["mean"] + 1e-15
