@@ -256,12 +256,14 @@ CASE_CONFIGS = {
 
 def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
                       weight_sets=((1, 0, 0), (7, 2, 1), (4, 4, 2), (3, 5, 2)), realizations=2, seed=0,
-                      precision="f64"):
+                      precision="f64", T=0):
     """<E> against N for Cases 2-5 (exact: the decaying advected sine series of
     Sec. 5.1) or Case 6 (exact: Cole-Hopf for u0 = amp sin x), for every delay law in
-    ``weight_sets`` (bin weights of k = 0, 1, 2; (1, 0, 0) is delay-free),
-    dt = r_alpha dx^2 / alpha at a fixed final time. Returns per weight set
-    the errors against N, their slopes, and the final fields (for moments)."""
+    ``weight_sets`` (bin weights of k = 0, 1, ...; (1, 0, ...) is delay-free),
+    dt = r_alpha dx^2 / alpha at a fixed final time. T = 1 runs the case's
+    standard scheme fed with delayed halos instead of its AT schemes (Sec. 5.2,
+    figure at-ord4-async). Returns per weight set the errors against N, their
+    slopes, and the final fields (for moments)."""
     cfg = CASE_CONFIGS[case]
     out = {}
     for w in weight_sets:
@@ -283,7 +285,7 @@ def convergence_study(case="case5", Ns=(32, 64, 128, 256), pe=4, L=3,
             for r in range(realizations if sum(w[1:]) else 1):
                 u = _gpu_run(n, pe, cfg["order"], cfg["integrator"], cfg["equation"], cfg["c"], cfg["alpha"], dt,
                              steps, u0, L, list(w), "rng", _member_key(seed, n, r), precision,
-                             cfg.get("scheme", "time"))
+                             cfg.get("scheme", "time"), T=T)
                 e_r.append(float(np.mean(np.abs(u - exact))))
                 f_r.append(u)
             errs.append(float(np.mean(e_r)))

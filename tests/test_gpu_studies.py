@@ -217,3 +217,23 @@ def test_case1_asynchronous_standard_scheme_against_at():
     o.run(r["steps"])
     e = (o.u - analytic.advected_modes(prob, modes, o.t)).abs().reshape(-1)
     assert abs(float(e.mean()) - r["mean"]) <= 1e-12 * r["mean"] + 1e-15
+
+
+def test_case4_standard_scheme_used_asynchronously_is_first_order():
+    """Sec. 5.2, figure at-ord4-async: the fourth-order standard CD of Case 4
+    (AD, AB2) fed with delayed halos keeps slope -4 only for p0 = 1; for p0 =
+    0.7, 0.3, 0.0 it falls to about -1 and the error grows as p0 decreases
+    (reading: two delay levels, p = {p0, 1 - p0})."""
+    from paper_1702_00496_amd import studies
+    sets = ((10, 0), (7, 3), (3, 7), (0, 1))
+    res = studies.convergence_study(case="case4", Ns=(32, 64, 128, 256), pe=4, L=2, weight_sets=sets,
+                                    realizations=1, T=1, precision="f64")
+    for w in sets:
+        row = res["per_law"][w]
+        _say(f"[study] case4 standard async p0={w[0] / sum(w):.1f}: E "
+             f"{', '.join(f'{e:.3e}' for e in row['E'])} slopes {', '.join(f'{s:.2f}' for s in row['slopes'])}")
+    assert -4.4 < res["per_law"][(10, 0)]["slopes"][-1] < -3.6
+    for w in sets[1:]:
+        assert -1.5 < res["per_law"][w]["slopes"][-1] < -0.7, w
+    e = [res["per_law"][w]["E"][-1] for w in sets]
+    assert e[0] < e[1] < e[2] < e[3], e
