@@ -64,3 +64,42 @@ def test_random_configuration_matches_the_oracle(seed):
         d = s.delays(0, case["steps"])
         for k in range(case["steps"]):
             assert np.array_equal(d[k], o.delays[k].numpy().reshape(d[k].shape)), k
+
+
+def draw_deep(seed):
+    """A 3-D problem for the generic sweep with deep PEs (16..40 planes, no
+    32 x 32 cross-section, few PEs), so that its planes are split over
+    several workgroups."""
+    rng = random.Random(seed)
+    scheme = rng.choice(("time", "time", "space212", "space222", "nonuniform212"))
+    order = 2 if scheme != "time" else rng.choice((2, 4, 6))
+    s = order // 2
+    need = max(2 * s, 3 if scheme == "space222" else 2)
+    pe = tuple(rng.choice((1, 2)) for _ in range(3))
+    b = (rng.randint(need, 12), rng.randint(need, 12), rng.randint(16, 40))
+    n = tuple(p * e for p, e in zip(pe, b))
+    equation = rng.choice(("advdiff", "advdiff", "burgers"))
+    alpha = 0.05 if equation == "burgers" else 0.1
+    dx = 2 * math.pi / max(n)
+    case = dict(ndim=3, n=n, pe=pe, order=order, integrator=rng.choice(("euler", "ab2", "ab3", "rk2")),
+                equation=equation, c=tuple(round(rng.uniform(-1, 1), 3) for _ in range(3)), alpha=alpha,
+                L=rng.randint(1, 5), T=0 if scheme != "time" else rng.choice((0, 0, 1)), weights=None,
+                scheme=scheme, seed=rng.randint(0, 2 ** 31), mode=rng.choice(("rng", "rng", "zero", "sync")),
+                dt=min(0.005 * dx * dx / alpha, 0.02 * dx), steps=rng.randint(3, 10), ic_seed=rng.randint(0, 100))
+    return case, rng.choice(("f64", "f32"))
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_deep_generic_configuration_matches_the_oracle(seed):
+    case, precision = draw_deep(3000 + seed)
+    print(f"[random] deep seed {seed}: {case} {precision}", flush=True)
+    u0 = initial_field(case)
+    s = solver_for(case, precision)
+    s.set_state(torch.from_numpy(u0))
+    s.step(case["steps"])
+    got = s.state().double().cpu()
+    o = oracle_for(case, u0)
+    o.run(case["steps"])
+    assert torch.isfinite(got).all()
+    err = rel_l2(got, o.u)
+    assert err <= TOL[precision], (case, precision, err)
