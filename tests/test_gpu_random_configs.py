@@ -103,3 +103,26 @@ def test_random_deep_generic_configuration_matches_the_oracle(seed):
     assert torch.isfinite(got).all()
     err = rel_l2(got, o.u)
     assert err <= TOL[precision], (case, precision, err)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configuration_checkpoint_and_graph_are_bitwise(seed):
+    """Plain launches against a graph-replayed run that is checkpointed,
+    driven past the checkpoint, restored and resumed: the same bits (one
+    solution buffer or two, every integrator and scheme family)."""
+    case, precision = (draw if seed % 2 == 0 else draw_deep)(5000 + seed)
+    steps = case["steps"] + 6
+    u0 = torch.from_numpy(initial_field(case))
+    a = solver_for(case, precision)
+    a.set_state(u0)
+    a.step(steps)
+    want = a.state()
+    b = solver_for(case, precision)
+    b.set_graph(3)
+    b.set_state(u0)
+    b.step(4)
+    ck = b.save()
+    b.step(5)
+    b.load(ck)
+    b.step(steps - 4)
+    assert torch.equal(b.state(), want), (case, precision)
