@@ -67,10 +67,10 @@ struct Sweep {
   const int* lev_slot;      // [6][kMaxT] ring slot of level n-k-m, -1 if weight 0
   const int* nbr;           // [6] neighbour PE of face
   const int* kpos;          // [6] face delay k > 0 (space-expanded stencils apply)
-  const double* nut;        // [6][kNuTaps] non-uniform taps (SP = 3)
+  const Real* nut;          // [6][kNuTaps] non-uniform taps (SP = 3), in the storage type
 
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
-                   const int* ls_, const int* nb_, const int* kp_, const double* nu_)
+                   const int* ls_, const int* nb_, const int* kp_, const Real* nu_)
       : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
     pid = blockIdx.x % p.npe;   // workgroups beyond npe take further z-chunks of the PEs
     qx = pid % p.px;
@@ -84,6 +84,12 @@ struct Sweep {
     const bool rk2 = p.stage == kStageRk2;
     centre = static_cast<const Real*>(rk2 ? p.ustar : p.ubuf[n & 1]);
     ring_rd = static_cast<const Real*>(rk2 ? p.sring : p.ring);
+  }
+
+  // v mod n for v in [-n, 2n): a periodic index one strip depth outside the box
+  static __device__ int wrap(int v, int n) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
   }
 
   __device__ int64_t gidx(int x, int y, int z) const {
@@ -182,16 +188,24 @@ struct Sweep {
       const int nxh = 2 * SD * by, nh = (parts & kPlaneHalos) ? nxh + (DIM >= 2 ? 2 * SD * bx : 0) : 0;
       for (int h = tid; h < nh; h += nt) {
         if (h < nxh) {
-          const int side = h / (SD * by), r = h % (SD * by), d = r % SD, y = r / SD;
+          const int side = h >= SD * by ? 1 : 0, r = side ? h - SD * by : h, d = r % SD, y = r / SD;
           const int xl = side ? bx + d : d - SD;
-          const int gx = (x0 + xl + p.nx) % p.nx;
+          const int gx = wrap(x0 + xl, p.nx);
           P[(DIM >= 2 ? y + SD : 0) * px_stride + xl + SD] =
               halo(side, zz, y * SD + d, side ? d : SD - 1 - d, gx, y0 + y, gz);
         } else {
           const int hy = h - nxh;
-          const int side = hy / (SD * bx), r = hy % (SD * bx), d = r / bx, x = r % bx;
+          const int side = hy >= SD * bx ? 1 : 0;
+          int x = side ? hy - SD * bx : hy, d = 0;   // x = r % bx, d = r / bx < SD
+#pragma unroll
+          for (int i = 1; i < SD; ++i) {
+            if (x >= bx) {
+              x -= bx;
+              ++d;
+            }
+          }
           const int yl = side ? by + d : d - SD;
-          const int gy = (y0 + yl + p.ny) % p.ny;
+          const int gy = wrap(y0 + yl, p.ny);
           P[(yl + SD) * px_stride + x + SD] = halo(2 + side, zz, d * bx + x, side ? d : SD - 1 - d, x0 + x, gy, gz);
         }
       }
@@ -199,9 +213,9 @@ struct Sweep {
       // z halo plane: producer strip [d][y][x]
       const int side = zz < 0 ? 0 : 1;
       const int d = side ? zz - bz : zz + SD;
-      const int gz = (z0 + zz + p.nz) % p.nz;
-      for (int i = tid; i < bx * by; i += nt) {
-        const int x = i % bx, y = i / bx;
+      const int gz = wrap(z0 + zz, p.nz);
+      for (PlaneIter it(tid, nt, bx); it.y < by; it.next()) {
+        const int x = it.x, y = it.y;
         P[(y + SD) * px_stride + x + SD] = halo(4 + side, d, y * bx + x, side ? d : SD - 1 - d, x0 + x, y0 + y, gz);
       }
     }
@@ -251,11 +265,17 @@ struct Sweep {
       for (int k = 0; k < kBatch; ++k) {
         px[k] = it.x;
         py[k] = it.y;
-        const bool in = it.y < by;
-        const int64_t g = gbase + static_cast<int64_t>(in ? it.y : by - 1) * p.nx + (in ? it.x : bx - 1);
-        pa[k] = (rk2 || ab) ? pre_a[g] : Real(0);
-        pb[k] = ab3 ? pre_b[g] : Real(0);
+        pa[k] = pb[k] = Real(0);
         it.next();
+      }
+      if (rk2 || ab) {   // uniform: Euler steps and the first RK2 stage read no previous level
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          const bool in = py[k] < by;
+          const int64_t g = gbase + static_cast<int64_t>(in ? py[k] : by - 1) * p.nx + (in ? px[k] : bx - 1);
+          pa[k] = pre_a[g];
+          if (ab3) pb[k] = pre_b[g];
+        }
       }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
@@ -284,12 +304,10 @@ struct Sweep {
             Real d2 = c2[a][0] * vm + c2[a][2] * vp;
             const int f = 2 * a + (at_hi[a] ? 1 : 0);
             if ((at_lo[a] || at_hi[a]) && kpos[f] != 0) {
-              const double* t = nut + f * kNuTaps;
+              const Real* t = nut + f * kNuTaps;
               const Real v2m = nb(-2) - u0, v2p = nb(2) - u0;
-              d1 = static_cast<Real>(t[0]) * v2m + static_cast<Real>(t[1]) * vm + static_cast<Real>(t[3]) * vp +
-                   static_cast<Real>(t[4]) * v2p;
-              d2 = static_cast<Real>(t[5]) * v2m + static_cast<Real>(t[6]) * vm + static_cast<Real>(t[8]) * vp +
-                   static_cast<Real>(t[9]) * v2p;
+              d1 = t[0] * v2m + t[1] * vm + t[3] * vp + t[4] * v2p;
+              d2 = t[5] * v2m + t[6] * vm + t[8] * vp + t[9] * v2p;
             }
             g1 += p.equation == AT_ADVDIFF ? vel[a] * d1 : d1;
             g2 += d2;
@@ -504,6 +522,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
   __shared__ int s_nbr[6];
   __shared__ int s_kpos[6];
   __shared__ double s_nu[SP == 3 ? 6 * kNuTaps : 1];
+  __shared__ Real s_nur[SP == 3 ? 6 * kNuTaps : 1];
 
   const int64_t n = p.counter[0];
   const int pid = blockIdx.x % p.npe;
@@ -515,7 +534,11 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     s_nbr[f] = neighbour(p, pid, f);
     s_kpos[f] = 0;
     if constexpr (SP == 3) {
-      if (p.mode != AT_SYNC) nonuniform_face(p, pid, f, n, s_kpos, s_slot, s_nu);
+      if (p.mode != AT_SYNC) {
+        nonuniform_face(p, pid, f, n, s_kpos, s_slot, s_nu);
+        // the stencil multiplies in the storage type: convert once per face
+        for (int i = 0; i < kNuTaps; ++i) s_nur[f * kNuTaps + i] = static_cast<Real>(s_nu[f * kNuTaps + i]);
+      }
       return;
     }
     if (p.mode != AT_SYNC) {
@@ -532,7 +555,7 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     }
   };
 
-  Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nu);
+  Sweep<Real, DIM, S, SP> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nur);
   if (DIM == 3) {
     // workgroup blockIdx.x / npe sweeps z-chunk [zc0, zc1) of its PE; the
     // SD planes on either side come from the PE (or across its z faces)
