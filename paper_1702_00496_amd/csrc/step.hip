@@ -686,14 +686,15 @@ int sweep_threads(const StepParams& p) {
 }
 
 // Workgroups per PE of the generic sweep. A 3-D PE's planes are split into
-// z-chunks (each reloads the SD planes around it) when the PEs alone leave
-// compute units idle: as many chunks as fit in one round of resident
-// workgroups (256 CUs, each holding as many as its LDS and thread slots
-// allow, at most four), with at least 8 planes per chunk. Only where no
-// chunk overwrites planes another one reads: the new level goes to the other
-// solution buffer, or the stage writes the RK2 predictor / reads it (Heun).
-// 1-D and 2-D PEs are a single plane.
-int sweep_chunks(const StepParams& p, size_t lds, int threads) {
+// z-chunks (each reloads the SD planes around it) within one round of
+// resident workgroups (256 CUs, each holding as many as its LDS and thread
+// slots allow, at most four). Only where no chunk overwrites planes another
+// one reads: the new level goes to the other solution buffer, or the stage
+// writes the RK2 predictor / reads it (Heun). 1-D and 2-D PEs are a single
+// plane.
+constexpr int kNumCUs = 256;   // compute units of an MI355X
+
+int sweep_chunks(const StepParams& p, size_t lds, int threads, int sd) {
   if (p.ndim != 3) return 1;
   if (p.ubuf[0] == p.ubuf[1] && p.integrator != AT_RK2) return 1;
   int per_cu = static_cast<int>((160 * 1024) / (lds > 0 ? lds : 1));
@@ -701,18 +702,41 @@ int sweep_chunks(const StepParams& p, size_t lds, int threads) {
   if (per_cu > by_threads) per_cu = by_threads;
   if (per_cu > 4) per_cu = 4;
   if (per_cu < 1) per_cu = 1;
-  const int want = 256 * per_cu / p.npe;
-  if (want <= 1) return 1;
-  int zper = (p.bz + want - 1) / want;
-  if (zper < 8) zper = 8;
-  return (p.bz + zper - 1) / zper;
+  const int64_t slots = static_cast<int64_t>(kNumCUs) * per_cu;
+  if (p.npe >= kNumCUs) {
+    // every CU already has a PE: chunks only add co-resident workgroups,
+    // as many as fill one resident round, of at least 8 planes each
+    const int want = static_cast<int>(slots / p.npe);
+    if (want <= 1) return 1;
+    int zper = (p.bz + want - 1) / want;
+    if (zper < 8) zper = 8;
+    return (p.bz + zper - 1) / zper;
+  }
+  // fewer PEs than CUs: a CU's time is about its workgroup count times the
+  // planes each loads (its chunk plus sd reloaded on either side); take the
+  // split with the smallest such product among those that stay in one
+  // resident round and leave no chunk empty (the fewest chunks on a tie)
+  int best = 1;
+  int64_t best_cost = -1;
+  for (int nch = 1; nch <= p.bz; ++nch) {
+    const int64_t wgs = static_cast<int64_t>(p.npe) * nch;
+    if (wgs > slots && nch > 1) break;
+    const int zper = (p.bz + nch - 1) / nch;
+    if ((p.bz + zper - 1) / zper != nch) continue;
+    const int64_t cost = ((wgs + kNumCUs - 1) / kNumCUs) * (zper + 2 * sd);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = nch;
+    }
+  }
+  return best;
 }
 
 template <typename Real, int DIM, int S, int SP>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
   const size_t lds = lds_bytes_t<Real, DIM, S, SP>(p);
   const int threads = sweep_threads(p);
-  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(p.npe * sweep_chunks(p, lds, threads)), dim3(threads),
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(p.npe * sweep_chunks(p, lds, threads, strip_depth<S, SP>())), dim3(threads),
                      lds, st, p);
   return hipGetLastError();
 }
