@@ -77,9 +77,12 @@ CASES = {
     "3d_fast_o2_space222_rk2_burgers": dict(ndim=3, n=(64, 64, 24), pe=(2, 2, 2), order=2, integrator="rk2", equation="burgers", alpha=0.05, L=3, scheme="space222", steps=10, ra=0.02),
     "3d_fast_o2_space222_ab3_bz6": dict(ndim=3, n=(32, 64, 12), pe=(1, 2, 2), order=2, integrator="ab3", c=(1.0, 1.0, 1.0), L=4, scheme="space222", steps=12, ra=0.02),
     # deep PEs on the generic 3-D sweep: their planes are split into z-chunks
-    # of several workgroups (6 and 3 chunks), with two solution buffers for AB2
+    # of several workgroups, with two solution buffers for AB2 (few PEs: down
+    # to single-plane chunks, each reloading the strip-depth planes around it;
+    # 4^3 PEs of 42 planes: 4 chunks of 11, the last one ragged)
     "3d_o4_ab2_chunked": dict(ndim=3, n=(40, 40, 48), pe=(2, 2, 1), order=4, integrator="ab2", c=(1.0, -0.5, 0.7), L=4, steps=10, ra=0.02),
     "3d_o6_rk2_chunked": dict(ndim=3, n=(30, 30, 40), pe=(1, 1, 2), order=6, integrator="rk2", c=(0.5, 0.5, 1.0), L=3, steps=8, ra=0.004),
+    "3d_o4_ab2_chunk_ragged": dict(ndim=3, n=(48, 48, 168), pe=(4, 4, 4), order=4, integrator="ab2", c=(0.7, 1.0, -0.5), L=4, steps=6, ra=0.02),
     # non-uniform delays at the two buffer points (Sec. 3.4 Example 1); L = 8
     # and L = 5 with uniform bins reach the singular set 3 k1 = k2 many times
     "1d_o2_nonuniform_case2": dict(ndim=1, n=(128,), pe=(16,), order=2, integrator="euler", c=(0.0,), L=8, scheme="nonuniform212", steps=200, ra=0.05),
@@ -138,7 +141,7 @@ def test_delays_bit_exact(name):
                                   "3d_fast_o6_rk2_burgers", "3d_fast_o4_ab2_bz16", "1d_o2_space222_case3",
                                   "2d_o2_space212_ragged", "3d_o2_space222_ab2", "3d_fast_o2_space222",
                                   "1d_o2_nonuniform_case2", "3d_o2_nonuniform_32x32_ab3", "3d_o4_ab2_chunked",
-                                  "3d_o6_rk2_chunked"])
+                                  "3d_o6_rk2_chunked", "3d_o4_ab2_chunk_ragged"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_zero_delays_equal_synchronous_bitwise(name, precision):
     case = _case(name)
