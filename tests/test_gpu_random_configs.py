@@ -105,6 +105,38 @@ def test_random_deep_generic_configuration_matches_the_oracle(seed):
     assert err <= TOL[precision], (case, precision, err)
 
 
+def draw_wide(seed):
+    """A deep-PE draw (as above) on up to 4 x 4 x 4 PEs of 8..48 planes, so
+    that the split of each PE's planes into z-chunks meets the limit of one
+    resident round and leaves ragged last chunks."""
+    case, precision = draw_deep(seed)
+    rng = random.Random(7 * seed + 1)
+    pe = tuple(rng.choice((1, 2, 3, 4)) for _ in range(3))
+    b = [e // p for e, p in zip(case["n"], case["pe"])]
+    b[2] = rng.randint(8, 48)
+    case["pe"] = pe
+    case["n"] = tuple(p * e for p, e in zip(pe, b))
+    dx = 2 * math.pi / max(case["n"])
+    case["dt"] = min(0.005 * dx * dx / case["alpha"], 0.02 * dx)
+    return case, precision
+
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_wide_generic_configuration_matches_the_oracle(seed):
+    case, precision = draw_wide(7000 + seed)
+    print(f"[random] wide seed {seed}: {case} {precision}", flush=True)
+    u0 = initial_field(case)
+    s = solver_for(case, precision)
+    s.set_state(torch.from_numpy(u0))
+    s.step(case["steps"])
+    got = s.state().double().cpu()
+    o = oracle_for(case, u0)
+    o.run(case["steps"])
+    assert torch.isfinite(got).all()
+    err = rel_l2(got, o.u)
+    assert err <= TOL[precision], (case, precision, err)
+
+
 @pytest.mark.parametrize("seed", range(12))
 def test_random_configuration_checkpoint_and_graph_are_bitwise(seed):
     """Plain launches against a graph-replayed run that is checkpointed,
