@@ -324,6 +324,16 @@ at_status at_ens_run(at_ens* ens, int64_t nsteps);
  * bit-identical for every choice. */
 at_status at_ens_set_tuning(at_ens* ens, int32_t groups_per_cu, int32_t threads);
 
+/* The workgroup schedule of the persistent launch (host arrays): `*nbins`
+ * workgroups; workgroup j runs the members order[bin_start[j]] ..
+ * order[bin_start[j+1] - 1] (bin_start: nbins + 1 entries, order: one entry
+ * per member; either may be NULL to query *nbins first). A workgroup holds
+ * the descriptors of at most AT_ENS_BATCH members at a time: a larger bin
+ * runs every step for its first AT_ENS_BATCH members, then for the next
+ * ones (members are independent problems). */
+enum { AT_ENS_BATCH = 24 };
+at_status at_ens_get_schedule(const at_ens* ens, int32_t* nbins, int32_t* bin_start, int32_t* order);
+
 /* Copy the packed current fields to `u_dev`. */
 at_status at_ens_get_state(at_ens* ens, void* u_dev);
 

@@ -31,8 +31,3 @@ def gradients(prob, dm, u0, alpha, nsteps, seed, key=None):
     gu, ga = torch.autograd.grad(J, (u, a))
     return gu.detach(), float(ga)
 
-
-def misfit(uN, target, cell_volume):
-    """J = 1/2 sum (u^N - target)^2 dV and its gradient (u^N - target) dV."""
-    d = torch.as_tensor(uN, dtype=torch.float64) - torch.as_tensor(target, dtype=torch.float64)
-    return 0.5 * float((d * d).sum()) * cell_volume, d * cell_volume

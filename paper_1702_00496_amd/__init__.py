@@ -307,6 +307,27 @@ class Ensemble:
         self._check(self._lib.at_ens_get_state(self._ctx, _as_ptr(out)))
         return out
 
+    def schedule(self):
+        """(bin_start, order): workgroup j runs members order[bin_start[j]:bin_start[j+1]]."""
+        nb = ctypes.c_int32(0)
+        self._check(self._lib.at_ens_get_schedule(self._ctx, ctypes.byref(nb), None, None))
+        starts = (ctypes.c_int32 * (nb.value + 1))()
+        order = (ctypes.c_int32 * self.count)()
+        self._check(self._lib.at_ens_get_schedule(self._ctx, ctypes.byref(nb), starts, order))
+        return np.array(starts[:], dtype=np.int64), np.array(order[:], dtype=np.int64)
+
+    def bin_sizes(self):
+        starts, _ = self.schedule()
+        return np.diff(starts)
+
+    def members_beyond_batch(self, batch=24):
+        """Members that their workgroup runs after its first ``batch`` members."""
+        starts, order = self.schedule()
+        out = []
+        for j in range(len(starts) - 1):
+            out.extend(int(i) for i in order[starts[j] + batch:starts[j + 1]])
+        return out
+
     def split(self, packed):
         return list(torch.split(packed, self.sizes))
 

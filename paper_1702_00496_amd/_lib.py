@@ -108,6 +108,7 @@ SIGNATURES = {
     "at_ens_set_state": (I32, [P, P]),
     "at_ens_run": (I32, [P, I64]),
     "at_ens_set_tuning": (I32, [P, I32, I32]),
+    "at_ens_get_schedule": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "at_ens_get_state": (I32, [P, P]),
     "at_ens_get_step": (I32, [P, ctypes.POINTER(I64)]),
     "at_ens_norms": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),

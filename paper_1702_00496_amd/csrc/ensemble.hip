@@ -225,7 +225,7 @@ __device__ inline void ens_member_sweep_s(const EnsMember& M, const Real* u, Rea
 }
 
 // Members whose descriptors a workgroup holds in LDS at a time.
-constexpr int kEnsLdsMembers = 24;
+constexpr int kEnsLdsMembers = AT_ENS_BATCH;
 
 // All steps of `count` members whose descriptors are in LDS.
 template <typename Real>

@@ -330,6 +330,16 @@ at_status at_ens_set_tuning(at_ens* e, int32_t groups_per_cu, int32_t threads) {
   return AT_OK;
 }
 
+at_status at_ens_get_schedule(const at_ens* e, int32_t* nbins, int32_t* bin_start, int32_t* order) {
+  if (!e || !nbins) return efail(nullptr, AT_EINVAL, "null argument");
+  *nbins = e->nbins;
+  if (bin_start)
+    for (size_t j = 0; j < e->bin_start.size(); ++j) bin_start[j] = e->bin_start[j];
+  if (order)
+    for (size_t j = 0; j < e->order.size(); ++j) order[j] = e->order[j];
+  return AT_OK;
+}
+
 at_status at_ens_get_state(at_ens* e, void* u_dev) {
   if (!e || !u_dev) return efail(e, AT_EINVAL, "null argument");
   ENS_TRY(e, hipMemcpyAsync(u_dev, e->ep.u[e->n & 1], e->field_bytes, hipMemcpyDeviceToDevice, e->stream));

@@ -4,7 +4,13 @@ import numpy as np
 import torch
 
 import workloads as W
-from oracle.solver import DelayModel, Oracle, Problem
+from oracle.solver import DelayModel, Oracle, Problem, boundary_mask
+
+
+def problem_for(case):
+    return Problem(ndim=case["ndim"], n=case["n"], pe=case["pe"], dt=case["dt"], order=case["order"],
+                   equation=case.get("equation", "advdiff"), c=case.get("c", (0.0, 0.0, 0.0)),
+                   alpha=case.get("alpha", 0.1), integrator=case.get("integrator", "euler"))
 
 
 def oracle_for(case, u0):
@@ -44,3 +50,38 @@ def rel_l2(a, b):
     a = torch.as_tensor(a, dtype=torch.float64).reshape(-1)
     b = torch.as_tensor(b, dtype=torch.float64).reshape(-1)
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def field_errors(got, want, prob=None):
+    """Relative errors of a field against the oracle's, element by element:
+    ``l2`` = ||d||_2 / ||want||_2 over all points, ``max`` = max|d| / max|want|
+    (relative Linf), and, when the problem is given, ``ib`` = the relative L2
+    over the boundary set I_B only (points within s of a PE face, where the
+    delayed levels enter)."""
+    g = torch.as_tensor(got, dtype=torch.float64)
+    w = torch.as_tensor(want, dtype=torch.float64)
+    if prob is not None:
+        g = g.reshape(prob.shape)
+        w = w.reshape(prob.shape)
+    d = g - w
+    out = {"l2": float(torch.linalg.norm(d.reshape(-1)) / torch.linalg.norm(w.reshape(-1))),
+           "max": float(d.abs().max() / w.abs().max())}
+    if prob is not None:
+        m = boundary_mask(prob)
+        if bool(m.any()):
+            out["ib"] = float(torch.linalg.norm(d[m]) / torch.linalg.norm(w[m]))
+    return out
+
+
+def check_field(got, want, tol, prob=None, label=""):
+    """Assert every error of ``field_errors`` is within ``tol`` (and the field
+    is finite); ``want`` may be an Oracle (its current level and problem are
+    used). Returns the errors."""
+    if isinstance(want, Oracle):
+        prob = want.prob if prob is None else prob
+        want = want.u
+    g = torch.as_tensor(got, dtype=torch.float64)
+    assert bool(torch.isfinite(g).all()), (label, "non-finite values")
+    e = field_errors(g, want, prob)
+    assert all(v <= tol for v in e.values()), (label, e, tol)
+    return e

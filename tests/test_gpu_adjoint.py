@@ -17,7 +17,7 @@ import torch
 import workloads as W
 from oracle.adjoint import gradients
 from oracle.solver import DelayModel, Problem
-from tests._cases import initial_field, rel_l2, solver_for
+from tests._cases import field_errors, initial_field, oracle_for, rel_l2, solver_for
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +86,8 @@ def test_adjoint_matches_oracle_gradients(name, precision):
     s, gu, ga = _gpu_grads(case, u0, seed, precision)
     tol = 1e-10 if precision == "f64" else 1e-4
     err = rel_l2(gu, gu_o)
-    _say(f"[adj]   du0 rel err {err:.3e}   dalpha {ga:.9e} vs {ga_o:.9e}")
+    _say(f"[adj]   du0 errors {field_errors(gu, gu_o, oracle_for(case, u0).prob)}   "
+         f"dalpha {ga:.9e} vs {ga_o:.9e} (rel {abs(ga - ga_o) / abs(ga_o):.3e})")
     assert err <= tol
     assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3)
     # the context ends at step N with the forward field of a plain run
@@ -282,5 +283,7 @@ def test_adjoint_random_configuration_matches_oracle_gradients(seed):
     gu_o, ga_o = _oracle_grads(case, u0, sd)
     s, gu, ga = _gpu_grads(case, u0, sd, precision)
     tol = 1e-10 if precision == "f64" else 1e-4
+    _say(f"[adj]   du0 errors {field_errors(gu, gu_o, oracle_for(case, u0).prob)}   "
+         f"dalpha rel {abs(ga - ga_o) / max(abs(ga_o), 1e-300):.3e}")
     assert rel_l2(gu, gu_o) <= tol, (case, precision, rel_l2(gu, gu_o))
     assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3), (case, precision, ga, ga_o)

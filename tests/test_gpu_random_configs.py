@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests._cases import initial_field, oracle_for, rel_l2, solver_for
+from tests._cases import check_field, initial_field, oracle_for, solver_for
 
 pytestmark = pytest.mark.gpu
 
@@ -57,9 +57,7 @@ def test_random_configuration_matches_the_oracle(seed):
     got = s.state().double().cpu()
     o = oracle_for(case, u0)
     o.run(case["steps"])
-    assert torch.isfinite(got).all()
-    err = rel_l2(got, o.u)
-    assert err <= TOL[precision], (case, precision, err)
+    check_field(got, o, TOL[precision], label=(case, precision))
     if case["mode"] == "rng":
         d = s.delays(0, case["steps"])
         for k in range(case["steps"]):
@@ -100,9 +98,7 @@ def test_random_deep_generic_configuration_matches_the_oracle(seed):
     got = s.state().double().cpu()
     o = oracle_for(case, u0)
     o.run(case["steps"])
-    assert torch.isfinite(got).all()
-    err = rel_l2(got, o.u)
-    assert err <= TOL[precision], (case, precision, err)
+    check_field(got, o, TOL[precision], label=(case, precision))
 
 
 def draw_wide(seed):
@@ -132,9 +128,7 @@ def test_random_wide_generic_configuration_matches_the_oracle(seed):
     got = s.state().double().cpu()
     o = oracle_for(case, u0)
     o.run(case["steps"])
-    assert torch.isfinite(got).all()
-    err = rel_l2(got, o.u)
-    assert err <= TOL[precision], (case, precision, err)
+    check_field(got, o, TOL[precision], label=(case, precision))
 
 
 @pytest.mark.parametrize("seed", range(12))

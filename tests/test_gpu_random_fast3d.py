@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests._cases import initial_field, oracle_for, rel_l2, solver_for
+from tests._cases import check_field, initial_field, oracle_for, solver_for
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,7 @@ def test_random_fast3d_configuration_matches_the_oracle(seed):
     got = s.state().double().cpu()
     o = oracle_for(case, u0)
     o.run(case["steps"])
-    assert torch.isfinite(got).all()
-    err = rel_l2(got, o.u)
-    assert err <= TOL[precision], (case, precision, depth, err)
+    check_field(got, o, TOL[precision], label=(case, precision, depth))
     if case["mode"] == "rng":
         d = s.delays(0, case["steps"])
         for k in range(case["steps"]):

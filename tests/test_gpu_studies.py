@@ -10,6 +10,8 @@ import numpy as np
 import pytest
 import torch
 
+from tests._cases import check_field
+
 from oracle.solver import DelayModel, Oracle, Problem
 
 pytestmark = pytest.mark.gpu
@@ -120,10 +122,8 @@ def test_convergence_study_fields_match_the_oracle(case):
     o = Oracle(prob, DelayModel(L=3, mode="rng", seed=studies._member_key(0, n, 0), weights=list(w)),
                u0.reshape(prob.shape))
     o.run(steps)
-    want = o.u.reshape(-1).numpy()
-    err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
-    _say(f"[study] {case} N=32 field rel L2 vs oracle {err:.3e}")
-    assert err < 1e-12
+    err = check_field(torch.as_tensor(got), o, 1e-12, label=case)
+    _say(f"[study] {case} N=32 field vs oracle {err}")
 
 
 def test_cases_5_and_6_converge_at_the_scheme_order_for_every_delay_law():

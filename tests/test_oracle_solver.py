@@ -98,12 +98,26 @@ def _discrete_fourier_sync(prob, kappa, steps):
         for _ in range(steps - 1):
             u_prev, u_cur = u_cur, u_cur + z * (1.5 * u_cur - 0.5 * u_prev)
         g = u_cur
+    elif prob.integrator == "ab3":
+        # start-up (reading S4): one Euler step, one AB2 step, then AB3
+        g_hist = [1.0 + 0j]
+        for n in range(steps):
+            f = [z * v for v in g_hist[::-1]]      # z * g^n, z * g^{n-1}, ...
+            if n == 0:
+                inc = f[0]
+            elif n == 1:
+                inc = 1.5 * f[0] - 0.5 * f[1]
+            else:
+                inc = (23.0 * f[0] - 16.0 * f[1] + 5.0 * f[2]) / 12.0
+            g_hist.append(g_hist[-1] + inc)
+        g = g_hist[-1]
     xs = np.meshgrid(*[np.arange(prob.n[a]) * prob.dx[a] for a in range(3)][::-1], indexing="ij")
     phase = sum(kappa[a] * xs[2 - a] for a in range(3))
     return np.imag(g * np.exp(1j * phase))
 
 
-@pytest.mark.parametrize("integ,order,ndim", [("euler", 2, 1), ("ab2", 4, 1), ("rk2", 6, 1), ("ab2", 4, 3), ("ab2", 4, 2)])
+@pytest.mark.parametrize("integ,order,ndim", [("euler", 2, 1), ("ab2", 4, 1), ("rk2", 6, 1), ("ab2", 4, 3), ("ab2", 4, 2),
+                                               ("ab3", 4, 1), ("ab3", 6, 2), ("ab3", 2, 3)])
 def test_synchronous_scheme_equals_discrete_fourier_solution(integ, order, ndim):
     n = {1: (64,), 2: (32, 16), 3: (16, 16, 16)}[ndim]
     pe = {1: (4,), 2: (2, 2), 3: (2, 2, 2)}[ndim]
@@ -239,6 +253,67 @@ def test_convergence_order_fourth_order_case4():
     assert all(abs(s + 4) < 0.2 for s in sy), sy
     assert all(abs(s + 4) < 0.25 for s in at), at
     assert all(-1.4 < s < -0.7 for s in st), st
+
+
+def _mode_eigenvalue(prob, kappa):
+    """Eigenvalue of the synchronous right-hand side on e^{i kappa x} (1-D)."""
+    dx, s = prob.dx[0], prob.s
+    ph = np.exp(1j * kappa * dx * np.arange(-s, s + 1))
+    d1 = (_taps(1, prob.order) * ph).sum() / dx
+    d2 = (_taps(2, prob.order) * ph).sum() / dx ** 2
+    return -prob.c[0] * d1 + prob.alpha * d2
+
+
+def test_ab3_from_exact_history_is_third_order_in_time():
+    """Sec. 4.1 eq. time_disc with three levels: an explicit three-step Adams
+    method u^{n+1} = u^n + dt (b0 f^n + b1 f^{n-1} + b2 f^{n-2}) is third-order
+    accurate only for (b0, b1, b2) = (23, -16, 5)/12 (the order conditions
+    b0 + b1 + b2 = 1, -(b1 + 2 b2) = 1/2, (b1 + 4 b2)/2 = 1/6 have that one
+    solution). Started from the exact past right-hand sides of one Fourier
+    mode, the oracle's error against the exact semi-discrete solution
+    e^{lambda t} must fall by 8x per halving of dt."""
+    kappa = 3
+    N, tf = 32, 0.6
+    errs = []
+    for dt in (0.03, 0.015, 0.0075):
+        prob = Problem(ndim=1, n=(N,), pe=(4,), dt=dt, order=4, integrator="ab3", c=(1.0,), alpha=0.1)
+        lam = _mode_eigenvalue(prob, kappa)
+        x = np.arange(N) * prob.dx[0]
+
+        def exact(t):
+            return torch.from_numpy(np.imag(np.exp(lam * t) * np.exp(1j * kappa * x)).reshape(prob.shape))
+
+        o = Oracle(prob, DelayModel(mode="sync"), exact(0.0))
+        K = delay_table(prob, DelayModel(mode="sync"), 0)
+        o.fhist = [o.rhs(exact(-dt), K), o.rhs(exact(-2 * dt), K)]   # f^{-1}, f^{-2}
+        steps = int(round(tf / dt))
+        o.run(steps)
+        errs.append(float((o.u - exact(steps * dt)).abs().max()))
+    sl = _slopes(errs)
+    assert all(-3.1 < v < -2.9 for v in sl), (errs, sl)
+
+
+@pytest.mark.slow
+def test_at_ab3_fourth_order_converges_at_slope_minus_four():
+    """AB3 with the fourth-order AT scheme ((1,4,2) + (2,4,2), T = 3), delays
+    L = 3 on 8 PEs, dt ~ dx^2: the spatial O(dx^4) error and the O(dt^2) =
+    O(dx^4) of the Euler start-up give slope -4 against the exact advected
+    decaying sine series (Sec. 5.2 workload)."""
+    modes = W.make_modes([(3,), (4,), (5,)], [2.0, 0.5, 1.5], seed=7)
+    tf = 0.1
+    errs = {"sync": [], "rng": []}
+    for N in (32, 64, 128):
+        dx = 2 * math.pi / N
+        steps = int(round(tf / (0.02 * dx * dx / 0.1)))
+        prob = Problem(ndim=1, n=(N,), pe=(8,) if N >= 64 else (4,), dt=tf / steps, order=4,
+                       integrator="ab3", c=(1.0,), alpha=0.1)
+        u0 = torch.from_numpy(W.eval_modes(modes, (N,), 1))
+        for mode in errs:
+            o = _run(prob, DelayModel(L=3, mode=mode, seed=13), u0, steps)
+            errs[mode].append(error_norms(o.u, advected_modes(prob, modes, o.t))["l2"])
+    for mode, e in errs.items():
+        sl = _slopes(e)
+        assert all(-4.3 < v < -3.7 for v in sl), (mode, e, sl)
 
 
 def test_first_configuration_against_analytic_solution():
