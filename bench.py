@@ -80,6 +80,17 @@ def bytes_per_update(precision, mode):
     return (4 + h * (levels + 1)) * w
 
 
+def graph_chunk():
+    """Steps per captured HIP graph: the largest divisor of the timed step count
+    not above --graph, so that every timed step runs from a graph replay."""
+    if args.graph <= 0:
+        return 0
+    return max(d for d in range(1, min(args.graph, args.steps) + 1) if args.steps % d == 0)
+
+
+GRAPH = graph_chunk()
+
+
 def time_arm(precision, mode):
     s = make(precision, mode)
     s.set_state(u0)
@@ -89,11 +100,11 @@ def time_arm(precision, mode):
     elif not args.no_autotune:
         s.step(3)
         tuned = s.autotune(nsteps=20)       # schedule choice, state restored
-    if args.graph:
-        s.set_graph(args.graph)
+    if GRAPH:
+        s.set_graph(GRAPH)
     s.set_state(u0)
-    if args.graph:
-        s.step(args.graph)                  # capture and instantiate the graph outside the timing
+    if GRAPH:
+        s.step(GRAPH)                       # capture and instantiate the graph outside the timing
     s.step(args.warmup)
     s.set_state(u0)                     # the timed run is steps 0..K-1 of the workload
     torch.cuda.synchronize()
@@ -180,6 +191,13 @@ def cpu_baseline():
     t0 = time.perf_counter()
     o.run(args.cpu_steps)
     dt_ = time.perf_counter() - t0
+    cores = torch.get_num_threads()
+    # one thread: the next step of the same run
+    torch.set_num_threads(1)
+    t0 = time.perf_counter()
+    o.run(1)
+    dt1 = time.perf_counter() - t0
+    torch.set_num_threads(cores)
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -187,9 +205,12 @@ def cpu_baseline():
     except OSError:
         pass
     return dict(value=npts * args.cpu_steps / dt_, unit="grid-pt updates/s",
-                cores=torch.get_num_threads(), cpu_model=model, kind="oracle",
+                cores=cores, cpu_model=model, kind="oracle",
                 sample=f"first {args.cpu_steps} of {cfg['steps']} steps of the {N}^3 workload, FP64, "
-                       f"{dt_:.1f} s")
+                       f"{dt_:.1f} s",
+                single_thread=dict(value=npts / dt1, cores=1,
+                                   sample=f"step {args.cpu_steps + 1} of the same run on one thread, "
+                                          f"{dt1:.1f} s"))
 
 
 arms = {}
@@ -520,7 +541,10 @@ def time_study():
 
 def time_ensemble():
     """512 independent 1-D members (N log-uniform in [1024, 65536], PE 64,
-    orders 2/4, L in {2, 4, 8}), 2000 steps in one persistent launch, FP32."""
+    orders 2/4, L in {2, 4, 8}), 2000 steps in one persistent launch, FP32;
+    schedule from the ensemble autotuner (timed outside the run). Reports the
+    ensemble mean and unbiased variance of the members' RMS error against the
+    exact solution, per order and per log-spaced dx bin."""
     from paper_1702_00496_amd import Ensemble
     inst = W.ensemble_instances()
     members = [dict(n=m["n"], pe=m["pe"], order=m["order"], integrator=m["integrator"], L=m["L"], T=m["T"],
@@ -528,6 +552,8 @@ def time_ensemble():
     u3 = torch.from_numpy(np.concatenate([W.eval_modes(m["modes"], (m["n"],), 1).reshape(-1) for m in inst]))
     ens = Ensemble(members, precision="f32")
     ens.set_state(u3)
+    default = ens.tuning()
+    tuned, tune_ms = ens.autotune(nsteps=100)
     ens.run(2000)                           # capture + warm-up
     ens.set_state(u3)
     torch.cuda.synchronize()
@@ -540,11 +566,24 @@ def time_ensemble():
     ms = e0.elapsed_time(e1)
     ph = np.array([[mo[2] for mo in m["modes"]] for m in inst])
     err = ens.norms([3, 4, 5], [2.0, 0.5, 1.5], ph)
+    dx = np.array([2 * math.pi / m["n"] for m in members])
+    nb = 8
+    edges = np.exp(np.linspace(np.log(dx.min()), np.log(dx.max() * (1 + 1e-9)), nb + 1))
+    stats = ens.error_stats(edges, [3, 4, 5], [2.0, 0.5, 1.5], ph)
+    table = {}
+    for g, order in ((0, 2), (1, 4)):
+        table[f"order{order}"] = [dict(dx_lo=float(edges[j]), dx_hi=float(edges[j + 1]), count=int(stats[g, j, 0]),
+                                       mean_dx=float(stats[g, j, 1]), mean_rms_error=float(stats[g, j, 2]),
+                                       var_rms_error=float(stats[g, j, 3]))
+                                  for j in range(nb) if stats[g, j, 0] > 0]
     ups = u3.numel() * 2000 / (ms / 1e3)
-    print(f"[bench] ensemble: {ms:.1f} ms for 2000 steps, {ups:.3e} upd/s", file=sys.stderr, flush=True)
+    print(f"[bench] ensemble: {ms:.1f} ms for 2000 steps, {ups:.3e} upd/s, schedule {tuned} "
+          f"(default {default})", file=sys.stderr, flush=True)
     return dict(workload="512-member 1-D delay ensemble, 7.5M points, 2000 steps, one persistent launch, FP32",
-                ms=ms, updates_per_s=ups, max_rms_error=float(err[:, 1].max()),
-                median_rms_error=float(np.median(err[:, 1])))
+                ms=ms, updates_per_s=ups, schedule=dict(groups_per_cu=tuned[0], threads=tuned[1]),
+                autotune_ms_per_step={f"{a}x{b}": v for (a, b), v in tune_ms.items()},
+                max_rms_error=float(err[:, 1].max()), median_rms_error=float(np.median(err[:, 1])),
+                error_vs_dx=table)
 
 
 def time_adjoint():
@@ -608,10 +647,12 @@ out = {
     "config": {"workload": f"3-D advection-diffusion {N}^3, {cfg['pe'][0]}^3 PEs of {args.b}^3, "
                            f"4th-order AT (T=3), L={cfg['L']} uniform delays, AB2, {cfg['steps']} steps",
                "grid": N, "pe_edge": args.b, "order": 4, "L": cfg["L"], "integrator": "ab2",
-               "dt": cfg["dt"], "graph_chunk": args.graph},
+               "dt": cfg["dt"], "graph_chunk": GRAPH},
     "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": head["frac"], "traffic": head["traffic_bytes"],
-                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
+                 "traffic_unit": "bytes per launch between L2 and the fabric (rocprofv3 FETCH_SIZE x 2 + "
+                                 "WRITE_SIZE, scaled by a copy kernel; includes Infinity Cache hits)",
+                 "frac_of_measured_copy": head["achieved_gbs"] / copy_gbs,
                  "kernel": f"at_step3d_fast_kernel<{'float' if head['precision'] == 'f32' else 'double'}, s=2, variant={head['depth']}, AB2, advection-diffusion>",
                  "bytes_per_update": head["bytes_per_update"],
                  "measured_copy_gbs": copy_gbs},

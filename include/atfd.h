@@ -334,6 +334,26 @@ at_status at_ens_set_tuning(at_ens* ens, int32_t groups_per_cu, int32_t threads)
 enum { AT_ENS_BATCH = 24 };
 at_status at_ens_get_schedule(const at_ens* ens, int32_t* nbins, int32_t* bin_start, int32_t* order);
 
+/* Bytes of device scratch at_ens_autotune needs to keep the current state
+ * (both field buffers, the AB2 history, the rings and the step counter). */
+at_status at_ens_state_size(const at_ens* ens, size_t* bytes);
+
+/* Autotune the schedule of the persistent launch (a12: launch shape search,
+ * not a part of the method): time nsteps steps for every candidate
+ * (workgroups per CU in {1, 2, 4}) x (threads in {256, 512, 1024}), candidate
+ * c = 3 * (index of groups) + (index of threads), each from the current state
+ * (saved to `scratch_dev`, >= at_ens_state_size bytes, and restored after
+ * every candidate), keep the fastest and leave the ensemble at the state and
+ * step it had. ms[AT_ENS_TUNE_CANDIDATES] (host, may be NULL) receives each
+ * candidate's milliseconds per step. Every candidate gives bit-identical
+ * results. AT_ESTATE before at_ens_set_state. Synchronises the stream. */
+enum { AT_ENS_TUNE_CANDIDATES = 9 };
+at_status at_ens_autotune(at_ens* ens, void* scratch_dev, size_t scratch_bytes, int64_t nsteps,
+                          int32_t* best_groups, int32_t* best_threads, double* ms);
+
+/* Current schedule choice (workgroups per CU, threads per workgroup). */
+at_status at_ens_get_tuning(const at_ens* ens, int32_t* groups_per_cu, int32_t* threads);
+
 /* Copy the packed current fields to `u_dev`. */
 at_status at_ens_get_state(at_ens* ens, void* u_dev);
 
@@ -349,6 +369,23 @@ at_status at_ens_get_step(const at_ens* ens, int64_t* n);
  * stream. At most 16 modes. */
 at_status at_ens_norms(at_ens* ens, int32_t nmodes, const int32_t* kappa, const double* amp,
                        const double* phase, const double* ref_dev, double* out);
+
+/* Ensemble statistics of the per-member RMS error against the grid spacing
+ * (Sec. 4 ensemble averages of the error over delay realisations; Sec. 5.1
+ * error E = u - u_a). Members are grouped by spatial order (group 0, 1, 2 for
+ * orders 2, 4, 6) and, within a group, by dx = length / n into `nbins`
+ * (1..AT_ENS_MAX_DX_BINS) bins with host edges dx_edges[0] < ... <
+ * dx_edges[nbins]; bin j holds edges[j] <= dx < edges[j+1], members outside
+ * every bin are not counted. Host output out[(g * nbins + j) * 4 + q]: q = 0
+ * member count, 1 mean dx, 2 mean of the members' RMS errors, 3 their
+ * unbiased variance (denominator count - 1; 0 when count < 2). Reference as
+ * for at_ens_norms; the per-member errors and the statistics are computed on
+ * the device in double with a fixed summation order. Returns AT_EUNSTABLE if
+ * any value is not finite, AT_EINVAL for bad bins. Synchronises the stream. */
+enum { AT_ENS_MAX_DX_BINS = 64 };
+at_status at_ens_error_stats(at_ens* ens, int32_t nmodes, const int32_t* kappa, const double* amp,
+                             const double* phase, const double* ref_dev, int32_t nbins, const double* dx_edges,
+                             double* out);
 
 /* Release the ensemble (device memory stays with the caller). */
 at_status at_ens_destroy(at_ens* ens);

@@ -37,3 +37,23 @@ def ensemble_mean_var(values):
     if v.numel() < 2:
         return float(v.mean()), 0.0
     return float(v.mean()), float(v.var(unbiased=True))
+
+
+def binned_mean_var(dx, values, groups, edges, ngroups=3):
+    """Ensemble mean and unbiased variance of per-member values binned by grid
+    spacing (Sec. 4 ensemble averages, taken over the members that share a
+    range of dx). Member i falls in group groups[i] and in bin j when
+    edges[j] <= dx[i] < edges[j + 1]. Returns a list over groups of lists over
+    bins of (count, mean dx, mean value, unbiased variance)."""
+    out = []
+    for g in range(ngroups):
+        row = []
+        for j in range(len(edges) - 1):
+            sel = [i for i in range(len(values)) if groups[i] == g and edges[j] <= dx[i] < edges[j + 1]]
+            if not sel:
+                row.append((0, 0.0, 0.0, 0.0))
+                continue
+            m, v = ensemble_mean_var([values[i] for i in sel])
+            row.append((len(sel), sum(dx[i] for i in sel) / len(sel), m, v))
+        out.append(row)
+    return out

@@ -14,6 +14,8 @@ import torch
 from . import _lib, tuning
 from ._lib import ATError, AtDelay, AtEnsMember, AtProblem, check
 
+ENS_TUNE_CANDIDATES = 9
+
 __all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS"]
 
 # schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
@@ -261,6 +263,7 @@ class Ensemble:
                 a.weights = ctypes.cast(w, ctypes.POINTER(ctypes.c_uint32))
             self.sizes.append(a.n)
         self._arr = arr
+        self._members = [dict(m) for m in members]
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.device = torch.device(device)
         self.total = sum(self.sizes)
@@ -301,6 +304,42 @@ class Ensemble:
 
     def set_tuning(self, groups_per_cu=0, threads=0):
         self._check(self._lib.at_ens_set_tuning(self._ctx, int(groups_per_cu), int(threads)))
+
+    def tuning(self):
+        """(workgroups per CU, threads per workgroup) of the persistent launch."""
+        g, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self._lib.at_ens_get_tuning(self._ctx, ctypes.byref(g), ctypes.byref(t)))
+        return g.value, t.value
+
+    def tuning_key(self):
+        props = torch.cuda.get_device_properties(self.device)
+        return tuning.make_ens_key(getattr(props, "gcnArchName", props.name), props.multi_processor_count,
+                                   self._members, "f64" if self.dtype == torch.float64 else "f32")
+
+    def autotune(self, nsteps=50, cache=None):
+        """Time every schedule candidate (``at_ens_autotune``) from the current
+        state (restored afterwards) and keep the fastest. Returns
+        ((groups_per_cu, threads), {(groups, threads): ms/step}). ``cache``: a
+        JSON tuning cache path; a stored entry for these members' shapes is
+        applied without timing."""
+        if cache is not None:
+            ent = tuning.lookup(cache, self.tuning_key())
+            if ent is not None and isinstance(ent["variant"], list):
+                g, t = ent["variant"]
+                self.set_tuning(g, t)
+                return (g, t), {tuple(int(x) for x in k.split("x")): v for k, v in ent.get("ms", {}).items()}
+        sz = ctypes.c_size_t(0)
+        self._check(self._lib.at_ens_state_size(self._ctx, ctypes.byref(sz)))
+        scratch = torch.empty(max(int(sz.value), 1), dtype=torch.uint8, device=self.device)
+        g, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        ms = (ctypes.c_double * ENS_TUNE_CANDIDATES)()
+        self._check(self._lib.at_ens_autotune(self._ctx, _as_ptr(scratch), sz.value, int(nsteps),
+                                              ctypes.byref(g), ctypes.byref(t), ms))
+        times = {(gc, tc): ms[3 * i + j] for i, gc in enumerate((1, 2, 4)) for j, tc in enumerate((256, 512, 1024))}
+        if cache is not None:
+            tuning.store(cache, self.tuning_key(), [g.value, t.value],
+                         {f"{a}x{b}": v for (a, b), v in times.items()})
+        return (g.value, t.value), times
 
     def state(self):
         out = torch.empty(self.total, dtype=self.dtype, device=self.device)
@@ -353,6 +392,30 @@ class Ensemble:
         else:
             ref = ref.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
             st = self._lib.at_ens_norms(self._ctx, 0, None, None, None, _as_ptr(ref), optr)
+        self._check(st)
+        return out
+
+
+    def error_stats(self, dx_edges, kappas=None, amps=None, phases=None, ref=None):
+        """Per order group (2, 4, 6) and dx bin: (count, mean dx, mean RMS error,
+        unbiased variance of the RMS error) as a (3, nbins, 4) numpy array
+        (``at_ens_error_stats``); the reference as for :meth:`norms`."""
+        edges = np.ascontiguousarray(dx_edges, dtype=np.float64)
+        nb = len(edges) - 1
+        out = np.zeros((3, nb, 4), dtype=np.float64)
+        optr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        eptr = edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if kappas is not None:
+            nm = len(kappas)
+            kap = (ctypes.c_int32 * nm)(*[int(k) for k in kappas])
+            amp = (ctypes.c_double * nm)(*[float(a) for a in amps])
+            ph = np.ascontiguousarray(phases, dtype=np.float64).reshape(self.count, nm)
+            st = self._lib.at_ens_error_stats(self._ctx, nm, kap, amp,
+                                              ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None,
+                                              nb, eptr, optr)
+        else:
+            ref = ref.to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+            st = self._lib.at_ens_error_stats(self._ctx, 0, None, None, None, _as_ptr(ref), nb, eptr, optr)
         self._check(st)
         return out
 

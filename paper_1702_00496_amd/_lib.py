@@ -108,10 +108,14 @@ SIGNATURES = {
     "at_ens_set_state": (I32, [P, P]),
     "at_ens_run": (I32, [P, I64]),
     "at_ens_set_tuning": (I32, [P, I32, I32]),
+    "at_ens_state_size": (I32, [P, ctypes.POINTER(SZ)]),
+    "at_ens_autotune": (I32, [P, P, SZ, I64, ctypes.POINTER(I32), ctypes.POINTER(I32), DP]),
+    "at_ens_get_tuning": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "at_ens_get_schedule": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "at_ens_get_state": (I32, [P, P]),
     "at_ens_get_step": (I32, [P, ctypes.POINTER(I64)]),
     "at_ens_norms": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),
+    "at_ens_error_stats": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, I32, DP, DP]),
     "at_ens_destroy": (I32, [P]),
     "at_ens_last_error": (ctypes.c_char_p, [P]),
     "at_derive_scheme": (I32, [I32, I32, I32, I32, IP, IP, LP, LP, ctypes.POINTER(AtDerivation)]),

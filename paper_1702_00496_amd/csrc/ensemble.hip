@@ -402,7 +402,71 @@ __global__ __launch_bounds__(kEnsNormThreads) void ens_norms_kernel(EnsNormParam
   }
 }
 
+// Binned ensemble statistics of the per-member RMS error (Sec. 4 ensemble
+// averages): one workgroup per (order group, dx bin). Two passes over the
+// members in index order (mean, then the sum of squared deviations), each
+// thread's partial sums combined by a wave64 shuffle tree and then wave by
+// wave: a fixed summation order.
+constexpr int kEnsStatsThreads = 256;
+
+__device__ inline void ens_stats_reduce(double* v, int nv, double (*part)[3]) {
+  for (int off = 32; off > 0; off >>= 1)
+    for (int q = 0; q < nv; ++q) v[q] += __shfl_down(v[q], off, 64);
+  const int wave = threadIdx.x / 64;
+  __syncthreads();   // earlier readers of `part` are done
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < nv; ++q) part[wave][q] = v[q];
+  __syncthreads();
+  for (int q = 0; q < nv; ++q) {
+    double t = 0.0;
+    for (int w = 0; w < kEnsStatsThreads / 64; ++w) t += part[w][q];
+    v[q] = t;
+  }
+}
+
+__global__ __launch_bounds__(kEnsStatsThreads) void ens_stats_kernel(EnsStatsParams p) {
+  __shared__ double part[kEnsStatsThreads / 64][3];
+  const int g = blockIdx.x / p.nbins, j = blockIdx.x % p.nbins;
+  const double lo = p.edges[j], hi = p.edges[j + 1];
+  double v[3] = {0.0, 0.0, 0.0};   // count, sum dx, sum rms
+  for (int i = threadIdx.x; i < p.count; i += kEnsStatsThreads) {
+    const EnsMember& M = p.mem[i];
+    const double dx = M.length / static_cast<double>(M.n);
+    if (M.s - 1 == g && dx >= lo && dx < hi) {
+      v[0] += 1.0;
+      v[1] += dx;
+      v[2] += sqrt(p.sums[4 * i + 1] / static_cast<double>(M.n));
+    }
+  }
+  ens_stats_reduce(v, 3, part);
+  const double cnt = v[0];
+  const double mean = cnt > 0.0 ? v[2] / cnt : 0.0;
+  double d[1] = {0.0};
+  for (int i = threadIdx.x; i < p.count; i += kEnsStatsThreads) {
+    const EnsMember& M = p.mem[i];
+    const double dx = M.length / static_cast<double>(M.n);
+    if (M.s - 1 == g && dx >= lo && dx < hi) {
+      const double e = sqrt(p.sums[4 * i + 1] / static_cast<double>(M.n)) - mean;
+      d[0] += e * e;
+    }
+  }
+  ens_stats_reduce(d, 1, part);
+  if (threadIdx.x == 0) {
+    double* o = p.out + static_cast<int64_t>(blockIdx.x) * 4;
+    o[0] = cnt;
+    o[1] = cnt > 0.0 ? v[1] / cnt : 0.0;
+    o[2] = mean;
+    o[3] = cnt > 1.0 ? d[0] / (cnt - 1.0) : 0.0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_ens_stats(const EnsStatsParams& p, hipStream_t st) {
+  if (p.nbins < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ens_stats_kernel, dim3(3 * p.nbins), dim3(kEnsStatsThreads), 0, st, p);
+  return hipGetLastError();
+}
 
 hipError_t launch_ens_steps(const EnsParams& p, bool f64, int nbins, int threads, hipStream_t st) {
   if (threads < 64 || threads > kEnsMaxThreads || threads % 64) return hipErrorInvalidValue;

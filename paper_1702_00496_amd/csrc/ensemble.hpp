@@ -48,6 +48,15 @@ struct EnsNormParams {
   double* out;                     // [count][4]: sum|E|, sum E^2, max|E|, non-finite count
 };
 
+struct EnsStatsParams {
+  const EnsMember* mem;
+  const double* sums;              // [count][4] from the norms kernel (sum E^2 at [1])
+  const double* edges;             // [nbins + 1] ascending dx bin edges
+  int count, nbins;
+  double* out;                     // [3 groups][nbins][4]: count, mean dx, mean rms, unbiased variance
+};
+
+hipError_t launch_ens_stats(const EnsStatsParams& p, hipStream_t st);
 hipError_t launch_ens_steps(const EnsParams& p, bool f64, int nbins, int threads, hipStream_t st);
 hipError_t launch_ens_publish_all(const EnsParams& p, bool f64, int count, hipStream_t st);
 hipError_t launch_ens_norms(const EnsNormParams& p, bool f64, int count, hipStream_t st);

@@ -26,7 +26,7 @@ struct at_ens {
   int groups_per_cu = 1, threads = 1024, nbins = 0, cus = 256;
   size_t total_points = 0, field_bytes = 0, ring_elems = 0, halo_elems = 0;
   size_t off_mem = 0, off_bins = 0, off_order = 0, off_u[2] = {0, 0}, off_f = 0, off_ring = 0, off_hbuf = 0;
-  size_t off_counter = 0, off_out = 0, off_phase = 0, total = 0;
+  size_t off_counter = 0, off_out = 0, off_phase = 0, off_stats = 0, total = 0;
   bool any_ab2 = false;
   EnsParams ep{};
   unsigned char* ws = nullptr;
@@ -43,6 +43,9 @@ struct at_ens {
 namespace {
 
 constexpr int kPhaseMax = 1 << 16;   // doubles of per-member phases staged for at_ens_norms
+// autotune candidates: workgroups per CU x threads per workgroup
+constexpr int kEnsTuneGroups[3] = {1, 2, 4};
+constexpr int kEnsTuneThreads[3] = {256, 512, 1024};
 
 at_status efail(at_ens* e, at_status st, const char* fmt, ...) {
   char buf[512];
@@ -150,6 +153,7 @@ at_status plan(at_ens* e, int32_t count, const at_ens_member* m, int32_t precisi
   e->off_counter = take(2 * sizeof(int64_t));
   e->off_out = take(sizeof(double) * 4 * count);
   e->off_phase = take(sizeof(double) * kPhaseMax);
+  e->off_stats = take(sizeof(double) * (AT_ENS_MAX_DX_BINS + 1 + 3 * AT_ENS_MAX_DX_BINS * 4));
   e->total = off;
   return AT_OK;
 }
@@ -193,6 +197,22 @@ at_status upload_schedule(at_ens* e) {
   ENS_TRY(e, hipMemcpyAsync(e->ws + e->off_order, e->order.data(), sizeof(int) * e->order.size(),
                             hipMemcpyHostToDevice, e->stream));
   ENS_TRY(e, hipStreamSynchronize(e->stream));
+  return AT_OK;
+}
+
+at_status ens_save(at_ens* e, unsigned char* dst) {
+  const size_t span = e->off_hbuf - e->off_u[0];
+  ENS_TRY(e, hipMemcpyAsync(dst, e->ws + e->off_u[0], span, hipMemcpyDeviceToDevice, e->stream));
+  ENS_TRY(e, hipMemcpyAsync(dst + span, e->ws + e->off_counter, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                            e->stream));
+  return AT_OK;
+}
+
+at_status ens_restore(at_ens* e, const unsigned char* src) {
+  const size_t span = e->off_hbuf - e->off_u[0];
+  ENS_TRY(e, hipMemcpyAsync(e->ws + e->off_u[0], src, span, hipMemcpyDeviceToDevice, e->stream));
+  ENS_TRY(e, hipMemcpyAsync(e->ws + e->off_counter, src + span, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                            e->stream));
   return AT_OK;
 }
 
@@ -330,6 +350,80 @@ at_status at_ens_set_tuning(at_ens* e, int32_t groups_per_cu, int32_t threads) {
   return AT_OK;
 }
 
+at_status at_ens_state_size(const at_ens* e, size_t* bytes) {
+  if (!e || !bytes) return efail(nullptr, AT_EINVAL, "null argument");
+  // both field buffers, the AB2 history and the rings (contiguous in the
+  // workspace), then the step counter
+  *bytes = (e->off_hbuf - e->off_u[0]) + 2 * sizeof(int64_t);
+  return AT_OK;
+}
+
+at_status at_ens_autotune(at_ens* e, void* scratch_dev, size_t scratch_bytes, int64_t nsteps,
+                          int32_t* best_groups, int32_t* best_threads, double* ms) {
+  if (!e || !scratch_dev || !best_groups || !best_threads || nsteps < 1)
+    return efail(e, AT_EINVAL, "bad arguments");
+  if (!e->state_set) return efail(e, AT_ESTATE, "at_ens_autotune before at_ens_set_state");
+  size_t need = 0;
+  at_ens_state_size(e, &need);
+  if (scratch_bytes < need) return efail(e, AT_ENOMEM, "scratch %zu < %zu bytes", scratch_bytes, need);
+  unsigned char* save = static_cast<unsigned char*>(scratch_dev);
+  const int64_t n0 = e->n;
+  at_status st = ens_save(e, save);
+  if (st != AT_OK) return st;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ENS_TRY(e, hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return efail(e, AT_EHIP, "hipEventCreate failed");
+  }
+  double best = -1.0;
+  int bg = e->groups_per_cu, bt = e->threads;
+  for (int c = 0; c < AT_ENS_TUNE_CANDIDATES && st == AT_OK; ++c) {
+    const int g = kEnsTuneGroups[c / 3], t = kEnsTuneThreads[c % 3];
+    st = at_ens_set_tuning(e, g, t);
+    // one untimed run captures the candidate's graph and warms the caches
+    for (int rep = 0; rep < 2 && st == AT_OK; ++rep) {
+      st = ens_restore(e, save);
+      e->n = n0;
+      if (st == AT_OK && rep == 1 && hipEventRecord(ev[0], e->stream) != hipSuccess)
+        st = efail(e, AT_EHIP, "hipEventRecord failed");
+      if (st == AT_OK) st = at_ens_run(e, nsteps);
+    }
+    if (st != AT_OK) break;
+    float t_ms = 0.f;
+    if (hipEventRecord(ev[1], e->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t_ms, ev[0], ev[1]) != hipSuccess) {
+      st = efail(e, AT_EHIP, "ensemble autotune timing failed");
+      break;
+    }
+    const double per = static_cast<double>(t_ms) / static_cast<double>(nsteps);
+    if (ms) ms[c] = per;
+    if (best < 0.0 || per < best) {
+      best = per;
+      bg = g;
+      bt = t;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st != AT_OK) return st;
+  st = at_ens_set_tuning(e, bg, bt);
+  if (st == AT_OK) st = ens_restore(e, save);
+  if (st != AT_OK) return st;
+  ENS_TRY(e, hipStreamSynchronize(e->stream));
+  e->n = n0;
+  *best_groups = bg;
+  *best_threads = bt;
+  return AT_OK;
+}
+
+at_status at_ens_get_tuning(const at_ens* e, int32_t* groups_per_cu, int32_t* threads) {
+  if (!e || !groups_per_cu || !threads) return efail(nullptr, AT_EINVAL, "null argument");
+  *groups_per_cu = e->groups_per_cu;
+  *threads = e->threads;
+  return AT_OK;
+}
+
 at_status at_ens_get_schedule(const at_ens* e, int32_t* nbins, int32_t* bin_start, int32_t* order) {
   if (!e || !nbins) return efail(nullptr, AT_EINVAL, "null argument");
   *nbins = e->nbins;
@@ -349,6 +443,33 @@ at_status at_ens_get_state(at_ens* e, void* u_dev) {
 at_status at_ens_get_step(const at_ens* e, int64_t* n) {
   if (!e || !n) return efail(nullptr, AT_EINVAL, "null argument");
   *n = e->n;
+  return AT_OK;
+}
+
+at_status at_ens_error_stats(at_ens* e, int32_t nmodes, const int32_t* kappa, const double* amp,
+                             const double* phase, const double* ref_dev, int32_t nbins, const double* dx_edges,
+                             double* out) {
+  if (!e || !out || !dx_edges) return efail(e, AT_EINVAL, "null argument");
+  if (nbins < 1 || nbins > AT_ENS_MAX_DX_BINS) return efail(e, AT_EINVAL, "1..%d dx bins", AT_ENS_MAX_DX_BINS);
+  for (int j = 0; j < nbins; ++j)
+    if (!(dx_edges[j] < dx_edges[j + 1])) return efail(e, AT_EINVAL, "dx bin edges must ascend");
+  // per-member sums on the device (and the finiteness check) first
+  std::vector<double> per(static_cast<size_t>(e->count) * 3);
+  at_status st = at_ens_norms(e, nmodes, kappa, amp, phase, ref_dev, per.data());
+  if (st != AT_OK) return st;
+  double* d_edges = reinterpret_cast<double*>(e->ws + e->off_stats);
+  double* d_out = d_edges + AT_ENS_MAX_DX_BINS + 1;
+  ENS_TRY(e, hipMemcpyAsync(d_edges, dx_edges, sizeof(double) * (nbins + 1), hipMemcpyHostToDevice, e->stream));
+  EnsStatsParams p{};
+  p.mem = e->ep.mem;
+  p.sums = reinterpret_cast<const double*>(e->ws + e->off_out);
+  p.edges = d_edges;
+  p.count = e->count;
+  p.nbins = nbins;
+  p.out = d_out;
+  ENS_TRY(e, launch_ens_stats(p, e->stream));
+  ENS_TRY(e, hipMemcpyAsync(out, d_out, sizeof(double) * 3 * nbins * 4, hipMemcpyDeviceToHost, e->stream));
+  ENS_TRY(e, hipStreamSynchronize(e->stream));
   return AT_OK;
 }
 

@@ -13,9 +13,12 @@ solution (Sec. 5.1 eq. ana_sol), computed in double on the device.
   aveE_scaling_gen_kmom: <E> - <E>_s ~ E[k (k+1) ... (k+T-1)], i.e.
   <k^2> + <k> for T = 2 and <k^3> + 3<k^2> + 2<k> for T = 3 (with p_k = 1/L:
   L^2 - 1 and L^3 + 2L^2 - L - 2, eq. aveE_scaling_gen_L).
+- ``delay_law_study``: the same for arbitrary delay laws p_k (several laws
+  of one or more L side by side).
 - ``pe_scaling_study``: <E> against the number of PEs P at fixed N (strong
-  scaling) or at fixed N/P (weak scaling), eq. aveE_scaling_gen2
-  (<E> ~ P dx^{a+1} sum gamma_m <k^m>).
+  scaling: linear in P), at fixed P under refinement (asynchronous part
+  ~ dx^{a+1}: slope -3 for a = 2) or at fixed P/N (weak scaling: ~ dx^a,
+  slope -2), eq. aveE_scaling_gen2 (<E> ~ P dx^{a+1} sum gamma_m <k^m>).
 
 Only argument marshalling and averaging happen here; the steps and the error
 norms run in the library's kernels.
@@ -119,6 +122,39 @@ def moment_study(order=2, Ls=(2, 3, 4, 5, 6), realizations=64, n=128, pe=16, r_a
         rows[L] = dict(E=e, E_sync=es, asynchronous=a, law=law, ratio=a / law if law else float("nan"),
                        perturbation=pert, perturbation_ratio=pert / law if law else float("nan"))
     return dict(order=order, T=T, steps=steps, dt=dt, members=members, per_L=rows)
+
+
+def delay_law_study(order=2, laws=((3, (2, 5, 3)), (3, (5, 3, 2)), (3, (1, 1, 8)), (3, (8, 1, 1)), (4, (1, 2, 3, 4))),
+                    realizations=64, n=128, pe=16, r_alpha=0.1, t_final=0.5, c=1.0, alpha=0.1, seed=0,
+                    precision="f64", device="cuda"):
+    """<E> for general delay laws p_k (Sec. 5.2 eq. aveE_scaling_gen_kmom: the
+    asynchronous part follows E[k (k+1) ... (k+T-1)] for any p_k, not only
+    p_k = 1/L): ``laws`` is a list of (L, bin weights); every law gets
+    ``realizations`` delay histories and the configuration one synchronous
+    member, all in one launch. Returns per law (in order): L, weights, E,
+    E_sync, asynchronous = (E - E_sync) / E_sync, law = E[k (k+1) ...
+    (k+T-1)], perturbation = mean over histories of mean |u - u_s| and its
+    ratio to the law."""
+    T = order // 2 + 1
+    integ = "euler" if order == 2 else "ab2"
+    dt = _dt(n, alpha, r_alpha)
+    steps = int(round(t_final / dt))
+    base = dict(n=n, pe=pe, order=order, integrator=integ, c=c, alpha=alpha, dt=dt)
+    members = [dict(base, L=1, mode="sync", seed=0)]
+    for i, (L, w) in enumerate(laws):
+        for r in range(realizations):
+            members.append(dict(base, L=L, mode="rng", seed=_member_key(seed, 5000 + i, r), weights=list(w)))
+    nrm, rel = run_members(members, steps, precision=precision, device=device, sync_ref=True)
+    es = float(nrm[0, 0])
+    rows = []
+    for i, (L, w) in enumerate(laws):
+        sl = slice(1 + i * realizations, 1 + (i + 1) * realizations)
+        e = float(np.mean(nrm[sl, 0]))
+        pert = float(np.mean(rel[sl, 0]))
+        law = delay_law(L, T, w)
+        rows.append(dict(L=L, weights=list(w), E=e, E_sync=es, asynchronous=(e - es) / es, law=law,
+                         perturbation=pert, perturbation_ratio=pert / law if law else float("nan")))
+    return dict(order=order, T=T, steps=steps, dt=dt, members=members, per_law=rows)
 
 
 def pe_scaling_study(order=2, configs=((512, 2), (512, 4), (512, 8), (512, 16), (512, 32)), L=3,

@@ -10,7 +10,7 @@ import json
 import os
 import tempfile
 
-__all__ = ["default_path", "make_key", "lookup", "store"]
+__all__ = ["default_path", "make_key", "make_ens_key", "lookup", "store"]
 
 
 def default_path():
@@ -24,6 +24,17 @@ def make_key(arch, cus, ndim, edges, order, T, scheme, precision, integrator, eq
            f"{integrator}|{equation}|{mode}"
 
 
+def make_ens_key(arch, cus, members, precision):
+    """Key of an ensemble's schedule: the device and the members' shapes and
+    schemes (not their data, delay keys or coefficients)."""
+    import hashlib
+    h = hashlib.sha256()
+    for m in members:
+        h.update(f"{int(m['n'])},{int(m['pe'])},{int(m['order'])},{m.get('integrator', 'euler')},"
+                 f"{int(m.get('L', 1))},{int(m.get('T', 0))},{m.get('mode', 'rng')};".encode())
+    return f"{arch}|cu{int(cus)}|ensemble|{len(members)}|{precision}|{h.hexdigest()[:16]}"
+
+
 def _load(path):
     try:
         with open(path) as f:
@@ -34,16 +45,17 @@ def _load(path):
 
 
 def lookup(path, key):
-    """The stored entry {"variant": int, "ms": {variant: ms}} or None."""
+    """The stored entry {"variant": int or [int, ...], "ms": {variant: ms}} or None."""
     ent = _load(path).get(key)
-    if isinstance(ent, dict) and isinstance(ent.get("variant"), int):
+    if isinstance(ent, dict) and isinstance(ent.get("variant"), (int, list)):
         return ent
     return None
 
 
 def store(path, key, variant, ms):
     data = _load(path)
-    data[key] = {"variant": int(variant), "ms": {str(k): float(v) for k, v in ms.items()}}
+    v = [int(x) for x in variant] if isinstance(variant, (list, tuple)) else int(variant)
+    data[key] = {"variant": v, "ms": {str(k): float(x) for k, x in ms.items()}}
     d = os.path.dirname(os.path.abspath(path))
     os.makedirs(d, exist_ok=True)
     fd, tmp = tempfile.mkstemp(dir=d, prefix=".tuning.", suffix=".json")

@@ -298,11 +298,13 @@ def test_ensemble_bins_of_more_than_24_members_match_oracle():
     spec = []
     for i in range(6400):
         order = rng.choice((2, 4))
-        pe = rng.choice((1, 2, 3))
-        n = pe * rng.choice((2 * (order // 2), 6, 8))
+        pe = rng.choice((2, 3, 4))
+        n = pe * rng.choice((4, 6, 8))
+        dx = 2 * math.pi / n
+        ra = 0.05 if order == 2 else 0.005
         spec.append(dict(n=n, pe=pe, order=order, integrator="euler" if order == 2 else "ab2",
                          L=rng.choice((2, 4, 8)) if order == 2 else rng.choice((2, 3)), mode="rng",
-                         c=round(rng.uniform(-1, 1), 3), ra=0.05 if order == 2 else 0.005, seed=100 + i))
+                         c=round(rng.uniform(-1, 1), 3), ra=min(ra, 0.005 / dx), seed=100 + i))
     members = _members(spec)
     ph = _phases(len(members), seed=8)
     u0 = torch.from_numpy(_u0(members, ph))
@@ -346,3 +348,113 @@ def test_ensemble_non_finite_member_reports_unstable():
     with pytest.raises(ATError) as ei:
         ens.norms(KAPPAS, AMPS, ph)
     assert ei.value.status == _lib.AT_EUNSTABLE
+
+
+def _dx_edges(members, nbins):
+    dx = [m["length"] / m["n"] for m in members]
+    lo, hi = min(dx), max(dx)
+    return np.exp(np.linspace(np.log(lo), np.log(hi * (1 + 1e-9)), nbins + 1))
+
+
+def test_ensemble_error_statistics_match_oracle_member_runs():
+    """Mean and unbiased variance of the per-member RMS error against the exact
+    solution, binned by grid spacing and grouped by order (the statistic the
+    ensemble workload reports), from the FP64 ensemble against the same
+    statistic over the FP64 oracle's member runs."""
+    from oracle.norms import binned_mean_var
+    import random
+    rng = random.Random(31)
+    spec = []
+    for i in range(36):
+        order = (2, 4)[i % 2]
+        pe = rng.choice((4, 8))
+        n = pe * rng.choice((8, 12, 16, 24, 32))
+        spec.append(dict(n=n, pe=pe, order=order, integrator="euler" if order == 2 else "ab2",
+                         L=rng.choice((2, 4, 8)), mode="rng", c=1.0, ra=0.1 if order == 2 else 0.005,
+                         seed=500 + i))
+    members = _members(spec)
+    ph = _phases(len(members), seed=12)
+    u0 = _u0(members, ph)
+    steps = 150
+    ens = _ensemble(members, "f64")
+    ens.set_state(torch.from_numpy(u0))
+    ens.run(steps)
+    edges = _dx_edges(members, 4)
+    got = ens.error_stats(edges, KAPPAS, AMPS, ph)
+    off = 0
+    rms, dxs, groups = [], [], []
+    for i, m in enumerate(members):
+        o = _oracle(m, u0[off:off + m["n"]])
+        o.run(steps)
+        modes = W.make_modes([(k,) for k in KAPPAS], AMPS, phis=list(ph[i]))
+        ua = advected_modes(o.prob, modes, o.t)
+        rms.append(error_norms(o.u, ua)["l2"])
+        dxs.append(m["length"] / m["n"])
+        groups.append(m["order"] // 2 - 1)
+        off += m["n"]
+    want = binned_mean_var(dxs, rms, groups, list(edges))
+    for g in range(3):
+        for j in range(len(edges) - 1):
+            cnt, mdx, mean, var = want[g][j]
+            assert got[g, j, 0] == cnt, (g, j)
+            assert got[g, j, 1] == pytest.approx(mdx, rel=1e-14, abs=0)
+            assert got[g, j, 2] == pytest.approx(mean, rel=1e-9, abs=1e-300)
+            assert got[g, j, 3] == pytest.approx(var, rel=1e-8, abs=1e-300)
+    assert got[:2, :, 0].sum() == len(members)
+
+
+def test_ensemble_workload_error_statistics_equal_host_binning():
+    """The 512-member workload after 2000 FP32 steps: the device's binned
+    statistics equal the binning of its per-member norms done on the host."""
+    from oracle.norms import binned_mean_var
+    inst, members, parts = _workload_members()
+    ens = _ensemble(members, "f32")
+    ens.set_state(torch.from_numpy(np.concatenate(parts)))
+    ens.run(2000)
+    ph = np.array([[mo[2] for mo in m["modes"]] for m in inst])
+    kap = [mo[0][0] for mo in inst[0]["modes"]]
+    amp = [mo[1] for mo in inst[0]["modes"]]
+    per = ens.norms(kap, amp, ph)
+    edges = _dx_edges(members, 12)
+    got = ens.error_stats(edges, kap, amp, ph)
+    want = binned_mean_var([m["length"] / m["n"] for m in members], list(per[:, 1]),
+                           [m["order"] // 2 - 1 for m in members], list(edges))
+    for g in range(3):
+        for j in range(12):
+            cnt, mdx, mean, var = want[g][j]
+            assert got[g, j, 0] == cnt
+            assert got[g, j, 2] == pytest.approx(mean, rel=1e-12, abs=1e-300)
+            assert got[g, j, 3] == pytest.approx(var, rel=1e-10, abs=1e-300)
+    assert got[:, :, 0].sum() == len(members)
+    _say(f"[ens] workload error table (order 2): {got[0, :, :].tolist()}")
+
+
+def test_ensemble_autotune_restores_state_and_caches(tmp_path):
+    """The ensemble autotuner times all nine (workgroups per CU, threads)
+    candidates from the current state, keeps the fastest and leaves the state
+    and step as they were (the continued run equals an untuned one bit for
+    bit); a second ensemble of the same member shapes takes the choice from
+    the JSON cache without timing."""
+    from paper_1702_00496_amd import tuning
+    members = _members(MEMBERS)
+    u0 = torch.from_numpy(_u0(members, _phases(len(members))))
+    ref = _ensemble(members, "f32")
+    ref.set_state(u0)
+    ref.run(30)
+    want = ref.state().cpu()
+    e = _ensemble(members, "f32")
+    e.set_state(u0)
+    e.run(10)
+    path = str(tmp_path / "tuning.json")
+    best, ms = e.autotune(nsteps=5, cache=path)
+    assert len(ms) == 9 and best in ms and all(v > 0 for v in ms.values())
+    assert e.tuning() == best and e.n_step == 10
+    e.run(20)
+    assert torch.equal(e.state().cpu(), want)
+    ent = tuning.lookup(path, e.tuning_key())
+    assert ent is not None and tuple(ent["variant"]) == best
+    f = _ensemble([dict(m, seed=m["seed"] + 1) for m in members], "f32")
+    f.set_state(2 * u0)
+    assert f.tuning_key() == e.tuning_key()
+    best2, ms2 = f.autotune(nsteps=5, cache=path)
+    assert best2 == best and f.tuning() == best and ms2 == ms

@@ -237,3 +237,101 @@ def test_case4_standard_scheme_used_asynchronously_is_first_order():
         assert -1.5 < res["per_law"][w]["slopes"][-1] < -0.7, w
     e = [res["per_law"][w]["E"][-1] for w in sets]
     assert e[0] < e[1] < e[2] < e[3], e
+
+
+def _slope(xs, ys):
+    return float(np.polyfit(np.log(xs), np.log(ys), 1)[0])
+
+
+def test_fixed_pe_refinement_asynchronous_part_falls_at_slope_minus_three():
+    """Sec. 5.2 figure at-ord2-procs, fixed P: Case 1 (order 2, T = 2, Euler,
+    L = 3, p = {0.2, 0.5, 0.3}), P = 8, N = 64..512 at fixed diffusive CFL and
+    final time: the asynchronous perturbation mean |u - u_s| ~ P dx^3 falls
+    with slope -3 (eq. aveE_scaling_gen2 with a = 2)."""
+    from paper_1702_00496_amd import studies
+    cfg = ((64, 8), (128, 8), (256, 8), (512, 8))
+    res = studies.pe_scaling_study(order=2, configs=cfg, L=3, weights=(2, 5, 3), realizations=16,
+                                   r_alpha=0.1, t_final=0.2, precision="f64")
+    asy = [res["per_config"][c]["asynchronous"] for c in cfg]
+    sl = _slope([n for n, _ in cfg], asy)
+    _say(f"[study] fixed P = 8 async: {', '.join(f'{a:.3e}' for a in asy)} slope {sl:.2f}")
+    assert -3.4 < sl < -2.6, (asy, sl)
+
+
+def test_weak_scaling_asynchronous_part_falls_at_slope_minus_two():
+    """Sec. 5.2 figure at-ord2-procs, fixed P/N = 1/32 (weak scaling): P and N
+    grow together (N = 64..512), so P dx^3 ~ dx^2: the asynchronous
+    perturbation falls with slope -2."""
+    from paper_1702_00496_amd import studies
+    cfg = ((64, 2), (128, 4), (256, 8), (512, 16))
+    res = studies.pe_scaling_study(order=2, configs=cfg, L=3, weights=(2, 5, 3), realizations=16,
+                                   r_alpha=0.1, t_final=0.2, precision="f64")
+    asy = [res["per_config"][c]["asynchronous"] for c in cfg]
+    sl = _slope([n for n, _ in cfg], asy)
+    _say(f"[study] weak scaling async: {', '.join(f'{a:.3e}' for a in asy)} slope {sl:.2f}")
+    assert -2.4 < sl < -1.6, (asy, sl)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_general_delay_laws_follow_the_moment_law(order):
+    """Sec. 5.2 eq. aveE_scaling_gen_kmom for non-uniform p_k: laws of L = 3
+    (p = {0.2, 0.5, 0.3}, {0.5, 0.3, 0.2}, {0.1, 0.1, 0.8}, {0.8, 0.1, 0.1})
+    and L = 4 (p = {0.1, 0.2, 0.3, 0.4}): the asynchronous perturbation mean
+    |u - u_s| divided by E[k (k+1) ... (k+T-1)] is the same for every law
+    (within 5 %)."""
+    from paper_1702_00496_amd import studies
+    kw = dict(realizations=64, n=128, pe=16, precision="f64")
+    if order == 2:
+        res = studies.delay_law_study(order=2, r_alpha=0.1, t_final=0.5, **kw)
+    else:
+        res = studies.delay_law_study(order=4, r_alpha=0.005, t_final=0.2, **kw)
+    ratios = [r["perturbation_ratio"] for r in res["per_law"]]
+    _say(f"[study] order {order} general laws: perturbation / law "
+         f"{', '.join(f'{r:.4e}' for r in ratios)} (laws {[round(r['law'], 3) for r in res['per_law']]})")
+    assert all(r > 0 for r in ratios)
+    assert max(ratios) / min(ratios) < 1.05, ratios
+
+
+def _oracle_perturbation(m, sync, steps, modes):
+    """mean |u - u_s| of one oracle member run against its synchronous run."""
+    x = torch.arange(m["n"], dtype=torch.float64) * (2 * math.pi / m["n"])
+    out = []
+    for mm in (m, sync):
+        prob = Problem(ndim=1, n=(mm["n"],), pe=(mm["pe"],), dt=mm["dt"], order=mm["order"], c=(mm["c"],),
+                       alpha=mm["alpha"], integrator=mm["integrator"])
+        u0 = sum(a * torch.sin(k * x) for k, a in modes).reshape(prob.shape)
+        o = Oracle(prob, DelayModel(L=mm["L"], mode=mm["mode"], seed=mm["seed"], weights=mm.get("weights")), u0)
+        o.run(steps)
+        out.append(o.u.reshape(-1))
+    return float((out[0] - out[1]).abs().mean())
+
+
+def test_scaling_and_law_studies_match_the_oracle():
+    """The averaged errors of the P-scaling and general-law studies (small
+    sizes) equal the same averages over the FP64 oracle's member runs."""
+    from paper_1702_00496_amd import studies
+    cfg = ((32, 2), (64, 4))
+    res = studies.pe_scaling_study(order=2, configs=cfg, L=3, weights=(2, 5, 3), realizations=2,
+                                   r_alpha=0.1, t_final=0.02, precision="f64")
+    mem = res["members"]
+    k = 0
+    for c in cfg:
+        group = mem[k:k + 3]
+        k += 3
+        steps = res["per_config"][c]["steps"]
+        e = np.mean([_oracle_mean_error(m, steps, studies.DEFAULT_MODES) for m in group[1:]])
+        p = np.mean([_oracle_perturbation(m, group[0], steps, studies.DEFAULT_MODES) for m in group[1:]])
+        row = res["per_config"][c]
+        _say(f"[study] scaling {c}: E {row['E']:.12e} / {e:.12e}, async {row['asynchronous']:.12e} / {p:.12e}")
+        assert abs(row["E"] - e) <= 1e-10 * e
+        assert abs(row["asynchronous"] - p) <= 1e-9 * p
+    res = studies.delay_law_study(order=4, laws=((3, (2, 5, 3)), (2, (1, 3))), realizations=2, n=64, pe=8,
+                                  r_alpha=0.005, t_final=0.01, precision="f64")
+    mem = res["members"]
+    for i, row in enumerate(res["per_law"]):
+        group = mem[1 + 2 * i: 3 + 2 * i]
+        e = np.mean([_oracle_mean_error(m, res["steps"], studies.DEFAULT_MODES) for m in group])
+        p = np.mean([_oracle_perturbation(m, mem[0], res["steps"], studies.DEFAULT_MODES) for m in group])
+        _say(f"[study] law {row['weights']}: E {row['E']:.12e} / {e:.12e}, pert {row['perturbation']:.12e} / {p:.12e}")
+        assert abs(row["E"] - e) <= 1e-10 * e
+        assert abs(row["perturbation"] - p) <= 1e-9 * p

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from oracle.analytic import advected_modes
-from oracle.norms import ensemble_mean_var, error_norms
+from oracle.norms import binned_mean_var, ensemble_mean_var, error_norms
 from oracle.solver import Problem, boundary_mask
 
 
@@ -75,6 +75,21 @@ def test_ensemble_mean_and_unbiased_variance():
     m, v = ensemble_mean_var([1.0, 2.0, 3.0, 4.0])
     assert m == 2.5
     assert v == pytest.approx(5.0 / 3.0, rel=1e-15)
+
+
+def test_binned_mean_and_variance_by_hand():
+    """Six members in two order groups and two dx bins (edges 0.1, 0.2, 0.4):
+    bin membership is half-open, a member outside every bin is dropped, a bin
+    with one member has variance 0 and an empty bin counts 0."""
+    dx = [0.1, 0.15, 0.2, 0.3, 0.4, 0.12]
+    vals = [1.0, 3.0, 10.0, 14.0, 99.0, 5.0]
+    groups = [0, 0, 0, 0, 0, 1]
+    t = binned_mean_var(dx, vals, groups, [0.1, 0.2, 0.4], ngroups=2)
+    assert t[0][0] == (2, 0.125, 2.0, 2.0)            # members 0, 1: mean 2, var ((1)^2 + (1)^2) / 1
+    assert t[0][1][0] == 2 and t[0][1][2] == 12.0 and t[0][1][3] == 8.0   # members 2, 3 (0.4 excluded)
+    assert t[0][1][1] == pytest.approx(0.25, rel=1e-15)
+    assert t[1][0] == (1, 0.12, 5.0, 0.0)
+    assert t[1][1] == (0, 0.0, 0.0, 0.0)
 
 
 def test_boundary_set_one_d_by_hand():
