@@ -393,13 +393,17 @@ def test_ensemble_error_statistics_match_oracle_member_runs():
         groups.append(m["order"] // 2 - 1)
         off += m["n"]
     want = binned_mean_var(dxs, rms, groups, list(edges))
+    # the RMS error is 1-Lipschitz in the field: each member's differs from the
+    # oracle's by at most the RMS field difference, which the FP64 parity bar
+    # puts below 1e-12 of the O(1) field (|u| <= 1.75 here)
+    d = 1e-12 * 1.75
     for g in range(3):
         for j in range(len(edges) - 1):
             cnt, mdx, mean, var = want[g][j]
             assert got[g, j, 0] == cnt, (g, j)
             assert got[g, j, 1] == pytest.approx(mdx, rel=1e-14, abs=0)
-            assert got[g, j, 2] == pytest.approx(mean, rel=1e-9, abs=1e-300)
-            assert got[g, j, 3] == pytest.approx(var, rel=1e-8, abs=1e-300)
+            assert abs(got[g, j, 2] - mean) <= d, (g, j, got[g, j], want[g][j])
+            assert abs(got[g, j, 3] - var) <= 2 * math.sqrt(var) * 2 * d + 4 * d * d, (g, j, got[g, j], want[g][j])
     assert got[:2, :, 0].sum() == len(members)
 
 
