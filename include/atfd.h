@@ -228,6 +228,17 @@ at_status at_get_point_delays(at_ctx* ctx, int64_t n0, int64_t count, int8_t* ho
 at_status at_norms(at_ctx* ctx, int32_t nmodes, const int32_t* kappa, const double* amp,
                    const double* phase, const double* ref_dev, double* out);
 
+/* Allocation-free variant of at_norms, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): same arguments, results and errors, but the
+ * per-workgroup partial sums and the result live in a static device array of
+ * the library (1024 x 8 + 16 doubles, one per GPU, held until the process
+ * ends) instead of the context's workspace. Calls no allocating routine.
+ * Must be called with the context's device current (AT_EINVAL otherwise).
+ * Calls that overlap on one GPU share that array and race: serialise them. */
+at_status at_norms_noalloc(at_ctx* ctx, int32_t nmodes, const int32_t* kappa, const double* amp,
+                           const double* phase, const double* ref_dev, double* out);
+
 /* Checkpoint: bytes needed, save to / restore from `ckpt_dev`. The state is
  * the field, the integrator history, every ring slot and the step counter; a
  * restored run continues bit for bit. */

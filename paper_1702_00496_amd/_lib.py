@@ -96,6 +96,7 @@ SIGNATURES = {
     "at_get_delays": (I32, [P, I64, I64, ctypes.POINTER(ctypes.c_int8)]),
     "at_get_point_delays": (I32, [P, I64, I64, ctypes.POINTER(ctypes.c_int8)]),
     "at_norms": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),
+    "at_norms_noalloc": (I32, [P, I32, ctypes.POINTER(I32), DP, DP, P, DP]),
     "at_checkpoint_size": (I32, [P, ctypes.POINTER(SZ)]),
     "at_save": (I32, [P, P]),
     "at_load": (I32, [P, P]),

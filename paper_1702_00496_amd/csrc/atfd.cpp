@@ -27,6 +27,7 @@ std::string& atfd::thread_error() {
 namespace {
 
 constexpr int kNormBlocks = 1024;
+static_assert(kNormBlocks <= kNormStaticBlocks, "the static norm scratch holds every workgroup's partials");
 
 struct Layout {
   size_t field_bytes = 0, ring_bytes = 0, host_tab_bytes = 0;
@@ -63,6 +64,7 @@ struct at_ctx {
   StepParams sp;
   unsigned char* ws = nullptr;
   hipStream_t stream = nullptr;
+  int device = 0;            // current device at at_create
   int64_t n = 0;
   bool state_set = false;
   std::string err;
@@ -365,6 +367,7 @@ at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev,
   c->lay = l;
   c->ws = static_cast<unsigned char*>(ws_dev);
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
   // thresholds are derived from the caller's weights now; keep a private copy
   {
     at_delay tmp = *delay;
@@ -564,37 +567,41 @@ at_status at_get_point_delays(at_ctx* c, int64_t n0, int64_t count, int8_t* host
   return AT_OK;
 }
 
-at_status at_norms(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double* amp,
-                   const double* phase, const double* ref_dev, double* out) {
+namespace {
+
+// Validation and parameters shared by at_norms and at_norms_noalloc.
+at_status norm_params(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double* amp, const double* phase,
+                      const double* ref_dev, double* out, NormParams* p, int* blocks) {
   if (!c || !out) return fail(c, AT_EINVAL, "null argument");
   if (!c->state_set) return fail(c, AT_ESTATE, "no state");
   if (nmodes < 0 || nmodes > kMaxModes) return fail(c, AT_EINVAL, "nmodes must be 0..%d", kMaxModes);
   if (nmodes == 0 && !ref_dev) return fail(c, AT_EINVAL, "need modes or a reference field");
   if (nmodes > 0 && (!kappa || !amp || !phase)) return fail(c, AT_EINVAL, "null mode arrays");
-  NormParams p;
-  std::memset(&p, 0, sizeof(p));
-  p.nx = int(c->g.n[0]); p.ny = int(c->g.n[1]); p.nz = int(c->g.n[2]);
-  p.bx = c->g.b[0]; p.by = c->g.b[1]; p.bz = c->g.b[2];
-  p.ndim = c->g.ndim;
-  p.s = c->g.s;
-  p.length = c->prob.length;
-  p.alpha = c->prob.alpha;
-  p.dt = c->prob.dt;
-  for (int a = 0; a < 3; ++a) p.vel[a] = a < c->g.ndim ? c->prob.c[a] : 0.0;
-  p.nmodes = nmodes;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = int(c->g.n[0]); p->ny = int(c->g.n[1]); p->nz = int(c->g.n[2]);
+  p->bx = c->g.b[0]; p->by = c->g.b[1]; p->bz = c->g.b[2];
+  p->ndim = c->g.ndim;
+  p->s = c->g.s;
+  p->length = c->prob.length;
+  p->alpha = c->prob.alpha;
+  p->dt = c->prob.dt;
+  for (int a = 0; a < 3; ++a) p->vel[a] = a < c->g.ndim ? c->prob.c[a] : 0.0;
+  p->nmodes = nmodes;
   for (int m = 0; m < nmodes; ++m) {
-    for (int a = 0; a < 3; ++a) p.kap[m][a] = kappa[3 * m + a];
-    p.amp[m] = amp[m];
-    p.phase[m] = phase[m];
+    for (int a = 0; a < 3; ++a) p->kap[m][a] = kappa[3 * m + a];
+    p->amp[m] = amp[m];
+    p->phase[m] = phase[m];
   }
-  p.u = c->sp.ubuf[c->n & 1];
-  p.ref = ref_dev;
-  p.partial = reinterpret_cast<double*>(c->ws + c->lay.off_partial);
-  p.counter = c->sp.counter;
-  double* res = reinterpret_cast<double*>(c->ws + c->lay.off_result);
-  int blocks = static_cast<int>((c->g.npts + 255) / 256);
-  if (blocks > kNormBlocks) blocks = kNormBlocks;
-  HIP_TRY(c, launch_norms(p, c->g.f64, blocks, res, c->stream));
+  p->u = c->sp.ubuf[c->n & 1];
+  p->ref = ref_dev;
+  p->counter = c->sp.counter;
+  int nb = static_cast<int>((c->g.npts + 255) / 256);
+  if (nb > kNormBlocks) nb = kNormBlocks;
+  *blocks = nb;
+  return AT_OK;
+}
+
+at_status norm_result(at_ctx* c, const double* res, double* out) {
   double host[10];
   HIP_TRY(c, hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -603,6 +610,40 @@ at_status at_norms(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double
     return fail(c, AT_EUNSTABLE, "%.0f non-finite values in the field at step %lld", host[9],
                 (long long)c->n);
   return AT_OK;
+}
+
+}  // namespace
+
+at_status at_norms(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double* amp,
+                   const double* phase, const double* ref_dev, double* out) {
+  NormParams p;
+  int blocks = 0;
+  at_status st = norm_params(c, nmodes, kappa, amp, phase, ref_dev, out, &p, &blocks);
+  if (st != AT_OK) return st;
+  p.partial = reinterpret_cast<double*>(c->ws + c->lay.off_partial);
+  double* res = reinterpret_cast<double*>(c->ws + c->lay.off_result);
+  HIP_TRY(c, launch_norms(p, c->g.f64, blocks, res, c->stream));
+  return norm_result(c, res, out);
+}
+
+at_status at_norms_noalloc(at_ctx* c, int32_t nmodes, const int32_t* kappa, const double* amp,
+                           const double* phase, const double* ref_dev, double* out) {
+  NormParams p;
+  int blocks = 0;
+  at_status st = norm_params(c, nmodes, kappa, amp, phase, ref_dev, out, &p, &blocks);
+  if (st != AT_OK) return st;
+  if (blocks > kNormStaticBlocks)
+    return fail(c, AT_EINVAL, "%d norm workgroups exceed the static scratch (%d)", blocks, kNormStaticBlocks);
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, AT_EINVAL, "current device %d is not the context's device %d", dev, c->device);
+  double* scr = nullptr;
+  HIP_TRY(c, norms_static_scratch(dev, &scr));
+  p.partial = scr;                                          // kNormStaticBlocks x 8 partials
+  double* res = scr + static_cast<size_t>(kNormStaticBlocks) * 8;   // 16 doubles
+  HIP_TRY(c, launch_norms(p, c->g.f64, blocks, res, c->stream));
+  return norm_result(c, res, out);
 }
 
 at_status at_checkpoint_size(const at_ctx* c, size_t* bytes) {

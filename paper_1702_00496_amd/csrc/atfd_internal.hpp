@@ -186,6 +186,12 @@ hipError_t launch_publish_all(const StepParams& p, bool f64, int s, hipStream_t 
 hipError_t launch_set_counter(int64_t* counter, int64_t n, hipStream_t st);
 hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t* out,
                          hipStream_t st);
+// Workgroups of the allocation-free norm evaluation, and its device scratch
+// (norms.hip: one array per GPU; `device` must be the current device).
+constexpr int kNormStaticBlocks = 1024;
+constexpr int kMaxDevices = 64;
+hipError_t norms_static_scratch(int device, double** ptr);
+
 hipError_t launch_norms(const NormParams& p, bool f64, int nblocks, double* result,
                         hipStream_t st);
 size_t step_lds_bytes(const StepParams& p, bool f64, int s);

@@ -7,6 +7,14 @@
 
 #include "atfd_internal.hpp"
 
+#include <mutex>
+
+// Device scratch of the allocation-free norm evaluation (at_norms_noalloc):
+// the per-workgroup partials (kNormStaticBlocks x 8 doubles) and the
+// 16-double result. One copy per GPU, held until the process ends; calls that
+// overlap on one GPU share it and race.
+static __device__ __align__(256) double scratch[atfd::kNormStaticBlocks * 8 + 16];
+
 namespace atfd {
 namespace {
 
@@ -218,6 +226,23 @@ __global__ __launch_bounds__(64) void norms_final_kernel(const double* partial, 
 }
 
 }  // namespace
+
+hipError_t norms_static_scratch(int device, double** ptr) {
+  // the array's device address, looked up once per device with that device
+  // current (the name itself is a host-side stand-in, not a device address)
+  static std::once_flag once[kMaxDevices];
+  static double* addr[kMaxDevices];
+  static hipError_t err[kMaxDevices];
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(once[device], [device]() {
+    void* a = nullptr;
+    err[device] = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    addr[device] = static_cast<double*>(a);
+  });
+  if (err[device] != hipSuccess) return err[device];
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 hipError_t launch_norms(const NormParams& p, bool f64, int nblocks, double* result,
                         hipStream_t st) {
