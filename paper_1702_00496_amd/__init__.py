@@ -19,7 +19,7 @@ ENS_TUNE_CANDIDATES = 9
 __all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS"]
 
 # schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
-VARIANTS = (1, 2, 4, 9, 10, 12)
+VARIANTS = (1, 2, 4, 9, 10, 12, 17, 18, 20)
 
 
 def lib():
@@ -145,7 +145,7 @@ class Solver:
                 return ent["variant"], {int(k): v for k, v in ent.get("ms", {}).items()}
         scratch = torch.empty(self.checkpoint_size(), dtype=torch.uint8, device=self.device)
         best = ctypes.c_int32(0)
-        ms = (ctypes.c_double * 6)()
+        ms = (ctypes.c_double * len(VARIANTS))()
         check(self._lib.at_autotune(self._ctx, _as_ptr(scratch), scratch.numel(), int(nsteps),
                                     ctypes.byref(best), ms), self._ctx)
         times = {d: ms[i] for i, d in enumerate(VARIANTS) if ms[i] >= 0}

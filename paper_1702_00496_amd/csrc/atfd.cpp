@@ -65,6 +65,7 @@ struct at_ctx {
   unsigned char* ws = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;            // current device at at_create
+  int sweep_parity = 0;      // z sweep direction of the next step (alternating variants)
   int64_t n = 0;
   bool state_set = false;
   std::string err;
@@ -307,14 +308,21 @@ void fill_params(at_ctx* c) {
 // Queue the kernels of one time step on `st`.
 at_status enqueue_step(at_ctx* c, hipStream_t st) {
   StepParams p = c->sp;
+  // alternating schedule variants: every launch sweeps z the other way from
+  // the one before it (the direction is a schedule choice only)
+  const bool alt = (p.depth & 16) != 0;
   if (c->prob.integrator == AT_RK2) {
     p.stage = kStageRk1;
     p.advance = 0;
+    p.sweep_down = 0;
     HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
     p.stage = kStageRk2;
     p.advance = 1;
+    p.sweep_down = alt ? 1 : 0;
     HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
   } else {
+    p.sweep_down = alt ? c->sweep_parity : 0;
+    c->sweep_parity ^= 1;
     HIP_TRY(c, launch_step(p, c->g.f64, c->g.s, st));
   }
   return AT_OK;
@@ -454,7 +462,8 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
 at_status at_set_tuning(at_ctx* c, int32_t depth) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
   if (depth == 0) depth = fast3d_default_depth(c->g.f64);
-  if (!fast3d_valid_variant(depth)) return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10 or 12");
+  if (!fast3d_valid_variant(depth))
+    return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10, 12, 17, 18 or 20");
   if (depth != c->sp.depth) drop_graph(c);
   c->sp.depth = depth;
   return AT_OK;
@@ -477,7 +486,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
     return fail(c, AT_EINVAL, "host delay table too short for autotuning");
   at_status st = at_save(c, scratch_dev);
   if (st != AT_OK) return st;
-  const int cand[6] = {1, 2, 4, 9, 10, 12};
+  const int cand[AT_TUNE_CANDIDATES] = {1, 2, 4, 9, 10, 12, 17, 18, 20};
   const int keep = c->sp.depth, keep_chunk = c->graph_chunk;
   double best_ms = 1e300;
   int best = keep;
@@ -485,7 +494,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
   c->graph_chunk = 0;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < AT_TUNE_CANDIDATES; ++i) {
     double ms = -1.0;
     StepParams trial = c->sp;
     trial.depth = cand[i];

@@ -144,7 +144,9 @@ struct StepParams {
   int64_t* counter;            // [0] = step n, [1] = finished workgroups
   int advance;                 // this launch ends the step: bump the counter
   int depth;                   // 3-D 32x32 path schedule: planes in flight D (1, 2, 4) with 4
-                               // points per thread, or 8 + D with 2 points per thread
+                               // points per thread, or 8 + D with 2 points per thread; 16 + D:
+                               // 4 points per thread, z sweep direction alternating per launch
+  int sweep_down;              // this launch sweeps z downward (alternating variants)
 };
 
 // Ring layout. The strip of face f of a PE is a stack of planes (x and y

@@ -7,7 +7,9 @@ namespace atfd {
 
 int fast3d_default_depth(bool f64) { (void)f64; return 2; }
 
-bool fast3d_valid_variant(int v) { return v == 1 || v == 2 || v == 4 || v == 9 || v == 10 || v == 12; }
+bool fast3d_valid_variant(int v) {
+  return v == 1 || v == 2 || v == 4 || v == 9 || v == 10 || v == 12 || v == 17 || v == 18 || v == 20;
+}
 
 bool fast3d_applies(const StepParams& p, bool f64) {
   (void)f64;

@@ -13,6 +13,11 @@
 //    combination of T delayed ring levels, in double) are issued D planes
 //    ahead in a rotating set of registers: the slot consumed for plane z is
 //    refilled with plane z + D, so no register copies stall the pipeline;
+//  - the z sweep alternates direction from launch to launch (multistep
+//    methods: by step parity; Heun: up in the first stage, down in the
+//    second), so that a launch starts on the planes the previous one touched
+//    last, which the Infinity Cache still holds when the working set is
+//    larger than it; the arithmetic per point is the same either way;
 //  - the integrator stage and the equation are template parameters and the
 //    stencil taps arrive pre-folded with velocity and diffusivity; every
 //    neighbour enters as (v - u0), which keeps float rounding relative to the
@@ -162,7 +167,7 @@ __device__ inline Vec<Real, W> combine_levels(const double* w, const Vec<Real, W
 // strip depth (2 or 3): the CD2 stencil everywhere plus, at a point next to a
 // face whose delay is positive, the difference between that scheme's stencil
 // and the CD2 one over the S buffer points of level n-k and the own points.
-template <typename Real, int S, int V, int D, int KIND, int EQ, int TT, int SP = 0>
+template <typename Real, int S, int V, int D, int KIND, int EQ, int TT, int SP = 0, bool REV = false>
 __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams p) {
   static_assert(S <= kHO, "the x halo must fit left of column kHO");
   static_assert(SP == 0 || TT == 1, "the space-expanded schemes combine one level");
@@ -186,7 +191,11 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   const int vi = tid % VPR, y = tid / VPR;
   const int x = V * vi;
   const int64_t n = p.counter[0];
-  const int pid = pe_of_workgroup(blockIdx.x, gridDim.x);
+  // a downward sweep also takes the PEs in the opposite order, so that when
+  // there are more PEs than resident workgroups the launch starts on the PEs
+  // the previous one finished last
+  const int wg = REV ? static_cast<int>(gridDim.x) - 1 - static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
+  const int pid = pe_of_workgroup(wg, gridDim.x);
   const int pex = pid % p.px, pey = (pid / p.px) % p.py, pez = pid / (p.px * p.py);
   const int x0 = pex * kB, y0 = pey * kB, z0 = pez * p.bz;
   const int bz = p.bz;
@@ -311,37 +320,6 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
     return Q{{b[0], b[estride], b[2 * estride], b[3 * estride]}};
   };
 
-  // The 2S planes beyond the PE's z faces (strip [d][y][x]) are loaded and
-  // combined once, before the sweep; the upper ones wait in LDS (they are
-  // picked by a run-time plane index).
-  VR zlo[S];
-  {
-    const int gzl = (z0 - S + p.nz) % p.nz, gzh = (z0 + bz) % p.nz;
-    const int64_t q0 = static_cast<int64_t>(y) * kB + x;
-    const Src lo = make_src(4, q0, static_cast<int64_t>(kB) * kB,
-                            (static_cast<int64_t>(gzl) * p.ny + y0 + y) * p.nx + x0 + x);
-    const Src hi = make_src(5, q0, static_cast<int64_t>(kB) * kB,
-                            (static_cast<int64_t>(gzh) * p.ny + y0 + y) * p.nx + x0 + x);
-#pragma unroll
-    for (int d = 0; d < S; ++d) {
-      VR rl[TT], rh[TT];
-#pragma unroll
-      for (int m = 0; m < TT; ++m) {
-        rl[m] = ldp<Real, V>(lo.lvl[m] + d * lo.stride);
-        rh[m] = ldp<Real, V>(hi.lvl[m] + d * hi.stride);
-      }
-      zlo[d] = combine_levels<Real, V, TT>(lo.w, rl, kSync);
-      stv<Real, V>(zhi_lds, static_cast<uint32_t>((d * kB + y) * kB + x),
-                   combine_levels<Real, V, TT>(hi.w, rh, kSync));
-    }
-  }
-  // values of plane zz in [0, bz + S): interior planes from u^n, the last S
-  // from LDS (each thread reads back what it wrote)
-  auto plane_vec = [&](int zz) -> VR {
-    if (zz < bz) return ldv<Real, V>(centre, col + zz * zstride);
-    return ldv<Real, V>(zhi_lds, static_cast<uint32_t>(((zz - bz) * kB + y) * kB + x));
-  };
-
   // integrator history: f^{n-1} (AB2, AB3), u^n (second RK2 stage). AB3 keeps
   // f^{n-1} in fbuf[(n-1)&1] and f^{n-2} in fbuf[n&1]; f^n overwrites f^{n-2}.
   // The reads are issued unconditionally (a value the formula does not use at
@@ -368,23 +346,6 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   const int64_t cxy = p.face_chunk[0];             // s * 32 (x and y faces)
   const int64_t cz = p.face_chunk[4];              // 32 * 32 (z faces)
 
-  // z queue (planes z-S .. z+S) and the rotating prefetch slots
-  VR qz[2 * S + 1];
-#pragma unroll
-  for (int i = 0; i < S; ++i) qz[i] = zlo[i];
-#pragma unroll
-  for (int i = 0; i < S; ++i) qz[S + i] = plane_vec(i);
-  VR A[D], F1[D], F2[D];
-  Q HR[D][TT];
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    A[j] = plane_vec(j + S);
-    F1[j] = hist1(j);
-    F2[j] = hist2(j);
-#pragma unroll
-    for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(j, m);
-  }
-
   // space-expanded schemes: low-face taps minus the CD2 taps, o = -S..S
   Real dl1[3][2 * S + 1], dl2[3][2 * S + 1];
   const Real alpha_r = static_cast<Real>(p.alpha);
@@ -401,161 +362,229 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   }
   const bool kpos0 = SP != 0 && s_kpos[0], kpos1 = SP != 0 && s_kpos[1], kpos2 = SP != 0 && s_kpos[2],
              kpos3 = SP != 0 && s_kpos[3], kpos4 = SP != 0 && s_kpos[4], kpos5 = SP != 0 && s_kpos[5];
-
   const int c_at = (y + S) * kRS + kHO + x;     // LDS index of this thread's first point
-  for (int zb = 0; zb < bz; zb += D) {
+
+  // The sweep over the PE's z-planes, upward (REV = false) or downward (the
+  // alternating variants: the host alternates the direction from launch to
+  // launch, so that a launch starts on the planes the previous one touched
+  // last, which are still in the Infinity Cache when the working set exceeds
+  // it). Per point the arithmetic is the same in both directions (the z
+  // neighbours are taken from the queue by their physical offset), so
+  // results are bit-identical.
+  {
+    // physical plane of sweep position zs
+    auto phys = [&](int zs) { return REV ? bz - 1 - zs : zs; };
+    // The 2S planes beyond the PE's z faces (strip [d][y][x]) are loaded and
+    // combined once, before the sweep: the S planes the sweep starts beyond
+    // into registers, the S planes it ends beyond into LDS (picked by a
+    // run-time plane index). Sweep position -S + i holds depth i of the low
+    // strip (upward) or depth S-1-i of the high strip (downward); position
+    // bz + e holds depth e of the high strip or depth S-1-e of the low one.
+    VR zst[S];
+    {
+      const int gzl = (z0 - S + p.nz) % p.nz, gzh = (z0 + bz) % p.nz;
+      const int64_t q0 = static_cast<int64_t>(y) * kB + x;
+      const Src lo = make_src(4, q0, static_cast<int64_t>(kB) * kB,
+                              (static_cast<int64_t>(gzl) * p.ny + y0 + y) * p.nx + x0 + x);
+      const Src hi = make_src(5, q0, static_cast<int64_t>(kB) * kB,
+                              (static_cast<int64_t>(gzh) * p.ny + y0 + y) * p.nx + x0 + x);
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        VR rl[TT], rh[TT];
+#pragma unroll
+        for (int m = 0; m < TT; ++m) {
+          rl[m] = ldp<Real, V>(lo.lvl[m] + d * lo.stride);
+          rh[m] = ldp<Real, V>(hi.lvl[m] + d * hi.stride);
+        }
+        const VR cl = combine_levels<Real, V, TT>(lo.w, rl, kSync);
+        const VR ch = combine_levels<Real, V, TT>(hi.w, rh, kSync);
+        zst[REV ? S - 1 - d : d] = REV ? ch : cl;
+        stv<Real, V>(zhi_lds, static_cast<uint32_t>(((REV ? S - 1 - d : d) * kB + y) * kB + x), REV ? cl : ch);
+      }
+    }
+    // values of sweep position zs in [0, bz + S): the PE's planes from u^n,
+    // the last S from LDS (each thread reads back what it wrote)
+    auto plane_vec = [&](int zs) -> VR {
+      if (zs < bz) return ldv<Real, V>(centre, col + phys(zs) * zstride);
+      return ldv<Real, V>(zhi_lds, static_cast<uint32_t>(((zs - bz) * kB + y) * kB + x));
+    };
+
+    // z queue (sweep positions zs-S .. zs+S) and the rotating prefetch slots
+    VR qz[2 * S + 1];
+#pragma unroll
+    for (int i = 0; i < S; ++i) qz[i] = zst[i];
+#pragma unroll
+    for (int i = 0; i < S; ++i) qz[S + i] = plane_vec(i);
+    VR A[D], F1[D], F2[D];
+    Q HR[D][TT];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const int z = zb + j;
-      qz[2 * S] = A[j];
-      const VR fo1 = F1[j], fo2 = F2[j];
-      Real* Lp = buf[z & 1];
-      stv<Real, V>(Lp, static_cast<uint32_t>(c_at), qz[S]);
-      if (is_h) {
-        const Q hv = combine_levels<Real, 4, TT>(hs.w, HR[j], kSync);
+      A[j] = plane_vec(j + S);
+      F1[j] = hist1(phys(j));
+      F2[j] = hist2(phys(j));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Lp[hp[i]] = hv.v[i];
-      }
-      // refill the slot with what iteration z + D consumes
-      if (z + D < bz) {
-        A[j] = plane_vec(z + D + S);
-        F1[j] = hist1(z + D);
-        F2[j] = hist2(z + D);
+      for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(phys(j), m);
+    }
+    // z neighbour at physical offset -o / +o of the current plane
+    auto zlow = [&](int o) -> const VR& { return REV ? qz[S + o] : qz[S - o]; };
+    auto zhigh = [&](int o) -> const VR& { return REV ? qz[S - o] : qz[S + o]; };
+
+    for (int zb = 0; zb < bz; zb += D) {
 #pragma unroll
-        for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(z + D, m);
-      }
-      __syncthreads();
-      // x row segment [x - S, x + V - 1 + S] and the y neighbour vectors
-      Real row[V + 2 * S];
+      for (int j = 0; j < D; ++j) {
+        const int zs = zb + j;
+        const int z = phys(zs);
+        qz[2 * S] = A[j];
+        const VR fo1 = F1[j], fo2 = F2[j];
+        Real* Lp = buf[zs & 1];
+        stv<Real, V>(Lp, static_cast<uint32_t>(c_at), qz[S]);
+        if (is_h) {
+          const Q hv = combine_levels<Real, 4, TT>(hs.w, HR[j], kSync);
 #pragma unroll
-      for (int i = 0; i < V + 2 * S; ++i) row[i] = Lp[c_at - S + i];
-      VR ym[S], yp[S];
-#pragma unroll
-      for (int o = 1; o <= S; ++o) {
-        ym[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at - o * kRS));
-        yp[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at + o * kRS));
-      }
-      VR un, fq;
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const Real u0 = qz[S].v[e];
-        Real fval;
-        if (EQ == AT_ADVDIFF) {
-          // f = sum over axes and taps of (alpha c2 - vel c1) (v - u0), one
-          // partial sum per axis
-          Real ax = 0, ay = 0, az = 0;
-#pragma unroll
-          for (int o = 1; o <= SS; ++o) {
-            ax += Taps<Real>::kad(p, 0, SS - o) * (row[S + e - o] - u0);
-            ay += Taps<Real>::kad(p, 1, SS - o) * (ym[o - 1].v[e] - u0);
-            az += Taps<Real>::kad(p, 2, SS - o) * (qz[S - o].v[e] - u0);
-            ax += Taps<Real>::kad(p, 0, SS + o) * (row[S + e + o] - u0);
-            ay += Taps<Real>::kad(p, 1, SS + o) * (yp[o - 1].v[e] - u0);
-            az += Taps<Real>::kad(p, 2, SS + o) * (qz[S + o].v[e] - u0);
-          }
-          fval = (ax + ay) + az;
-        } else {
-          // f = alpha lap u - u (sum_d du/dx_d)
-          Real lx = 0, ly = 0, lz = 0, gx = 0, gy = 0, gz = 0;
-#pragma unroll
-          for (int o = 1; o <= SS; ++o) {
-            const Real xm = row[S + e - o] - u0, xp = row[S + e + o] - u0;
-            const Real ymv = ym[o - 1].v[e] - u0, ypv = yp[o - 1].v[e] - u0;
-            const Real zm = qz[S - o].v[e] - u0, zp = qz[S + o].v[e] - u0;
-            lx += Taps<Real>::d2a(p, 0, SS - o) * xm + Taps<Real>::d2a(p, 0, SS + o) * xp;
-            ly += Taps<Real>::d2a(p, 1, SS - o) * ymv + Taps<Real>::d2a(p, 1, SS + o) * ypv;
-            lz += Taps<Real>::d2a(p, 2, SS - o) * zm + Taps<Real>::d2a(p, 2, SS + o) * zp;
-            gx += Taps<Real>::d1(p, 0, SS - o) * xm + Taps<Real>::d1(p, 0, SS + o) * xp;
-            gy += Taps<Real>::d1(p, 1, SS - o) * ymv + Taps<Real>::d1(p, 1, SS + o) * ypv;
-            gz += Taps<Real>::d1(p, 2, SS - o) * zm + Taps<Real>::d1(p, 2, SS + o) * zp;
-          }
-          fval = ((lx + ly) + lz) - u0 * ((gx + gy) + gz);
+          for (int i = 0; i < 4; ++i) Lp[hp[i]] = hv.v[i];
         }
-        if constexpr (SP != 0) {
-          // space-expanded stencils at points next to a face with k > 0: the
-          // difference to the CD2 taps, over o = -S..S (the high face mirrors
-          // the low-face taps: first derivative odd, second even)
-          Real c1s = 0, c2s = 0, adv = 0;
-          auto add_axis = [&](int a, bool lo, bool hi, auto val) {
-            if (!(lo || hi)) return;
-            Real t1 = 0, t2 = 0;
+        // refill the slot with what sweep position zs + D consumes
+        if (zs + D < bz) {
+          A[j] = plane_vec(zs + D + S);
+          F1[j] = hist1(phys(zs + D));
+          F2[j] = hist2(phys(zs + D));
 #pragma unroll
-            for (int o = -S; o <= S; ++o) {
-              if (o == 0) continue;
-              const Real v = val(o) - u0;
-              t1 += (lo ? dl1[a][o + S] : -dl1[a][S - o]) * v;
-              t2 += (lo ? dl2[a][o + S] : dl2[a][S - o]) * v;
+          for (int m = 0; m < TT; ++m) HR[j][m] = halo_raw(phys(zs + D), m);
+        }
+        __syncthreads();
+        // x row segment [x - S, x + V - 1 + S] and the y neighbour vectors
+        Real row[V + 2 * S];
+#pragma unroll
+        for (int i = 0; i < V + 2 * S; ++i) row[i] = Lp[c_at - S + i];
+        VR ym[S], yp[S];
+#pragma unroll
+        for (int o = 1; o <= S; ++o) {
+          ym[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at - o * kRS));
+          yp[o - 1] = ldv<Real, V>(Lp, static_cast<uint32_t>(c_at + o * kRS));
+        }
+        VR un, fq;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const Real u0 = qz[S].v[e];
+          Real fval;
+          if (EQ == AT_ADVDIFF) {
+            // f = sum over axes and taps of (alpha c2 - vel c1) (v - u0), one
+            // partial sum per axis
+            Real ax = 0, ay = 0, az = 0;
+#pragma unroll
+            for (int o = 1; o <= SS; ++o) {
+              ax += Taps<Real>::kad(p, 0, SS - o) * (row[S + e - o] - u0);
+              ay += Taps<Real>::kad(p, 1, SS - o) * (ym[o - 1].v[e] - u0);
+              az += Taps<Real>::kad(p, 2, SS - o) * (zlow(o).v[e] - u0);
+              ax += Taps<Real>::kad(p, 0, SS + o) * (row[S + e + o] - u0);
+              ay += Taps<Real>::kad(p, 1, SS + o) * (yp[o - 1].v[e] - u0);
+              az += Taps<Real>::kad(p, 2, SS + o) * (zhigh(o).v[e] - u0);
             }
-            c1s += EQ == AT_ADVDIFF ? Real(0) : t1;
-            adv += EQ == AT_ADVDIFF ? vel[a] * t1 : Real(0);
-            c2s += t2;
-          };
-          add_axis(0, e == 0 && x == 0 && kpos0, e == V - 1 && x + e == kB - 1 && kpos1,
-                   [&](int o) { return row[S + e + o]; });
-          add_axis(1, y == 0 && kpos2, y == kB - 1 && kpos3,
-                   [&](int o) { return o < 0 ? ym[-o - 1].v[e] : yp[o - 1].v[e]; });
-          add_axis(2, z == 0 && kpos4, z == bz - 1 && kpos5, [&](int o) { return qz[S + o].v[e]; });
-          fval += EQ == AT_ADVDIFF ? alpha_r * c2s - adv : alpha_r * c2s - u0 * c1s;
-        }
-        fq.v[e] = fval;
-        Real r;
-        if (KIND == kRk1 || KIND == kEuler) {
-          r = u0 + dt * fval;
-        } else if (KIND == kRk2) {
-          r = Real(0.5) * (fo1.v[e] + u0) + (Real(0.5) * dt) * fval;
-        } else if (KIND == kAb2) {
-          r = n == 0 ? u0 + dt * fval : u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e]);
-        } else {   // AB3: Euler, then AB2, then AB3
-          r = n == 0 ? u0 + dt * fval
-            : n == 1 ? u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e])
-                     : u0 + dt * ((Real(23) * fval - Real(16) * fo1.v[e] + Real(5) * fo2.v[e]) / Real(12));
-        }
-        un.v[e] = r;
-      }
-      const uint32_t g = col + z * zstride;
-      stv<Real, V>(unext, g, un);
-      if (KIND == kAb2 || KIND == kAb3) stv<Real, V>(fout, g, fq);
-      if (!kSync) {
-        // publish the new edge values into the ring slot of their level;
-        // x faces: plane [y][d], one run of s values per row
-        const int64_t xyplane = (static_cast<int64_t>(z) * p.npe + pid) * cxy;
-        const int64_t xrow = xyplane + static_cast<int64_t>(y) * S;
-        if constexpr (V == 4) {
-          // the first quad of a row holds the low-face depths, the last one
-          // the high-face depths: one store of s values for both faces
-          const bool lo = vi == 0, hi = vi == VPR - 1;
-          if (lo || hi) {
-            Real w[S];
+            fval = (ax + ay) + az;
+          } else {
+            // f = alpha lap u - u (sum_d du/dx_d)
+            Real lx = 0, ly = 0, lz = 0, gx = 0, gy = 0, gz = 0;
 #pragma unroll
-            for (int d = 0; d < S; ++d) w[d] = hi ? un.v[V - S + d] : un.v[d];
-            // (select between the two uniform offsets: an index that varies
-            // per lane would turn the kernel-argument read into a memory load)
-            const int64_t fo = hi ? p.face_off[1] : p.face_off[0];
-            st_run<Real, S>(pslotp + fo + xrow, w);
+            for (int o = 1; o <= SS; ++o) {
+              const Real xm = row[S + e - o] - u0, xp = row[S + e + o] - u0;
+              const Real ymv = ym[o - 1].v[e] - u0, ypv = yp[o - 1].v[e] - u0;
+              const Real zm = zlow(o).v[e] - u0, zp = zhigh(o).v[e] - u0;
+              lx += Taps<Real>::d2a(p, 0, SS - o) * xm + Taps<Real>::d2a(p, 0, SS + o) * xp;
+              ly += Taps<Real>::d2a(p, 1, SS - o) * ymv + Taps<Real>::d2a(p, 1, SS + o) * ypv;
+              lz += Taps<Real>::d2a(p, 2, SS - o) * zm + Taps<Real>::d2a(p, 2, SS + o) * zp;
+              gx += Taps<Real>::d1(p, 0, SS - o) * xm + Taps<Real>::d1(p, 0, SS + o) * xp;
+              gy += Taps<Real>::d1(p, 1, SS - o) * ymv + Taps<Real>::d1(p, 1, SS + o) * ypv;
+              gz += Taps<Real>::d1(p, 2, SS - o) * zm + Taps<Real>::d1(p, 2, SS + o) * zp;
+            }
+            fval = ((lx + ly) + lz) - u0 * ((gx + gy) + gz);
           }
-        } else {
+          if constexpr (SP != 0) {
+            // space-expanded stencils at points next to a face with k > 0: the
+            // difference to the CD2 taps, over o = -S..S (the high face mirrors
+            // the low-face taps: first derivative odd, second even)
+            Real c1s = 0, c2s = 0, adv = 0;
+            auto add_axis = [&](int a, bool lo, bool hi, auto val) {
+              if (!(lo || hi)) return;
+              Real t1 = 0, t2 = 0;
 #pragma unroll
-          for (int e = 0; e < V; ++e) {
-            if (x + e < S) pslotp[p.face_off[0] + xrow + x + e] = un.v[e];
-            if (x + e >= kB - S) pslotp[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
+              for (int o = -S; o <= S; ++o) {
+                if (o == 0) continue;
+                const Real v = val(o) - u0;
+                t1 += (lo ? dl1[a][o + S] : -dl1[a][S - o]) * v;
+                t2 += (lo ? dl2[a][o + S] : dl2[a][S - o]) * v;
+              }
+              c1s += EQ == AT_ADVDIFF ? Real(0) : t1;
+              adv += EQ == AT_ADVDIFF ? vel[a] * t1 : Real(0);
+              c2s += t2;
+            };
+            add_axis(0, e == 0 && x == 0 && kpos0, e == V - 1 && x + e == kB - 1 && kpos1,
+                     [&](int o) { return row[S + e + o]; });
+            add_axis(1, y == 0 && kpos2, y == kB - 1 && kpos3,
+                     [&](int o) { return o < 0 ? ym[-o - 1].v[e] : yp[o - 1].v[e]; });
+            add_axis(2, z == 0 && kpos4, z == bz - 1 && kpos5,
+                     [&](int o) { return o < 0 ? zlow(-o).v[e] : o > 0 ? zhigh(o).v[e] : qz[S].v[e]; });
+            fval += EQ == AT_ADVDIFF ? alpha_r * c2s - adv : alpha_r * c2s - u0 * c1s;
           }
+          fq.v[e] = fval;
+          Real r;
+          if (KIND == kRk1 || KIND == kEuler) {
+            r = u0 + dt * fval;
+          } else if (KIND == kRk2) {
+            r = Real(0.5) * (fo1.v[e] + u0) + (Real(0.5) * dt) * fval;
+          } else if (KIND == kAb2) {
+            r = n == 0 ? u0 + dt * fval : u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e]);
+          } else {   // AB3: Euler, then AB2, then AB3
+            r = n == 0 ? u0 + dt * fval
+              : n == 1 ? u0 + dt * (Real(1.5) * fval - Real(0.5) * fo1.v[e])
+                       : u0 + dt * ((Real(23) * fval - Real(16) * fo1.v[e] + Real(5) * fo2.v[e]) / Real(12));
+          }
+          un.v[e] = r;
         }
-        // y faces: plane [d][x]; rows 0..s-1 and kB-s..kB-1, one store
-        if (y < S || y >= kB - S) {
-          const int64_t fo = y < S ? p.face_off[2] : p.face_off[3];
-          const int d = y < S ? y : y - (kB - S);
-          stv<Real, V>(pslotp + fo + xyplane, static_cast<uint32_t>(d * kB + x), un);
-        }
-        // z faces: depth plane [y][x]
-        if (z < S)
-          stv<Real, V>(pslotp + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * cz,
-                       static_cast<uint32_t>(y * kB + x), un);
-        if (z >= bz - S)
-          stv<Real, V>(pslotp + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * cz,
-                       static_cast<uint32_t>(y * kB + x), un);
-      }
+        const uint32_t g = col + z * zstride;
+        stv<Real, V>(unext, g, un);
+        if (KIND == kAb2 || KIND == kAb3) stv<Real, V>(fout, g, fq);
+        if (!kSync) {
+          // publish the new edge values into the ring slot of their level;
+          // x faces: plane [y][d], one run of s values per row
+          const int64_t xyplane = (static_cast<int64_t>(z) * p.npe + pid) * cxy;
+          const int64_t xrow = xyplane + static_cast<int64_t>(y) * S;
+          if constexpr (V == 4) {
+            // the first quad of a row holds the low-face depths, the last one
+            // the high-face depths: one store of s values for both faces
+            const bool lo = vi == 0, hi = vi == VPR - 1;
+            if (lo || hi) {
+              Real w[S];
 #pragma unroll
-      for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];
+              for (int d = 0; d < S; ++d) w[d] = hi ? un.v[V - S + d] : un.v[d];
+              // (select between the two uniform offsets: an index that varies
+              // per lane would turn the kernel-argument read into a memory load)
+              const int64_t fo = hi ? p.face_off[1] : p.face_off[0];
+              st_run<Real, S>(pslotp + fo + xrow, w);
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              if (x + e < S) pslotp[p.face_off[0] + xrow + x + e] = un.v[e];
+              if (x + e >= kB - S) pslotp[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
+            }
+          }
+          // y faces: plane [d][x]; rows 0..s-1 and kB-s..kB-1, one store
+          if (y < S || y >= kB - S) {
+            const int64_t fo = y < S ? p.face_off[2] : p.face_off[3];
+            const int d = y < S ? y : y - (kB - S);
+            stv<Real, V>(pslotp + fo + xyplane, static_cast<uint32_t>(d * kB + x), un);
+          }
+          // z faces: depth plane [y][x]
+          if (z < S)
+            stv<Real, V>(pslotp + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * cz,
+                         static_cast<uint32_t>(y * kB + x), un);
+          if (z >= bz - S)
+            stv<Real, V>(pslotp + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * cz,
+                         static_cast<uint32_t>(y * kB + x), un);
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];
+      }
     }
   }
 
@@ -566,41 +595,49 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   }
 }
 
-template <typename Real, int S, int V, int D, int KIND, int TT, int SP = 0>
-hipError_t launch_eq(const StepParams& p, hipStream_t st) {
+template <typename Real, int S, int V, int D, int KIND, int TT, int SP, bool REV>
+hipError_t launch_dir(const StepParams& p, hipStream_t st) {
   constexpr int NT = kB * kB / V;
   if (p.equation == AT_ADVDIFF)
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_ADVDIFF, TT, SP>), dim3(p.npe),
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_ADVDIFF, TT, SP, REV>), dim3(p.npe),
                        dim3(NT), 0, st, p);
   else
-    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_BURGERS, TT, SP>), dim3(p.npe),
+    hipLaunchKernelGGL((at_step3d_fast_kernel<Real, S, V, D, KIND, AT_BURGERS, TT, SP, REV>), dim3(p.npe),
                        dim3(NT), 0, st, p);
   return hipGetLastError();
 }
 
-// The synchronous arm reads one value per halo point; the AT schemes read the
-// T = s + 1 delayed levels of the time-expanded family.
-template <typename Real, int S, int V, int D, int KIND>
-hipError_t launch_kind(const StepParams& p, hipStream_t st) {
-  if (p.mode == AT_SYNC) return launch_eq<Real, S, V, D, KIND, 1>(p, st);
-  return launch_eq<Real, S, V, D, KIND, S + 1>(p, st);
+// ALT: the launch's sweep direction comes from p.sweep_down.
+template <typename Real, int S, int V, int D, int KIND, int TT, int SP = 0, bool ALT = false>
+hipError_t launch_eq(const StepParams& p, hipStream_t st) {
+  if (ALT && p.sweep_down) return launch_dir<Real, S, V, D, KIND, TT, SP, true>(p, st);
+  return launch_dir<Real, S, V, D, KIND, TT, SP, false>(p, st);
 }
 
-template <typename Real, int S, int V, int D>
+// The synchronous arm reads one value per halo point; the AT schemes read the
+// T = s + 1 delayed levels of the time-expanded family.
+template <typename Real, int S, int V, int D, int KIND, bool ALT>
+hipError_t launch_kind(const StepParams& p, hipStream_t st) {
+  if (p.mode == AT_SYNC) return launch_eq<Real, S, V, D, KIND, 1, 0, ALT>(p, st);
+  return launch_eq<Real, S, V, D, KIND, S + 1, 0, ALT>(p, st);
+}
+
+template <typename Real, int S, int V, int D, bool ALT = false>
 hipError_t launch_fast_d(const StepParams& p, hipStream_t st) {
-  if (p.stage == kStageRk1) return launch_kind<Real, S, V, D, kRk1>(p, st);
-  if (p.stage == kStageRk2) return launch_kind<Real, S, V, D, kRk2>(p, st);
+  if (p.stage == kStageRk1) return launch_kind<Real, S, V, D, kRk1, ALT>(p, st);
+  if (p.stage == kStageRk2) return launch_kind<Real, S, V, D, kRk2, ALT>(p, st);
   switch (p.integrator) {
-    case AT_EULER: return launch_kind<Real, S, V, D, kEuler>(p, st);
-    case AT_AB2: return launch_kind<Real, S, V, D, kAb2>(p, st);
-    case AT_AB3: return launch_kind<Real, S, V, D, kAb3>(p, st);
+    case AT_EULER: return launch_kind<Real, S, V, D, kEuler, ALT>(p, st);
+    case AT_AB2: return launch_kind<Real, S, V, D, kAb2, ALT>(p, st);
+    case AT_AB3: return launch_kind<Real, S, V, D, kAb3, ALT>(p, st);
   }
   return hipErrorInvalidValue;
 }
 
 // Schedule variants (the tunables of this path): planes of reads in flight
 // D in {1, 2, 4} and points per thread V in {2, 4}, encoded as
-// variant = D for V = 4 and 8 + D for V = 2. All variants compute
+// variant = D for V = 4 and 8 + D for V = 2, and 16 + D for V = 4 with the
+// z sweep direction alternating from launch to launch. All variants compute
 // bit-identical results.
 template <typename Real, int S>
 hipError_t launch_fast_t(const StepParams& p, hipStream_t st) {
@@ -611,6 +648,9 @@ hipError_t launch_fast_t(const StepParams& p, hipStream_t st) {
     case 9: return launch_fast_d<Real, S, 2, 1>(p, st);
     case 10: return launch_fast_d<Real, S, 2, 2>(p, st);
     case 12: return launch_fast_d<Real, S, 2, 4>(p, st);
+    case 17: return launch_fast_d<Real, S, 4, 1, true>(p, st);
+    case 18: return launch_fast_d<Real, S, 4, 2, true>(p, st);
+    case 20: return launch_fast_d<Real, S, 4, 4, true>(p, st);
   }
   return hipErrorInvalidValue;
 }

@@ -41,7 +41,11 @@ def draw(seed):
                 steps=rng.randint(3, 9), ic_seed=rng.randint(0, 100))
     if rng.random() < 0.4:
         case["weights"] = [rng.randint(1, 5) for _ in range(case["L"])]
-    return case, rng.choice(("f64", "f32")), depth
+    precision = rng.choice(("f64", "f32"))
+    # the alternating-direction twins of the 4-point variants
+    if scheme == "time" and depth in (1, 2, 4) and rng.random() < 0.5:
+        depth += 16
+    return case, precision, depth
 
 
 @pytest.mark.parametrize("seed", range(48))
