@@ -224,17 +224,25 @@ for arm in args.arms.split(","):
 
 def time_burgers():
     """3-D viscous Burgers, 512^3, 16^3 PEs of 32^3, sixth order (T = 4), L = 8,
-    Heun RK2, 200 steps, FP32 bulk with FP64 AT combination, and the
-    synchronous arm. Bytes per update (two launches per step): u^n and u* read
-    or written 5 times, plus per stage the halo reads h E[levels] and the
-    publish h, h = 2 * 3 * 3 / 32, E[levels] = p0 + (1 - p0) T, p0 = 1/8."""
+    Heun RK2, 200 steps: FP32 bulk with FP64 AT combination, full FP64, and
+    the synchronous FP32 arm; the relative L2 and Linf difference of the FP32
+    field from the FP64 one after 200 steps; the adjoint of the final energy
+    J = 1/2 sum u_T^2 dx^3 with respect to u0 (checkpoints every 40 steps),
+    FP32. Bytes per update (two launches per step): u^n and u* read or written
+    5 times, plus per stage the halo reads h E[levels] and the publish h,
+    h = 2 * 3 * 3 / 32, E[levels] = p0 + (1 - p0) T, p0 = 1/8."""
     c5 = W.config_3d_burgers()
     n5 = c5["n"]
-    u5 = torch.from_numpy(W.burgers_spectrum_field(n5[0], 3, seed=c5["seed"]))
+    u5 = torch.from_numpy(W.burgers_spectrum_field(n5[0], 3, seed=c5["seed"])).to(dev)
     res = {}
-    for mode in ("rng", "sync"):
-        s = Solver(ndim=3, n=n5, pe=c5["pe"], dt=c5["dt"], order=6, equation="burgers", alpha=c5["alpha"],
-                   integrator="rk2", precision="f32", L=c5["L"], T=c5["T"], mode=mode, seed=c5["seed"])
+    fields = {}
+
+    def make(precision, mode):
+        return Solver(ndim=3, n=n5, pe=c5["pe"], dt=c5["dt"], order=6, equation="burgers", alpha=c5["alpha"],
+                      integrator="rk2", precision=precision, L=c5["L"], T=c5["T"], mode=mode, seed=c5["seed"])
+
+    for arm, precision, mode in (("at32", "f32", "rng"), ("at64", "f64", "rng"), ("sync32", "f32", "sync")):
+        s = make(precision, mode)
         s.set_state(u5)
         s.step(2)
         best = s.autotune(nsteps=5)[0]
@@ -250,19 +258,47 @@ def time_burgers():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        finite = bool(torch.isfinite(s.state()).all())
+        st = s.state()
+        finite = bool(torch.isfinite(st).all())
+        if mode == "rng":
+            fields[precision] = st.to(torch.float64)
+        w = 8 if precision == "f64" else 4
         h = 2 * 3 * 3 / 32
         p0 = 1.0 / c5["L"]
-        bpu = 4 * (5 + (2 * h * (p0 + (1 - p0) * c5["T"] + 1) if mode == "rng" else 0.0))
+        bpu = w * (5 + (2 * h * (p0 + (1 - p0) * c5["T"] + 1) if mode == "rng" else 0.0))
         ups = n5[0] ** 3 * c5["steps"] / (ms / 1e3)
-        res[mode] = dict(ms_per_step=ms / c5["steps"], updates_per_s=ups, bytes_per_update=bpu,
-                         achieved_gbs=ups * bpu / 1e9, frac=ups * bpu / 1e9 / HBM_PEAK_GBS, variant=best,
-                         finite=finite)
-        print(f"[bench] burgers {mode}: {ms / c5['steps']:.3f} ms/step {ups:.3e} upd/s", file=sys.stderr, flush=True)
-        del s
+        res[arm] = dict(ms_per_step=ms / c5["steps"], updates_per_s=ups, bytes_per_update=bpu,
+                        achieved_gbs=ups * bpu / 1e9, frac=ups * bpu / 1e9 / HBM_PEAK_GBS, variant=best,
+                        finite=finite)
+        print(f"[bench] burgers {arm}: {ms / c5['steps']:.3f} ms/step {ups:.3e} upd/s", file=sys.stderr, flush=True)
+        del s, st
         torch.cuda.empty_cache()
+    d = fields["f32"] - fields["f64"]
+    f32_vs_f64 = dict(rel_l2=float(torch.linalg.norm(d) / torch.linalg.norm(fields["f64"])),
+                      rel_linf=float(d.abs().max() / fields["f64"].abs().max()))
+    del d, fields
+    torch.cuda.empty_cache()
+    # adjoint: J = 1/2 sum u_T^2 dV, seed dJ/du_T = u_T dV
+    dV = (2 * math.pi / n5[0]) ** 3
+    s = make("f32", "rng")
+    s.set_state(u5)
+    s.step(c5["steps"])
+    seed = s.state().to(torch.float64) * dV
+    s = make("f32", "rng")
+    s.set_state(u5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adjoint(c5["steps"], seed, 40)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] burgers adjoint: {adj_ms:.1f} ms", file=sys.stderr, flush=True)
+    del s, seed
+    torch.cuda.empty_cache()
     return dict(workload="3-D viscous Burgers 512^3, 16^3 PEs of 32^3, 6th-order AT (T=4), L=8, RK2, "
-                         "200 steps, FP32 bulk / FP64 AT combination", arms=res)
+                         "200 steps: FP32 bulk / FP64 AT combination, full FP64, synchronous FP32; adjoint of "
+                         "the final energy w.r.t. u0 (FP32, checkpoints every 40)",
+                arms=res, f32_vs_f64=f32_vs_f64, adjoint_ms=adj_ms,
+                adjoint_ratio_to_forward=adj_ms / (res["at32"]["ms_per_step"] * c5["steps"]))
 
 
 def time_space():

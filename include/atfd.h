@@ -159,17 +159,34 @@ const char* at_version(void);
 at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_t* bytes);
 
 /* Create a context on `ws_dev` (>= at_workspace_size bytes, 256-B aligned)
- * queuing work on `hip_stream` (a hipStream_t; NULL = default stream).
+ * queuing work on `hip_stream` (a hipStream_t; NULL = default stream): the
+ * problem of Sec. 5 eq. general (advection-diffusion or viscous Burgers,
+ * periodic box) split into PEs as in Sec. 2, with the delay model of
+ * Sec. 5.1 (one delay per PE face and step, drawn from the generator above,
+ * zero, or a host table). Derives the central-difference taps and the level
+ * weights c_m(k) of the AT combination (Sec. 3.4 Example 3, eq. cd4-at).
  * Validates: ndim 1..3; divisibility; PE edge >= 2s on used axes; order in
- * {2,4,6}; 1 <= L <= 8; 1 <= T <= 4; host delays < L. */
+ * {2,4,6}; 1 <= L <= 8; 1 <= T <= 4; host delays < L (AT_EINVAL);
+ * AT_ENOMEM when ws_bytes is too small. The library keeps `ws_dev` and the
+ * stream; the caller keeps ownership of both and of every host array. */
 at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev,
                     size_t ws_bytes, void* hip_stream, at_ctx** out);
 
-/* Set u^0 (bulk precision, device) and reset the step counter to 0. Every
- * ring slot is filled with the edge strips of u^0. */
+/* Set u^0 (the initial condition of Sec. 5.1 eq. IC or any field; bulk
+ * precision, device, [nz][ny][nx] x fastest, copied) and reset the step
+ * counter to 0. Every ring slot is filled with the edge strips of u^0 (no
+ * level exists before t = 0; the start-up clamp of the delays keeps their
+ * weights at zero). AT_EINVAL for a null pointer. */
 at_status at_set_state(at_ctx* ctx, const void* u0_dev);
 
-/* Advance nsteps time steps (queued, asynchronous). */
+/* Advance nsteps time steps (queued on the context's stream, asynchronous):
+ * per step the delay draw (Sec. 5.1), the AT combination of the delayed ring
+ * levels at the points of I_B and the standard central difference elsewhere
+ * (Sec. 2 eqs. general_deriv, general_deriv_async; Sec. 3.4 eq. cd4-at), the
+ * right-hand side of Sec. 5 eq. general and the time update of Sec. 4.1
+ * (eqs. time_disc, time_ab2; AB3; Heun), then the publish of the new edge
+ * strips into the ring slot of level n+1. AT_ESTATE before at_set_state,
+ * AT_EINVAL when a host delay table is too short, AT_EHIP on launch failure. */
 at_status at_step(at_ctx* ctx, int64_t nsteps);
 
 /* Capture chunks of `chunk` steps into a HIP graph and replay it inside
@@ -201,10 +218,13 @@ enum { AT_TUNE_CANDIDATES = 9 };
 at_status at_autotune(at_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t nsteps,
                       int32_t* best_depth, double* ms_out);
 
-/* Copy the current field u^n (bulk precision) to `u_dev`. */
+/* Copy the current field u^n (bulk precision, [nz][ny][nx], x fastest) to
+ * the caller's device buffer `u_dev` (Sec. 2: the solution at time level n).
+ * AT_ESTATE before at_set_state. Queued on the context's stream. */
 at_status at_get_state(at_ctx* ctx, void* u_dev);
 
-/* Current step number n (host-side mirror; no synchronisation). */
+/* Current step number n, i.e. t = n dt (host-side mirror; no
+ * synchronisation). */
 at_status at_get_step(const at_ctx* ctx, int64_t* n);
 
 /* Delays k (after the start-up clamp) of steps n0 .. n0+count-1, computed on

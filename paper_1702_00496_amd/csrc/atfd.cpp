@@ -219,7 +219,7 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
     l.off_ring = take(l.ring_bytes);
     if (l.star) l.off_sring = take(l.ring_bytes);
   }
-  l.off_counter = take(2 * sizeof(int64_t));
+  l.off_counter = take(kCounterWords * sizeof(int64_t));
   l.off_partial = take(static_cast<size_t>(kNormBlocks) * 8 * sizeof(double));
   l.off_result = take(16 * sizeof(double));
   l.off_delays = take(kDelayScratch);

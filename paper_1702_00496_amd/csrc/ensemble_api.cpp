@@ -150,7 +150,7 @@ at_status plan(at_ens* e, int32_t count, const at_ens_member* m, int32_t precisi
   e->off_f = e->any_ab2 ? take(e->field_bytes) : 0;
   e->off_ring = ring ? take(ring * w) : 0;
   e->off_hbuf = take(halo * w);
-  e->off_counter = take(2 * sizeof(int64_t));
+  e->off_counter = take(kCounterWords * sizeof(int64_t));
   e->off_out = take(sizeof(double) * 4 * count);
   e->off_phase = take(sizeof(double) * kPhaseMax);
   e->off_stats = take(sizeof(double) * (AT_ENS_MAX_DX_BINS + 1 + 3 * AT_ENS_MAX_DX_BINS * 4));
@@ -277,7 +277,7 @@ at_status at_ens_create(int32_t count, const at_ens_member* members, int32_t pre
   p.counter = reinterpret_cast<int64_t*>(e->ws + e->off_counter);
   hipError_t he = hipMemcpyAsync(e->ws + e->off_mem, e->mem.data(), sizeof(EnsMember) * count,
                                  hipMemcpyHostToDevice, e->stream);
-  if (he == hipSuccess) he = hipMemsetAsync(p.counter, 0, 2 * sizeof(int64_t), e->stream);
+  if (he == hipSuccess) he = hipMemsetAsync(p.counter, 0, kCounterWords * sizeof(int64_t), e->stream);
   if (he != hipSuccess) {
     delete e;
     return efail(nullptr, AT_EHIP, "ensemble set-up: %s", hipGetErrorString(he));
@@ -294,7 +294,7 @@ at_status at_ens_create(int32_t count, const at_ens_member* members, int32_t pre
 at_status at_ens_set_state(at_ens* e, const void* u0_dev) {
   if (!e || !u0_dev) return efail(e, AT_EINVAL, "null argument");
   ENS_TRY(e, hipMemcpyAsync(e->ep.u[0], u0_dev, e->field_bytes, hipMemcpyDeviceToDevice, e->stream));
-  ENS_TRY(e, hipMemsetAsync(e->ep.counter, 0, 2 * sizeof(int64_t), e->stream));
+  ENS_TRY(e, hipMemsetAsync(e->ep.counter, 0, kCounterWords * sizeof(int64_t), e->stream));
   // the sweep reads f^{n-1} at every step and weights it by an exact zero at
   // n = 0 (and for Euler members): it must hold finite values from the start
   if (e->ep.f) ENS_TRY(e, hipMemsetAsync(e->ep.f, 0, e->field_bytes, e->stream));
