@@ -28,6 +28,8 @@
 
 #include "adjoint.hpp"
 
+#include <algorithm>
+
 namespace atfd {
 namespace {
 
@@ -389,6 +391,307 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
   }
 }
 
+// PE-tiled form of adj_lambda_kernel (same formula, same per-point order of
+// the sums): one workgroup per PE, every global value loaded once.
+//  - 1-D / 2-D: the PE's plane in LDS: the stage values c with the frame of
+//    forward halo values (hbuf) the stencil reads across the PE's faces, and
+//    the two mu fields y0, y1 with a zero frame (taps of consumer points
+//    outside the PE reach this point through the adjoint ring instead).
+//  - 3-D: each thread owns one (x, y) column of the PE and streams it in z
+//    with register queues of 2S+1 planes of c, y0 and y1 (the z halo values
+//    of c from hbuf, zeros for y0 and y1 beyond the PE), the x/y neighbours
+//    from a double-buffered LDS plane laid out like the 2-D one. The loads of
+//    the plane S+1 ahead are in flight while a plane is computed.
+// The alpha-gradient part of the workgroup goes to partial[PE].
+constexpr int kAdjPeThreads = 1024;
+
+template <typename Real, int DIM, int S>
+__global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams q) {
+  const StepParams& p = q.sp;
+  extern __shared__ __align__(16) unsigned char adj_smem[];
+  const int pe = blockIdx.x;
+  const int qx = pe % p.px, qy = (pe / p.px) % p.py, qz = pe / (p.px * p.py);
+  const int bx = p.bx, by = DIM >= 2 ? p.by : 1, bz = DIM == 3 ? p.bz : 1;
+  const int x0 = qx * p.bx, y0 = qy * p.by, z0 = qz * p.bz;
+  const int W = bx + 2 * S, H = DIM >= 2 ? by + 2 * S : 1;   // LDS plane: rows of W, x = 0 at column S
+  const int plane = W * H;
+  const int nbuf = DIM == 3 ? 2 : 1;
+  Real* Cl = reinterpret_cast<Real*>(adj_smem);            // [nbuf][plane]
+  Real* Y0l = Cl + nbuf * plane;
+  Real* Y1l = Y0l + nbuf * plane;
+  Real* __restrict__ out = static_cast<Real*>(q.out);
+  const Real* __restrict__ X0 = static_cast<const Real*>(q.x0);
+  const Real* __restrict__ X1 = static_cast<const Real*>(q.b1 != 0.0 ? q.x1 : q.x0);
+  const Real* __restrict__ Yg0 = static_cast<const Real*>(q.y0);
+  const Real* __restrict__ Yg1 = static_cast<const Real*>(q.m1 != 0.0 ? q.y1 : q.y0);
+  const Real* __restrict__ C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
+  const Real* __restrict__ hpe = static_cast<const Real*>(q.hbuf) + static_cast<int64_t>(pe) * p.pe_block;
+  Real* __restrict__ aring = static_cast<Real*>(q.aring);
+  const int slot_n = static_cast<int>(q.n % q.anslots);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double m0 = q.m0, m1 = q.m1;
+  // taps in LDS (read with uniform addresses where a point needs them)
+  __shared__ double s_c1[3][2 * S + 1], s_c2a[3][2 * S + 1], s_kad[3][2 * S + 1], s_c2[3][2 * S + 1];
+  if (tid < 3 * (2 * S + 1)) {
+    const int a = tid / (2 * S + 1), o = tid % (2 * S + 1);
+    s_c1[a][o] = p.c1[a][o];
+    s_c2[a][o] = p.c2[a][o];
+    s_c2a[a][o] = p.alpha * p.c2[a][o];
+    s_kad[a][o] = p.kad[a][o];
+  }
+  const bool burg = q.burgers != 0;
+  // tap K_{i,a,o} at a point with stage value ci (as tap_k)
+  auto tapk = [&](int a, int o, double ci) -> double {
+    return burg ? s_c2a[a][o + S] - ci * s_c1[a][o + S] : s_kad[a][o + S];
+  };
+  // forward halo value across face f (a = f >> 1) for the PE coordinates l
+  // whose axis-a coordinate ta lies outside the PE
+  auto halo_c = [&](int f, int* l, int ta) -> Real {
+    const int a = f >> 1, b = a == 0 ? bx : a == 1 ? by : bz;
+    l[a] = (f & 1) ? ta - b : ta + b;
+    const int64_t pfo = f == 0 ? q.pfo[0] : f == 1 ? q.pfo[1] : f == 2 ? q.pfo[2] : f == 3 ? q.pfo[3]
+                      : f == 4 ? q.pfo[4] : q.pfo[5];
+    return hpe[pfo + strip_elem(p, f ^ 1, l, S)];
+  };
+  // zero frames of y0, y1; the x/y halo frame of c is written per plane
+  for (int i = tid; i < nbuf * plane; i += nt) {
+    Y0l[i] = Real(0);
+    Y1l[i] = Real(0);
+  }
+  __syncthreads();   // the zeros land before any own value is written over them
+  // the per-point adjoint (x, y, z PE coordinates; global index g); cget(a, o)
+  // / yget(a, o) give c and (y0, y1) at offset o along axis a
+  double da = 0.0;
+  auto point = [&](int x, int y, int z, int64_t g, double cj, double y0j, double y1j, double x0j, double x1j,
+                   auto cget, auto yget) {
+    const double mu = m0 * y0j + m1 * y1j;
+    double acc = q.b0 * x0j + q.b1 * x1j;
+    double lap = 0.0, grad = 0.0, sumk = 0.0;
+    const int l[3] = {x, y, z};
+    // one axis at a time (not unrolled over axes: bounds the values in flight)
+#pragma unroll 1
+    for (int a = 0; a < DIM; ++a) {
+      const int b = a == 0 ? bx : a == 1 ? by : bz;
+#pragma unroll
+      for (int o = -S; o <= S; ++o) {
+        if (o == 0) continue;
+        sumk += tapk(a, o, cj);
+        // transposed interior tap from i = j - o (zero mu outside the PE)
+        double yi0, yi1;
+        yget(a, -o, yi0, yi1);
+        const double mi = m0 * yi0 + m1 * yi1;
+        const double ci = burg ? cget(a, -o) : 0.0;
+        const int ia = l[a] - o;
+        acc += (ia >= 0 && ia < b) ? tapk(a, o, ci) * mi : 0.0;
+        // forward stencil of the stage field at j
+        const double v = cget(a, o) - cj;
+        lap += s_c2[a][o + S] * v;
+        grad += s_c1[a][o + S] * v;
+      }
+    }
+    // drain the adjoint-ring entries of the strips j lies in
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const int b = a == 0 ? bx : a == 1 ? by : bz;
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        if (side ? l[a] >= b - S : l[a] < S) {
+          Real* src = aring + ring_at_pt(p, slot_n, pe, 2 * a + side, l, S);
+          acc += static_cast<double>(*src);
+          *src = Real(0);
+        }
+      }
+    }
+    acc += (-sumk - (burg ? grad : 0.0)) * mu;
+    out[g] = static_cast<Real>(acc);
+    da += mu * lap;
+  };
+
+  if constexpr (DIM <= 2) {
+    // the plane: own values, then the x (and y) frame of c
+    for (int i = tid; i < bx * by; i += nt) {
+      const int y = i / bx, x = i - y * bx;
+      const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+      const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
+      Cl[at] = C[g];
+      Y0l[at] = Yg0[g];
+      Y1l[at] = Yg1[g];
+    }
+    const int nfx = 2 * S * by, nf = nfx + (DIM >= 2 ? 2 * S * bx : 0);
+    for (int h = tid; h < nf; h += nt) {
+      int l[3] = {0, 0, 0};
+      if (h < nfx) {
+        const int side = h >= S * by ? 1 : 0, r = side ? h - S * by : h, y = r / S, d = r - y * S;
+        const int ta = side ? bx + d : d - S;
+        l[1] = y;
+        Cl[(DIM >= 2 ? y + S : 0) * W + ta + S] = halo_c(side, l, ta);
+      } else {
+        const int hy = h - nfx, side = hy >= S * bx ? 1 : 0, r = side ? hy - S * bx : hy, d = r / bx, x = r - d * bx;
+        const int ta = side ? by + d : d - S;
+        l[0] = x;
+        Cl[(ta + S) * W + x + S] = halo_c(2 + side, l, ta);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < bx * by; i += nt) {
+      const int y = i / bx, x = i - y * bx;
+      const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
+      auto cget = [&](int a, int o) -> double { return static_cast<double>(Cl[at + (a == 0 ? o : o * W)]); };
+      auto yget = [&](int a, int o, double& v0, double& v1) {
+        const int k = at + (a == 0 ? o : o * W);
+        v0 = static_cast<double>(Y0l[k]);
+        v1 = static_cast<double>(Y1l[k]);
+      };
+      const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+      point(x, y, 0, g, static_cast<double>(Cl[at]), static_cast<double>(Y0l[at]), static_cast<double>(Y1l[at]),
+            static_cast<double>(X0[g]), static_cast<double>(X1[g]), cget, yget);
+    }
+  } else {
+    // one column per thread (the host launches bx * by threads)
+    const int x = tid % bx, y = tid / bx;
+    const int at = (y + S) * W + x + S;
+    const int64_t col = gindex(p, x0 + x, y0 + y, z0);
+    const int64_t zs = static_cast<int64_t>(p.nx) * p.ny;
+    // values of plane zz (from -S to bz + S - 1): own planes from memory,
+    // beyond the PE's z faces c from the halo buffer and y0 = y1 = 0
+    auto fetch = [&](int zz, Real& cv, Real& a0, Real& a1) {
+      if (zz >= 0 && zz < bz) {
+        const int64_t g = col + zz * zs;
+        cv = C[g];
+        a0 = Yg0[g];
+        a1 = Yg1[g];
+      } else {
+        int l[3] = {x, y, 0};
+        cv = halo_c(zz < 0 ? 4 : 5, l, zz);
+        a0 = a1 = Real(0);
+      }
+    };
+    Real cq[2 * S + 1], yq0[2 * S + 1], yq1[2 * S + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * S; ++i) fetch(i - S, cq[i], yq0[i], yq1[i]);
+    Real pc, p0, p1;   // plane S ahead, prefetched
+    fetch(S, pc, p0, p1);
+    // x and y frame of c: thread h < nf owns one frame element of every plane
+    // (its LDS position, and its halo-buffer address of plane 0 plus a
+    // per-plane stride: x strips [z][y][d], y strips [z][d][x]); the value of
+    // the next plane is loaded while a plane is computed
+    const int nf = 2 * S * (by + bx);
+    const bool has_f = tid < nf;
+    int f_at = 0;
+    int64_t f_addr = 0, f_stride = 0;
+    if (has_f) {
+      int l[3] = {0, 0, 0};
+      int f, ta;
+      if (tid < 2 * S * by) {
+        const int side = tid >= S * by ? 1 : 0, r = side ? tid - S * by : tid, yy = r / S, d = r - yy * S;
+        ta = side ? bx + d : d - S;
+        l[1] = yy;
+        f = side;
+        f_at = (yy + S) * W + ta + S;
+        f_stride = static_cast<int64_t>(by) * S;
+      } else {
+        const int hy = tid - 2 * S * by, side = hy >= S * bx ? 1 : 0, r = side ? hy - S * bx : hy;
+        const int d = r / bx, xx = r - d * bx;
+        ta = side ? by + d : d - S;
+        l[0] = xx;
+        f = 2 + side;
+        f_at = (ta + S) * W + xx + S;
+        f_stride = static_cast<int64_t>(S) * bx;
+      }
+      const int a = f >> 1, b = a == 0 ? bx : by;
+      l[a] = (f & 1) ? ta - b : ta + b;
+      const int64_t pfo = f == 0 ? q.pfo[0] : f == 1 ? q.pfo[1] : f == 2 ? q.pfo[2] : q.pfo[3];
+      f_addr = pfo + strip_elem(p, f ^ 1, l, S);
+    }
+    Real fv = has_f ? hpe[f_addr] : Real(0);
+    // base terms of the point, one plane ahead
+    Real xv0 = X0[col], xv1 = X1[col];
+    for (int z = 0; z < bz; ++z) {
+      const Real xc0 = xv0, xc1 = xv1;
+      if (z + 1 < bz) {
+        xv0 = X0[col + (z + 1) * zs];
+        xv1 = X1[col + (z + 1) * zs];
+      }
+      cq[2 * S] = pc;
+      yq0[2 * S] = p0;
+      yq1[2 * S] = p1;
+      if (z + S + 1 < bz + S) fetch(z + S + 1, pc, p0, p1);
+      Real* Cp = Cl + (z & 1) * plane;
+      Real* P0 = Y0l + (z & 1) * plane;
+      Real* P1 = Y1l + (z & 1) * plane;
+      Cp[at] = cq[S];
+      P0[at] = yq0[S];
+      P1[at] = yq1[S];
+      if (has_f) {
+        Cp[f_at] = fv;
+        if (z + 1 < bz) fv = hpe[f_addr + (z + 1) * f_stride];
+      }
+      __syncthreads();
+      auto cget = [&](int a, int o) -> double {
+        return static_cast<double>(a == 2 ? cq[S + o] : Cp[at + (a == 0 ? o : o * W)]);
+      };
+      auto yget = [&](int a, int o, double& v0, double& v1) {
+        if (a == 2) {
+          v0 = static_cast<double>(yq0[S + o]);
+          v1 = static_cast<double>(yq1[S + o]);
+        } else {
+          const int k = at + (a == 0 ? o : o * W);
+          v0 = static_cast<double>(P0[k]);
+          v1 = static_cast<double>(P1[k]);
+        }
+      };
+      point(x, y, z, col + z * zs, static_cast<double>(cq[S]), static_cast<double>(yq0[S]),
+            static_cast<double>(yq1[S]), static_cast<double>(xc0), static_cast<double>(xc1), cget, yget);
+#pragma unroll
+      for (int i = 0; i < 2 * S; ++i) {
+        cq[i] = cq[i + 1];
+        yq0[i] = yq0[i + 1];
+        yq1[i] = yq1[i + 1];
+      }
+    }
+  }
+  // fixed-order block reduction of the alpha-gradient part
+  for (int off = 32; off > 0; off >>= 1) da += __shfl_down(da, off, 64);
+  __shared__ double part[kAdjPeThreads / 64];
+  if ((tid & 63) == 0) part[tid / 64] = da;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nt / 64; ++w) s += part[w];
+    q.partial[pe] += s;
+  }
+}
+
+template <typename Real>
+size_t adj_pe_lds(const StepParams& p) {
+  const int S = p.s;
+  const size_t W = p.bx + 2 * S, H = p.ndim >= 2 ? p.by + 2 * S : 1;
+  return (p.ndim == 3 ? 2 : 1) * 3 * W * H * sizeof(Real);
+}
+
+template <typename Real>
+hipError_t launch_lambda_pe(const AdjParams& q, hipStream_t st) {
+  const StepParams& p = q.sp;
+  const size_t lds = adj_pe_lds<Real>(p);
+  const int pts = p.bx * (p.ndim >= 2 ? p.by : 1);
+  const int threads = p.ndim == 3 ? (pts + 63) / 64 * 64 : std::min(kAdjPeThreads, (pts + 63) / 64 * 64);
+  // 3-D: every frame element of a plane has its own thread
+  if (p.ndim == 3 && 2 * p.s * (p.bx + p.by) > threads) return hipErrorInvalidValue;
+  const int key = p.ndim * 10 + p.s;
+  switch (key) {
+#define ATFD_ADJ_PE_CASE(D, S)                                                                          \
+  case D * 10 + S:                                                                                      \
+    hipLaunchKernelGGL((adj_lambda_pe_kernel<Real, D, S>), dim3(p.npe), dim3(threads), lds, st, q);      \
+    break;
+    ATFD_ADJ_PE_CASE(1, 1) ATFD_ADJ_PE_CASE(1, 2) ATFD_ADJ_PE_CASE(1, 3)
+    ATFD_ADJ_PE_CASE(2, 1) ATFD_ADJ_PE_CASE(2, 2) ATFD_ADJ_PE_CASE(2, 3)
+    ATFD_ADJ_PE_CASE(3, 1) ATFD_ADJ_PE_CASE(3, 2) ATFD_ADJ_PE_CASE(3, 3)
+#undef ATFD_ADJ_PE_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename Real>
 hipError_t launch_lambda(const AdjParams& q, int blocks, hipStream_t st) {
   const int key = q.sp.ndim * 10 + q.sp.s;
@@ -423,22 +726,35 @@ int adj_blocks(int64_t npts) {
   return static_cast<int>(b < kAdjBlocks ? b : kAdjBlocks);
 }
 
+bool adj_pe_applies(const StepParams& p, bool f64) {
+  const size_t lds = f64 ? adj_pe_lds<double>(p) : adj_pe_lds<float>(p);
+  if (lds > 64 * 1024) return false;
+  // 3-D: one thread per column, whole waves; the FP64 register queues of
+  // s >= 2 would spill
+  if (p.ndim == 3 && f64 && p.s >= 2) return false;
+  return p.ndim <= 2 || (p.bx * p.by <= kAdjPeThreads && (p.bx * p.by) % 64 == 0 &&
+                         2 * p.s * (p.bx + p.by) <= p.bx * p.by);
+}
+
 hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   const int64_t strips = static_cast<int64_t>(q.sp.npe) * q.sp.pe_block;
   const int64_t sb = (strips + kAdjThreads - 1) / kAdjThreads;
   const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
   const int lblocks = adj_blocks(q.npts);
+  const bool pe = adj_pe_applies(q.sp, f64);
   if (f64) {
     hipLaunchKernelGGL(adj_strip_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipError_t e = launch_lambda<double>(q, lblocks, st);
+    hipError_t e = pe ? launch_lambda_pe<double>(q, st) : launch_lambda<double>(q, lblocks, st);
     if (e != hipSuccess) return e;
   } else {
     hipLaunchKernelGGL(adj_strip_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
-    hipError_t e = launch_lambda<float>(q, lblocks, st);
+    hipError_t e = pe ? launch_lambda_pe<float>(q, st) : launch_lambda<float>(q, lblocks, st);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
+
+int adj_partials(const StepParams& p) { return p.npe > kAdjBlocks ? p.npe : kAdjBlocks; }
 
 hipError_t launch_adj_sum(const double* partial, int count, double* out, hipStream_t st) {
   hipLaunchKernelGGL(adj_sum_kernel, dim3(1), dim3(64), 0, st, partial, count, out);

@@ -29,10 +29,13 @@ struct AdjParams {
   int64_t pfo[6];                  // offset of face f's strip inside one PE's pe_block values
   void* aring;                     // adjoint ring of the stage field, anslots slots
   int anslots;
-  double* partial;                 // [kAdjBlocks] alpha-gradient partial sums
+  double* partial;                 // [adj_partials] alpha-gradient partial sums
 };
 
 int adj_blocks(int64_t npts);
+// alpha-gradient partial sums the stage kernels write (>= kAdjBlocks; one per
+// PE for the PE-tiled kernel)
+int adj_partials(const StepParams& p);
 hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st);
 hipError_t launch_adj_sum(const double* partial, int count, double* out, hipStream_t st);
 

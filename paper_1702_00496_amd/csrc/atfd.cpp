@@ -766,7 +766,7 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   if (a.rk2) a.off_bring = take(a.aring_bytes);
   a.off_ring0 = take(l.ring_bytes);
   if (a.rk2) a.off_sring0 = take(l.ring_bytes);
-  a.off_partial = take(kAdjBlocks * sizeof(double));
+  a.off_partial = take(static_cast<size_t>(adj_partials(c->sp)) * sizeof(double));
   a.off_out = take(sizeof(double));
   a.total = off;
   return a;
@@ -827,7 +827,8 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
   HIP_TRY(c, hipMemsetAsync(lam[i2], 0, l.field_bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(sc + a.off_aring, 0, a.aring_bytes, c->stream));
   if (a.rk2) HIP_TRY(c, hipMemsetAsync(sc + a.off_bring, 0, a.aring_bytes, c->stream));
-  HIP_TRY(c, hipMemsetAsync(sc + a.off_partial, 0, kAdjBlocks * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(sc + a.off_partial, 0, static_cast<size_t>(adj_partials(c->sp)) * sizeof(double),
+                            c->stream));
   unsigned char* levels = sc + a.off_levels;
   unsigned char* slevels = a.rk2 ? sc + a.off_slevels : nullptr;
   const double dt = c->prob.dt;
@@ -906,7 +907,7 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
   }
   HIP_TRY(c, hipMemcpyAsync(grad_u0_dev, lam[i1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
   double* out = reinterpret_cast<double*>(sc + a.off_out);
-  HIP_TRY(c, launch_adj_sum(reinterpret_cast<double*>(sc + a.off_partial), kAdjBlocks, out, c->stream));
+  HIP_TRY(c, launch_adj_sum(reinterpret_cast<double*>(sc + a.off_partial), adj_partials(c->sp), out, c->stream));
   HIP_TRY(c, hipMemcpyAsync(grad_alpha, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   // leave the context at the end of the forward run
   st = at_load(c, sc + a.ck * a.nck);

@@ -45,6 +45,9 @@ CASES = {
     "2d_o4_rk2_burgers_sync": dict(ndim=2, n=(32, 24), pe=(2, 2), order=4, integrator="rk2", equation="burgers", alpha=0.05, mode="sync", steps=12, every=5, ra=0.01),
     "3d_o6_rk2_burgers": dict(ndim=3, n=(24, 24, 24), pe=(2, 2, 2), order=6, integrator="rk2", equation="burgers", alpha=0.05, L=4, steps=6, every=4, ra=0.004),
     "3d_fast_o6_rk2_burgers": dict(ndim=3, n=(64, 64, 32), pe=(2, 2, 1), order=6, integrator="rk2", equation="burgers", alpha=0.05, L=4, steps=6, every=4, ra=0.004),
+    # PE cross-sections of 64 points: the column-streaming stage kernel
+    "3d_o4_ab2_pe8x8": dict(ndim=3, n=(16, 16, 12), pe=(2, 2, 2), order=4, integrator="ab2", c=(0.5, -1.0, 1.0), L=4, steps=10, every=3, ra=0.02),
+    "3d_o6_rk2_burgers_pe8x8": dict(ndim=3, n=(16, 16, 18), pe=(2, 2, 3), order=6, integrator="rk2", equation="burgers", alpha=0.05, L=3, steps=8, every=3, ra=0.004),
 }
 
 
