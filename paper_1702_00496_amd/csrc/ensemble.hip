@@ -123,7 +123,7 @@ __device__ inline void ens_store(Real* p, const Real* src) {
 // Loads of chunk c (points V c .. V c + V - 1 of member M). A neighbour
 // position outside the PE reads the halo value of that face instead: the
 // address is selected, so no load sits behind a branch.
-template <typename Real, int S, int V>
+template <typename Real, int S, int V, bool AB2>
 __device__ inline EnsChunk<Real, S, V> ens_chunk_load(const EnsMember& M, const Real* __restrict__ u,
                                                       const Real* __restrict__ f,
                                                       const Real* __restrict__ hb, int c) {
@@ -144,21 +144,21 @@ __device__ inline EnsChunk<Real, S, V> ens_chunk_load(const EnsMember& M, const 
     const Real* ar = pr < M.b ? u + k.g0 + V - 1 + o : hr + (pr - M.b);
     k.w[S + V - 1 + o] = *ar;
   }
-  // f^{n-1}, read for every member (a non-AB2 member reads its own u^n; the
-  // update weights it by an exact zero, as it does f at n = 0, which
-  // at_ens_set_state zeroes), so that the load does not sit behind a branch
-  ens_load<Real, V>((M.integrator == AT_AB2 ? f : u) + k.g0, k.fo);
+  // f^{n-1} of an AB2 member (the sweep is instantiated per integrator, so
+  // Euler members load nothing here; at n = 0 the update weights f, which
+  // at_ens_set_state zeroes, by an exact zero)
+  if constexpr (AB2) ens_load<Real, V>(f + k.g0, k.fo);
   return k;
 }
 
 // Right-hand side, update, stores and the publish of new edge values.
-template <typename Real, int S, int V>
+template <typename Real, int S, int V, bool AB2>
 __device__ inline void ens_chunk_finish(const EnsMember& M, const EnsChunk<Real, S, V>& k, Real* __restrict__ un,
                                         Real* __restrict__ f, Real* __restrict__ ring, int64_t n) {
   const Real dt = static_cast<Real>(M.dt);
   // AB2 after its first step: u + dt (3/2 f^n - 1/2 f^{n-1}); Euler (and the
-  // first AB2 step): u + dt f^n, with an exact zero weight on f^{n-1}
-  const bool ab2 = M.integrator == AT_AB2 && n > 0;
+  // first AB2 step): u + dt f^n
+  const bool ab2 = AB2 && n > 0;
   const Real b1 = ab2 ? Real(1.5) : Real(1), b2 = ab2 ? Real(-0.5) : Real(0);
   Real r[V], acc[V];
 #pragma unroll
@@ -173,10 +173,13 @@ __device__ inline void ens_chunk_finish(const EnsMember& M, const EnsChunk<Real,
       a += ens_tap<Real>(M, S + o) * (k.w[S + e + o] - u0);
     }
     acc[e] = a;
-    r[e] = u0 + dt * (b1 * a + b2 * k.fo[e]);
+    if constexpr (AB2)
+      r[e] = u0 + dt * (b1 * a + b2 * k.fo[e]);
+    else
+      r[e] = u0 + dt * (b1 * a);
   }
   ens_store<Real, V>(un + k.g0, r);
-  if (M.integrator == AT_AB2) ens_store<Real, V>(f + k.g0, acc);
+  if constexpr (AB2) ens_store<Real, V>(f + k.g0, acc);
   if (M.mode != AT_SYNC && (k.l0 < S || k.l0 + V - 1 >= M.b - S)) {
     const int pslot = static_cast<int>((n + 1) % M.nslots);
     Real* base = ring + M.ring_off + (static_cast<int64_t>(pslot) * M.npe + k.pe) * 2 * S;
@@ -192,7 +195,7 @@ __device__ inline void ens_chunk_finish(const EnsMember& M, const EnsChunk<Real,
 // Phase 2 of a step: the sweep over member M's points, V per chunk and U
 // chunks per thread and iteration, all U chunks' loads issued before any
 // result is stored so that they are in flight together.
-template <typename Real, int S, int V, int U>
+template <typename Real, int S, int V, int U, bool AB2>
 __device__ inline void ens_member_sweep(const EnsMember& M, const Real* __restrict__ u, Real* __restrict__ un,
                                         Real* __restrict__ f, Real* __restrict__ ring,
                                         const Real* __restrict__ hb, int64_t n) {
@@ -204,31 +207,41 @@ __device__ inline void ens_member_sweep(const EnsMember& M, const Real* __restri
     for (int j = 0; j < U; ++j) {
       // chunks past the end re-load chunk c (in range) and are not stored
       const int cj = c + j * bd < nch ? c + j * bd : c;
-      k[j] = ens_chunk_load<Real, S, V>(M, u, f, hb, cj);
+      k[j] = ens_chunk_load<Real, S, V, AB2>(M, u, f, hb, cj);
     }
 #pragma unroll
     for (int j = 0; j < U; ++j)
-      if (c + j * bd < nch) ens_chunk_finish<Real, S, V>(M, k[j], un, f, ring, n);
+      if (c + j * bd < nch) ens_chunk_finish<Real, S, V, AB2>(M, k[j], un, f, ring, n);
   }
 }
 
-template <typename Real, int S>
+template <typename Real, int S, int UX>
 __device__ inline void ens_member_sweep_s(const EnsMember& M, const Real* u, Real* un, Real* f, Real* ring,
                                           const Real* hb, int64_t n) {
   // as many chunks in flight as the 128 registers of a 1024-thread
-  // workgroup hold without spilling
-  constexpr int U = sizeof(Real) == 4 ? (S <= 2 ? 4 : 2) : (S <= 2 ? 2 : 1);
-  if (M.vec)
-    ens_member_sweep<Real, S, 4, U>(M, u, un, f, ring, hb, n);
-  else
-    ens_member_sweep<Real, S, 1, sizeof(Real) == 4 ? 4 : 2>(M, u, un, f, ring, hb, n);
+  // workgroup hold without spilling; UX = 2 for workgroups of at most 512
+  // threads (256 registers)
+  constexpr int U = UX * (sizeof(Real) == 4 ? (S <= 2 ? 4 : 2) : (S <= 2 ? 2 : 1));
+  constexpr int U1 = UX * (sizeof(Real) == 4 ? 2 : 1);
+  // the integrator is uniform per member: one instantiation each
+  if (M.integrator == AT_AB2) {
+    if (M.vec)
+      ens_member_sweep<Real, S, 4, U, true>(M, u, un, f, ring, hb, n);
+    else
+      ens_member_sweep<Real, S, 1, U1, true>(M, u, un, f, ring, hb, n);
+  } else {
+    if (M.vec)
+      ens_member_sweep<Real, S, 4, U, false>(M, u, un, f, ring, hb, n);
+    else
+      ens_member_sweep<Real, S, 1, U1, false>(M, u, un, f, ring, hb, n);
+  }
 }
 
 // Members whose descriptors a workgroup holds in LDS at a time.
 constexpr int kEnsLdsMembers = AT_ENS_BATCH;
 
 // All steps of `count` members whose descriptors are in LDS.
-template <typename Real>
+template <typename Real, int UX>
 __device__ inline void ens_run(const EnsParams& p, int64_t n0, const EnsMember* mem, int count) {
   Real* f = static_cast<Real*>(p.f);
   Real* ring = static_cast<Real*>(p.ring);
@@ -250,9 +263,9 @@ __device__ inline void ens_run(const EnsParams& p, int64_t n0, const EnsMember* 
     for (int i = 0; i < count; ++i) {
       const EnsMember& M = mem[i];
       switch (M.s) {
-        case 1: ens_member_sweep_s<Real, 1>(M, u, un, f, ring, hb, n); break;
-        case 2: ens_member_sweep_s<Real, 2>(M, u, un, f, ring, hb, n); break;
-        default: ens_member_sweep_s<Real, 3>(M, u, un, f, ring, hb, n); break;
+        case 1: ens_member_sweep_s<Real, 1, UX>(M, u, un, f, ring, hb, n); break;
+        case 2: ens_member_sweep_s<Real, 2, UX>(M, u, un, f, ring, hb, n); break;
+        default: ens_member_sweep_s<Real, 3, UX>(M, u, un, f, ring, hb, n); break;
       }
     }
     // every member's level n+1 (field and ring) is complete, and the halo
@@ -264,8 +277,8 @@ __device__ inline void ens_run(const EnsParams& p, int64_t n0, const EnsMember* 
 // One workgroup per bin of members. Members are independent problems, so a
 // bin larger than the LDS descriptor cache runs all steps for one batch of
 // members, then for the next.
-template <typename Real>
-__global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) {
+template <typename Real, int MAXT, int UX>
+__global__ __launch_bounds__(MAXT) void ens_steps_kernel(EnsParams p) {
   __shared__ EnsMember s_mem[kEnsLdsMembers];
   constexpr int kWords = sizeof(EnsMember) / sizeof(uint32_t);
   static_assert(sizeof(EnsMember) % sizeof(uint32_t) == 0, "descriptors are copied as words");
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kEnsMaxThreads) void ens_steps_kernel(EnsParams p) 
       dst[i] = reinterpret_cast<const uint32_t*>(p.mem + p.order[b0 + j])[i - j * kWords];
     }
     __syncthreads();
-    ens_run<Real>(p, n0, s_mem, count);
+    ens_run<Real, UX>(p, n0, s_mem, count);
   }
   if (threadIdx.x == 0) advance_counter(p.counter, n0 + p.nsteps - 1);
 }
@@ -470,10 +483,19 @@ hipError_t launch_ens_stats(const EnsStatsParams& p, hipStream_t st) {
 
 hipError_t launch_ens_steps(const EnsParams& p, bool f64, int nbins, int threads, hipStream_t st) {
   if (threads < 64 || threads > kEnsMaxThreads || threads % 64) return hipErrorInvalidValue;
-  if (f64)
-    hipLaunchKernelGGL(ens_steps_kernel<double>, dim3(nbins), dim3(threads), 0, st, p);
-  else
-    hipLaunchKernelGGL(ens_steps_kernel<float>, dim3(nbins), dim3(threads), 0, st, p);
+  // workgroups of up to 512 threads have twice the registers: twice the
+  // chunks in flight
+  if (f64) {
+    if (threads > 512)
+      hipLaunchKernelGGL((ens_steps_kernel<double, 1024, 1>), dim3(nbins), dim3(threads), 0, st, p);
+    else
+      hipLaunchKernelGGL((ens_steps_kernel<double, 512, 2>), dim3(nbins), dim3(threads), 0, st, p);
+  } else {
+    if (threads > 512)
+      hipLaunchKernelGGL((ens_steps_kernel<float, 1024, 1>), dim3(nbins), dim3(threads), 0, st, p);
+    else
+      hipLaunchKernelGGL((ens_steps_kernel<float, 512, 2>), dim3(nbins), dim3(threads), 0, st, p);
+  }
   return hipGetLastError();
 }
 
