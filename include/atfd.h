@@ -200,7 +200,11 @@ at_status at_set_graph(at_ctx* ctx, int32_t chunk);
  * 2 points per thread and 512 threads per PE, or 16 + D with 4 points per
  * thread and the z sweep direction alternating from launch to launch (each
  * launch starts on the planes the previous one touched last, which the
- * Infinity Cache still holds); 0 = the library default. Every
+ * Infinity Cache still holds); 0 = the library default. For the generic
+ * 3-D sweep (other PE shapes), 32 + c with c in {1, 2, 4, 8, 16} splits
+ * every PE's planes into c z-chunks of one workgroup each (clamped to the
+ * PE depth; only where the sweep may split a PE: two solution buffers or
+ * Heun) instead of the cost-model split. Every
  * variant computes bit-identical results; only speed differs. Other shapes
  * ignore it. The space-expanded schemes have variants 1 and 2 on this path;
  * with another variant they run on the generic sweep (same scheme, results
@@ -210,11 +214,13 @@ at_status at_get_tuning(const at_ctx* ctx, int32_t* depth);
 
 /* Autotune: time `nsteps` steps for every candidate schedule, keep the
  * fastest and return it in *best_depth (ms per step of each candidate in
- * ms_out[AT_TUNE_CANDIDATES] for variants 1, 2, 4, 9, 10, 12, 17, 18, 20, -1
- * where a variant does not apply; may be NULL). The field and all history are
+ * ms_out[AT_TUNE_CANDIDATES] for variants 1, 2, 4, 9, 10, 12, 17, 18, 20, 33, 34,
+ * 36, 40, 48, -1 where a variant does not apply; the z-chunk variants apply
+ * only to problems the 32 x 32 path does not take; may be NULL). The field
+ * and all history are
  * saved to `scratch_dev` (>= at_checkpoint_size bytes) first and restored
  * afterwards, so the simulation is unchanged. Synchronises the stream. */
-enum { AT_TUNE_CANDIDATES = 9 };
+enum { AT_TUNE_CANDIDATES = 14 };
 at_status at_autotune(at_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t nsteps,
                       int32_t* best_depth, double* ms_out);
 

@@ -16,10 +16,15 @@ from ._lib import ATError, AtDelay, AtEnsMember, AtProblem, check
 
 ENS_TUNE_CANDIDATES = 9
 
-__all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS"]
+__all__ = ["Solver", "Ensemble", "ATEvolve", "evolve", "ATError", "lib", "VARIANTS", "FAST_VARIANTS", "CHUNK_VARIANTS"]
 
 # schedule variants of the 3-D 32x32 sweep (see at_set_tuning)
-VARIANTS = (1, 2, 4, 9, 10, 12, 17, 18, 20)
+# schedule variants: the 32 x 32 3-D path's (planes in flight, points per
+# thread, alternating sweep direction) and the generic 3-D sweep's z-chunk
+# counts; at_autotune reports them in this order
+FAST_VARIANTS = (1, 2, 4, 9, 10, 12, 17, 18, 20)
+CHUNK_VARIANTS = (33, 34, 36, 40, 48)
+VARIANTS = FAST_VARIANTS + CHUNK_VARIANTS
 
 
 def lib():

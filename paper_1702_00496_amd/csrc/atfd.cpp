@@ -462,8 +462,8 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
 at_status at_set_tuning(at_ctx* c, int32_t depth) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
   if (depth == 0) depth = fast3d_default_depth(c->g.f64);
-  if (!fast3d_valid_variant(depth))
-    return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10, 12, 17, 18 or 20");
+  if (!fast3d_valid_variant(depth) && !chunk_variant(depth))
+    return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10, 12, 17, 18, 20, 33, 34, 36, 40 or 48");
   if (depth != c->sp.depth) drop_graph(c);
   c->sp.depth = depth;
   return AT_OK;
@@ -486,7 +486,12 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
     return fail(c, AT_EINVAL, "host delay table too short for autotuning");
   at_status st = at_save(c, scratch_dev);
   if (st != AT_OK) return st;
-  const int cand[AT_TUNE_CANDIDATES] = {1, 2, 4, 9, 10, 12, 17, 18, 20};
+  const int cand[AT_TUNE_CANDIDATES] = {1, 2, 4, 9, 10, 12, 17, 18, 20, 33, 34, 36, 40, 48};
+  // the z-chunk variants are timed only for problems the 32 x 32 path does
+  // not take by default and whose planes the generic sweep may split
+  StepParams deflt = c->sp;
+  deflt.depth = fast3d_default_depth(c->g.f64);
+  const bool chunks_apply = !fast3d_applies(deflt, c->g.f64) && sweep_can_chunk(c->sp);
   const int keep = c->sp.depth, keep_chunk = c->graph_chunk;
   double best_ms = 1e300;
   int best = keep;
@@ -498,7 +503,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
     double ms = -1.0;
     StepParams trial = c->sp;
     trial.depth = cand[i];
-    if (fast3d_applies(trial, c->g.f64)) {
+    if (chunk_variant(cand[i]) ? chunks_apply : fast3d_applies(trial, c->g.f64)) {
       c->sp.depth = cand[i];
       st = at_load(c, scratch_dev);
       if (st == AT_OK) st = enqueue_step(c, c->stream);          // warm-up

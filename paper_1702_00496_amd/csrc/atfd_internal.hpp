@@ -216,6 +216,16 @@ size_t step_lds_bytes(const StepParams& p, bool f64, int s);
 bool fast3d_applies(const StepParams& p, bool f64);
 int fast3d_default_depth(bool f64);
 bool fast3d_valid_variant(int v);
+// Schedule variants of the generic 3-D sweep: kChunkVariant + c forces c
+// z-chunks per PE (c in {1, 2, 4, 8, 16}, clamped to the PE depth; only where
+// the sweep may split a PE), instead of the cost model.
+constexpr int kChunkVariant = 32;
+inline bool chunk_variant(int v) {
+  return v == kChunkVariant + 1 || v == kChunkVariant + 2 || v == kChunkVariant + 4 || v == kChunkVariant + 8 ||
+         v == kChunkVariant + 16;
+}
+// the generic sweep may split a PE's planes over several workgroups
+bool sweep_can_chunk(const StepParams& p);
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st);
 
 }  // namespace atfd

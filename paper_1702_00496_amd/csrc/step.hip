@@ -123,11 +123,14 @@ int sweep_threads(const StepParams& p) {
   return static_cast<int>(t);
 }
 
-// Workgroup size of the vector path: two quads of a plane per thread (their
-// loads issued together), with the same cap as above.
+// Workgroup size of the vector path: two quads of a plane per thread in 1-D
+// and 2-D (their loads issued together), one in 3-D, with the same cap as
+// above.
 int vec_threads(const StepParams& p) {
   const int64_t quads = static_cast<int64_t>(p.bx / 4) * (p.ndim >= 2 ? p.by : 1);
-  int64_t t = ((quads + 1) / 2 + 63) / 64 * 64;
+  // 3-D: one quad of a plane per thread (a barrier per plane); 1-D / 2-D:
+  // two quads per thread
+  int64_t t = ((p.ndim == 3 ? quads : (quads + 1) / 2) + 63) / 64 * 64;
   if (t < 64) t = 64;
   const int64_t cap = (p.ndim == 3 || p.npe < 4 * 256) ? kMaxSweepThreads : 256;
   if (t > cap) t = cap;
@@ -144,8 +147,14 @@ int vec_threads(const StepParams& p) {
 constexpr int kNumCUs = 256;   // compute units of an MI355X
 
 int sweep_chunks(const StepParams& p, size_t lds, int threads, int sd) {
-  if (p.ndim != 3) return 1;
-  if (p.ubuf[0] == p.ubuf[1] && p.integrator != AT_RK2) return 1;
+  if (!sweep_can_chunk(p)) return 1;
+  if (chunk_variant(p.depth)) {
+    // a forced count (schedule variant), clamped to the depth, no empty chunk
+    int nch = p.depth - kChunkVariant;
+    if (nch > p.bz) nch = p.bz;
+    const int zper = (p.bz + nch - 1) / nch;
+    return (p.bz + zper - 1) / zper;
+  }
   int per_cu = static_cast<int>((160 * 1024) / (lds > 0 ? lds : 1));
   const int by_threads = 2048 / threads;
   if (per_cu > by_threads) per_cu = by_threads;
@@ -180,6 +189,14 @@ int sweep_chunks(const StepParams& p, size_t lds, int threads, int sd) {
   }
   return best;
 }
+
+}  // namespace
+
+bool sweep_can_chunk(const StepParams& p) {
+  return p.ndim == 3 && (p.ubuf[0] != p.ubuf[1] || p.integrator == AT_RK2);
+}
+
+namespace {
 
 template <typename Real, int DIM>
 hipError_t launch_vec_unit(const StepParams& p, hipStream_t st, int blocks, int threads, size_t lds) {

@@ -395,7 +395,7 @@ def test_schedule_depths_bit_identical_and_autotune_restores_state(precision):
     case = _case("3d_fast_o4_ab2_bz16")
     u0 = torch.from_numpy(initial_field(case))
     outs = []
-    from paper_1702_00496_amd import VARIANTS
+    from paper_1702_00496_amd import FAST_VARIANTS as VARIANTS
     for depth in VARIANTS:
         s = solver_for(case, precision)
         s.set_tuning(depth)
@@ -500,3 +500,36 @@ def test_non_finite_field_reports_unstable(precision):
     with pytest.raises(ATError) as ei:
         s.norms(modes=modes)
     assert ei.value.status == _lib.AT_EUNSTABLE
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_generic_sweep_chunk_variants_bit_identical_and_autotuned(precision):
+    """The generic 3-D sweep's z-chunk schedule variants (1, 2, 4, 8, 16
+    chunks per PE) give the cost-model split's field bit for bit and the
+    oracle's within the bar; the autotuner times exactly those variants on
+    such a problem, restores the state and keeps the fastest."""
+    from paper_1702_00496_amd import CHUNK_VARIANTS
+    case = _case("3d_o4_ab2_chunked")
+    u0 = torch.from_numpy(initial_field(case))
+    ref = solver_for(case, precision)
+    ref.set_state(u0)
+    ref.step(case["steps"])
+    want = ref.state()
+    for v in CHUNK_VARIANTS:
+        s = solver_for(case, precision)
+        s.set_tuning(v)
+        s.set_state(u0)
+        s.step(case["steps"])
+        assert torch.equal(s.state(), want), v
+    o = oracle_for(case, u0.numpy())
+    o.run(case["steps"])
+    check_field(want.double().cpu(), o, TOL[precision], label="chunked")
+    s = solver_for(case, precision)
+    s.set_state(u0)
+    s.step(3)
+    before = s.state()
+    best, ms = s.autotune(nsteps=3)
+    assert best in CHUNK_VARIANTS and set(ms) == set(CHUNK_VARIANTS), (best, ms)
+    assert torch.equal(s.state(), before) and s.n_step == 3
+    s.step(case["steps"] - 3)
+    assert torch.equal(s.state(), want)
