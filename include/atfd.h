@@ -153,7 +153,9 @@ const char* at_version(void);
  * sub-buffers: the solution (one buffer updated in place, or two used by
  * step parity for the synchronous arm and for 3-D problems of fewer than
  * 1024 PEs without a 32 x 32 PE cross-section, or with the non-uniform
- * scheme, that do not use RK2),
+ * scheme, that do not use RK2; problems the 32 x 32 path takes keep their
+ * fields PE after PE internally, which at_set_state and at_get_state
+ * translate),
  * the integrator history, the RK2 predictor, the face rings of L+T slots,
  * delay tables, counters and reduction scratch). */
 at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_t* bytes);
@@ -206,9 +208,10 @@ at_status at_set_graph(at_ctx* ctx, int32_t chunk);
  * PE depth; only where the sweep may split a PE: two solution buffers or
  * Heun) instead of the cost-model split. Every
  * variant computes bit-identical results; only speed differs. Other shapes
- * ignore it. The space-expanded schemes have variants 1 and 2 on this path;
- * with another variant they run on the generic sweep (same scheme, results
- * equal to rounding, not bitwise), and at_autotune times only 1 and 2. */
+ * ignore it. Problems of the 32 x 32 path accept only the variants that
+ * path runs for them (D must divide the PE depth; the space-expanded schemes
+ * take 1 and 2): AT_EINVAL otherwise. The default is 2, or 1 where two
+ * planes in flight do not divide the PE depth. */
 at_status at_set_tuning(at_ctx* ctx, int32_t depth);
 at_status at_get_tuning(const at_ctx* ctx, int32_t* depth);
 

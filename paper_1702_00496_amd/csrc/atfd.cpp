@@ -32,6 +32,7 @@ static_assert(kNormBlocks <= kNormStaticBlocks, "the static norm scratch holds e
 struct Layout {
   size_t field_bytes = 0, ring_bytes = 0, host_tab_bytes = 0;
   size_t off_u[2] = {0, 0}, off_f[2] = {0, 0}, off_ustar = 0, off_ring = 0, off_sring = 0;
+  bool pe_major = false;   // fields stored PE after PE (the 32 x 32 path's problems)
   size_t off_counter = 0, off_partial = 0, off_result = 0, off_delays = 0, off_host = 0;
   size_t total = 0;
   int nslots = 0;
@@ -188,6 +189,8 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
                          (g.b[0] != 32 || g.b[1] != 32 || g.scheme == AT_SCHEME_NONUNIFORM_212);
   const bool two = d->mode == AT_SYNC || (generic3d && p->integrator != AT_RK2);
   l.off_u[1] = two ? take(l.field_bytes) : l.off_u[0];
+  l.pe_major = fast3d_shape(g.ndim, g.b[0], g.b[1], g.scheme, d->mode, g.T, g.s,
+                            static_cast<int64_t>(l.field_bytes));
   l.nfbuf = p->integrator == AT_AB2 ? 1 : p->integrator == AT_AB3 ? 2 : 0;
   for (int i = 0; i < l.nfbuf; ++i) l.off_f[i] = take(l.field_bytes);
   l.star = p->integrator == AT_RK2;
@@ -229,6 +232,16 @@ Layout make_layout(const at_problem* p, const at_delay* d, const Geometry& g) {
   }
   l.total = off;
   return l;
+}
+
+// The library's schedule variant: the 32 x 32 path's default, or variant 1
+// (one plane in flight) where the default's planes in flight do not divide
+// the PE depth.
+int default_variant(const StepParams& p, bool f64) {
+  StepParams t = p;
+  t.depth = fast3d_default_depth(f64);
+  if (p.pe_major && !fast3d_applies(t, f64)) return 1;
+  return t.depth;
 }
 
 void fill_params(at_ctx* c) {
@@ -274,7 +287,6 @@ void fill_params(at_ctx* c) {
       p.sl2[a][kMaxS] = 1.0 / (dx * dx);
     }
   }
-  p.depth = fast3d_default_depth(g.f64);
   p.alpha = c->prob.alpha;
   p.dt = c->prob.dt;
   p.equation = c->prob.equation;
@@ -303,6 +315,8 @@ void fill_params(at_ctx* c) {
   }
   p.counter = reinterpret_cast<int64_t*>(ws + l.off_counter);
   p.advance = 1;
+  p.pe_major = l.pe_major ? 1 : 0;
+  p.depth = default_variant(p, g.f64);
 }
 
 // Queue the kernels of one time step on `st`.
@@ -409,7 +423,7 @@ at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev,
 
 at_status at_set_state(at_ctx* c, const void* u0_dev) {
   if (!c || !u0_dev) return fail(c, AT_EINVAL, "null argument");
-  HIP_TRY(c, hipMemcpyAsync(c->sp.ubuf[0], u0_dev, c->lay.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, u0_dev, c->sp.ubuf[0], true, c->stream));
   HIP_TRY(c, launch_set_counter(c->sp.counter, 0, c->stream));
   if (c->delay.mode != AT_SYNC) HIP_TRY(c, launch_publish_all(c->sp, c->g.f64, c->g.sd, c->stream));
   c->n = 0;
@@ -461,9 +475,16 @@ at_status at_step(at_ctx* c, int64_t nsteps) {
 
 at_status at_set_tuning(at_ctx* c, int32_t depth) {
   if (!c) return fail(nullptr, AT_EINVAL, "null context");
-  if (depth == 0) depth = fast3d_default_depth(c->g.f64);
+  if (depth == 0) depth = default_variant(c->sp, c->g.f64);
   if (!fast3d_valid_variant(depth) && !chunk_variant(depth))
     return fail(c, AT_EINVAL, "schedule variant must be 1, 2, 4, 9, 10, 12, 17, 18, 20, 33, 34, 36, 40 or 48");
+  if (c->sp.pe_major) {
+    StepParams trial = c->sp;
+    trial.depth = depth;
+    if (!fast3d_applies(trial, c->g.f64))
+      return fail(c, AT_EINVAL, "schedule variant %d does not apply to this problem (32 x 32 path: the planes in "
+                  "flight must divide the PE depth %d; the space-expanded schemes take 1 and 2)", depth, c->g.b[2]);
+  }
   if (depth != c->sp.depth) drop_graph(c);
   c->sp.depth = depth;
   return AT_OK;
@@ -489,9 +510,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
   const int cand[AT_TUNE_CANDIDATES] = {1, 2, 4, 9, 10, 12, 17, 18, 20, 33, 34, 36, 40, 48};
   // the z-chunk variants are timed only for problems the 32 x 32 path does
   // not take by default and whose planes the generic sweep may split
-  StepParams deflt = c->sp;
-  deflt.depth = fast3d_default_depth(c->g.f64);
-  const bool chunks_apply = !fast3d_applies(deflt, c->g.f64) && sweep_can_chunk(c->sp);
+  const bool chunks_apply = !c->sp.pe_major && sweep_can_chunk(c->sp);
   const int keep = c->sp.depth, keep_chunk = c->graph_chunk;
   double best_ms = 1e300;
   int best = keep;
@@ -537,7 +556,7 @@ at_status at_autotune(at_ctx* c, void* scratch_dev, size_t scratch_bytes, int32_
 at_status at_get_state(at_ctx* c, void* u_dev) {
   if (!c || !u_dev) return fail(c, AT_EINVAL, "null argument");
   if (!c->state_set) return fail(c, AT_ESTATE, "no state");
-  HIP_TRY(c, hipMemcpyAsync(u_dev, c->sp.ubuf[c->n & 1], c->lay.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], u_dev, false, c->stream));
   return AT_OK;
 }
 
@@ -607,6 +626,9 @@ at_status norm_params(at_ctx* c, int32_t nmodes, const int32_t* kappa, const dou
     p->phase[m] = phase[m];
   }
   p->u = c->sp.ubuf[c->n & 1];
+  p->pe_major = c->sp.pe_major;
+  p->px = c->g.pe[0];
+  p->py = c->g.pe[1];
   p->ref = ref_dev;
   p->counter = c->sp.counter;
   int nb = static_cast<int>((c->g.npts + 255) / 256);
@@ -842,7 +864,8 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
     if (st != AT_OK) return st;
     const int64_t seg = s * every;
     const int64_t len = std::min<int64_t>(every, N - seg);
-    HIP_TRY(c, hipMemcpyAsync(levels, c->sp.ubuf[c->n & 1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
+    // the adjoint kernels take the levels in the [z][y][x] layout
+    HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels, false, c->stream));
     if (l.ring_bytes) {
       HIP_TRY(c, hipMemcpyAsync(sc + a.off_ring0, c->sp.ring, l.ring_bytes, hipMemcpyDeviceToDevice, c->stream));
       if (a.rk2)
@@ -853,11 +876,11 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       st = enqueue_step(c, c->stream);
       if (st != AT_OK) return st;
       c->n += 1;
-      HIP_TRY(c, hipMemcpyAsync(levels + l.field_bytes * j, c->sp.ubuf[c->n & 1], l.field_bytes,
-                                hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels + l.field_bytes * j, false,
+                                   c->stream));
       if (a.rk2)
-        HIP_TRY(c, hipMemcpyAsync(slevels + l.field_bytes * (j - 1), c->sp.ustar, l.field_bytes,
-                                  hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ustar, slevels + l.field_bytes * (j - 1), false,
+                                     c->stream));
     }
     for (int64_t n = seg + len - 1; n >= seg; --n) {
       AdjParams q;

@@ -162,7 +162,20 @@ struct StepParams {
                                // points per thread, or 8 + D with 2 points per thread; 16 + D:
                                // 4 points per thread, z sweep direction alternating per launch
   int sweep_down;              // this launch sweeps z downward (alternating variants)
+  int pe_major;                // u, f and u* stored PE after PE (the 32 x 32 path), see pe_major_offset
 };
+
+// Problems the 3-D path for 32 x 32 PE cross-sections takes store the
+// solution, the integrator history and the RK2 predictor PE after PE:
+// [pe][z][y][x] with the PE's own strides, so that a workgroup's z-plane is
+// one contiguous block (4 KB in FP32) instead of 32 rows of 128 B at the
+// global row pitch. Offset of global point (x, y, z) in that layout (PE edges
+// 32 in x and y, bz in z; px, py PEs along x and y):
+__host__ __device__ inline int64_t pe_major_offset(int x, int y, int z, int bz, int px, int py) {
+  const int qz = z / bz;
+  const int64_t pe = (x >> 5) + static_cast<int64_t>(px) * ((y >> 5) + static_cast<int64_t>(py) * qz);
+  return ((pe * bz + (z - qz * bz)) << 10) + ((y & 31) << 5) + (x & 31);
+}
 
 // Ring layout. The strip of face f of a PE is a stack of planes (x and y
 // faces: one per z-plane of the PE, [y][d] and [d][x] inside; z faces: one per
@@ -171,8 +184,18 @@ struct StepParams {
 //   [slot][face][plane][pe][chunk].
 // Workgroups sweep their PEs' z-planes in step, so the strips that all of them
 // publish or read at one moment form one contiguous run of memory.
+// PE-major problems (the 32 x 32 path) put the slots innermost instead:
+//   [face][plane][pe][slot][chunk],
+// so the T delayed levels a halo value combines (consecutive slots) are one
+// contiguous run rather than T runs a slot apart; face f starts at nslots x
+// face_off[f]. A ring of one slot (the adjoint ring of the synchronous arm,
+// whose forward ring has none) takes nslots = 1.
 __host__ __device__ inline int64_t ring_index(const StepParams& p, int slot, int pe, int f, int64_t plane,
                                               int64_t r) {
+  if (p.pe_major) {
+    const int64_t ns = p.nslots > 0 ? p.nslots : 1;
+    return ns * p.face_off[f] + ((plane * p.npe + pe) * ns + slot) * p.face_chunk[f] + r;
+  }
   return static_cast<int64_t>(slot) * p.npe * p.pe_block + p.face_off[f] +
          (plane * p.npe + pe) * p.face_chunk[f] + r;
 }
@@ -195,11 +218,16 @@ struct NormParams {
   const double* ref;
   double* partial;             // [nblocks][8]
   int64_t* counter;            // step n (time t = n dt)
+  int pe_major, px, py;        // u stored PE after PE (pe_major_offset); ref is always [z][y][x]
 };
 
 // Launchers (step.hip / norms.hip). Return the HIP error of the launch.
 hipError_t launch_step(const StepParams& p, bool f64, int s, hipStream_t st);
 hipError_t launch_publish_all(const StepParams& p, bool f64, int s, hipStream_t st);
+// Copy a field between the caller's [z][y][x] layout and the context's
+// (PE-major where p.pe_major is set, else a plain copy).
+hipError_t launch_field_copy(const StepParams& p, bool f64, const void* src, void* dst, bool to_internal,
+                             hipStream_t st);
 hipError_t launch_set_counter(int64_t* counter, int64_t n, hipStream_t st);
 hipError_t launch_delays(const StepParams& p, int64_t n0, int64_t count, int8_t* out,
                          hipStream_t st);
@@ -212,7 +240,13 @@ hipError_t norms_static_scratch(int device, double** ptr);
 hipError_t launch_norms(const NormParams& p, bool f64, int nblocks, double* result,
                         hipStream_t st);
 size_t step_lds_bytes(const StepParams& p, bool f64, int s);
-// 3-D sweep for 32 x 32 PE cross-sections (step3d_fast.hip)
+// 3-D sweep for 32 x 32 PE cross-sections (step3d_fast.hip). fast3d_shape:
+// the problems it takes (with some schedule variant): 3-D, 32 x 32 PE
+// cross-sections, a field below 4 GB, and the synchronous arm, the
+// time-expanded schemes with T = s + 1 or the space-expanded ones with T = 1.
+// Their fields are stored PE-major and only this path steps them.
+bool fast3d_shape(int ndim, int bx, int by, int scheme, int mode, int T, int s, int64_t field_bytes);
+// the schedule variant p.depth applies to p (a PE-major problem)
 bool fast3d_applies(const StepParams& p, bool f64);
 int fast3d_default_depth(bool f64);
 bool fast3d_valid_variant(int v);

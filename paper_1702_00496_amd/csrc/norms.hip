@@ -77,6 +77,11 @@ __global__ __launch_bounds__(256) void norms_partial_kernel(NormParams p) {
                       double(p.kap[m][2]) * p.kap[m][2];
     return p.amp[m] * exp(-p.alpha * k2 * t);
   };
+  // offset of point (x, y, z) in the field (ref is always [z][y][x])
+  auto at = [&](int x, int y, int z) -> size_t {
+    if (p.pe_major) return static_cast<size_t>(pe_major_offset(x, y, z, p.bz, p.px, p.py));
+    return (static_cast<size_t>(z) * p.ny + y) * p.nx + x;
+  };
   NormAcc acc;
   if constexpr (Table) {
     const int nm = p.nmodes, nx = p.nx, ny = p.ny, nz = p.nz;
@@ -129,8 +134,10 @@ __global__ __launch_bounds__(256) void norms_partial_kernel(NormParams p) {
 #pragma unroll
       for (int g = 0; g < kRows; ++g) {
         const unsigned row = min(rg * kRows + g, nrows - 1);
+        const unsigned rz = row / ny;
+        const int ry = static_cast<int>(row - rz * ny);
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) v[g][k] = u[static_cast<size_t>(row) * nx + min(x0 + 64 * k, nx - 1)];
+        for (int k = 0; k < kPer; ++k) v[g][k] = u[at(min(x0 + 64 * k, nx - 1), ry, static_cast<int>(rz))];
       }
 #pragma unroll
       for (int g = 0; g < kRows; ++g) {
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(256) void norms_partial_kernel(NormParams p) {
       bool inb = in_boundary_layer(x, p.bx, p.s);
       if (p.ndim >= 2) inb |= in_boundary_layer(y, p.by, p.s);
       if (p.ndim == 3) inb |= in_boundary_layer(z, p.bz, p.s);
-      acc.add(static_cast<double>(u[i]) - ref, inb);
+      acc.add(static_cast<double>(u[p.pe_major ? at(x, y, z) : i]) - ref, inb);
     }
   }
   __shared__ double red[4][kNP];

@@ -18,6 +18,8 @@
 // f^{n-1} read and f^n written (AB2), plus the face strips (1/b of the points
 // per face and level).
 
+#include <algorithm>
+
 #include "step_sweep.hpp"
 
 namespace atfd {
@@ -50,13 +52,32 @@ __global__ __launch_bounds__(kThreads) void publish_all_kernel(StepParams p) {
     if (DIM == 3 && z < S) { face[nf] = 4; q[nf++] = (static_cast<int64_t>(z) * p.by + y) * p.bx + x; }
     if (DIM == 3 && z >= p.bz - S) { face[nf] = 5; q[nf++] = (static_cast<int64_t>(z - (p.bz - S)) * p.by + y) * p.bx + x; }
     if (!nf) continue;
-    const Real v = u[(static_cast<int64_t>(z0 + z) * p.ny + y0 + y) * p.nx + x0 + x];
+    const Real v = p.pe_major ? u[pid * npts + i] : u[(static_cast<int64_t>(z0 + z) * p.ny + y0 + y) * p.nx + x0 + x];
     for (int j = 0; j < nf; ++j)
       for (int sl = 0; sl < p.nslots; ++sl) {
         const int64_t off = ring_index_q(p, sl, pid, face[j], q[j]);
         R[off] = v;
         if (SR) SR[off] = v;
       }
+  }
+}
+
+// Copy between the [z][y][x] layout and the PE-major one, four consecutive x
+// values (one quad) per thread; q counts quads in PE-major order. Word = a
+// type of four values' size (vector path) or one value (any alignment).
+template <typename Word, int WPQ>
+__global__ __launch_bounds__(kThreads) void field_copy_kernel(const Word* src, Word* dst, uint32_t nquads,
+                                                              int nx, int ny, int bz, int px, int py,
+                                                              int to_pe_major) {
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nquads; q += gridDim.x * blockDim.x) {
+    // PE-major quad q: PE edges 32 x 32 x bz, 8 quads per row
+    const uint32_t xq = q & 7, ly = (q >> 3) & 31, r = q >> 8;
+    const uint32_t pe = r / bz, lz = r - pe * bz;
+    const uint32_t qx = pe % px, qy = (pe / px) % py, qz = pe / (px * py);
+    const uint32_t g = ((qz * bz + lz) * ny + qy * 32 + ly) * (nx / 4) + qx * 8 + xq;
+    const uint32_t si = to_pe_major ? g : q, di = to_pe_major ? q : g;
+#pragma unroll
+    for (int w = 0; w < WPQ; ++w) dst[static_cast<size_t>(di) * WPQ + w] = src[static_cast<size_t>(si) * WPQ + w];
   }
 }
 
@@ -280,9 +301,37 @@ size_t lds_dim(const StepParams& p, int s) {
 }  // namespace
 
 hipError_t launch_step(const StepParams& p, bool f64, int s, hipStream_t st) {
-  const int64_t field_bytes = static_cast<int64_t>(p.nx) * p.ny * p.nz * (f64 ? 8 : 4);
-  if (fast3d_applies(p, f64) && field_bytes < (int64_t(1) << 32)) return launch_step_fast3d(p, f64, s, st);
+  // PE-major fields are stepped by the 32 x 32 path only (the host accepts
+  // only schedule variants that apply)
+  if (p.pe_major) return fast3d_applies(p, f64) ? launch_step_fast3d(p, f64, s, st) : hipErrorInvalidValue;
   return f64 ? dispatch_dim<double>(p, s, st, false) : dispatch_dim<float>(p, s, st, false);
+}
+
+hipError_t launch_field_copy(const StepParams& p, bool f64, const void* src, void* dst, bool to_internal,
+                             hipStream_t st) {
+  const size_t bytes = static_cast<size_t>(p.nx) * p.ny * p.nz * (f64 ? 8 : 4);
+  if (!p.pe_major) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+  const uint32_t nquads = static_cast<uint32_t>(static_cast<size_t>(p.nx) * p.ny * p.nz / 4);
+  const int blocks = static_cast<int>(std::min<uint32_t>((nquads + kThreads - 1) / kThreads, 8192u));
+  const bool vec = (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 == 0;
+  const int tp = to_internal ? 1 : 0;
+  if (vec && f64)
+    hipLaunchKernelGGL((field_copy_kernel<uint4, 2>), dim3(blocks), dim3(kThreads), 0, st,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), nquads, p.nx, p.ny, p.bz, p.px,
+                       p.py, tp);
+  else if (vec)
+    hipLaunchKernelGGL((field_copy_kernel<uint4, 1>), dim3(blocks), dim3(kThreads), 0, st,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), nquads, p.nx, p.ny, p.bz, p.px,
+                       p.py, tp);
+  else if (f64)
+    hipLaunchKernelGGL((field_copy_kernel<uint64_t, 4>), dim3(blocks), dim3(kThreads), 0, st,
+                       static_cast<const uint64_t*>(src), static_cast<uint64_t*>(dst), nquads, p.nx, p.ny, p.bz,
+                       p.px, p.py, tp);
+  else
+    hipLaunchKernelGGL((field_copy_kernel<uint32_t, 4>), dim3(blocks), dim3(kThreads), 0, st,
+                       static_cast<const uint32_t*>(src), static_cast<uint32_t*>(dst), nquads, p.nx, p.ny, p.bz,
+                       p.px, p.py, tp);
+  return hipGetLastError();
 }
 
 hipError_t launch_publish_all(const StepParams& p, bool f64, int s, hipStream_t st) {

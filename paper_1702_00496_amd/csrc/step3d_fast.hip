@@ -11,18 +11,24 @@ bool fast3d_valid_variant(int v) {
   return v == 1 || v == 2 || v == 4 || v == 9 || v == 10 || v == 12 || v == 17 || v == 18 || v == 20;
 }
 
-bool fast3d_applies(const StepParams& p, bool f64) {
-  (void)f64;
+bool fast3d_shape(int ndim, int bx, int by, int scheme, int mode, int T, int s, int64_t field_bytes) {
   // the non-uniform-delay scheme runs the generic sweep in every mode, so
   // that its zero-delay and synchronous arms share one kernel
-  if (p.scheme == AT_SCHEME_NONUNIFORM_212) return false;
-  // time-expanded AT (T = s + 1), the space-expanded schemes (schedule
-  // variants 1 and 2) or the synchronous arm; other T take the generic kernel
-  const bool space = p.mode != AT_SYNC && (p.scheme == AT_SCHEME_SPACE_212 || p.scheme == AT_SCHEME_SPACE_222);
-  const bool levels_ok = p.mode == AT_SYNC || (p.scheme == AT_SCHEME_TIME && p.T == p.s + 1) ||
-                         (space && p.T == 1 && (p.depth == 1 || p.depth == 2));
-  return p.ndim == 3 && p.bx == fast3d::kB && p.by == fast3d::kB && levels_ok &&
-         fast3d_valid_variant(p.depth) && p.bz % (p.depth & 7) == 0;
+  if (scheme == AT_SCHEME_NONUNIFORM_212) return false;
+  // the synchronous arm, time-expanded AT with T = s + 1 or the
+  // space-expanded schemes (one level); other T take the generic sweep
+  const bool space = mode != AT_SYNC && (scheme == AT_SCHEME_SPACE_212 || scheme == AT_SCHEME_SPACE_222);
+  const bool levels_ok = mode == AT_SYNC || (scheme == AT_SCHEME_TIME && T == s + 1) || (space && T == 1);
+  // 32-bit element offsets of the field
+  return ndim == 3 && bx == fast3d::kB && by == fast3d::kB && levels_ok && field_bytes < (int64_t(1) << 32);
+}
+
+bool fast3d_applies(const StepParams& p, bool f64) {
+  (void)f64;
+  if (!p.pe_major || !fast3d_valid_variant(p.depth) || p.bz % (p.depth & 7) != 0) return false;
+  // the space-expanded schemes have variants 1 and 2
+  const bool space = p.mode != AT_SYNC && p.scheme != AT_SCHEME_TIME;
+  return !space || p.depth == 1 || p.depth == 2;
 }
 
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st) {

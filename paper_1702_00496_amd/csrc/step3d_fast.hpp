@@ -4,7 +4,9 @@
 // Same scheme as the generic sweep in step.hip, organised for HBM bandwidth:
 //  - one PE per workgroup; each thread owns V consecutive x points of one row
 //    (V = 4: 256 threads, V = 2: 512 threads) and streams the PE's z-planes,
-//    so every bulk global access is an 8- or 16-byte vector access;
+//    so every bulk global access is an 8- or 16-byte vector access; the
+//    fields are stored PE-major, so a plane is one contiguous block (a
+//    streaming copy's access pattern, not 32 rows at the global pitch);
 //  - the z neighbours of a thread's points live in a register queue of 2s+1
 //    vectors; x/y neighbours come from a double-buffered LDS plane (row
 //    stride 40 with the x halo at columns 4-s..3 and 36..35+s, so vectors stay
@@ -196,8 +198,6 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   // the previous one finished last
   const int wg = REV ? static_cast<int>(gridDim.x) - 1 - static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x);
   const int pid = pe_of_workgroup(wg, gridDim.x);
-  const int pex = pid % p.px, pey = (pid / p.px) % p.py, pez = pid / (p.px * p.py);
-  const int x0 = pex * kB, y0 = pey * kB, z0 = pez * p.bz;
   const int bz = p.bz;
 
   if (tid < 6) {
@@ -225,14 +225,19 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
 
   const Real* centre = static_cast<const Real*>(KIND == kRk2 ? p.ustar : p.ubuf[n & 1]);
   const Real* ring = static_cast<const Real*>(KIND == kRk2 ? p.sring : p.ring);
-  // field offsets fit 32 bits (the host checks the field size)
-  const uint32_t zstride = static_cast<uint32_t>(p.nx) * p.ny;
-  const uint32_t col = (static_cast<uint32_t>(z0) * p.ny + (y0 + y)) * p.nx + (x0 + x);
-  const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
+  // The field is PE-major ([pe][z][y][x], 32 x 32 x bz values per PE): each
+  // plane of the PE is one contiguous block. Offsets fit 32 bits (the host
+  // checks the field size).
+  const uint32_t pe_size = static_cast<uint32_t>(kB * kB) * bz;
+  constexpr uint32_t zstride = kB * kB;
+  const uint32_t col = static_cast<uint32_t>(pid) * pe_size + y * kB + x;
+  // ring_index of PE-major problems: [face][plane][pe][slot][chunk]
+  const int64_t nsl = p.nslots > 0 ? p.nslots : 1;
 
   // A halo source: one pointer per level to the element of plane 0, a
   // per-plane stride and the level weights. AT: the neighbour's strip in the
-  // ring slots of the delayed levels; SYNC: the neighbour's u^n.
+  // ring slots of the delayed levels; SYNC: the neighbour's u^n (sync_g: the
+  // offset of the value at the PE's plane 0 in the neighbour's block).
   struct Src {
     const Real* lvl[TT];
     double w[TT];
@@ -252,14 +257,14 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
     const int64_t foff = pf == 0 ? p.face_off[0] : pf == 1 ? p.face_off[1] : pf == 2 ? p.face_off[2]
                        : pf == 3 ? p.face_off[3] : pf == 4 ? p.face_off[4] : p.face_off[5];
     const int64_t chunk = pf < 4 ? p.face_chunk[0] : p.face_chunk[4];
-    const Real* strip = ring + foff + static_cast<int64_t>(s_nbr[f]) * chunk + q0;
+    const Real* strip = ring + nsl * foff + static_cast<int64_t>(s_nbr[f]) * nsl * chunk + q0;
 #pragma unroll
     for (int m = 0; m < TT; ++m) {
-      r.lvl[m] = strip + s_slot[f * kMaxT + m] * slot_stride;
+      r.lvl[m] = strip + s_slot[f * kMaxT + m] * chunk;
       r.w[m] = s_w[f * kMaxT + m];
     }
-    // the next plane of the same strip is npe chunks further (ring_index)
-    r.stride = static_cast<int64_t>(p.npe) * chunk;
+    // the next plane of the same strip is npe groups of nslots chunks further
+    r.stride = static_cast<int64_t>(p.npe) * nsl * chunk;
     (void)qstride;
     return r;
   };
@@ -286,13 +291,14 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   if (hid < NHX) {
     const int side = hid / (S * QPR), r = hid % (S * QPR);
     if (kSync) {
+      // column xl of this PE's frame is column lx of the x neighbour
       const int d = r / QPR, yq = 4 * (r % QPR);
       const int xl = side ? kB + d : d - S;
-      const int gx = (x0 + xl + p.nx) % p.nx;
+      const int lx = side ? d : kB - S + d;
 #pragma unroll
       for (int i = 0; i < 4; ++i) hp[i] = (yq + i + S) * kRS + kHO + xl;
-      estride = p.nx;
-      hs = make_src(side, 0, 0, (static_cast<int64_t>(z0) * p.ny + y0 + yq) * p.nx + gx);
+      estride = kB;
+      hs = make_src(side, 0, 0, static_cast<int64_t>(s_nbr[side]) * pe_size + yq * kB + lx);
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -306,12 +312,12 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
     const int h = hid - NHX;
     const int side = h / (S * QPR), r = h % (S * QPR), d = r / QPR, xq = 4 * (r % QPR);
     const int yl = side ? kB + d : d - S;
-    const int gy = (y0 + yl + p.ny) % p.ny;
+    const int ly = side ? d : kB - S + d;          // row of the y neighbour
 #pragma unroll
     for (int i = 0; i < 4; ++i) hp[i] = (yl + S) * kRS + kHO + xq + i;
     estride = 1;
     hs = make_src(2 + side, static_cast<int64_t>(d) * kB + xq, static_cast<int64_t>(S) * kB,
-                  (static_cast<int64_t>(z0) * p.ny + gy) * p.nx + x0 + xq);
+                  static_cast<int64_t>(s_nbr[2 + side]) * pe_size + ly * kB + xq);
   }
   // raw read of level m of this thread's halo item at plane zz
   auto halo_raw = [&](int zz, int m) -> Q {
@@ -340,11 +346,16 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   Real* pub = static_cast<Real*>(KIND == kRk1 ? p.sring : p.ring);
   const int pslot = static_cast<int>((KIND == kRk1 ? n : n + 1) % (p.nslots > 0 ? p.nslots : 1));
   // this PE's strips in the ring slot of the new level (ring_index): plane
-  // z of an x or y face at face_off + (z npe + pid) chunk, depth d of a z
-  // face at face_off + (d npe + pid) chunk
-  Real* pslotp = kSync ? nullptr : pub + static_cast<int64_t>(pslot) * p.npe * p.pe_block;
+  // z of an x or y face at nslots face_off + ((z npe + pid) nslots + slot)
+  // chunk, depth d of a z face likewise with plane d
   const int64_t cxy = p.face_chunk[0];             // s * 32 (x and y faces)
   const int64_t cz = p.face_chunk[4];              // 32 * 32 (z faces)
+  auto pub_xy = [&](int64_t fo, int zz) -> Real* {
+    return pub + nsl * fo + ((static_cast<int64_t>(zz) * p.npe + pid) * nsl + pslot) * cxy;
+  };
+  auto pub_z = [&](int64_t fo, int d) -> Real* {
+    return pub + nsl * fo + ((static_cast<int64_t>(d) * p.npe + pid) * nsl + pslot) * cz;
+  };
 
   // space-expanded schemes: low-face taps minus the CD2 taps, o = -S..S
   Real dl1[3][2 * S + 1], dl2[3][2 * S + 1];
@@ -382,12 +393,12 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
     // bz + e holds depth e of the high strip or depth S-1-e of the low one.
     VR zst[S];
     {
-      const int gzl = (z0 - S + p.nz) % p.nz, gzh = (z0 + bz) % p.nz;
+      // synchronous arm: the last S planes of the low z neighbour, the first
+      // S of the high one (bz >= 2s, checked at creation)
       const int64_t q0 = static_cast<int64_t>(y) * kB + x;
       const Src lo = make_src(4, q0, static_cast<int64_t>(kB) * kB,
-                              (static_cast<int64_t>(gzl) * p.ny + y0 + y) * p.nx + x0 + x);
-      const Src hi = make_src(5, q0, static_cast<int64_t>(kB) * kB,
-                              (static_cast<int64_t>(gzh) * p.ny + y0 + y) * p.nx + x0 + x);
+                              static_cast<int64_t>(s_nbr[4]) * pe_size + (bz - S) * zstride + q0);
+      const Src hi = make_src(5, q0, static_cast<int64_t>(kB) * kB, static_cast<int64_t>(s_nbr[5]) * pe_size + q0);
 #pragma unroll
       for (int d = 0; d < S; ++d) {
         VR rl[TT], rh[TT];
@@ -546,8 +557,7 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
         if (!kSync) {
           // publish the new edge values into the ring slot of their level;
           // x faces: plane [y][d], one run of s values per row
-          const int64_t xyplane = (static_cast<int64_t>(z) * p.npe + pid) * cxy;
-          const int64_t xrow = xyplane + static_cast<int64_t>(y) * S;
+          const int xrow = y * S;
           if constexpr (V == 4) {
             // the first quad of a row holds the low-face depths, the last one
             // the high-face depths: one store of s values for both faces
@@ -559,28 +569,24 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
               // (select between the two uniform offsets: an index that varies
               // per lane would turn the kernel-argument read into a memory load)
               const int64_t fo = hi ? p.face_off[1] : p.face_off[0];
-              st_run<Real, S>(pslotp + fo + xrow, w);
+              st_run<Real, S>(pub_xy(fo, z) + xrow, w);
             }
           } else {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              if (x + e < S) pslotp[p.face_off[0] + xrow + x + e] = un.v[e];
-              if (x + e >= kB - S) pslotp[p.face_off[1] + xrow + x + e - (kB - S)] = un.v[e];
+              if (x + e < S) pub_xy(p.face_off[0], z)[xrow + x + e] = un.v[e];
+              if (x + e >= kB - S) pub_xy(p.face_off[1], z)[xrow + x + e - (kB - S)] = un.v[e];
             }
           }
           // y faces: plane [d][x]; rows 0..s-1 and kB-s..kB-1, one store
           if (y < S || y >= kB - S) {
             const int64_t fo = y < S ? p.face_off[2] : p.face_off[3];
             const int d = y < S ? y : y - (kB - S);
-            stv<Real, V>(pslotp + fo + xyplane, static_cast<uint32_t>(d * kB + x), un);
+            stv<Real, V>(pub_xy(fo, z), static_cast<uint32_t>(d * kB + x), un);
           }
           // z faces: depth plane [y][x]
-          if (z < S)
-            stv<Real, V>(pslotp + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * cz,
-                         static_cast<uint32_t>(y * kB + x), un);
-          if (z >= bz - S)
-            stv<Real, V>(pslotp + p.face_off[5] + (static_cast<int64_t>(z - (bz - S)) * p.npe + pid) * cz,
-                         static_cast<uint32_t>(y * kB + x), un);
+          if (z < S) stv<Real, V>(pub_z(p.face_off[4], z), static_cast<uint32_t>(y * kB + x), un);
+          if (z >= bz - S) stv<Real, V>(pub_z(p.face_off[5], z - (bz - S)), static_cast<uint32_t>(y * kB + x), un);
         }
 #pragma unroll
         for (int i = 0; i < 2 * S; ++i) qz[i] = qz[i + 1];

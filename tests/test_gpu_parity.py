@@ -533,3 +533,51 @@ def test_generic_sweep_chunk_variants_bit_identical_and_autotuned(precision):
     assert torch.equal(s.state(), before) and s.n_step == 3
     s.step(case["steps"] - 3)
     assert torch.equal(s.state(), want)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_pe_major_fields_round_trip_and_variant_checks(precision):
+    """Problems of the 32 x 32 path keep u PE-major inside the library: a
+    [z][y][x] field set and read back comes out bit for bit through the
+    16-byte vector copy and through the element-wise copy that unaligned
+    caller buffers take; the state after steps does not depend on the
+    alignment of the buffers; a schedule variant whose planes in flight do
+    not divide the PE depth is refused (AT_EINVAL), and where the default's
+    do not, the default is variant 1. Then the odd-depth problem matches the
+    oracle within the bar."""
+    import ctypes
+    from paper_1702_00496_amd import ATError, _lib
+    case = dict(ndim=3, n=(64, 32, 15), pe=(2, 1, 3), order=4, integrator="ab2", c=(1.0, -1.0, 0.5), L=4,
+                steps=7)
+    case["dt"] = _dt(case, 0.02)
+    dtype = torch.float32 if precision == "f32" else torch.float64
+    u0 = torch.from_numpy(initial_field(case)).to(dtype)
+    s = solver_for(case, precision)
+    assert s.tuning() == 1                      # bz = 5: two planes in flight do not divide it
+    for v in (2, 4, 10, 18):
+        with pytest.raises(ATError) as ei:
+            s.set_tuning(v)
+        assert ei.value.status == _lib.AT_EINVAL
+    assert s.tuning() == 1
+    s.set_tuning(17)                            # one plane in flight, alternating
+    # unaligned caller buffers: one element into a larger allocation
+    big = torch.empty(u0.numel() + 1, dtype=dtype, device="cuda")
+    big[1:].copy_(u0.reshape(-1).cuda())
+    raw = s._lib.at_set_state(s._ctx, ctypes.c_void_p(big[1:].data_ptr()))
+    assert raw == _lib.AT_OK
+    back = torch.empty(u0.numel() + 1, dtype=dtype, device="cuda")
+    assert s._lib.at_get_state(s._ctx, ctypes.c_void_p(back[1:].data_ptr())) == _lib.AT_OK
+    torch.cuda.synchronize()
+    assert torch.equal(back[1:].cpu().reshape(u0.shape), u0)
+    s.step(case["steps"])
+    assert s._lib.at_get_state(s._ctx, ctypes.c_void_p(back[1:].data_ptr())) == _lib.AT_OK
+    torch.cuda.synchronize()
+    t = solver_for(case, precision)             # aligned buffers, default variant
+    t.set_state(u0)
+    assert torch.equal(t.state().cpu(), u0)
+    t.step(case["steps"])
+    want = t.state()
+    assert torch.equal(back[1:].reshape(want.shape), want)
+    o = oracle_for(case, u0.double().numpy())
+    o.run(case["steps"])
+    check_field(want.double().cpu(), o, TOL[precision], prob=problem_for(case), label="bz=5 PE-major")
