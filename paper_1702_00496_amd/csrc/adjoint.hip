@@ -29,6 +29,7 @@
 #include "adjoint.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace atfd {
 namespace {
@@ -178,7 +179,7 @@ __device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
 // collects the transposed taps of the consumer PE across F, weighted by the
 // consumer's level weights, into the adjoint ring slots of levels n-k-m.
 template <typename Real>
-__device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
+__device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT]) {
   const StepParams& p = q.sp;
   const int S = p.s;
   Real* aring = static_cast<Real*>(q.aring);
@@ -208,9 +209,8 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp) {
     g += valid ? t : 0.0;
   }
   const int k = adj_delay(p, cons, cf, q.n);
-  double w[kMaxT];
+  const double* w = wt[k];
   const int T = adj_levels(p);
-  level_weights(k, T, w);
   int lsF[3] = {l[0], l[1], l[2]};   // the strip value's PE coordinates
   lsF[a] = (F & 1) ? b - S + d : d;
   Real* dst[kMaxT];
@@ -253,7 +253,7 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int slot, in
 // combination of the stored levels (the synchronous scheme: level n).
 // hbuf[pe * pe_block + (per-PE offset of face f) + e].
 template <typename Real>
-__device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp) {
+__device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, const double (*wt)[kMaxT]) {
   const StepParams& p = q.sp;
   const int S = p.s;
   const int T = adj_levels(p);
@@ -266,8 +266,7 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp) {
   const int sq[3] = {src % p.px, (src / p.px) % p.py, src / (p.px * p.py)};
   const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
   const int k = adj_delay(p, pe, f, q.n);
-  double w[kMaxT];
-  level_weights(k, T, w);
+  const double* w = wt[k];
   if (p.mode == AT_SYNC) {   // level n, always stored
     hb[t] = static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
     return;
@@ -291,11 +290,20 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp) {
 // adjoint-ring scatter (producer view) share the decode of t.
 template <typename Real>
 __global__ __launch_bounds__(kAdjThreads) void adj_strip_kernel(AdjParams q) {
+  // the level weights c_m(k) of every delay k < L (the delays are clamped
+  // below L), once per workgroup
+  __shared__ double s_wt[kMaxL][kMaxT];
+  if (threadIdx.x < kMaxL) {
+    double w[kMaxT] = {0.0, 0.0, 0.0, 0.0};
+    level_weights(static_cast<int>(threadIdx.x), adj_levels(q.sp), w);
+    for (int m = 0; m < kMaxT; ++m) s_wt[threadIdx.x][m] = w[m];
+  }
+  __syncthreads();
   const int total = q.sp.npe * static_cast<int>(q.sp.pe_block);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
     const StripPt sp = strip_point(q, t);
-    halo_elem<Real>(q, t, sp);
-    scatter_elem<Real>(q, sp);
+    halo_elem<Real>(q, t, sp, s_wt);
+    scatter_elem<Real>(q, sp, s_wt);
   }
 }
 
@@ -462,43 +470,67 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   // the per-point adjoint (x, y, z PE coordinates; global index g); cget(a, o)
   // / yget(a, o) give c and (y0, y1) at offset o along axis a
   double da = 0.0;
+  // dr: the adjoint-ring entries of the strips the point lies in, one per
+  // axis (dr[a], where din[a]), loaded (and cleared) by the caller; nullptr:
+  // loaded and cleared here
   auto point = [&](int x, int y, int z, int64_t g, double cj, double y0j, double y1j, double x0j, double x1j,
-                   auto cget, auto yget) {
+                   auto cget, auto yget, const Real* dr, const bool* din) {
     const double mu = m0 * y0j + m1 * y1j;
     double acc = q.b0 * x0j + q.b1 * x1j;
     double lap = 0.0, grad = 0.0, sumk = 0.0;
     const int l[3] = {x, y, z};
-    // one axis at a time (not unrolled over axes: bounds the values in flight)
-#pragma unroll 1
-    for (int a = 0; a < DIM; ++a) {
+    // the taps of axis a: from the kernel arguments where a is a compile-time
+    // constant (scalar registers), else from LDS (uniform addresses)
+    auto axis = [&](int a, auto args) {
+      constexpr bool kArgs = decltype(args)::value;
       const int b = a == 0 ? bx : a == 1 ? by : bz;
+      auto c1t = [&](int o) -> double { return kArgs ? p.c1[a][o + S] : s_c1[a][o + S]; };
+      auto c2t = [&](int o) -> double { return kArgs ? p.c2[a][o + S] : s_c2[a][o + S]; };
+      auto tk = [&](int o, double ci) -> double {
+        if (!kArgs) return tapk(a, o, ci);
+        return burg ? p.alpha * p.c2[a][o + S] - ci * p.c1[a][o + S] : p.kad[a][o + S];
+      };
 #pragma unroll
       for (int o = -S; o <= S; ++o) {
         if (o == 0) continue;
-        sumk += tapk(a, o, cj);
+        sumk += tk(o, cj);
         // transposed interior tap from i = j - o (zero mu outside the PE)
         double yi0, yi1;
         yget(a, -o, yi0, yi1);
         const double mi = m0 * yi0 + m1 * yi1;
         const double ci = burg ? cget(a, -o) : 0.0;
         const int ia = l[a] - o;
-        acc += (ia >= 0 && ia < b) ? tapk(a, o, ci) * mi : 0.0;
+        acc += (ia >= 0 && ia < b) ? tk(o, ci) * mi : 0.0;
         // forward stencil of the stage field at j
         const double v = cget(a, o) - cj;
-        lap += s_c2[a][o + S] * v;
-        grad += s_c1[a][o + S] * v;
+        lap += c2t(o) * v;
+        grad += c1t(o) * v;
       }
+    };
+    if constexpr (DIM <= 2) {
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) axis(a, std::true_type{});
+    } else {
+      // one axis at a time (not unrolled over axes: bounds the values in flight)
+#pragma unroll 1
+      for (int a = 0; a < DIM; ++a) axis(a, std::false_type{});
     }
     // drain the adjoint-ring entries of the strips j lies in
+    if (dr) {
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const int b = a == 0 ? bx : a == 1 ? by : bz;
+      for (int a = 0; a < DIM; ++a)
+        if (din[a]) acc += static_cast<double>(dr[a]);
+    } else {
 #pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        if (side ? l[a] >= b - S : l[a] < S) {
-          Real* src = aring + ring_at_pt(p, slot_n, pe, 2 * a + side, l, S);
-          acc += static_cast<double>(*src);
-          *src = Real(0);
+      for (int a = 0; a < DIM; ++a) {
+        const int b = a == 0 ? bx : a == 1 ? by : bz;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (side ? l[a] >= b - S : l[a] < S) {
+            Real* src = aring + ring_at_pt(p, slot_n, pe, 2 * a + side, l, S);
+            acc += static_cast<double>(*src);
+            *src = Real(0);
+          }
         }
       }
     }
@@ -508,6 +540,32 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   };
 
   if constexpr (DIM <= 2) {
+    // A thread's first kPre points: their base terms and adjoint-ring entries
+    // are loaded with the plane, so that every global load of the workgroup
+    // is in flight before the barrier (one memory round trip, not three).
+    constexpr int kPre = sizeof(Real) == 4 ? 4 : 3;
+    Real pre_x0[kPre], pre_x1[kPre], pre_r[kPre][2];
+    bool pre_in[kPre][2];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = tid + k * nt;
+      pre_in[k][0] = pre_in[k][1] = false;
+      pre_x0[k] = pre_x1[k] = pre_r[k][0] = pre_r[k][1] = Real(0);
+      if (i < bx * by) {
+        const int y = i / bx, x = i - y * bx;
+        const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+        pre_x0[k] = X0[g];
+        pre_x1[k] = X1[g];
+        const int l[3] = {x, y, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const int b = a == 0 ? bx : by;
+          const bool lo = l[a] < S, hi = l[a] >= b - S;
+          pre_in[k][a] = lo || hi;
+          if (lo || hi) pre_r[k][a] = aring[ring_at_pt(p, slot_n, pe, 2 * a + (hi ? 1 : 0), l, S)];
+        }
+      }
+    }
     // the plane: own values, then the x (and y) frame of c
     for (int i = tid; i < bx * by; i += nt) {
       const int y = i / bx, x = i - y * bx;
@@ -533,7 +591,7 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
       }
     }
     __syncthreads();
-    for (int i = tid; i < bx * by; i += nt) {
+    auto plane_point = [&](int i, const Real* pv, const bool* din) {
       const int y = i / bx, x = i - y * bx;
       const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
       auto cget = [&](int a, int o) -> double { return static_cast<double>(Cl[at + (a == 0 ? o : o * W)]); };
@@ -544,8 +602,28 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
       };
       const int64_t g = gindex(p, x0 + x, y0 + y, 0);
       point(x, y, 0, g, static_cast<double>(Cl[at]), static_cast<double>(Y0l[at]), static_cast<double>(Y1l[at]),
-            static_cast<double>(X0[g]), static_cast<double>(X1[g]), cget, yget);
+            static_cast<double>(pv ? pv[0] : X0[g]), static_cast<double>(pv ? pv[1] : X1[g]), cget, yget,
+            pv ? pv + 2 : static_cast<const Real*>(nullptr), din);
+    };
+    // the prefetched points (their ring entries are cleared first: point()
+    // adds the loaded values), then any further ones
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = tid + k * nt;
+      if (i < bx * by) {
+        const int y = i / bx, x = i - y * bx;
+        const int l[3] = {x, y, 0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const int b = a == 0 ? bx : by;
+          if (pre_in[k][a]) aring[ring_at_pt(p, slot_n, pe, 2 * a + (l[a] >= b - S ? 1 : 0), l, S)] = Real(0);
+        }
+        const Real pv[4] = {pre_x0[k], pre_x1[k], pre_r[k][0], pre_r[k][1]};
+        plane_point(i, pv, pre_in[k]);
+      }
     }
+    for (int i = tid + kPre * nt; i < bx * by; i += nt)
+      plane_point(i, static_cast<const Real*>(nullptr), static_cast<const bool*>(nullptr));
   } else {
     // one column per thread (the host launches bx * by threads)
     const int x = tid % bx, y = tid / bx;
@@ -641,7 +719,8 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
         }
       };
       point(x, y, z, col + z * zs, static_cast<double>(cq[S]), static_cast<double>(yq0[S]),
-            static_cast<double>(yq1[S]), static_cast<double>(xc0), static_cast<double>(xc1), cget, yget);
+            static_cast<double>(yq1[S]), static_cast<double>(xc0), static_cast<double>(xc1), cget, yget,
+            static_cast<const Real*>(nullptr), static_cast<const bool*>(nullptr));
 #pragma unroll
       for (int i = 0; i < 2 * S; ++i) {
         cq[i] = cq[i + 1];

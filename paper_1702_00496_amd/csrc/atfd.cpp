@@ -319,9 +319,9 @@ void fill_params(at_ctx* c) {
   p.depth = default_variant(p, g.f64);
 }
 
-// Queue the kernels of one time step on `st`.
-at_status enqueue_step(at_ctx* c, hipStream_t st) {
-  StepParams p = c->sp;
+// Queue the kernels of one time step on `st`, with the context's parameters
+// or with `p` (the same problem, other solution buffers).
+at_status enqueue_step_p(at_ctx* c, StepParams p, hipStream_t st) {
   // alternating schedule variants: every launch sweeps z the other way from
   // the one before it (the direction is a schedule choice only)
   const bool alt = (p.depth & 16) != 0;
@@ -341,6 +341,8 @@ at_status enqueue_step(at_ctx* c, hipStream_t st) {
   }
   return AT_OK;
 }
+
+at_status enqueue_step(at_ctx* c, hipStream_t st) { return enqueue_step_p(c, c->sp, st); }
 
 // Teardown calls below: a failure to release leaves nothing to recover, so
 // their status is deliberately discarded.
@@ -873,14 +875,29 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
                                   c->stream));
     }
     for (int64_t j = 1; j <= len; ++j) {
-      st = enqueue_step(c, c->stream);
-      if (st != AT_OK) return st;
-      c->n += 1;
-      HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels + l.field_bytes * j, false,
-                                   c->stream));
-      if (a.rk2)
-        HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ustar, slevels + l.field_bytes * (j - 1), false,
+      if (c->sp.pe_major) {
+        // the 32 x 32 path keeps its fields PE-major: step, then copy the
+        // levels out in the [z][y][x] layout the adjoint kernels read
+        st = enqueue_step(c, c->stream);
+        if (st != AT_OK) return st;
+        c->n += 1;
+        HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels + l.field_bytes * j, false,
                                      c->stream));
+        if (a.rk2)
+          HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ustar, slevels + l.field_bytes * (j - 1), false,
+                                       c->stream));
+      } else {
+        // the step reads level seg+j-1 from the segment's levels and writes
+        // level seg+j (and the RK2 predictor) straight into them: no copies
+        // (the generic sweep takes two solution buffers as well as one)
+        StepParams p = c->sp;
+        p.ubuf[c->n & 1] = levels + l.field_bytes * (j - 1);
+        p.ubuf[(c->n + 1) & 1] = levels + l.field_bytes * j;
+        if (a.rk2) p.ustar = slevels + l.field_bytes * (j - 1);
+        st = enqueue_step_p(c, p, c->stream);
+        if (st != AT_OK) return st;
+        c->n += 1;
+      }
     }
     for (int64_t n = seg + len - 1; n >= seg; --n) {
       AdjParams q;
