@@ -3,9 +3,16 @@ gradients (reverse-mode autograd of the FP64 forward steps), and the full-size
 gradient checks against central finite differences of the GPU forward (the
 2-D advection-diffusion workload and the 512^3 Burgers workload).
 
-Tolerances: FP64 relative L2 <= 1e-10 for dJ/du0 and relative 1e-10 for
-dJ/dalpha (both sides are exact transposes up to rounding); FP32 bulk 1e-4
-against the FP64 oracle; finite differences (FP32, eps = 1e-3) 1e-3 relative.
+Tolerances. FP64: relative L2 (and the element-wise measures) <= 1e-12 for
+dJ/du0 and relative 1e-12 for dJ/dalpha, the forward's FP64 bar: both sides
+are exact transposes of the same discrete map, evaluated in different orders,
+so they differ by rounding only (measured: <= 1.8e-15 and <= 7.8e-14). FP32
+bulk against the FP64 oracle: dJ/du0 <= 1e-5, the forward's FP32 bar (the
+adjoint fields and the stored forward levels are rounded to FP32 every step;
+measured <= 2.2e-7); dJ/dalpha 1e-4, a sum over all points and steps of mu
+times the Laplacian of FP32-rounded levels, which cancels to a value small
+against its terms (measured <= 2.9e-5, 1-D Burgers RK2). Finite differences
+(FP32 forward, eps = 1e-3): 1e-3 relative.
 """
 import math
 import sys
@@ -87,12 +94,13 @@ def test_adjoint_matches_oracle_gradients(name, precision):
     seed = _seed(case)
     gu_o, ga_o = _oracle_grads(case, u0, seed)
     s, gu, ga = _gpu_grads(case, u0, seed, precision)
-    tol = 1e-10 if precision == "f64" else 1e-4
+    tol = 1e-12 if precision == "f64" else 1e-5
     err = rel_l2(gu, gu_o)
     _say(f"[adj]   du0 errors {field_errors(gu, gu_o, oracle_for(case, u0).prob)}   "
          f"dalpha {ga:.9e} vs {ga_o:.9e} (rel {abs(ga - ga_o) / abs(ga_o):.3e})")
-    assert err <= tol
-    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3)
+    errs = field_errors(gu, gu_o, oracle_for(case, u0).prob)
+    assert err <= tol and errs["max"] <= tol and errs["ib"] <= tol, errs
+    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-4)
     # the context ends at step N with the forward field of a plain run
     assert s.n_step == case["steps"]
     ref = solver_for(case, precision)
@@ -140,8 +148,8 @@ def test_autograd_function_matches_oracle():
     J.backward()
     seed = (uN - target).detach().cpu().numpy()
     gu_o, ga_o = _oracle_grads(case, initial_field(case), seed)
-    assert rel_l2(u0.grad.cpu(), gu_o) <= 1e-10
-    assert float(alpha.grad) == pytest.approx(ga_o, rel=1e-10)
+    assert rel_l2(u0.grad.cpu(), gu_o) <= 1e-12
+    assert float(alpha.grad) == pytest.approx(ga_o, rel=1e-12)
 
 
 def test_adjoint_full_2d_workload_against_finite_differences():
@@ -285,8 +293,8 @@ def test_adjoint_random_configuration_matches_oracle_gradients(seed):
     sd = _seed(case)
     gu_o, ga_o = _oracle_grads(case, u0, sd)
     s, gu, ga = _gpu_grads(case, u0, sd, precision)
-    tol = 1e-10 if precision == "f64" else 1e-4
+    tol = 1e-12 if precision == "f64" else 1e-5
     _say(f"[adj]   du0 errors {field_errors(gu, gu_o, oracle_for(case, u0).prob)}   "
          f"dalpha rel {abs(ga - ga_o) / max(abs(ga_o), 1e-300):.3e}")
     assert rel_l2(gu, gu_o) <= tol, (case, precision, rel_l2(gu, gu_o))
-    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-3), (case, precision, ga, ga_o)
+    assert ga == pytest.approx(ga_o, rel=tol if precision == "f64" else 1e-4), (case, precision, ga, ga_o)
