@@ -64,13 +64,23 @@ __device__ inline int64_t gindex(const StepParams& p, int x, int y, int z) {
 
 __device__ inline int edge_of(const StepParams& p, int a) { return a == 0 ? p.bx : a == 1 ? p.by : p.bz; }
 
+// Component a of a 3-vector, and a write of it, by selects: a run-time index
+// into a local array would put the array in scratch memory.
+__device__ inline int sel3(int a, int v0, int v1, int v2) { return a == 0 ? v0 : a == 1 ? v1 : v2; }
+__device__ inline void set3(int* l, int a, int v) {
+  l[0] = a == 0 ? v : l[0];
+  l[1] = a == 1 ? v : l[1];
+  l[2] = a == 2 ? v : l[2];
+}
+
 // Element of the strip of face F = 2a + side of a PE for the point with PE
 // coordinates l (which must lie in that strip): x faces [z][y][d], y faces
 // [z][d][x], z faces [d][y][x], with depth d counted from the PE's low side.
 __device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, int S) {
   const int a = F >> 1;
   const int b = edge_of(p, a);
-  const int d = (F & 1) ? l[a] - (b - S) : l[a];
+  const int la = sel3(a, l[0], l[1], l[2]);
+  const int d = (F & 1) ? la - (b - S) : la;
   if (a == 0) return (static_cast<int64_t>(l[2]) * p.by + l[1]) * S + d;
   if (a == 1) return (static_cast<int64_t>(l[2]) * S + d) * p.bx + l[0];
   return (static_cast<int64_t>(d) * p.by + l[1]) * p.bx + l[0];
@@ -81,7 +91,8 @@ __device__ inline int64_t strip_elem(const StepParams& p, int F, const int* l, i
 __device__ inline int64_t ring_at_pt(const StepParams& p, int slot, int pe, int F, const int* l, int S) {
   const int a = F >> 1;
   const int b = edge_of(p, a);
-  const int d = (F & 1) ? l[a] - (b - S) : l[a];
+  const int la = sel3(a, l[0], l[1], l[2]);
+  const int d = (F & 1) ? la - (b - S) : la;
   if (a == 0) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(l[1]) * S + d);
   if (a == 1) return ring_index(p, slot, pe, F, l[2], static_cast<int64_t>(d) * p.bx + l[0]);
   return ring_index(p, slot, pe, F, d, static_cast<int64_t>(l[1]) * p.bx + l[0]);
@@ -132,9 +143,9 @@ __device__ inline StripPt strip_point(const AdjParams& q, int t) {
 
 __device__ inline int nbr_pe(const StepParams& p, int pid, int f) {
   int q[3] = {pid % p.px, (pid / p.px) % p.py, pid / (p.px * p.py)};
-  const int ext[3] = {p.px, p.py, p.pz};
   const int a = f >> 1;
-  q[a] = (q[a] + ((f & 1) ? 1 : ext[a] - 1)) % ext[a];
+  const int ext = sel3(a, p.px, p.py, p.pz);
+  set3(q, a, (sel3(a, q[0], q[1], q[2]) + ((f & 1) ? 1 : ext - 1)) % ext);
   return q[0] + p.px * (q[1] + p.py * q[2]);
 }
 
@@ -202,7 +213,7 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const
     const int ia = jp - o;
     const bool valid = ia >= 0 && ia < b;
     int c[3] = {org[0] + l[0], org[1] + l[1], org[2] + l[2]};
-    c[a] = org[a] + min(max(ia, 0), b - 1);
+    set3(c, a, sel3(a, org[0], org[1], org[2]) + min(max(ia, 0), b - 1));
     const int64_t gi = gindex(p, c[0], c[1], c[2]);
     const double ci = q.burgers ? centre_at<Real>(q, gi) : 0.0;   // Burgers taps only
     const double t = tap_k(q, a, o, ci) * mu_at<Real>(q, gi);
@@ -212,7 +223,7 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const
   const double* w = wt[k];
   const int T = adj_levels(p);
   int lsF[3] = {l[0], l[1], l[2]};   // the strip value's PE coordinates
-  lsF[a] = (F & 1) ? b - S + d : d;
+  set3(lsF, a, (F & 1) ? b - S + d : d);
   Real* dst[kMaxT];
   double old[kMaxT];
 #pragma unroll
@@ -261,7 +272,7 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, c
   const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
   int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
   const int b = edge_of(p, a);
-  ls[a] = (pf & 1) ? b - S + d : d;
+  set3(ls, a, (pf & 1) ? b - S + d : d);
   const int src = nbr_pe(p, pe, f);
   const int sq[3] = {src % p.px, (src / p.px) % p.py, src / (p.px * p.py)};
   const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
@@ -433,8 +444,10 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   const Real* __restrict__ Yg0 = static_cast<const Real*>(q.y0);
   const Real* __restrict__ Yg1 = static_cast<const Real*>(q.m1 != 0.0 ? q.y1 : q.y0);
   const Real* __restrict__ C = static_cast<const Real*>(q.levels) + (q.n - q.seg_start) * q.npts;
-  const Real* __restrict__ hpe = static_cast<const Real*>(q.hbuf) + static_cast<int64_t>(pe) * p.pe_block;
-  Real* __restrict__ aring = static_cast<Real*>(q.aring);
+  // (not restrict: in 1-D / 2-D this kernel writes both through the strip
+  // work's own pointers first)
+  const Real* hpe = static_cast<const Real*>(q.hbuf) + static_cast<int64_t>(pe) * p.pe_block;
+  Real* aring = static_cast<Real*>(q.aring);
   const int slot_n = static_cast<int>(q.n % q.anslots);
   const int tid = threadIdx.x, nt = blockDim.x;
   const double m0 = q.m0, m1 = q.m1;
@@ -456,7 +469,7 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   // whose axis-a coordinate ta lies outside the PE
   auto halo_c = [&](int f, int* l, int ta) -> Real {
     const int a = f >> 1, b = a == 0 ? bx : a == 1 ? by : bz;
-    l[a] = (f & 1) ? ta - b : ta + b;
+    set3(l, a, (f & 1) ? ta - b : ta + b);
     const int64_t pfo = f == 0 ? q.pfo[0] : f == 1 ? q.pfo[1] : f == 2 ? q.pfo[2] : f == 3 ? q.pfo[3]
                       : f == 4 ? q.pfo[4] : q.pfo[5];
     return hpe[pfo + strip_elem(p, f ^ 1, l, S)];
@@ -465,6 +478,13 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   for (int i = tid; i < nbuf * plane; i += nt) {
     Y0l[i] = Real(0);
     Y1l[i] = Real(0);
+  }
+  // 1-D / 2-D: the level weights c_m(k) of every k < L for the strip work
+  __shared__ double s_wt[kMaxL][kMaxT];
+  if (DIM <= 2 && tid < kMaxL) {
+    double w[kMaxT] = {0.0, 0.0, 0.0, 0.0};
+    level_weights(tid, adj_levels(p), w);
+    for (int m = 0; m < kMaxT; ++m) s_wt[tid][m] = w[m];
   }
   __syncthreads();   // the zeros land before any own value is written over them
   // the per-point adjoint (x, y, z PE coordinates; global index g); cget(a, o)
@@ -540,22 +560,54 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   };
 
   if constexpr (DIM <= 2) {
-    // A thread's first kPre points: their base terms and adjoint-ring entries
-    // are loaded with the plane, so that every global load of the workgroup
-    // is in flight before the barrier (one memory round trip, not three).
+    // This PE's strip values (the strip kernel's work, which only this
+    // workgroup touches): the forward halo values of its frame into the halo
+    // buffer (consumer view) and, in gather form, the transposed taps of the
+    // neighbour that reads each of its strip values into its own adjoint-ring
+    // slots (producer view; level n included, drained below). Issued with the
+    // plane's loads; a barrier then makes the writes visible to the workgroup.
+    {
+      const int blk = static_cast<int>(p.pe_block);
+      for (int r = tid; r < blk; r += nt) {
+        const int t = pe * blk + r;
+        const StripPt sp = strip_point(q, t);
+        halo_elem<Real>(q, t, sp, s_wt);
+        scatter_elem<Real>(q, sp, s_wt);
+      }
+    }
+    // A thread's first kPre points: their base terms are loaded with the plane
     constexpr int kPre = sizeof(Real) == 4 ? 4 : 3;
     Real pre_x0[kPre], pre_x1[kPre], pre_r[kPre][2];
     bool pre_in[kPre][2];
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
       const int i = tid + k * nt;
-      pre_in[k][0] = pre_in[k][1] = false;
-      pre_x0[k] = pre_x1[k] = pre_r[k][0] = pre_r[k][1] = Real(0);
+      pre_x0[k] = pre_x1[k] = Real(0);
       if (i < bx * by) {
         const int y = i / bx, x = i - y * bx;
         const int64_t g = gindex(p, x0 + x, y0 + y, 0);
         pre_x0[k] = X0[g];
         pre_x1[k] = X1[g];
+      }
+    }
+    // the plane's own values
+    for (int i = tid; i < bx * by; i += nt) {
+      const int y = i / bx, x = i - y * bx;
+      const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+      const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
+      Cl[at] = C[g];
+      Y0l[at] = Yg0[g];
+      Y1l[at] = Yg1[g];
+    }
+    __syncthreads();   // the strip work's halo-buffer and adjoint-ring writes
+    // adjoint-ring entries (level n) of the first kPre points' strips
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = tid + k * nt;
+      pre_in[k][0] = pre_in[k][1] = false;
+      pre_r[k][0] = pre_r[k][1] = Real(0);
+      if (i < bx * by) {
+        const int y = i / bx, x = i - y * bx;
         const int l[3] = {x, y, 0};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -566,15 +618,7 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
         }
       }
     }
-    // the plane: own values, then the x (and y) frame of c
-    for (int i = tid; i < bx * by; i += nt) {
-      const int y = i / bx, x = i - y * bx;
-      const int64_t g = gindex(p, x0 + x, y0 + y, 0);
-      const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
-      Cl[at] = C[g];
-      Y0l[at] = Yg0[g];
-      Y1l[at] = Yg1[g];
-    }
+    // the x (and y) frame of c from the halo buffer
     const int nfx = 2 * S * by, nf = nfx + (DIM >= 2 ? 2 * S * bx : 0);
     for (int h = tid; h < nf; h += nt) {
       int l[3] = {0, 0, 0};
@@ -677,7 +721,7 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
         f_stride = static_cast<int64_t>(S) * bx;
       }
       const int a = f >> 1, b = a == 0 ? bx : by;
-      l[a] = (f & 1) ? ta - b : ta + b;
+      set3(l, a, (f & 1) ? ta - b : ta + b);
       const int64_t pfo = f == 0 ? q.pfo[0] : f == 1 ? q.pfo[1] : f == 2 ? q.pfo[2] : q.pfo[3];
       f_addr = pfo + strip_elem(p, f ^ 1, l, S);
     }
@@ -821,12 +865,14 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   const int sblocks = static_cast<int>(sb < kAdjBlocks ? (sb > 0 ? sb : 1) : kAdjBlocks);
   const int lblocks = adj_blocks(q.npts);
   const bool pe = adj_pe_applies(q.sp, f64);
+  // the 1-D / 2-D PE-tiled stage kernel does its PE's strip work itself
+  const bool strip_kernel = !(pe && q.sp.ndim <= 2);
   if (f64) {
-    hipLaunchKernelGGL(adj_strip_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    if (strip_kernel) hipLaunchKernelGGL(adj_strip_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = pe ? launch_lambda_pe<double>(q, st) : launch_lambda<double>(q, lblocks, st);
     if (e != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(adj_strip_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    if (strip_kernel) hipLaunchKernelGGL(adj_strip_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
     hipError_t e = pe ? launch_lambda_pe<float>(q, st) : launch_lambda<float>(q, lblocks, st);
     if (e != hipSuccess) return e;
   }
