@@ -306,8 +306,11 @@ const char* at_last_error(const at_ctx* ctx);
  * dJ/dalpha = sum_n <dJ/df^n, d f^n / d alpha>, accumulated in double in a
  * fixed order. The context is left at step N with the forward field.
  * Scratch (device, 256-B aligned) of at_adjoint_scratch_size bytes holds the
- * checkpoints, one segment of levels, three adjoint fields and the adjoint
- * ring. Synchronises the stream. AT_ESTATE unless the context is at step 0.
+ * checkpoints, the levels of one segment (two when a segment's levels and
+ * ring copies take at most 4 GB: segment s-1 is then recomputed on a second
+ * stream of the library, at default priority, while segment s is reversed),
+ * three adjoint fields and the adjoint ring. Synchronises the stream.
+ * AT_ESTATE unless the context is at step 0.
  */
 at_status at_adjoint_scratch_size(at_ctx* ctx, int64_t nsteps, int32_t every, size_t* bytes);
 at_status at_adjoint(at_ctx* ctx, int64_t nsteps, int32_t every, const void* seed_dev, void* scratch_dev,

@@ -75,6 +75,8 @@ struct at_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
+  // the adjoint's recomputation stream (default priority)
+  hipStream_t aux_stream = nullptr;
 };
 
 namespace {
@@ -693,13 +695,14 @@ at_status at_checkpoint_size(const at_ctx* c, size_t* bytes) {
 }
 
 namespace {
-at_status ckpt_copy(at_ctx* c, unsigned char* dst_base, const unsigned char* src_base, bool save) {
+at_status ckpt_copy(at_ctx* c, unsigned char* dst_base, const unsigned char* src_base, bool save,
+                    hipStream_t st) {
   const Layout& l = c->lay;
   size_t off = 0;
   auto cp = [&](size_t ws_off, size_t bytes) -> hipError_t {
     unsigned char* wsp = c->ws + ws_off;
-    hipError_t e = save ? hipMemcpyAsync(dst_base + off, wsp, bytes, hipMemcpyDeviceToDevice, c->stream)
-                        : hipMemcpyAsync(wsp, src_base + off, bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipError_t e = save ? hipMemcpyAsync(dst_base + off, wsp, bytes, hipMemcpyDeviceToDevice, st)
+                        : hipMemcpyAsync(wsp, src_base + off, bytes, hipMemcpyDeviceToDevice, st);
     off += align_up(bytes);
     return e;
   };
@@ -717,7 +720,7 @@ at_status ckpt_copy(at_ctx* c, unsigned char* dst_base, const unsigned char* src
 at_status at_save(at_ctx* c, void* ckpt_dev) {
   if (!c || !ckpt_dev) return fail(c, AT_EINVAL, "null argument");
   if (!c->state_set) return fail(c, AT_ESTATE, "no state");
-  return ckpt_copy(c, static_cast<unsigned char*>(ckpt_dev), nullptr, true);
+  return ckpt_copy(c, static_cast<unsigned char*>(ckpt_dev), nullptr, true, c->stream);
 }
 
 at_status at_load(at_ctx* c, const void* ckpt_dev) {
@@ -733,7 +736,7 @@ at_status at_load(at_ctx* c, const void* ckpt_dev) {
   if (cnt[0] < 0) return fail(c, AT_EINVAL, "corrupt checkpoint");
   c->n = cnt[0];
   // the saved solution goes to the buffer of its level's parity
-  at_status st = ckpt_copy(c, nullptr, static_cast<const unsigned char*>(ckpt_dev), false);
+  at_status st = ckpt_copy(c, nullptr, static_cast<const unsigned char*>(ckpt_dev), false, c->stream);
   c->state_set = st == AT_OK;
   return st;
 }
@@ -742,6 +745,7 @@ at_status at_destroy(at_ctx* c) {
   if (!c) return AT_OK;
   drop_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
   delete c;
   return AT_OK;
 }
@@ -757,13 +761,23 @@ namespace {
 
 // Scratch layout of at_adjoint: nck + 1 checkpoints; the levels of one
 // segment (contiguous fields: u^seg .. u^{seg+every}, and for RK2 the
-// predictors u*^seg .. u*^{seg+every-1}); the adjoint fields (lambda x3,
-// sigma); the forward halo buffer; the adjoint ring (two for RK2); the
-// forward rings at the segment start; alpha partial sums.
+// predictors u*^seg .. u*^{seg+every-1}) with the forward rings at the
+// segment start, twice when the two sets fit kOverlapBytes (then segment s-1
+// is recomputed on a second stream while segment s is reversed); the adjoint
+// fields (lambda x3, sigma); the forward halo buffer; the adjoint ring (two
+// for RK2); alpha partial sums.
+constexpr size_t kOverlapBytes = size_t(4) << 30;
+
+struct AdjSet {
+  size_t levels = 0, slevels = 0, ring0 = 0, sring0 = 0;
+};
+
 struct AdjLayout {
-  size_t ck = 0, off_levels = 0, off_slevels = 0, off_lam[3] = {0, 0, 0}, off_sigma = 0;
-  size_t off_hbuf = 0, off_aring = 0, off_bring = 0, off_ring0 = 0, off_sring0 = 0;
+  size_t ck = 0, off_lam[3] = {0, 0, 0}, off_sigma = 0;
+  size_t off_hbuf = 0, off_aring = 0, off_bring = 0;
   size_t off_partial = 0, off_out = 0, total = 0, aring_bytes = 0;
+  AdjSet set[2];
+  int nsets = 1;
   int64_t nck = 0;
   int anslots = 0;
   bool rk2 = false;
@@ -784,8 +798,15 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   };
   const Layout& l = c->lay;
   const size_t w = c->g.f64 ? 8 : 4;
-  a.off_levels = take(l.field_bytes * static_cast<size_t>(every + 1));
-  if (a.rk2) a.off_slevels = take(l.field_bytes * static_cast<size_t>(every));
+  const size_t seg_bytes = l.field_bytes * static_cast<size_t>(every + 1) +
+                           (a.rk2 ? l.field_bytes * static_cast<size_t>(every) + l.ring_bytes : 0) + l.ring_bytes;
+  a.nsets = a.nck > 1 && seg_bytes <= kOverlapBytes ? 2 : 1;
+  for (int k = 0; k < a.nsets; ++k) {
+    a.set[k].levels = take(l.field_bytes * static_cast<size_t>(every + 1));
+    if (a.rk2) a.set[k].slevels = take(l.field_bytes * static_cast<size_t>(every));
+    a.set[k].ring0 = take(l.ring_bytes);
+    if (a.rk2) a.set[k].sring0 = take(l.ring_bytes);
+  }
   for (int i = 0; i < 3; ++i) a.off_lam[i] = take(l.field_bytes);
   if (a.rk2) a.off_sigma = take(l.field_bytes);
   a.off_hbuf = take(static_cast<size_t>(c->g.npe) * l.pe_block * w);
@@ -793,8 +814,6 @@ AdjLayout adj_layout(const at_ctx* c, int64_t nsteps, int every) {
   a.aring_bytes = static_cast<size_t>(a.anslots) * c->g.npe * l.pe_block * w;
   a.off_aring = take(a.aring_bytes);
   if (a.rk2) a.off_bring = take(a.aring_bytes);
-  a.off_ring0 = take(l.ring_bytes);
-  if (a.rk2) a.off_sring0 = take(l.ring_bytes);
   a.off_partial = take(static_cast<size_t>(adj_partials(c->sp)) * sizeof(double));
   a.off_out = take(sizeof(double));
   a.total = off;
@@ -858,34 +877,35 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
   if (a.rk2) HIP_TRY(c, hipMemsetAsync(sc + a.off_bring, 0, a.aring_bytes, c->stream));
   HIP_TRY(c, hipMemsetAsync(sc + a.off_partial, 0, static_cast<size_t>(adj_partials(c->sp)) * sizeof(double),
                             c->stream));
-  unsigned char* levels = sc + a.off_levels;
-  unsigned char* slevels = a.rk2 ? sc + a.off_slevels : nullptr;
   const double dt = c->prob.dt;
-  for (int64_t s = a.nck - 1; s >= 0; --s) {
-    st = at_load(c, sc + a.ck * s);
-    if (st != AT_OK) return st;
+  // Recompute segment s into level set k on stream st: restore its
+  // checkpoint into the context, keep the forward rings at its start and
+  // step through it with every level kept.
+  auto recompute = [&](int64_t s, int k, hipStream_t st) -> at_status {
+    const AdjSet& z = a.set[k];
+    unsigned char* levels = sc + z.levels;
+    unsigned char* slevels = a.rk2 ? sc + z.slevels : nullptr;
     const int64_t seg = s * every;
     const int64_t len = std::min<int64_t>(every, N - seg);
+    c->n = seg;
+    at_status r = ckpt_copy(c, nullptr, sc + a.ck * s, false, st);
+    if (r != AT_OK) return r;
     // the adjoint kernels take the levels in the [z][y][x] layout
-    HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels, false, c->stream));
+    HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels, false, st));
     if (l.ring_bytes) {
-      HIP_TRY(c, hipMemcpyAsync(sc + a.off_ring0, c->sp.ring, l.ring_bytes, hipMemcpyDeviceToDevice, c->stream));
-      if (a.rk2)
-        HIP_TRY(c, hipMemcpyAsync(sc + a.off_sring0, c->sp.sring, l.ring_bytes, hipMemcpyDeviceToDevice,
-                                  c->stream));
+      HIP_TRY(c, hipMemcpyAsync(sc + z.ring0, c->sp.ring, l.ring_bytes, hipMemcpyDeviceToDevice, st));
+      if (a.rk2) HIP_TRY(c, hipMemcpyAsync(sc + z.sring0, c->sp.sring, l.ring_bytes, hipMemcpyDeviceToDevice, st));
     }
     for (int64_t j = 1; j <= len; ++j) {
       if (c->sp.pe_major) {
         // the 32 x 32 path keeps its fields PE-major: step, then copy the
-        // levels out in the [z][y][x] layout the adjoint kernels read
-        st = enqueue_step(c, c->stream);
-        if (st != AT_OK) return st;
+        // levels out in the [z][y][x] layout
+        r = enqueue_step(c, st);
+        if (r != AT_OK) return r;
         c->n += 1;
-        HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels + l.field_bytes * j, false,
-                                     c->stream));
+        HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ubuf[c->n & 1], levels + l.field_bytes * j, false, st));
         if (a.rk2)
-          HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ustar, slevels + l.field_bytes * (j - 1), false,
-                                       c->stream));
+          HIP_TRY(c, launch_field_copy(c->sp, c->g.f64, c->sp.ustar, slevels + l.field_bytes * (j - 1), false, st));
       } else {
         // the step reads level seg+j-1 from the segment's levels and writes
         // level seg+j (and the RK2 predictor) straight into them: no copies
@@ -894,11 +914,60 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
         p.ubuf[c->n & 1] = levels + l.field_bytes * (j - 1);
         p.ubuf[(c->n + 1) & 1] = levels + l.field_bytes * j;
         if (a.rk2) p.ustar = slevels + l.field_bytes * (j - 1);
-        st = enqueue_step_p(c, p, c->stream);
-        if (st != AT_OK) return st;
+        r = enqueue_step_p(c, p, st);
+        if (r != AT_OK) return r;
         c->n += 1;
       }
     }
+    return AT_OK;
+  };
+  // Two level sets: segment s-1 is recomputed on the auxiliary stream while
+  // segment s is reversed on the context's stream. Events order the reuse of
+  // a set (the recomputation of s-1 waits for the reversal of s+1, which
+  // read the same set) and the start of each reversal (it waits for its
+  // recomputation). The reversal reads only the level set, the ring copies
+  // and the adjoint's own buffers, never the context's live fields, which
+  // the recomputation overwrites.
+  const bool overlap = a.nsets == 2;
+  hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
+  struct EventGuard {
+    hipEvent_t* e[5];
+    ~EventGuard() {
+      for (hipEvent_t* p : e)
+        if (*p) (void)hipEventDestroy(*p);
+    }
+  } guard{{&ev_start, &ev_rec[0], &ev_rec[1], &ev_rev[0], &ev_rev[1]}};
+  hipStream_t aux = c->stream;
+  if (overlap) {
+    if (!c->aux_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+    aux = c->aux_stream;
+    for (hipEvent_t* e : guard.e) HIP_TRY(c, hipEventCreateWithFlags(e, hipEventDisableTiming));
+    // the recomputations start after the forward run and the initialisation
+    HIP_TRY(c, hipEventRecord(ev_start, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(aux, ev_start, 0));
+    st = recompute(a.nck - 1, (a.nck - 1) & 1, aux);
+    if (st != AT_OK) return st;
+    HIP_TRY(c, hipEventRecord(ev_rec[(a.nck - 1) & 1], aux));
+  }
+  for (int64_t s = a.nck - 1; s >= 0; --s) {
+    const int k = overlap ? static_cast<int>(s & 1) : 0;
+    if (overlap) {
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, ev_rec[k], 0));
+      if (s >= 1) {
+        // set (s-1) & 1 was last read by the reversal of segment s+1
+        if (s + 1 <= a.nck - 1) HIP_TRY(c, hipStreamWaitEvent(aux, ev_rev[(s + 1) & 1], 0));
+        st = recompute(s - 1, static_cast<int>((s - 1) & 1), aux);
+        if (st != AT_OK) return st;
+        HIP_TRY(c, hipEventRecord(ev_rec[(s - 1) & 1], aux));
+      }
+    } else {
+      st = recompute(s, 0, c->stream);
+      if (st != AT_OK) return st;
+    }
+    unsigned char* levels = sc + a.set[k].levels;
+    unsigned char* slevels = a.rk2 ? sc + a.set[k].slevels : nullptr;
+    const int64_t seg = s * every;
+    const int64_t len = std::min<int64_t>(every, N - seg);
     for (int64_t n = seg + len - 1; n >= seg; --n) {
       AdjParams q;
       std::memset(&q, 0, sizeof(q));
@@ -920,7 +989,7 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
         q2.b0 = 0.5;
         q2.out = sc + a.off_sigma;
         q2.levels = slevels;
-        q2.ring0 = sc + a.off_sring0;
+        q2.ring0 = sc + a.set[k].sring0;
         q2.aring = sc + a.off_bring;
         HIP_TRY(c, launch_adj_step(q2, c->g.f64, c->stream));
         // stage 1: lambda^n from mu = dt sigma
@@ -941,7 +1010,7 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       }
       q.out = lam[i0];
       q.levels = levels;
-      q.ring0 = sc + a.off_ring0;
+      q.ring0 = sc + a.set[k].ring0;
       q.aring = sc + a.off_aring;
       HIP_TRY(c, launch_adj_step(q, c->g.f64, c->stream));
       const int t = i2;
@@ -949,6 +1018,7 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       i1 = i0;
       i0 = t;
     }
+    if (overlap) HIP_TRY(c, hipEventRecord(ev_rev[k], c->stream));
   }
   HIP_TRY(c, hipMemcpyAsync(grad_u0_dev, lam[i1], l.field_bytes, hipMemcpyDeviceToDevice, c->stream));
   double* out = reinterpret_cast<double*>(sc + a.off_out);
