@@ -190,7 +190,8 @@ __device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
 // collects the transposed taps of the consumer PE across F, weighted by the
 // consumer's level weights, into the adjoint ring slots of levels n-k-m.
 template <typename Real>
-__device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT]) {
+__device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT],
+                                    Real* drain = nullptr) {
   const StepParams& p = q.sp;
   const int S = p.s;
   Real* aring = static_cast<Real*>(q.aring);
@@ -234,6 +235,21 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const
     dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
     old[m] = static_cast<double>(*dst[m]);
   }
+  if (drain) {
+    // the caller drains level n here: its entry (this step's contribution
+    // added when k = 0, as below) goes to *drain and the ring entry is
+    // cleared; only older levels stay in the ring
+    const int slot_n = static_cast<int>(q.n % q.anslots);
+    Real* en = aring + ring_at_pt(p, slot_n, pe, F, lsF, S);
+    *drain = k == 0 ? static_cast<Real>(old[0] + w[0] * g) : *en;
+    *en = Real(0);
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) {
+      if (m >= T) break;
+      if (k + m > 0 && w[m] != 0.0) *dst[m] = static_cast<Real>(old[m] + w[m] * g);
+    }
+    return;
+  }
 #pragma unroll
   for (int m = 0; m < kMaxT; ++m) {
     if (m >= T) break;
@@ -264,11 +280,10 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int slot, in
 // combination of the stored levels (the synchronous scheme: level n).
 // hbuf[pe * pe_block + (per-PE offset of face f) + e].
 template <typename Real>
-__device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, const double (*wt)[kMaxT]) {
+__device__ inline Real halo_value(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT]) {
   const StepParams& p = q.sp;
   const int S = p.s;
   const int T = adj_levels(p);
-  Real* hb = static_cast<Real*>(q.hbuf);
   const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
   int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
   const int b = edge_of(p, a);
@@ -278,10 +293,8 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, c
   const int gx = sq[0] * p.bx + ls[0], gy = sq[1] * p.by + ls[1], gz = sq[2] * p.bz + ls[2];
   const int k = adj_delay(p, pe, f, q.n);
   const double* w = wt[k];
-  if (p.mode == AT_SYNC) {   // level n, always stored
-    hb[t] = static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
-    return;
-  }
+  if (p.mode == AT_SYNC)   // level n, always stored
+    return static_cast<const Real*>(q.levels)[(q.n - q.seg_start) * q.npts + gindex(p, gx, gy, gz)];
   // all kMaxT levels are loaded unconditionally (a level m >= T repeats
   // level T - 1 and is dropped below), so the loads overlap
   const int rn = static_cast<int>(q.n % p.nslots);
@@ -294,7 +307,12 @@ __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, c
 #pragma unroll
   for (int m = 0; m < kMaxT; ++m)
     if (m < T && w[m] != 0.0) v += w[m] * lv[m];
-  hb[t] = static_cast<Real>(v);
+  return static_cast<Real>(v);
+}
+
+template <typename Real>
+__device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, const double (*wt)[kMaxT]) {
+  static_cast<Real*>(q.hbuf)[t] = halo_value<Real>(q, sp, wt);
 }
 
 // One thread per strip value t: its forward halo value (consumer view) and its
@@ -560,25 +578,9 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   };
 
   if constexpr (DIM <= 2) {
-    // This PE's strip values (the strip kernel's work, which only this
-    // workgroup touches): the forward halo values of its frame into the halo
-    // buffer (consumer view) and, in gather form, the transposed taps of the
-    // neighbour that reads each of its strip values into its own adjoint-ring
-    // slots (producer view; level n included, drained below). Issued with the
-    // plane's loads; a barrier then makes the writes visible to the workgroup.
-    {
-      const int blk = static_cast<int>(p.pe_block);
-      for (int r = tid; r < blk; r += nt) {
-        const int t = pe * blk + r;
-        const StripPt sp = strip_point(q, t);
-        halo_elem<Real>(q, t, sp, s_wt);
-        scatter_elem<Real>(q, sp, s_wt);
-      }
-    }
     // A thread's first kPre points: their base terms are loaded with the plane
     constexpr int kPre = sizeof(Real) == 4 ? 4 : 3;
-    Real pre_x0[kPre], pre_x1[kPre], pre_r[kPre][2];
-    bool pre_in[kPre][2];
+    Real pre_x0[kPre], pre_x1[kPre];
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
       const int i = tid + k * nt;
@@ -599,43 +601,54 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
       Y0l[at] = Yg0[g];
       Y1l[at] = Yg1[g];
     }
-    __syncthreads();   // the strip work's halo-buffer and adjoint-ring writes
-    // adjoint-ring entries (level n) of the first kPre points' strips
-#pragma unroll
-    for (int k = 0; k < kPre; ++k) {
-      const int i = tid + k * nt;
-      pre_in[k][0] = pre_in[k][1] = false;
-      pre_r[k][0] = pre_r[k][1] = Real(0);
-      if (i < bx * by) {
-        const int y = i / bx, x = i - y * bx;
-        const int l[3] = {x, y, 0};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          const int b = a == 0 ? bx : by;
-          const bool lo = l[a] < S, hi = l[a] >= b - S;
-          pre_in[k][a] = lo || hi;
-          if (lo || hi) pre_r[k][a] = aring[ring_at_pt(p, slot_n, pe, 2 * a + (hi ? 1 : 0), l, S)];
+    // This PE's strip values (the strip kernel's work, which only this
+    // workgroup touches), behind the plane's loads. Items 0..blk-1: the
+    // forward halo value that this PE reads across its face f (consumer
+    // view), straight into the frame of the LDS plane. Items blk..2 blk-1:
+    // in gather form, the transposed taps of the neighbour that reads this
+    // PE's strip value into its older adjoint-ring levels, and the drained
+    // level-n entry (this step's contribution included) into Dl, clearing
+    // the ring entry. The two halves run in different waves side by side.
+    Real* Dl = Y1l + nbuf * plane;                        // [pe_block]
+    {
+      const int blk = static_cast<int>(p.pe_block);
+      for (int r = tid; r < 2 * blk; r += nt) {
+        const bool scat = r >= blk;
+        const int rr = scat ? r - blk : r;
+        const StripPt sp = strip_point(q, pe * blk + rr);
+        if (scat) {
+          scatter_elem<Real>(q, sp, s_wt, Dl + rr);
+        } else {
+          // frame position of the value: depth d of the producer strip is
+          // column d - S (low face) or b + d (high face) along its axis
+          const int a = sp.F >> 1, b = a == 0 ? bx : by;
+          const int ta = (sp.F & 1) ? b + sp.d : sp.d - S;
+          const int at = a == 0 ? (DIM >= 2 ? sp.l[1] + S : 0) * W + ta + S : (ta + S) * W + sp.l[0] + S;
+          Cl[at] = halo_value<Real>(q, sp, s_wt);
         }
       }
     }
-    // the x (and y) frame of c from the halo buffer
-    const int nfx = 2 * S * by, nf = nfx + (DIM >= 2 ? 2 * S * bx : 0);
-    for (int h = tid; h < nf; h += nt) {
-      int l[3] = {0, 0, 0};
-      if (h < nfx) {
-        const int side = h >= S * by ? 1 : 0, r = side ? h - S * by : h, y = r / S, d = r - y * S;
-        const int ta = side ? bx + d : d - S;
-        l[1] = y;
-        Cl[(DIM >= 2 ? y + S : 0) * W + ta + S] = halo_c(side, l, ta);
-      } else {
-        const int hy = h - nfx, side = hy >= S * bx ? 1 : 0, r = side ? hy - S * bx : hy, d = r / bx, x = r - d * bx;
-        const int ta = side ? by + d : d - S;
-        l[0] = x;
-        Cl[(ta + S) * W + x + S] = halo_c(2 + side, l, ta);
-      }
-    }
     __syncthreads();
-    auto plane_point = [&](int i, const Real* pv, const bool* din) {
+    // the drained level-n entries of a point's strips (x, y), from Dl
+    auto drains = [&](int x, int y, Real* dr, bool* din) {
+      const int l[3] = {x, y, 0};
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        din[a] = false;
+        dr[a] = Real(0);
+        if (a < DIM) {
+          const int b = a == 0 ? bx : by, la = a == 0 ? x : y;
+          const bool lo = la < S, hi = la >= b - S;
+          if (lo || hi) {
+            const int F = 2 * a + (hi ? 1 : 0);
+            const int64_t pfo = F == 0 ? q.pfo[0] : F == 1 ? q.pfo[1] : F == 2 ? q.pfo[2] : q.pfo[3];
+            din[a] = true;
+            dr[a] = Dl[pfo + strip_elem(p, F, l, S)];
+          }
+        }
+      }
+    };
+    auto plane_point = [&](int i, Real vx0, Real vx1) {
       const int y = i / bx, x = i - y * bx;
       const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
       auto cget = [&](int a, int o) -> double { return static_cast<double>(Cl[at + (a == 0 ? o : o * W)]); };
@@ -645,29 +658,22 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
         v1 = static_cast<double>(Y1l[k]);
       };
       const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+      Real dr[2];
+      bool din[2];
+      drains(x, y, dr, din);
       point(x, y, 0, g, static_cast<double>(Cl[at]), static_cast<double>(Y0l[at]), static_cast<double>(Y1l[at]),
-            static_cast<double>(pv ? pv[0] : X0[g]), static_cast<double>(pv ? pv[1] : X1[g]), cget, yget,
-            pv ? pv + 2 : static_cast<const Real*>(nullptr), din);
+            static_cast<double>(vx0), static_cast<double>(vx1), cget, yget, dr, din);
     };
-    // the prefetched points (their ring entries are cleared first: point()
-    // adds the loaded values), then any further ones
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
       const int i = tid + k * nt;
-      if (i < bx * by) {
-        const int y = i / bx, x = i - y * bx;
-        const int l[3] = {x, y, 0};
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-          const int b = a == 0 ? bx : by;
-          if (pre_in[k][a]) aring[ring_at_pt(p, slot_n, pe, 2 * a + (l[a] >= b - S ? 1 : 0), l, S)] = Real(0);
-        }
-        const Real pv[4] = {pre_x0[k], pre_x1[k], pre_r[k][0], pre_r[k][1]};
-        plane_point(i, pv, pre_in[k]);
-      }
+      if (i < bx * by) plane_point(i, pre_x0[k], pre_x1[k]);
     }
-    for (int i = tid + kPre * nt; i < bx * by; i += nt)
-      plane_point(i, static_cast<const Real*>(nullptr), static_cast<const bool*>(nullptr));
+    for (int i = tid + kPre * nt; i < bx * by; i += nt) {
+      const int y = i / bx, x = i - y * bx;
+      const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+      plane_point(i, X0[g], X1[g]);
+    }
   } else {
     // one column per thread (the host launches bx * by threads)
     const int x = tid % bx, y = tid / bx;
@@ -789,7 +795,9 @@ template <typename Real>
 size_t adj_pe_lds(const StepParams& p) {
   const int S = p.s;
   const size_t W = p.bx + 2 * S, H = p.ndim >= 2 ? p.by + 2 * S : 1;
-  return (p.ndim == 3 ? 2 : 1) * 3 * W * H * sizeof(Real);
+  // 1-D / 2-D: plus the drained adjoint-ring entries of the PE's strips
+  return (p.ndim == 3 ? 2 : 1) * 3 * W * H * sizeof(Real) +
+         (p.ndim <= 2 ? static_cast<size_t>(p.pe_block) * sizeof(Real) : 0);
 }
 
 template <typename Real>
