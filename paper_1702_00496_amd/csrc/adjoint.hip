@@ -322,11 +322,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_strip_kernel(AdjParams q) {
   // the level weights c_m(k) of every delay k < L (the delays are clamped
   // below L), once per workgroup
   __shared__ double s_wt[kMaxL][kMaxT];
-  if (threadIdx.x < kMaxL) {
-    double w[kMaxT] = {0.0, 0.0, 0.0, 0.0};
-    level_weights(static_cast<int>(threadIdx.x), adj_levels(q.sp), w);
-    for (int m = 0; m < kMaxT; ++m) s_wt[threadIdx.x][m] = w[m];
-  }
+  if (threadIdx.x < kMaxL * kMaxT) s_wt[threadIdx.x / kMaxT][threadIdx.x % kMaxT] = q.wt[threadIdx.x / kMaxT][threadIdx.x % kMaxT];
   __syncthreads();
   const int total = q.sp.npe * static_cast<int>(q.sp.pe_block);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
@@ -499,11 +495,7 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
   }
   // 1-D / 2-D: the level weights c_m(k) of every k < L for the strip work
   __shared__ double s_wt[kMaxL][kMaxT];
-  if (DIM <= 2 && tid < kMaxL) {
-    double w[kMaxT] = {0.0, 0.0, 0.0, 0.0};
-    level_weights(tid, adj_levels(p), w);
-    for (int m = 0; m < kMaxT; ++m) s_wt[tid][m] = w[m];
-  }
+  if (DIM <= 2 && tid < kMaxL * kMaxT) s_wt[tid / kMaxT][tid % kMaxT] = q.wt[tid / kMaxT][tid % kMaxT];
   __syncthreads();   // the zeros land before any own value is written over them
   // the per-point adjoint (x, y, z PE coordinates; global index g); cget(a, o)
   // / yget(a, o) give c and (y0, y1) at offset o along axis a
@@ -592,8 +584,23 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
         pre_x1[k] = X1[g];
       }
     }
-    // the plane's own values
-    for (int i = tid; i < bx * by; i += nt) {
+    // the plane's own values: a thread's first kPre points are loaded into
+    // registers here and stored to LDS after the strip work, so that those
+    // loads and the strip work's are in flight together
+    Real pc[kPre], p0[kPre], p1[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = tid + k * nt;
+      pc[k] = p0[k] = p1[k] = Real(0);
+      if (i < bx * by) {
+        const int y = i / bx, x = i - y * bx;
+        const int64_t g = gindex(p, x0 + x, y0 + y, 0);
+        pc[k] = C[g];
+        p0[k] = Yg0[g];
+        p1[k] = Yg1[g];
+      }
+    }
+    for (int i = tid + kPre * nt; i < bx * by; i += nt) {
       const int y = i / bx, x = i - y * bx;
       const int64_t g = gindex(p, x0 + x, y0 + y, 0);
       const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
@@ -626,6 +633,17 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
           const int at = a == 0 ? (DIM >= 2 ? sp.l[1] + S : 0) * W + ta + S : (ta + S) * W + sp.l[0] + S;
           Cl[at] = halo_value<Real>(q, sp, s_wt);
         }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int i = tid + k * nt;
+      if (i < bx * by) {
+        const int y = i / bx, x = i - y * bx;
+        const int at = (DIM >= 2 ? y + S : 0) * W + x + S;
+        Cl[at] = pc[k];
+        Y0l[at] = p0[k];
+        Y1l[at] = p1[k];
       }
     }
     __syncthreads();

@@ -30,6 +30,7 @@ struct AdjParams {
   void* aring;                     // adjoint ring of the stage field, anslots slots
   int anslots;
   double* partial;                 // [adj_partials] alpha-gradient partial sums
+  double wt[kMaxL][kMaxT];         // level weights c_m(k) of every delay k < L (host-computed)
 };
 
 int adj_blocks(int64_t npts);

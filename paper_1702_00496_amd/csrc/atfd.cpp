@@ -979,6 +979,11 @@ at_status at_adjoint(at_ctx* c, int64_t nsteps, int32_t every, const void* seed_
       q.anslots = a.anslots;
       q.seg_start = seg;
       q.partial = reinterpret_cast<double*>(sc + a.off_partial);
+      for (int k = 0; k < kMaxL; ++k) {
+        double w[kMaxT] = {0.0, 0.0, 0.0, 0.0};
+        level_weights(k, c->delay.mode == AT_SYNC ? 1 : c->g.T, w);
+        for (int m = 0; m < kMaxT; ++m) q.wt[k][m] = w[m];
+      }
       for (int f = 0; f < 6; ++f) q.pfo[f] = c->lay.face_off[f] / c->g.npe;
       if (a.rk2) {
         // stage 2: sigma = dJ/du*^n from mu = dt/2 lambda^{n+1}
