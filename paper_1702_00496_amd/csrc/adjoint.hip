@@ -108,9 +108,10 @@ struct StripPt {
   int l[3];
 };
 
+template <int S>
 __device__ inline StripPt strip_point(const AdjParams& q, int t) {
   const StepParams& p = q.sp;
-  const int S = p.s, blk = static_cast<int>(p.pe_block);
+  const int blk = static_cast<int>(p.pe_block);
   StripPt s;
   s.pe = t / blk;
   const int r = t - s.pe * blk;
@@ -189,11 +190,10 @@ __device__ inline double tap_k(const AdjParams& q, int a, int o, double ci) {
 // Scatter of step n (gather form): every strip value e of face F of PE q
 // collects the transposed taps of the consumer PE across F, weighted by the
 // consumer's level weights, into the adjoint ring slots of levels n-k-m.
-template <typename Real>
+template <typename Real, int S>
 __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT],
                                     Real* drain = nullptr) {
   const StepParams& p = q.sp;
-  const int S = p.s;
   Real* aring = static_cast<Real*>(q.aring);
   const int pe = sp.pe, F = sp.F, d = sp.d, a = F >> 1;
   const int* l = sp.l;
@@ -209,6 +209,7 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const
   // select after unconditional loads from a clamped (in-PE) point, so that
   // every load of the element is in flight together
   double g = 0.0;
+#pragma unroll
   for (int o = -S; o <= S; ++o) {
     if (o == 0) continue;
     const int ia = jp - o;
@@ -235,13 +236,18 @@ __device__ inline void scatter_elem(const AdjParams& q, const StripPt& sp, const
     dst[m] = aring + ring_at_pt(p, slot, pe, F, lsF, S);
     old[m] = static_cast<double>(*dst[m]);
   }
+  // the level-n entry, read with the others (before the taps' sum is used)
+  Real* en = nullptr;
+  Real en_old = Real(0);
+  if (drain) {
+    en = aring + ring_at_pt(p, static_cast<int>(q.n % q.anslots), pe, F, lsF, S);
+    en_old = *en;
+  }
   if (drain) {
     // the caller drains level n here: its entry (this step's contribution
     // added when k = 0, as below) goes to *drain and the ring entry is
     // cleared; only older levels stay in the ring
-    const int slot_n = static_cast<int>(q.n % q.anslots);
-    Real* en = aring + ring_at_pt(p, slot_n, pe, F, lsF, S);
-    *drain = k == 0 ? static_cast<Real>(old[0] + w[0] * g) : *en;
+    *drain = k == 0 ? static_cast<Real>(old[0] + w[0] * g) : en_old;
     *en = Real(0);
 #pragma unroll
     for (int m = 0; m < kMaxT; ++m) {
@@ -279,10 +285,9 @@ __device__ inline double level_value(const AdjParams& q, int64_t l, int slot, in
 // consumer PE, face f and element e of the producer strip it reads, the AT
 // combination of the stored levels (the synchronous scheme: level n).
 // hbuf[pe * pe_block + (per-PE offset of face f) + e].
-template <typename Real>
+template <typename Real, int S>
 __device__ inline Real halo_value(const AdjParams& q, const StripPt& sp, const double (*wt)[kMaxT]) {
   const StepParams& p = q.sp;
-  const int S = p.s;
   const int T = adj_levels(p);
   const int pe = sp.pe, f = sp.F, d = sp.d, a = f >> 1, pf = f ^ 1;
   int ls[3] = {sp.l[0], sp.l[1], sp.l[2]};
@@ -310,14 +315,14 @@ __device__ inline Real halo_value(const AdjParams& q, const StripPt& sp, const d
   return static_cast<Real>(v);
 }
 
-template <typename Real>
+template <typename Real, int S>
 __device__ inline void halo_elem(const AdjParams& q, int t, const StripPt& sp, const double (*wt)[kMaxT]) {
-  static_cast<Real*>(q.hbuf)[t] = halo_value<Real>(q, sp, wt);
+  static_cast<Real*>(q.hbuf)[t] = halo_value<Real, S>(q, sp, wt);
 }
 
 // One thread per strip value t: its forward halo value (consumer view) and its
 // adjoint-ring scatter (producer view) share the decode of t.
-template <typename Real>
+template <typename Real, int S>
 __global__ __launch_bounds__(kAdjThreads) void adj_strip_kernel(AdjParams q) {
   // the level weights c_m(k) of every delay k < L (the delays are clamped
   // below L), once per workgroup
@@ -326,9 +331,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_strip_kernel(AdjParams q) {
   __syncthreads();
   const int total = q.sp.npe * static_cast<int>(q.sp.pe_block);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-    const StripPt sp = strip_point(q, t);
-    halo_elem<Real>(q, t, sp, s_wt);
-    scatter_elem<Real>(q, sp, s_wt);
+    const StripPt sp = strip_point<S>(q, t);
+    halo_elem<Real, S>(q, t, sp, s_wt);
+    scatter_elem<Real, S>(q, sp, s_wt);
   }
 }
 
@@ -622,16 +627,16 @@ __global__ __launch_bounds__(kAdjPeThreads) void adj_lambda_pe_kernel(AdjParams 
       for (int r = tid; r < 2 * blk; r += nt) {
         const bool scat = r >= blk;
         const int rr = scat ? r - blk : r;
-        const StripPt sp = strip_point(q, pe * blk + rr);
+        const StripPt sp = strip_point<S>(q, pe * blk + rr);
         if (scat) {
-          scatter_elem<Real>(q, sp, s_wt, Dl + rr);
+          scatter_elem<Real, S>(q, sp, s_wt, Dl + rr);
         } else {
           // frame position of the value: depth d of the producer strip is
           // column d - S (low face) or b + d (high face) along its axis
           const int a = sp.F >> 1, b = a == 0 ? bx : by;
           const int ta = (sp.F & 1) ? b + sp.d : sp.d - S;
           const int at = a == 0 ? (DIM >= 2 ? sp.l[1] + S : 0) * W + ta + S : (ta + S) * W + sp.l[0] + S;
-          Cl[at] = halo_value<Real>(q, sp, s_wt);
+          Cl[at] = halo_value<Real, S>(q, sp, s_wt);
         }
       }
     }
@@ -842,6 +847,17 @@ hipError_t launch_lambda_pe(const AdjParams& q, hipStream_t st) {
 }
 
 template <typename Real>
+hipError_t launch_strip(const AdjParams& q, int blocks, hipStream_t st) {
+  switch (q.sp.s) {
+    case 1: hipLaunchKernelGGL((adj_strip_kernel<Real, 1>), dim3(blocks), dim3(kAdjThreads), 0, st, q); break;
+    case 2: hipLaunchKernelGGL((adj_strip_kernel<Real, 2>), dim3(blocks), dim3(kAdjThreads), 0, st, q); break;
+    case 3: hipLaunchKernelGGL((adj_strip_kernel<Real, 3>), dim3(blocks), dim3(kAdjThreads), 0, st, q); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
 hipError_t launch_lambda(const AdjParams& q, int blocks, hipStream_t st) {
   const int key = q.sp.ndim * 10 + q.sp.s;
   switch (key) {
@@ -894,11 +910,17 @@ hipError_t launch_adj_step(const AdjParams& q, bool f64, hipStream_t st) {
   // the 1-D / 2-D PE-tiled stage kernel does its PE's strip work itself
   const bool strip_kernel = !(pe && q.sp.ndim <= 2);
   if (f64) {
-    if (strip_kernel) hipLaunchKernelGGL(adj_strip_kernel<double>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    if (strip_kernel) {
+      hipError_t e = launch_strip<double>(q, sblocks, st);
+      if (e != hipSuccess) return e;
+    }
     hipError_t e = pe ? launch_lambda_pe<double>(q, st) : launch_lambda<double>(q, lblocks, st);
     if (e != hipSuccess) return e;
   } else {
-    if (strip_kernel) hipLaunchKernelGGL(adj_strip_kernel<float>, dim3(sblocks), dim3(kAdjThreads), 0, st, q);
+    if (strip_kernel) {
+      hipError_t e = launch_strip<float>(q, sblocks, st);
+      if (e != hipSuccess) return e;
+    }
     hipError_t e = pe ? launch_lambda_pe<float>(q, st) : launch_lambda<float>(q, lblocks, st);
     if (e != hipSuccess) return e;
   }
