@@ -16,9 +16,10 @@
 //   out_j = (base terms) + D_j mu_j + sum_{o: j-o in the PE of j} K_{j-o,a,o} mu_{j-o} + A^n_j,
 // where A^l gathers, at the edge strips that neighbours read, K_{i,a,o} c_m(k)
 // mu_i of every later step with n - k - m = l: an adjoint ring of the forward
-// ring's shape, filled by the strip kernel (in gather form: one thread per
-// strip value) and drained when the sweep reaches level l. The
-// alpha-gradient adds <mu, dF/dalpha> = <mu, AT Laplacian of c>.
+// ring's shape, filled in gather form (one thread per strip value: the strip
+// kernel in 3-D, the stage kernel's own strip phase in 1-D / 2-D) and drained
+// when the sweep reaches level l. The alpha-gradient adds
+// <mu, dF/dalpha> = <mu, AT Laplacian of c>.
 //
 // Euler/AB2 (Sec. 4.1 eqs. time_disc, time_ab2): one stage per step, mu =
 // dt (beta0 lambda^{n+1} + beta1 lambda^{n+2}), out = lambda^n with base
@@ -432,9 +433,12 @@ __global__ __launch_bounds__(kAdjThreads) void adj_lambda_kernel(AdjParams q) {
 // PE-tiled form of adj_lambda_kernel (same formula, same per-point order of
 // the sums): one workgroup per PE, every global value loaded once.
 //  - 1-D / 2-D: the PE's plane in LDS: the stage values c with the frame of
-//    forward halo values (hbuf) the stencil reads across the PE's faces, and
-//    the two mu fields y0, y1 with a zero frame (taps of consumer points
-//    outside the PE reach this point through the adjoint ring instead).
+//    forward halo values the stencil reads across the PE's faces, and the two
+//    mu fields y0, y1 with a zero frame (taps of consumer points outside the
+//    PE reach this point through the adjoint ring instead). The workgroup
+//    first does its PE's strip work (the halo values straight into the frame,
+//    the gather-form scatter into its own adjoint-ring entries, the level-n
+//    drains into LDS), so no strip kernel runs before it.
 //  - 3-D: each thread owns one (x, y) column of the PE and streams it in z
 //    with register queues of 2S+1 planes of c, y0 and y1 (the z halo values
 //    of c from hbuf, zeros for y0 and y1 beyond the PE), the x/y neighbours
