@@ -285,7 +285,7 @@ def _random_case(seed):
     return case, rng.choice(("f64", "f32"))
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(48))
 def test_adjoint_random_configuration_matches_oracle_gradients(seed):
     case, precision = _random_case(7000 + seed)
     _say(f"[adj] random {seed}: {case} {precision}")

@@ -48,7 +48,7 @@ def draw(seed):
     return case, precision, depth
 
 
-@pytest.mark.parametrize("seed", range(48))
+@pytest.mark.parametrize("seed", range(128))
 def test_random_fast3d_configuration_matches_the_oracle(seed):
     case, precision, depth = draw(500 + seed)
     print(f"[fast3d] seed {seed}: {case} {precision} variant {depth}", flush=True)
