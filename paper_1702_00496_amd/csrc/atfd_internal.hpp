@@ -15,6 +15,7 @@ constexpr int kMaxS = 3;
 constexpr int kMaxModes = 16;
 constexpr int kThreads = 256;          // workgroup size of the helper kernels
 constexpr int kMaxSweepThreads = 1024; // largest workgroup of the generic sweep
+constexpr int kMaxVec3Threads = 768;   // ... of its pipelined 3-D vector path (168 VGPRs per lane)
 constexpr size_t kLdsLimit = 160 * 1024;
 
 // ---------------------------------------------------------------- generator
@@ -260,6 +261,18 @@ inline bool chunk_variant(int v) {
 }
 // the generic sweep may split a PE's planes over several workgroups
 bool sweep_can_chunk(const StepParams& p);
+
+// Whether a 3-D PE is swept by the pipelined form of the generic sweep's
+// vector path (where the instance has it): every thread owns at most one
+// quad and one halo item (of the 2 sd (bx + by)) of a plane, at most
+// kMaxVec3Threads threads.
+inline bool vec_pipe(const StepParams& p, int sd) {
+  if (p.ndim != 3) return false;
+  const int64_t quads = static_cast<int64_t>(p.bx / 4) * p.by;
+  const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + p.by);
+  return quads <= kMaxVec3Threads && halos <= kMaxVec3Threads;
+}
+
 hipError_t launch_step_fast3d(const StepParams& p, bool f64, int s, hipStream_t st);
 
 }  // namespace atfd

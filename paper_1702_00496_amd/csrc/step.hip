@@ -146,11 +146,15 @@ int sweep_threads(const StepParams& p) {
 
 // Workgroup size of the vector path: two quads of a plane per thread in 1-D
 // and 2-D (their loads issued together), one in 3-D, with the same cap as
-// above.
-int vec_threads(const StepParams& p) {
+// above; where the 3-D sweep is pipelined, as many threads as the larger of
+// the plane's quad and halo item counts.
+int vec_threads(const StepParams& p, int sd) {
   const int64_t quads = static_cast<int64_t>(p.bx / 4) * (p.ndim >= 2 ? p.by : 1);
-  // 3-D: one quad of a plane per thread (a barrier per plane); 1-D / 2-D:
-  // two quads per thread
+  if (vec_pipe(p, sd)) {
+    const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + p.by);
+    const int64_t t = ((quads > halos ? quads : halos) + 63) / 64 * 64;
+    return static_cast<int>(t < kMaxVec3Threads ? t : kMaxVec3Threads);
+  }
   int64_t t = ((p.ndim == 3 ? quads : (quads + 1) / 2) + 63) / 64 * 64;
   if (t < 64) t = 64;
   const int64_t cap = (p.ndim == 3 || p.npe < 4 * 256) ? kMaxSweepThreads : 256;
@@ -235,7 +239,7 @@ template <typename Real, int DIM, int S, int SP>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
   const size_t lds = lds_bytes_t<Real, DIM, S, SP>(p);
   const bool vec = use_vec(p);
-  const int threads = vec ? vec_threads(p) : sweep_threads(p);
+  const int threads = vec ? vec_threads(p, strip_depth<S, SP>()) : sweep_threads(p);
   const int blocks = p.npe * sweep_chunks(p, lds, threads, strip_depth<S, SP>());
   if (vec) return launch_vec_unit<Real, DIM>(p, st, blocks, threads, lds);
   hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(blocks), dim3(threads), lds, st, p);

@@ -132,23 +132,33 @@ struct Sweep {
   // the producer strip; m = the buffer point's distance from the face - 1.
   // AT: sum over the T delayed levels, in double. SYNC: the neighbour's
   // level-n value at global position (gx, gy, gz). Non-uniform scheme: the
-  // single level of buffer point m.
-  __device__ Real halo(int f, int plane, int r, int m, int gx, int gy, int gz) const {
-    if (p.mode == AT_SYNC) return centre[gidx(gx, gy, gz)];
+  // single level of buffer point m. halo_raw issues the loads, halo_sum
+  // combines them, so that a pipelined sweep can load a plane's halo values
+  // one plane ahead of their combination.
+  __device__ void halo_raw(int f, int plane, int r, int m, int gx, int gy, int gz, Real (&v)[kMaxT]) const {
+    if (p.mode == AT_SYNC) {
+      v[0] = centre[gidx(gx, gy, gz)];
+      return;
+    }
     const int pf = f ^ 1;   // producer face: the opposite side
     const int nb = nbr[f];
-    if constexpr (SP == 3) return ring_rd[ring_off(lev_slot[f * kMaxT + m], nb, pf, plane, r)];
+    if constexpr (SP == 3) {
+      v[0] = ring_rd[ring_off(lev_slot[f * kMaxT + m], nb, pf, plane, r)];
+      return;
+    }
     // every level is loaded from an in-range slot so that the T loads are in
     // flight together; a level of weight zero (k = 0: exact synchronous
     // value) is then dropped by the select
     const int64_t base = ring_off(0, nb, pf, plane, r);
     const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
-    Real v[kMaxT];
 #pragma unroll
-    for (int m = 0; m < kMaxT; ++m) {
-      const int sl = lev_slot[f * kMaxT + m];
-      v[m] = ring_rd[base + (m < p.T && sl > 0 ? sl : 0) * slot_stride];
+    for (int mm = 0; mm < kMaxT; ++mm) {
+      const int sl = lev_slot[f * kMaxT + mm];
+      v[mm] = ring_rd[base + (mm < p.T && sl > 0 ? sl : 0) * slot_stride];
     }
+  }
+  __device__ Real halo_sum(int f, const Real (&v)[kMaxT]) const {
+    if (p.mode == AT_SYNC || SP == 3) return v[0];
     double acc = 0.0;
 #pragma unroll
     for (int m = 0; m < kMaxT; ++m) {
@@ -156,6 +166,54 @@ struct Sweep {
       if (m < p.T && sl >= 0) acc += w[f * kMaxT + m] * static_cast<double>(v[m]);
     }
     return static_cast<Real>(acc);
+  }
+  __device__ Real halo(int f, int plane, int r, int m, int gx, int gy, int gz) const {
+    Real v[kMaxT];
+    halo_raw(f, plane, r, m, gx, gy, gz, v);
+    return halo_sum(f, v);
+  }
+
+  // Item h < 2 SD (by + bx) of an in-box plane's x/y halo frame: the x halos
+  // (producer strip [z][y][d]) first, then the y halos (producer strip
+  // [z][d][x]). at = LDS offset in the plane, f = face, r = element of the
+  // producer strip's plane, m = distance from the face - 1, (gx, gy) = the
+  // global position (synchronous arm).
+  struct HaloItem {
+    int at, f, r, m, gx, gy;
+  };
+  __device__ HaloItem halo_item(int h) const {
+    const int bx = p.bx, by = p.by;
+    const int nxh = 2 * SD * by;
+    HaloItem it;
+    if (h < nxh) {
+      const int side = h >= SD * by ? 1 : 0, r = side ? h - SD * by : h, d = r % SD, y = r / SD;
+      const int xl = side ? bx + d : d - SD;
+      it.at = (DIM >= 2 ? y + SD : 0) * px_stride + xl + co;
+      it.f = side;
+      it.r = y * SD + d;
+      it.m = side ? d : SD - 1 - d;
+      it.gx = wrap(x0 + xl, p.nx);
+      it.gy = y0 + y;
+    } else {
+      const int hy = h - nxh;
+      const int side = hy >= SD * bx ? 1 : 0;
+      int x = side ? hy - SD * bx : hy, d = 0;   // x = r % bx, d = r / bx < SD
+#pragma unroll
+      for (int i = 1; i < SD; ++i) {
+        if (x >= bx) {
+          x -= bx;
+          ++d;
+        }
+      }
+      const int yl = side ? by + d : d - SD;
+      it.at = (yl + SD) * px_stride + x + co;
+      it.f = 2 + side;
+      it.r = d * bx + x;
+      it.m = side ? d : SD - 1 - d;
+      it.gx = x0 + x;
+      it.gy = wrap(y0 + yl, p.ny);
+    }
+    return it;
   }
 
   // Point i = tid + k nt of a bx * by plane as (x, y), stepped from k to k + 1
@@ -178,7 +236,7 @@ struct Sweep {
     }
   };
 
-  __device__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
+  __device__ __forceinline__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
     Real* P = lds + slot_of<DIM, SD>(zz) * plane;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
@@ -225,31 +283,11 @@ struct Sweep {
             if (at[k] >= 0) P[at[k]] = v[k];
         }
       }
-      // x halos (producer strip [z][y][d]) and y halos (producer strip
-      // [z][d][x]) in one pass, so that their loads overlap
-      const int nxh = 2 * SD * by, nh = (parts & kPlaneHalos) ? nxh + (DIM >= 2 ? 2 * SD * bx : 0) : 0;
+      // x halos and y halos in one pass, so that their loads overlap
+      const int nh = (parts & kPlaneHalos) ? 2 * SD * by + (DIM >= 2 ? 2 * SD * bx : 0) : 0;
       for (int h = tid; h < nh; h += nt) {
-        if (h < nxh) {
-          const int side = h >= SD * by ? 1 : 0, r = side ? h - SD * by : h, d = r % SD, y = r / SD;
-          const int xl = side ? bx + d : d - SD;
-          const int gx = wrap(x0 + xl, p.nx);
-          P[(DIM >= 2 ? y + SD : 0) * px_stride + xl + co] =
-              halo(side, zz, y * SD + d, side ? d : SD - 1 - d, gx, y0 + y, gz);
-        } else {
-          const int hy = h - nxh;
-          const int side = hy >= SD * bx ? 1 : 0;
-          int x = side ? hy - SD * bx : hy, d = 0;   // x = r % bx, d = r / bx < SD
-#pragma unroll
-          for (int i = 1; i < SD; ++i) {
-            if (x >= bx) {
-              x -= bx;
-              ++d;
-            }
-          }
-          const int yl = side ? by + d : d - SD;
-          const int gy = wrap(y0 + yl, p.ny);
-          P[(yl + SD) * px_stride + x + co] = halo(2 + side, zz, d * bx + x, side ? d : SD - 1 - d, x0 + x, gy, gz);
-        }
+        const HaloItem hi = halo_item(h);
+        P[hi.at] = halo(hi.f, zz, hi.r, hi.m, hi.gx, hi.gy, gz);
       }
     } else {
       // z halo plane: producer strip [d][y][x]
@@ -263,7 +301,107 @@ struct Sweep {
     }
   }
 
-  __device__ void compute_plane(int z) {
+  // Previous-level fields the update of a vector-path stage reads: pre_a
+  // (f^{n-1}, or u^n for the second Heun stage), pre_b (f^{n-2}, AB3 from
+  // n = 2); any = whether the stage reads one at all.
+  template <int KIND>
+  __device__ void history(const Real*& pre_a, const Real*& pre_b, bool& any, bool& ab3) const {
+    const bool ab = (KIND == kVAb2 || KIND == kVAb3) && n > 0;
+    ab3 = KIND == kVAb3 && n >= 2;
+    any = KIND == kVRk2 || ab;
+    pre_a = static_cast<const Real*>(KIND == kVRk2 ? p.ubuf[n & 1] : ab3 ? p.fbuf[(n - 1) & 1] : p.fbuf[0]);
+    pre_b = static_cast<const Real*>(p.fbuf[n & 1]);
+  }
+
+  // Pipelined 3-D vector sweep. The global loads of a plane (the thread's
+  // quad of u, the kMaxT raw delayed levels of its halo item, its history
+  // quads) are issued one plane ahead into registers and written to LDS
+  // (the halo levels combined) when the plane enters the stencil, so that
+  // their latency overlaps the stencil work of the plane before. Every
+  // thread owns at most one quad and one halo item of a plane (the 3-D
+  // workgroup has as many threads as the larger count, up to 768: cross-
+  // sections of up to 768 quads). Addresses are fixed per thread and advance
+  // by a plane stride; loads go to clamped in-box planes and lanes, with no
+  // branch around them, and a load whose plane lies beyond the PE's high z
+  // face is not used (that plane comes from the z strips).
+  struct PipeAddr {
+    const Real* c;           // the thread's quad of u at plane 0
+    const Real* h[kMaxT];    // its halo item's levels at plane 0
+    int64_t hstride;         // halo plane stride
+    const Real* a;           // history quads at plane 0
+    const Real* b;
+    int c_at, h_at, hf;      // LDS offsets (-1: none) and the halo item's face
+  };
+  struct Prefetch {
+    Vec4<Real> c, pa, pb;
+    Real hv[kMaxT];
+  };
+  template <int KIND>
+  __device__ void pipe_setup(PipeAddr& pa) const {
+    const int tid = threadIdx.x;
+    const int qpr = p.bx >> 2, quads = qpr * p.by;
+    const int q = tid < quads ? tid : quads - 1;
+    const int qy = q / qpr, qx = q - qy * qpr;
+    const int64_t g0 = gidx(x0 + 4 * qx, y0 + qy, z0);
+    pa.c = centre + g0;
+    pa.c_at = tid < quads ? (qy + SD) * px_stride + 4 * qx + co : -1;
+    const Real *ha, *hb;
+    bool any, ab3;
+    history<KIND>(ha, hb, any, ab3);
+    pa.a = ha + g0;
+    pa.b = hb + g0;
+    const int nh = 2 * SD * (p.by + p.bx);
+    const HaloItem hi = halo_item(tid < nh ? tid : nh - 1);
+    pa.h_at = tid < nh ? hi.at : -1;
+    pa.hf = hi.f;
+    if (p.mode == AT_SYNC) {
+      // the neighbour's level-n value
+      const Real* src = centre + gidx(hi.gx, hi.gy, z0);
+#pragma unroll
+      for (int m = 0; m < kMaxT; ++m) pa.h[m] = src;
+      pa.hstride = static_cast<int64_t>(p.nx) * p.ny;
+      return;
+    }
+    const int nb = nbr[hi.f], pf = hi.f ^ 1;
+    pa.hstride = static_cast<int64_t>(p.npe) * (hi.f < 2 ? p.face_chunk[0] : p.face_chunk[2]);
+    if constexpr (SP == 3) {
+      const Real* src = ring_rd + ring_off(lev_slot[hi.f * kMaxT + hi.m], nb, pf, 0, hi.r);
+#pragma unroll
+      for (int m = 0; m < kMaxT; ++m) pa.h[m] = src;
+    } else {
+      const int64_t base = ring_off(0, nb, pf, 0, hi.r);
+      const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
+#pragma unroll
+      for (int m = 0; m < kMaxT; ++m) {
+        const int sl = lev_slot[hi.f * kMaxT + m];
+        pa.h[m] = ring_rd + base + (m < p.T && sl > 0 ? sl : 0) * slot_stride;
+      }
+    }
+  }
+  // Loads of in-box plane zz (u and halo) and, with hist, of the history of
+  // plane zh. The history fields of the multistep and second Heun stages
+  // exist from the first step on (a value loaded before the history is
+  // written is not used), so their loads need no branch.
+  template <int KIND>
+  __device__ __forceinline__ void pipe_load(const PipeAddr& pa, int zz, int zh, bool hist, Prefetch& pf) const {
+    const int64_t ps = static_cast<int64_t>(p.nx) * p.ny;
+    pf.c = ld4<Real>(pa.c + zz * ps);
+    const int64_t ho = zz * pa.hstride;
+#pragma unroll
+    for (int m = 0; m < kMaxT; ++m) pf.hv[m] = pa.h[m][ho];
+    if (hist && (KIND == kVAb2 || KIND == kVAb3 || KIND == kVRk2)) {
+      pf.pa = ld4<Real>(pa.a + zh * ps);
+      if (KIND == kVAb3) pf.pb = ld4<Real>(pa.b + zh * ps);
+    }
+  }
+  // The values loaded for plane zz into its LDS slot.
+  __device__ __forceinline__ void pipe_commit(const PipeAddr& pa, const Prefetch& pf, int zz) {
+    Real* P = lds + slot_of<DIM, SD>(zz) * plane;
+    if (pa.c_at >= 0) st4<Real>(P + pa.c_at, pf.c);
+    if (pa.h_at >= 0) P[pa.h_at] = halo_sum(pa.hf, pf.hv);
+  }
+
+  __device__ __forceinline__ void compute_plane(int z) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
     const Real* C = lds + slot_of<DIM, SD>(z) * plane;
@@ -460,8 +598,10 @@ struct Sweep {
   // Tables atschemes-left/right are added as a correction (their taps minus
   // the CD2 ones) only on the quads next to a face whose delay calls for them,
   // so the common quad runs no face logic.
+  // hist: the thread's history quads (pa, pb) when they were prefetched (one
+  // quad per thread), else nullptr.
   template <int KIND, int EQ>
-  __device__ void compute_plane_vec(int z) {
+  __device__ __forceinline__ void compute_plane_vec(int z, const Vec4<Real>* hist = nullptr) {
     static_assert(VEC, "vector layout only");
     using Q = Vec4<Real>;
     constexpr int QB = 2;   // quads per thread whose loads are issued together
@@ -491,10 +631,9 @@ struct Sweep {
     const int64_t gbase = gidx(x0, y0, z0 + z);
     // history and destinations of this stage
     const bool ab = (KIND == kVAb2 || KIND == kVAb3) && n > 0;
-    const bool ab3 = KIND == kVAb3 && n >= 2;
-    const Real* pre_a = static_cast<const Real*>(KIND == kVRk2 ? p.ubuf[n & 1]
-                                                : ab3 ? p.fbuf[(n - 1) & 1] : p.fbuf[0]);
-    const Real* pre_b = static_cast<const Real*>(p.fbuf[n & 1]);
+    const Real *pre_a, *pre_b;
+    bool any_hist, ab3;
+    history<KIND>(pre_a, pre_b, any_hist, ab3);
     Real* uout = static_cast<Real*>(KIND == kVRk1 ? p.ustar : p.ubuf[(n + 1) & 1]);
     Real* fout = static_cast<Real*>(KIND == kVAb3 ? (n == 0 ? p.fbuf[0] : n == 1 ? p.fbuf[1] : p.fbuf[n & 1])
                                                   : p.fbuf[0]);
@@ -513,7 +652,11 @@ struct Sweep {
         ys[j] = it.y;
         it.next();
       }
-      if (KIND == kVRk2 || ab) {   // uniform
+      if (hist != nullptr) {
+        // one quad per thread: the only live one is j = 0
+        pa[0] = hist[0];
+        pb[0] = hist[1];
+      } else if (any_hist) {   // uniform
 #pragma unroll
         for (int j = 0; j < QB; ++j) {
           const bool in = ys[j] < rows;
@@ -794,8 +937,18 @@ __device__ inline void nonuniform_face(const StepParams& p, int pid, int f, int6
 
 // VEC: the vector layout and path, specialised on the integrator stage KIND
 // and the equation EQ (the scalar path reads both at run time).
-template <typename Real, int DIM, int S, int SP, bool VEC = false, int KIND = 0, int EQ = 0>
-__global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p) {
+// Whether a 3-D vector-path instance has the pipelined form (the space-
+// expanded and non-uniform stencils, whose face corrections take more
+// registers, and sixth order in FP64 do not).
+template <typename Real, int S, int SP>
+constexpr bool pipe_form() {
+  return SP == 0 && (sizeof(Real) == 4 || S < 3);
+}
+
+// PIPE (3-D vector path only): the pipelined sweep, at most kMaxVec3Threads
+// threads, so that it may hold 168 VGPRs per lane.
+template <typename Real, int DIM, int S, int SP, bool VEC = false, int KIND = 0, int EQ = 0, bool PIPE = false>
+__global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_step_kernel(StepParams p) {
   constexpr int SD = strip_depth<S, SP>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
@@ -853,7 +1006,54 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
     const int zc1 = zc0 + zper < p.bz ? zc0 + zper : p.bz;
     faces();
     __syncthreads();
-    if (zc0 < zc1) {
+    if constexpr (PIPE) {
+      static_assert(VEC && DIM == 3 && pipe_form<Real, S, SP>(), "pipelined form");
+      // plane z + 1 + SD (u, halo) and the history of plane z + 1 are loaded
+      // while plane z is computed (two planes ahead measured no faster and
+      // takes more registers). The host launches this form only where every
+      // thread owns at most one quad and one halo item of a plane.
+      using SW = Sweep<Real, DIM, S, SP, VEC>;
+      if (zc0 < zc1) {
+        typename SW::PipeAddr pa;
+        sw.template pipe_setup<KIND>(pa);
+        const int bz = p.bz;
+        auto cl = [&](int zz) { return zz < 0 ? 0 : zz < bz ? zz : bz - 1; };
+        // the 2 SD planes before the first one computed: their loads, then
+        // those of the first iteration, are issued together
+        typename SW::Prefetch pro[2 * SD], pf;
+#pragma unroll
+        for (int i = 0; i < 2 * SD; ++i) sw.template pipe_load<KIND>(pa, cl(zc0 - SD + i), 0, false, pro[i]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pf.pa.v[e] = pf.pb.v[e] = Real(0);
+        sw.template pipe_load<KIND>(pa, cl(zc0 + SD), zc0, true, pf);
+#pragma unroll
+        for (int i = 0; i < 2 * SD; ++i) {
+          const int zz = zc0 - SD + i;
+          if (zz < 0 || zz >= bz)
+            sw.load_plane(zz);
+          else
+            sw.pipe_commit(pa, pro[i], zz);
+        }
+        // planes z whose plane z + SD lies in the PE: every load is
+        // unconditional (no register copies that would wait for them)
+        const int zm = zc1 < bz - SD ? zc1 : bz - SD;
+        int z = zc0;
+        for (; z < zm; ++z) {
+          sw.pipe_commit(pa, pf, z + SD);
+          const Vec4<Real> hq[2] = {pf.pa, pf.pb};
+          __syncthreads();
+          sw.template pipe_load<KIND>(pa, cl(z + 1 + SD), cl(z + 1), true, pf);
+          sw.template compute_plane_vec<KIND, EQ>(z, hq);
+        }
+        // the last SD planes of the PE (last chunk): plane z + SD comes
+        // from the z strips beyond the high face
+        for (; z < zc1; ++z) {
+          sw.load_plane(z + SD);
+          __syncthreads();
+          sw.template compute_plane_vec<KIND, EQ>(z);
+        }
+      }
+    } else if (zc0 < zc1) {
       for (int zz = zc0 - SD; zz < zc0 + SD; ++zz) sw.load_plane(zz);
       for (int z = zc0; z < zc1; ++z) {
         sw.load_plane(z + SD);
@@ -882,15 +1082,28 @@ __global__ __launch_bounds__(kMaxSweepThreads) void at_step_kernel(StepParams p)
 // Vector-path launches for one precision and dimension (instantiated in
 // step_vec_*.hip): dispatch on the scheme (half-width, space-expanded or
 // non-uniform family), the integrator stage and the equation.
+template <typename Real, int DIM, int S, int SP, int KIND, bool PIPE>
+hipError_t launch_vec_e(const StepParams& p, hipStream_t st, int blocks, int threads, size_t lds) {
+  if (p.equation == AT_ADVDIFF)
+    hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP, true, KIND, AT_ADVDIFF, PIPE>), dim3(blocks), dim3(threads),
+                       lds, st, p);
+  else
+    hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP, true, KIND, AT_BURGERS, PIPE>), dim3(blocks), dim3(threads),
+                       lds, st, p);
+  return hipGetLastError();
+}
+
 template <typename Real, int DIM, int S, int SP, int KIND>
 hipError_t launch_vec_k(const StepParams& p, hipStream_t st, int blocks, int threads, size_t lds) {
-  if (p.equation == AT_ADVDIFF)
-    hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP, true, KIND, AT_ADVDIFF>), dim3(blocks), dim3(threads), lds,
-                       st, p);
-  else
-    hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP, true, KIND, AT_BURGERS>), dim3(blocks), dim3(threads), lds,
-                       st, p);
-  return hipGetLastError();
+  if constexpr (DIM == 3 && pipe_form<Real, S, SP>()) {
+    if (vec_pipe(p, strip_depth<S, SP>())) {
+      // one quad and one halo item per thread (see vec_threads)
+      const int quads = (p.bx / 4) * p.by, halos = 2 * strip_depth<S, SP>() * (p.bx + p.by);
+      if (threads < quads || threads < halos || threads > kMaxVec3Threads) return hipErrorInvalidConfiguration;
+      return launch_vec_e<Real, DIM, S, SP, KIND, true>(p, st, blocks, threads, lds);
+    }
+  }
+  return launch_vec_e<Real, DIM, S, SP, KIND, false>(p, st, blocks, threads, lds);
 }
 
 template <typename Real, int DIM, int S, int SP>
