@@ -164,6 +164,7 @@ struct StepParams {
                                // 4 points per thread, z sweep direction alternating per launch
   int sweep_down;              // this launch sweeps z downward (alternating variants)
   int pe_major;                // u, f and u* stored PE after PE (the 32 x 32 path), see pe_major_offset
+  int yslices;                 // generic 3-D sweep: workgroups per PE along y (set per launch; 0, 1: one)
 };
 
 // Problems the 3-D path for 32 x 32 PE cross-sections takes store the
@@ -262,14 +263,14 @@ inline bool chunk_variant(int v) {
 // the generic sweep may split a PE's planes over several workgroups
 bool sweep_can_chunk(const StepParams& p);
 
-// Whether a 3-D PE is swept by the pipelined form of the generic sweep's
-// vector path (where the instance has it): every thread owns at most one
-// quad and one halo item (of the 2 sd (bx + by)) of a plane, at most
-// kMaxVec3Threads threads.
-inline bool vec_pipe(const StepParams& p, int sd) {
+// Whether a 3-D PE, swept in y-slices of `rows` rows, is swept by the
+// pipelined form of the generic sweep's vector path (where the instance has
+// it): every thread owns at most one quad and one halo item (of the
+// 2 sd (bx + rows)) of a slice's plane, at most kMaxVec3Threads threads.
+inline bool vec_pipe(const StepParams& p, int sd, int rows) {
   if (p.ndim != 3) return false;
-  const int64_t quads = static_cast<int64_t>(p.bx / 4) * p.by;
-  const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + p.by);
+  const int64_t quads = static_cast<int64_t>(p.bx / 4) * rows;
+  const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + rows);
   return quads <= kMaxVec3Threads && halos <= kMaxVec3Threads;
 }
 

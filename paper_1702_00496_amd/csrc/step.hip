@@ -121,7 +121,8 @@ size_t lds_bytes_t(const StepParams& p) {
   constexpr int SD = strip_depth<S, SP>();
   const int nsl = DIM == 3 ? 2 * SD + 2 : 1;
   const size_t row = use_vec(p) ? p.bx + 8 : p.bx + 2 * SD;
-  const size_t plane = static_cast<size_t>(DIM >= 2 ? p.by + 2 * SD : 1) * row;
+  const int rows = p.yslices > 1 ? p.by / p.yslices : p.by;   // a workgroup's y-slice
+  const size_t plane = static_cast<size_t>(DIM >= 2 ? rows + 2 * SD : 1) * row;
   return nsl * plane * sizeof(Real);
 }
 
@@ -147,11 +148,12 @@ int sweep_threads(const StepParams& p) {
 // Workgroup size of the vector path: two quads of a plane per thread in 1-D
 // and 2-D (their loads issued together), one in 3-D, with the same cap as
 // above; where the 3-D sweep is pipelined, as many threads as the larger of
-// the plane's quad and halo item counts.
+// the quad and halo item counts of a y-slice's plane.
 int vec_threads(const StepParams& p, int sd) {
-  const int64_t quads = static_cast<int64_t>(p.bx / 4) * (p.ndim >= 2 ? p.by : 1);
-  if (vec_pipe(p, sd)) {
-    const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + p.by);
+  const int rows = p.yslices > 1 ? p.by / p.yslices : p.by;
+  const int64_t quads = static_cast<int64_t>(p.bx / 4) * (p.ndim >= 2 ? rows : 1);
+  if (vec_pipe(p, sd, rows)) {
+    const int64_t halos = 2 * static_cast<int64_t>(sd) * (p.bx + rows);
     const int64_t t = ((quads > halos ? quads : halos) + 63) / 64 * 64;
     return static_cast<int>(t < kMaxVec3Threads ? t : kMaxVec3Threads);
   }
@@ -160,6 +162,20 @@ int vec_threads(const StepParams& p, int sd) {
   const int64_t cap = (p.ndim == 3 || p.npe < 4 * 256) ? kMaxSweepThreads : 256;
   if (t > cap) t = cap;
   return static_cast<int>(t);
+}
+
+// Workgroups per PE along y of the 3-D vector sweep: two halves of the PE's
+// rows where a whole cross-section is too large for the pipelined form but a
+// half is not (more than 768 quads, e.g. 64 x 64: 256^3 in 4^3 PEs 99 -> 82
+// us per step), the instance has that form and the planes may be split (as
+// for z-chunks). Halving cross-sections that are pipelined already measured
+// slower (192^3 in 4^3 PEs 43.9 -> 47.4 us).
+template <typename Real, int S, int SP>
+int sweep_yslices(const StepParams& p) {
+  constexpr int sd = strip_depth<S, SP>();
+  if (!pipe_form<Real, S, SP>() || p.ndim != 3 || !use_vec(p) || !sweep_can_chunk(p)) return 1;
+  if (vec_pipe(p, sd, p.by) || p.by % 2 != 0 || p.by / 2 < sd || !vec_pipe(p, sd, p.by / 2)) return 1;
+  return 2;
 }
 
 // Workgroups per PE of the generic sweep. A 3-D PE's planes are split into
@@ -189,7 +205,7 @@ int sweep_chunks(const StepParams& p, size_t lds, int threads, int sd) {
   if (p.npe >= kNumCUs) {
     // every CU already has a PE: chunks only add co-resident workgroups,
     // as many as fill one resident round, of at least 8 planes each
-    const int want = static_cast<int>(slots / p.npe);
+    const int want = static_cast<int>(slots / (static_cast<int64_t>(p.npe) * (p.yslices > 1 ? p.yslices : 1)));
     if (want <= 1) return 1;
     int zper = (p.bz + want - 1) / want;
     if (zper < 8) zper = 8;
@@ -201,8 +217,9 @@ int sweep_chunks(const StepParams& p, size_t lds, int threads, int sd) {
   // resident round and leave no chunk empty (the fewest chunks on a tie)
   int best = 1;
   int64_t best_cost = -1;
+  const int nys = p.yslices > 1 ? p.yslices : 1;
   for (int nch = 1; nch <= p.bz; ++nch) {
-    const int64_t wgs = static_cast<int64_t>(p.npe) * nch;
+    const int64_t wgs = static_cast<int64_t>(p.npe) * nch * nys;
     if (wgs > slots && nch > 1) break;
     const int zper = (p.bz + nch - 1) / nch;
     if ((p.bz + zper - 1) / zper != nch) continue;
@@ -235,14 +252,23 @@ hipError_t launch_vec_unit(const StepParams& p, hipStream_t st, int blocks, int 
                     : launch_step_vec_f64_d3(p, st, blocks, threads, lds);
 }
 
+// The launch parameters of one sweep: p with the y-slice count set.
+template <typename Real, int DIM, int S, int SP>
+StepParams launch_params(const StepParams& p) {
+  StepParams q = p;
+  q.yslices = DIM == 3 && use_vec(p) ? sweep_yslices<Real, S, SP>(p) : 1;
+  return q;
+}
+
 template <typename Real, int DIM, int S, int SP>
 hipError_t launch_t(const StepParams& p, hipStream_t st) {
-  const size_t lds = lds_bytes_t<Real, DIM, S, SP>(p);
   const bool vec = use_vec(p);
-  const int threads = vec ? vec_threads(p, strip_depth<S, SP>()) : sweep_threads(p);
-  const int blocks = p.npe * sweep_chunks(p, lds, threads, strip_depth<S, SP>());
-  if (vec) return launch_vec_unit<Real, DIM>(p, st, blocks, threads, lds);
-  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(blocks), dim3(threads), lds, st, p);
+  const StepParams q = launch_params<Real, DIM, S, SP>(p);
+  const size_t lds = lds_bytes_t<Real, DIM, S, SP>(q);
+  const int threads = vec ? vec_threads(q, strip_depth<S, SP>()) : sweep_threads(q);
+  const int blocks = p.npe * sweep_chunks(q, lds, threads, strip_depth<S, SP>()) * q.yslices;
+  if (vec) return launch_vec_unit<Real, DIM>(q, st, blocks, threads, lds);
+  hipLaunchKernelGGL((at_step_kernel<Real, DIM, S, SP>), dim3(blocks), dim3(threads), lds, st, q);
   return hipGetLastError();
 }
 
@@ -279,15 +305,21 @@ hipError_t dispatch_dim(const StepParams& p, int s, hipStream_t st, bool pub) {
   return hipErrorInvalidValue;
 }
 
+// LDS of one workgroup of the sweep as launch_t launches it
+template <typename Real, int DIM, int S, int SP>
+size_t lds_launch(const StepParams& p) {
+  return lds_bytes_t<Real, DIM, S, SP>(launch_params<Real, DIM, S, SP>(p));
+}
+
 template <typename Real, int DIM>
 size_t lds_s(const StepParams& p, int s) {
-  if (p.scheme == AT_SCHEME_SPACE_212) return lds_bytes_t<Real, DIM, 1, 1>(p);
-  if (p.scheme == AT_SCHEME_SPACE_222) return lds_bytes_t<Real, DIM, 1, 2>(p);
-  if (p.scheme == AT_SCHEME_NONUNIFORM_212) return lds_bytes_t<Real, DIM, 1, 3>(p);
+  if (p.scheme == AT_SCHEME_SPACE_212) return lds_launch<Real, DIM, 1, 1>(p);
+  if (p.scheme == AT_SCHEME_SPACE_222) return lds_launch<Real, DIM, 1, 2>(p);
+  if (p.scheme == AT_SCHEME_NONUNIFORM_212) return lds_launch<Real, DIM, 1, 3>(p);
   switch (s) {
-    case 1: return lds_bytes_t<Real, DIM, 1, 0>(p);
-    case 2: return lds_bytes_t<Real, DIM, 2, 0>(p);
-    case 3: return lds_bytes_t<Real, DIM, 3, 0>(p);
+    case 1: return lds_launch<Real, DIM, 1, 0>(p);
+    case 2: return lds_launch<Real, DIM, 2, 0>(p);
+    case 3: return lds_launch<Real, DIM, 3, 0>(p);
   }
   return ~size_t(0);
 }

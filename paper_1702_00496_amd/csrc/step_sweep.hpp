@@ -79,6 +79,7 @@ struct Sweep {
   int pid, qx, qy, qz, x0, y0, z0;
   int px_stride, plane;     // LDS row stride and plane size
   int co;                   // LDS column of x = 0
+  int yl0, rows_sl;         // the workgroup's y-slice of the PE: first row, rows
   int64_t n;
   const Real* centre;       // field whose level-n values feed the stencil
   const Real* ring_rd;      // ring the halos come from
@@ -92,7 +93,7 @@ struct Sweep {
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
                    const int* ls_, const int* nb_, const int* kp_, const Real* nu_)
       : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
-    pid = blockIdx.x % p.npe;   // workgroups beyond npe take further z-chunks of the PEs
+    pid = blockIdx.x % p.npe;   // workgroups beyond npe take further z-chunks (y-slices) of the PEs
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
     qz = pid / (p.px * p.py);
@@ -101,10 +102,21 @@ struct Sweep {
     z0 = qz * p.bz;
     co = VEC ? 4 : SD;
     px_stride = VEC ? p.bx + 8 : p.bx + 2 * SD;
+    yl0 = 0;
+    rows_sl = p.by;
     plane = (DIM >= 2 ? p.by + 2 * SD : 1) * px_stride;
     const bool rk2 = p.stage == kStageRk2;
     centre = static_cast<const Real*>(rk2 ? p.ustar : p.ubuf[n & 1]);
     ring_rd = static_cast<const Real*>(rk2 ? p.sring : p.ring);
+  }
+
+  // Slice ys of nys equal y-slices (3-D pipelined sweep): the workgroup's
+  // LDS planes then hold its rows and the SD rows on either side, which come
+  // from the PE's own level-n values where the slice edge is inside the PE.
+  __device__ void set_slice(int ys, int nys) {
+    rows_sl = p.by / nys;
+    yl0 = ys * rows_sl;
+    plane = (rows_sl + 2 * SD) * px_stride;
   }
 
   // v mod n for v in [-n, 2n): a periodic index one strip depth outside the box
@@ -177,23 +189,27 @@ struct Sweep {
   // (producer strip [z][y][d]) first, then the y halos (producer strip
   // [z][d][x]). at = LDS offset in the plane, f = face, r = element of the
   // producer strip's plane, m = distance from the face - 1, (gx, gy) = the
-  // global position (synchronous arm).
+  // global position (synchronous arm; and the y halos of a y-slice whose edge
+  // is inside the PE, inner: the PE's own level-n values). Rows are those of
+  // the workgroup's y-slice.
   struct HaloItem {
     int at, f, r, m, gx, gy;
+    bool inner;
   };
   __device__ HaloItem halo_item(int h) const {
-    const int bx = p.bx, by = p.by;
+    const int bx = p.bx, by = rows_sl;
     const int nxh = 2 * SD * by;
     HaloItem it;
+    it.inner = false;
     if (h < nxh) {
       const int side = h >= SD * by ? 1 : 0, r = side ? h - SD * by : h, d = r % SD, y = r / SD;
       const int xl = side ? bx + d : d - SD;
       it.at = (DIM >= 2 ? y + SD : 0) * px_stride + xl + co;
       it.f = side;
-      it.r = y * SD + d;
+      it.r = (yl0 + y) * SD + d;
       it.m = side ? d : SD - 1 - d;
       it.gx = wrap(x0 + xl, p.nx);
-      it.gy = y0 + y;
+      it.gy = y0 + yl0 + y;
     } else {
       const int hy = h - nxh;
       const int side = hy >= SD * bx ? 1 : 0;
@@ -211,7 +227,8 @@ struct Sweep {
       it.r = d * bx + x;
       it.m = side ? d : SD - 1 - d;
       it.gx = x0 + x;
-      it.gy = wrap(y0 + yl, p.ny);
+      it.gy = wrap(y0 + yl0 + yl, p.ny);
+      it.inner = side ? yl0 + by < p.by : yl0 > 0;
     }
     return it;
   }
@@ -239,7 +256,7 @@ struct Sweep {
   __device__ __forceinline__ void load_plane(int zz, int parts = kPlaneCentre | kPlaneHalos) {
     Real* P = lds + slot_of<DIM, SD>(zz) * plane;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int bx = p.bx, by = p.by, bz = p.bz;
+    const int bx = p.bx, by = rows_sl, bz = p.bz;
     if (zz >= 0 && zz < bz) {
       const int gz = z0 + zz;
       // kBatch loads per thread are issued before any LDS write, from
@@ -247,7 +264,7 @@ struct Sweep {
       if (VEC && (parts & kPlaneCentre)) {
         // quads: one aligned 16-byte (FP32) or 32-byte (FP64) access each,
         // kBatch of them in flight per thread before the LDS stores
-        const Real* cz = centre + gidx(x0, y0, gz);
+        const Real* cz = centre + gidx(x0, y0 + yl0, gz);
         const int qpr = bx >> 2;
         PlaneIter it(tid, nt, qpr);
         const int rows = DIM >= 2 ? by : 1;
@@ -266,7 +283,7 @@ struct Sweep {
             if (at[k] >= 0) st4<Real>(P + at[k], v[k]);
         }
       } else if (parts & kPlaneCentre) {
-        const Real* cz = centre + gidx(x0, y0, gz);
+        const Real* cz = centre + gidx(x0, y0 + yl0, gz);
         PlaneIter it(tid, nt, bx);
         while (it.y < by) {
           Real v[kBatch];
@@ -287,7 +304,7 @@ struct Sweep {
       const int nh = (parts & kPlaneHalos) ? 2 * SD * by + (DIM >= 2 ? 2 * SD * bx : 0) : 0;
       for (int h = tid; h < nh; h += nt) {
         const HaloItem hi = halo_item(h);
-        P[hi.at] = halo(hi.f, zz, hi.r, hi.m, hi.gx, hi.gy, gz);
+        P[hi.at] = hi.inner ? centre[gidx(hi.gx, hi.gy, gz)] : halo(hi.f, zz, hi.r, hi.m, hi.gx, hi.gy, gz);
       }
     } else {
       // z halo plane: producer strip [d][y][x]
@@ -296,7 +313,8 @@ struct Sweep {
       const int gz = wrap(z0 + zz, p.nz);
       for (PlaneIter it(tid, nt, bx); it.y < by; it.next()) {
         const int x = it.x, y = it.y;
-        P[(y + SD) * px_stride + x + co] = halo(4 + side, d, y * bx + x, side ? d : SD - 1 - d, x0 + x, y0 + y, gz);
+        P[(y + SD) * px_stride + x + co] =
+            halo(4 + side, d, (yl0 + y) * bx + x, side ? d : SD - 1 - d, x0 + x, y0 + yl0 + y, gz);
       }
     }
   }
@@ -330,7 +348,8 @@ struct Sweep {
     int64_t hstride;         // halo plane stride
     const Real* a;           // history quads at plane 0
     const Real* b;
-    int c_at, h_at, hf;      // LDS offsets (-1: none) and the halo item's face
+    int c_at, h_at;          // LDS offsets (-1: none)
+    int hf;                  // the halo item's face (-1: a single level-n value)
   };
   struct Prefetch {
     Vec4<Real> c, pa, pb;
@@ -339,10 +358,10 @@ struct Sweep {
   template <int KIND>
   __device__ void pipe_setup(PipeAddr& pa) const {
     const int tid = threadIdx.x;
-    const int qpr = p.bx >> 2, quads = qpr * p.by;
+    const int qpr = p.bx >> 2, quads = qpr * rows_sl;
     const int q = tid < quads ? tid : quads - 1;
     const int qy = q / qpr, qx = q - qy * qpr;
-    const int64_t g0 = gidx(x0 + 4 * qx, y0 + qy, z0);
+    const int64_t g0 = gidx(x0 + 4 * qx, y0 + yl0 + qy, z0);
     pa.c = centre + g0;
     pa.c_at = tid < quads ? (qy + SD) * px_stride + 4 * qx + co : -1;
     const Real *ha, *hb;
@@ -350,16 +369,17 @@ struct Sweep {
     history<KIND>(ha, hb, any, ab3);
     pa.a = ha + g0;
     pa.b = hb + g0;
-    const int nh = 2 * SD * (p.by + p.bx);
+    const int nh = 2 * SD * (rows_sl + p.bx);
     const HaloItem hi = halo_item(tid < nh ? tid : nh - 1);
     pa.h_at = tid < nh ? hi.at : -1;
     pa.hf = hi.f;
-    if (p.mode == AT_SYNC) {
-      // the neighbour's level-n value
+    if (p.mode == AT_SYNC || hi.inner) {
+      // the neighbour's (or the PE's own) level-n value
       const Real* src = centre + gidx(hi.gx, hi.gy, z0);
 #pragma unroll
       for (int m = 0; m < kMaxT; ++m) pa.h[m] = src;
       pa.hstride = static_cast<int64_t>(p.nx) * p.ny;
+      pa.hf = -1;
       return;
     }
     const int nb = nbr[hi.f], pf = hi.f ^ 1;
@@ -398,7 +418,7 @@ struct Sweep {
   __device__ __forceinline__ void pipe_commit(const PipeAddr& pa, const Prefetch& pf, int zz) {
     Real* P = lds + slot_of<DIM, SD>(zz) * plane;
     if (pa.c_at >= 0) st4<Real>(P + pa.c_at, pf.c);
-    if (pa.h_at >= 0) P[pa.h_at] = halo_sum(pa.hf, pf.hv);
+    if (pa.h_at >= 0) P[pa.h_at] = pa.hf < 0 ? pf.hv[0] : halo_sum(pa.hf, pf.hv);
   }
 
   __device__ __forceinline__ void compute_plane(int z) {
@@ -607,7 +627,7 @@ struct Sweep {
     constexpr int QB = 2;   // quads per thread whose loads are issued together
     const int tid = threadIdx.x, nt = blockDim.x;
     const int bx = p.bx, by = p.by, bz = p.bz;
-    const int rows = DIM >= 2 ? by : 1;
+    const int rows = DIM >= 2 ? rows_sl : 1;   // the workgroup's y-slice
     const int qpr = bx >> 2;
     const Real* C = lds + slot_of<DIM, SD>(z) * plane;
     const Real* Zlo[S];   // z neighbour planes z - o and z + o, o = 1..S
@@ -628,7 +648,7 @@ struct Sweep {
       }
     const Real dt = static_cast<Real>(p.dt), alpha = static_cast<Real>(p.alpha);
     const Real vel[3] = {static_cast<Real>(p.vel[0]), static_cast<Real>(p.vel[1]), static_cast<Real>(p.vel[2])};
-    const int64_t gbase = gidx(x0, y0, z0 + z);
+    const int64_t gbase = gidx(x0, y0 + yl0, z0 + z);
     // history and destinations of this stage
     const bool ab = (KIND == kVAb2 || KIND == kVAb3) && n > 0;
     const Real *pre_a, *pre_b;
@@ -669,6 +689,7 @@ struct Sweep {
       for (int j = 0; j < QB; ++j) {
         const int y = ys[j];
         if (y >= rows) break;
+        const int ype = y + yl0;   // row within the PE
         const int qx = qxs[j], x = 4 * qx;
         const int ly = DIM >= 2 ? y + SD : 0;
         const int c_at = ly * px_stride + x + co;
@@ -736,8 +757,8 @@ struct Sweep {
         }
         if constexpr (SP != 0) {
           // quads next to a face with a delayed stencil: add its correction
-          const bool special = (qx == 0 && kp0) || (qx == qpr - 1 && kp1) || (y == 0 && kp2) ||
-                               (y == by - 1 && kp3) || (z == 0 && kp4) || (z == bz - 1 && kp5);
+          const bool special = (qx == 0 && kp0) || (qx == qpr - 1 && kp1) || (ype == 0 && kp2) ||
+                               (ype == by - 1 && kp3) || (z == 0 && kp4) || (z == bz - 1 && kp5);
           if (special) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -745,7 +766,7 @@ struct Sweep {
               Real c1s = 0, c2s = 0, adv = 0;
 #pragma unroll
               for (int a = 0; a < DIM; ++a) {
-                const int pos = a == 0 ? x + e : a == 1 ? y : z;
+                const int pos = a == 0 ? x + e : a == 1 ? ype : z;
                 const int ext = a == 0 ? bx : a == 1 ? by : bz;
                 const bool lo = pos == 0 && kpos[2 * a] != 0, hi = pos == ext - 1 && kpos[2 * a + 1] != 0;
                 if (!(lo || hi)) continue;
@@ -803,27 +824,27 @@ struct Sweep {
           // the new edge values of this quad into the strips they lie in
           if (qx == 0)
 #pragma unroll
-            for (int e = 0; e < SD; ++e) pub[0][y * SD + e] = un.v[e];
+            for (int e = 0; e < SD; ++e) pub[0][ype * SD + e] = un.v[e];
           if (qx == qpr - 1)
 #pragma unroll
-            for (int e = 4 - SD; e < 4; ++e) pub[1][y * SD + e - (4 - SD)] = un.v[e];
+            for (int e = 4 - SD; e < 4; ++e) pub[1][ype * SD + e - (4 - SD)] = un.v[e];
           if (DIM >= 2) {
-            if (y < SD)
+            if (ype < SD)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) pub[2][y * bx + x + e] = un.v[e];
-            if (y >= by - SD)
+              for (int e = 0; e < 4; ++e) pub[2][ype * bx + x + e] = un.v[e];
+            if (ype >= by - SD)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) pub[3][(y - (by - SD)) * bx + x + e] = un.v[e];
+              for (int e = 0; e < 4; ++e) pub[3][(ype - (by - SD)) * bx + x + e] = un.v[e];
           }
           if (DIM == 3) {
             if (z < SD) {
-              Real* zs = slot_base + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * p.face_chunk[4] + y * bx + x;
+              Real* zs = slot_base + p.face_off[4] + (static_cast<int64_t>(z) * p.npe + pid) * p.face_chunk[4] + ype * bx + x;
 #pragma unroll
               for (int e = 0; e < 4; ++e) zs[e] = un.v[e];
             }
             if (z >= bz - SD) {
               Real* zs = slot_base + p.face_off[5] + (static_cast<int64_t>(z - (bz - SD)) * p.npe + pid) * p.face_chunk[5] +
-                         y * bx + x;
+                         ype * bx + x;
 #pragma unroll
               for (int e = 0; e < 4; ++e) zs[e] = un.v[e];
             }
@@ -998,20 +1019,26 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
       sw.compute_plane(z);
   };
   if (DIM == 3) {
-    // workgroup blockIdx.x / npe sweeps z-chunk [zc0, zc1) of its PE; the
-    // SD planes on either side come from the PE (or across its z faces)
-    const int nch = gridDim.x / p.npe;
+    // workgroup blockIdx.x / npe = ci + nch * ys sweeps z-chunk ci,
+    // [zc0, zc1), of y-slice ys of its PE (pipelined form; else one slice);
+    // the SD planes on either side come from the PE (or across its z faces)
+    const int nys = PIPE && p.yslices > 1 ? p.yslices : 1;
+    const int nch = gridDim.x / (p.npe * nys);
+    const int wi = static_cast<int>(blockIdx.x / p.npe);
+    const int ci = wi % nch;
+    if (nys > 1) sw.set_slice(wi / nch, nys);
     const int zper = (p.bz + nch - 1) / nch;
-    const int zc0 = static_cast<int>(blockIdx.x / p.npe) * zper;
+    const int zc0 = ci * zper;
     const int zc1 = zc0 + zper < p.bz ? zc0 + zper : p.bz;
     faces();
     __syncthreads();
     if constexpr (PIPE) {
       static_assert(VEC && DIM == 3 && pipe_form<Real, S, SP>(), "pipelined form");
       // plane z + 1 + SD (u, halo) and the history of plane z + 1 are loaded
-      // while plane z is computed (two planes ahead measured no faster and
-      // takes more registers). The host launches this form only where every
-      // thread owns at most one quad and one halo item of a plane.
+      // while plane z is computed, issued after the barrier (two planes ahead
+      // measured no faster and takes more registers; issuing them before the
+      // barrier, slower). The host launches this form only where every
+      // thread owns at most one quad and one halo item of a slice's plane.
       using SW = Sweep<Real, DIM, S, SP, VEC>;
       if (zc0 < zc1) {
         typename SW::PipeAddr pa;
@@ -1095,14 +1122,20 @@ hipError_t launch_vec_e(const StepParams& p, hipStream_t st, int blocks, int thr
 
 template <typename Real, int DIM, int S, int SP, int KIND>
 hipError_t launch_vec_k(const StepParams& p, hipStream_t st, int blocks, int threads, size_t lds) {
+  const int nys = p.yslices > 1 ? p.yslices : 1;
   if constexpr (DIM == 3 && pipe_form<Real, S, SP>()) {
-    if (vec_pipe(p, strip_depth<S, SP>())) {
-      // one quad and one halo item per thread (see vec_threads)
-      const int quads = (p.bx / 4) * p.by, halos = 2 * strip_depth<S, SP>() * (p.bx + p.by);
-      if (threads < quads || threads < halos || threads > kMaxVec3Threads) return hipErrorInvalidConfiguration;
+    if (vec_pipe(p, strip_depth<S, SP>(), p.by / nys)) {
+      // one quad and one halo item of a slice's plane per thread (see
+      // vec_threads); slices of equal rows, at least SD each
+      const int rows = p.by / nys;
+      const int quads = (p.bx / 4) * rows, halos = 2 * strip_depth<S, SP>() * (p.bx + rows);
+      if (threads < quads || threads < halos || threads > kMaxVec3Threads || rows * nys != p.by ||
+          rows < strip_depth<S, SP>() || blocks % (p.npe * nys) != 0)
+        return hipErrorInvalidConfiguration;
       return launch_vec_e<Real, DIM, S, SP, KIND, true>(p, st, blocks, threads, lds);
     }
   }
+  if (nys != 1) return hipErrorInvalidConfiguration;   // y-slices: pipelined form only
   return launch_vec_e<Real, DIM, S, SP, KIND, false>(p, st, blocks, threads, lds);
 }
 
