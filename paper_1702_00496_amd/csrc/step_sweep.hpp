@@ -31,6 +31,29 @@ constexpr int strip_depth() {
   return SP == 0 ? S : SP == 2 ? 3 : 2;
 }
 
+// Part of a PE a workgroup of the sweep takes: PE pid, z-chunk ci of nch,
+// y-slice ys. 3-D grids whose size is a multiple of the 8 XCDs are
+// renumbered so that consecutive logical indices run on one XCD (the
+// dispatcher places workgroup b on XCD b mod 8) and the chunks of a PE come
+// first, then its neighbours along x: the planes a chunk reloads from the
+// next one, and the cache lines PEs share at their x edges when a PE row is
+// not a multiple of 128 bytes, stay in one L2.
+struct SweepPart {
+  int pid, ci, ys, nch;
+};
+template <int DIM>
+__device__ inline SweepPart sweep_part(const StepParams& p) {
+  const int g = static_cast<int>(gridDim.x), b = static_cast<int>(blockIdx.x);
+  const int nys = p.yslices > 1 ? p.yslices : 1;
+  SweepPart r;
+  r.nch = g / (p.npe * nys);
+  const int L = DIM == 3 && g % 8 == 0 ? (b % 8) * (g / 8) + b / 8 : b;
+  r.ci = L % r.nch;
+  r.pid = (L / r.nch) % p.npe;
+  r.ys = L / (r.nch * p.npe);
+  return r;
+}
+
 // Per-face taps of the non-uniform scheme, [face][derivative][o + 2]
 constexpr int kNuTaps = 10;
 
@@ -93,7 +116,7 @@ struct Sweep {
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
                    const int* ls_, const int* nb_, const int* kp_, const Real* nu_)
       : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
-    pid = blockIdx.x % p.npe;   // workgroups beyond npe take further z-chunks (y-slices) of the PEs
+    pid = sweep_part<DIM>(p).pid;
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
     qz = pid / (p.px * p.py);
@@ -981,7 +1004,7 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
   __shared__ Real s_nur[SP == 3 ? 6 * kNuTaps : 1];
 
   const int64_t n = p.counter[0];
-  const int pid = blockIdx.x % p.npe;
+  const int pid = sweep_part<DIM>(p).pid;
   const int tid = threadIdx.x;
   // neighbours, delays and level weights of the 2 * DIM faces
   auto faces = [&]() {
@@ -1019,14 +1042,14 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
       sw.compute_plane(z);
   };
   if (DIM == 3) {
-    // workgroup blockIdx.x / npe = ci + nch * ys sweeps z-chunk ci,
-    // [zc0, zc1), of y-slice ys of its PE (pipelined form; else one slice);
-    // the SD planes on either side come from the PE (or across its z faces)
+    // the workgroup sweeps z-chunk ci, [zc0, zc1), of y-slice ys of its PE
+    // (y-slices: pipelined form only); the SD planes on either side come
+    // from the PE (or across its z faces)
+    const SweepPart part = sweep_part<DIM>(p);
     const int nys = PIPE && p.yslices > 1 ? p.yslices : 1;
-    const int nch = gridDim.x / (p.npe * nys);
-    const int wi = static_cast<int>(blockIdx.x / p.npe);
-    const int ci = wi % nch;
-    if (nys > 1) sw.set_slice(wi / nch, nys);
+    const int nch = part.nch;
+    const int ci = part.ci;
+    if (nys > 1) sw.set_slice(part.ys, nys);
     const int zper = (p.bz + nch - 1) / nch;
     const int zc0 = ci * zper;
     const int zc1 = zc0 + zper < p.bz ? zc0 + zper : p.bz;
