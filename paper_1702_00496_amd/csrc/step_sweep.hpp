@@ -57,6 +57,10 @@ __device__ inline SweepPart sweep_part(const StepParams& p) {
 // Per-face taps of the non-uniform scheme, [face][derivative][o + 2]
 constexpr int kNuTaps = 10;
 
+// Per-face table of the vector path's face correction: [face][o + 3] first
+// derivative, [face][7 + o + 3] second, o = -3..3
+constexpr int kDtaps = 14;
+
 // Stage of the time integrator a vector-path kernel is specialised on.
 enum VKind : int { kVEuler = 0, kVAb2 = 1, kVAb3 = 2, kVRk1 = 3, kVRk2 = 4 };
 
@@ -112,10 +116,11 @@ struct Sweep {
   const int* nbr;           // [6] neighbour PE of face
   const int* kpos;          // [6] face delay k > 0 (space-expanded stencils apply)
   const Real* nut;          // [6][kNuTaps] non-uniform taps (SP = 3), in the storage type
+  const Real* dtap;         // [6][kDtaps] face stencil minus the CD2 taps (SP != 0, faces with kpos)
 
   __device__ Sweep(const StepParams& p_, Real* lds_, int64_t n_, const double* w_,
-                   const int* ls_, const int* nb_, const int* kp_, const Real* nu_)
-      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_) {
+                   const int* ls_, const int* nb_, const int* kp_, const Real* nu_, const Real* dt_)
+      : p(p_), lds(lds_), n(n_), w(w_), lev_slot(ls_), nbr(nb_), kpos(kp_), nut(nu_), dtap(dt_) {
     pid = sweep_part<DIM>(p).pid;
     qx = pid % p.px;
     qy = (pid / p.px) % p.py;
@@ -779,47 +784,63 @@ struct Sweep {
           fq.v[e] = fval;
         }
         if constexpr (SP != 0) {
-          // quads next to a face with a delayed stencil: add its correction
-          const bool special = (qx == 0 && kp0) || (qx == qpr - 1 && kp1) || (ype == 0 && kp2) ||
-                               (ype == by - 1 && kp3) || (z == 0 && kp4) || (z == bz - 1 && kp5);
-          if (special) {
+          // points next to a face whose delay calls for the face stencil:
+          // add its difference from the CD2 taps (per-face table in LDS) times
+          // the differences (v_o - u0) along the face's axis
+          auto corr = [&](int f, Real u0, const Real (&v)[2 * SD + 1]) -> Real {
+            const Real* t = dtap + f * kDtaps;
+            Real d1 = 0, d2 = 0;
+#pragma unroll
+            for (int o = -SD; o <= SD; ++o) {
+              if (o == 0) continue;
+              const Real dv = v[o + SD] - u0;
+              d1 += t[o + 3] * dv;
+              d2 += t[7 + o + 3] * dv;
+            }
+            return EQ == AT_ADVDIFF ? alpha * d2 - vel[f >> 1] * d1 : alpha * d2 - u0 * d1;
+          };
+          // x faces: the first point of a row's first quad, the last of its last
+          if (qx == 0 && kp0) {
+            Real v[2 * SD + 1];
+#pragma unroll
+            for (int o = -SD; o <= SD; ++o) v[o + SD] = row[4 + o];
+            fq.v[0] += corr(0, row[4], v);
+          }
+          if (qx == qpr - 1 && kp1) {
+            Real v[2 * SD + 1];
+#pragma unroll
+            for (int o = -SD; o <= SD; ++o) v[o + SD] = row[7 + o];
+            fq.v[3] += corr(1, row[7], v);
+          }
+          // y and z faces: all four points of the quad
+          auto face_quad = [&](int f, const Real* base, int stride) {
+            Q nq[2 * SD + 1];
+#pragma unroll
+            for (int o = -SD; o <= SD; ++o) nq[o + SD] = ld4<Real>(base + o * stride);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const Real u0 = row[4 + e];
-              Real c1s = 0, c2s = 0, adv = 0;
+              Real v[2 * SD + 1];
 #pragma unroll
-              for (int a = 0; a < DIM; ++a) {
-                const int pos = a == 0 ? x + e : a == 1 ? ype : z;
-                const int ext = a == 0 ? bx : a == 1 ? by : bz;
-                const bool lo = pos == 0 && kpos[2 * a] != 0, hi = pos == ext - 1 && kpos[2 * a + 1] != 0;
-                if (!(lo || hi)) continue;
-                Real t1 = 0, t2 = 0;
+              for (int o = -SD; o <= SD; ++o) v[o + SD] = nq[o + SD].v[e];
+              fq.v[e] += corr(f, row[4 + e], v);
+            }
+          };
+          if (DIM >= 2 && ((ype == 0 && kp2) || (ype == by - 1 && kp3)))
+            face_quad(ype == 0 && kp2 ? 2 : 3, C + c_at, px_stride);
+          if constexpr (DIM == 3) {
+            if ((z == 0 && kp4) || (z == bz - 1 && kp5)) {
+              // planes z - SD .. z + SD of the LDS ring, at this quad
+              const int f = z == 0 && kp4 ? 4 : 5;
+              Q nq[2 * SD + 1];
 #pragma unroll
-                for (int o = -SD; o <= SD; ++o) {
-                  if (o == 0) continue;
-                  const Real v = (a == 0 ? C[c_at + e + o] : a == 1 ? C[c_at + e + o * px_stride]
-                                                                 : lds[slot_of<DIM, SD>(z + o) * plane + c_at + e]) - u0;
-                  const Real cd1 = (o >= -1 && o <= 1) ? static_cast<Real>(p.c1[a][o + 1]) : Real(0);
-                  const Real cd2 = (o >= -1 && o <= 1) ? static_cast<Real>(p.c2[a][o + 1]) : Real(0);
-                  Real w1, w2;
-                  if constexpr (SP == 3) {
-                    const int f = 2 * a + (hi ? 1 : 0);
-                    w1 = (o >= -2 && o <= 2) ? nut[f * kNuTaps + o + 2] - cd1 : Real(0);
-                    w2 = (o >= -2 && o <= 2) ? nut[f * kNuTaps + 5 + o + 2] - cd2 : Real(0);
-                  } else {
-                    w1 = lo ? static_cast<Real>(p.sl1[a][o + kMaxS]) - cd1
-                            : -(static_cast<Real>(p.sl1[a][-o + kMaxS]) - ((-o >= -1 && -o <= 1) ? static_cast<Real>(p.c1[a][-o + 1]) : Real(0)));
-                    w2 = lo ? static_cast<Real>(p.sl2[a][o + kMaxS]) - cd2
-                            : static_cast<Real>(p.sl2[a][-o + kMaxS]) - ((-o >= -1 && -o <= 1) ? static_cast<Real>(p.c2[a][-o + 1]) : Real(0));
-                  }
-                  t1 += w1 * v;
-                  t2 += w2 * v;
-                }
-                c1s += t1;
-                adv += vel[a] * t1;
-                c2s += t2;
+              for (int o = -SD; o <= SD; ++o) nq[o + SD] = ld4<Real>(lds + slot_of<DIM, SD>(z + o) * plane + c_at);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                Real v[2 * SD + 1];
+#pragma unroll
+                for (int o = -SD; o <= SD; ++o) v[o + SD] = nq[o + SD].v[e];
+                fq.v[e] += corr(f, row[4 + e], v);
               }
-              fq.v[e] += EQ == AT_ADVDIFF ? alpha * c2s - adv : alpha * c2s - u0 * c1s;
             }
           }
         }
@@ -981,6 +1002,34 @@ __device__ inline void nonuniform_face(const StepParams& p, int pid, int f, int6
 
 // VEC: the vector layout and path, specialised on the integrator stage KIND
 // and the equation EQ (the scalar path reads both at run time).
+// The face stencil of face f (the space-expanded single-level taps of
+// Sec. 3.4 and Tables atschemes-left/right, mirrored for a high face, or the
+// non-uniform taps nu of Example 1) minus the CD2 taps it replaces, by
+// offset o = -3..3 along the face's axis, into dt[kDtaps]: the vector path
+// adds their product with the differences (v_o - u0) at the points next to a
+// face whose delay calls for the face stencil.
+template <typename Real, int SP>
+__device__ inline void face_delta_taps(const StepParams& p, int f, const double* nu, Real* dt) {
+  const int a = f >> 1;
+  const bool lo = (f & 1) == 0;
+  auto cd1 = [&](int o) { return o >= -1 && o <= 1 ? p.c1[a][o + 1] : 0.0; };
+  auto cd2 = [&](int o) { return o >= -1 && o <= 1 ? p.c2[a][o + 1] : 0.0; };
+  for (int o = -3; o <= 3; ++o) {
+    double t1 = 0.0, t2 = 0.0;
+    if constexpr (SP == 3) {
+      if (o >= -2 && o <= 2) {
+        t1 = nu[f * kNuTaps + o + 2] - cd1(o);
+        t2 = nu[f * kNuTaps + 5 + o + 2] - cd2(o);
+      }
+    } else {
+      t1 = lo ? p.sl1[a][o + kMaxS] - cd1(o) : -(p.sl1[a][-o + kMaxS] - cd1(-o));
+      t2 = lo ? p.sl2[a][o + kMaxS] - cd2(o) : p.sl2[a][-o + kMaxS] - cd2(-o);
+    }
+    dt[o + 3] = static_cast<Real>(t1);
+    dt[7 + o + 3] = static_cast<Real>(t2);
+  }
+}
+
 // Whether a 3-D vector-path instance has the pipelined form (the space-
 // expanded and non-uniform stencils, whose face corrections take more
 // registers, and sixth order in FP64 do not).
@@ -1002,6 +1051,7 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
   __shared__ int s_kpos[6];
   __shared__ double s_nu[SP == 3 ? 6 * kNuTaps : 1];
   __shared__ Real s_nur[SP == 3 ? 6 * kNuTaps : 1];
+  __shared__ Real s_dt[SP != 0 ? 6 * kDtaps : 1];
 
   const int64_t n = p.counter[0];
   const int pid = sweep_part<DIM>(p).pid;
@@ -1017,12 +1067,15 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
         nonuniform_face(p, pid, f, n, s_kpos, s_slot, s_nu);
         // the stencil multiplies in the storage type: convert once per face
         for (int i = 0; i < kNuTaps; ++i) s_nur[f * kNuTaps + i] = static_cast<Real>(s_nu[f * kNuTaps + i]);
+        if (VEC && s_kpos[f]) face_delta_taps<Real, SP>(p, f, s_nu, s_dt + f * kDtaps);
       }
       return;
     }
     if (p.mode != AT_SYNC) {
       const int k = face_delay(p, pid, f, n);
       s_kpos[f] = k > 0;
+      if constexpr (SP != 0)
+        if (VEC && k > 0) face_delta_taps<Real, SP>(p, f, nullptr, s_dt + f * kDtaps);
       const int r0 = static_cast<int>(n % p.nslots);
       double w[kMaxT];
       level_weights(k, p.T, w);
@@ -1034,7 +1087,7 @@ __global__ __launch_bounds__(PIPE ? kMaxVec3Threads : kMaxSweepThreads) void at_
     }
   };
 
-  Sweep<Real, DIM, S, SP, VEC> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nur);
+  Sweep<Real, DIM, S, SP, VEC> sw(p, lds, n, s_w, s_slot, s_nbr, s_kpos, s_nur, s_dt);
   auto compute = [&](int z) {
     if constexpr (VEC)
       sw.template compute_plane_vec<KIND, EQ>(z);
