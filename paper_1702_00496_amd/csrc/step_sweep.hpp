@@ -366,10 +366,12 @@ struct Sweep {
   // their latency overlaps the stencil work of the plane before. Every
   // thread owns at most one quad and one halo item of a plane (the 3-D
   // workgroup has as many threads as the larger count, up to 768: cross-
-  // sections of up to 768 quads). Addresses are fixed per thread and advance
+  // sections, or y-slices of them, of up to 768 quads). Addresses are fixed
+  // per thread and advance
   // by a plane stride; loads go to clamped in-box planes and lanes, with no
-  // branch around them, and a load whose plane lies beyond the PE's high z
-  // face is not used (that plane comes from the z strips).
+  // branch around them (a level beyond T or of weight zero reads slot 0 and
+  // is dropped by the combination), and a load whose plane lies beyond the
+  // PE's high z face is not used (that plane comes from the z strips).
   struct PipeAddr {
     const Real* c;           // the thread's quad of u at plane 0
     const Real* h[kMaxT];    // its halo item's levels at plane 0
