@@ -187,14 +187,16 @@ struct Sweep {
       return;
     }
     // every level is loaded from an in-range slot so that the T loads are in
-    // flight together; a level of weight zero (k = 0: exact synchronous
-    // value) is then dropped by the select
+    // flight together; a level beyond T or of weight zero (k = 0: exact
+    // synchronous value) re-reads level 0 (a cache hit) and is then dropped
+    // by the select
     const int64_t base = ring_off(0, nb, pf, plane, r);
     const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
+    const int s0 = lev_slot[f * kMaxT] > 0 ? lev_slot[f * kMaxT] : 0;
 #pragma unroll
     for (int mm = 0; mm < kMaxT; ++mm) {
       const int sl = lev_slot[f * kMaxT + mm];
-      v[mm] = ring_rd[base + (mm < p.T && sl > 0 ? sl : 0) * slot_stride];
+      v[mm] = ring_rd[base + (mm < p.T && sl >= 0 ? sl : s0) * slot_stride];
     }
   }
   __device__ Real halo_sum(int f, const Real (&v)[kMaxT]) const {
@@ -369,9 +371,10 @@ struct Sweep {
   // sections, or y-slices of them, of up to 768 quads). Addresses are fixed
   // per thread and advance
   // by a plane stride; loads go to clamped in-box planes and lanes, with no
-  // branch around them (a level beyond T or of weight zero reads slot 0 and
-  // is dropped by the combination), and a load whose plane lies beyond the
-  // PE's high z face is not used (that plane comes from the z strips).
+  // branch around them (a level beyond T or of weight zero re-reads level
+  // 0, a cache hit, and is dropped by the combination), and a load whose
+  // plane lies beyond the PE's high z face is not used (that plane comes
+  // from the z strips).
   struct PipeAddr {
     const Real* c;           // the thread's quad of u at plane 0
     const Real* h[kMaxT];    // its halo item's levels at plane 0
@@ -421,10 +424,11 @@ struct Sweep {
     } else {
       const int64_t base = ring_off(0, nb, pf, 0, hi.r);
       const int64_t slot_stride = static_cast<int64_t>(p.npe) * p.pe_block;
+      const int s0 = lev_slot[hi.f * kMaxT] > 0 ? lev_slot[hi.f * kMaxT] : 0;
 #pragma unroll
       for (int m = 0; m < kMaxT; ++m) {
         const int sl = lev_slot[hi.f * kMaxT + m];
-        pa.h[m] = ring_rd + base + (m < p.T && sl > 0 ? sl : 0) * slot_stride;
+        pa.h[m] = ring_rd + base + (m < p.T && sl >= 0 ? sl : s0) * slot_stride;
       }
     }
   }
