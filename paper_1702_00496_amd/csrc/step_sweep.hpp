@@ -696,8 +696,16 @@ struct Sweep {
     const bool kp2 = SP != 0 && DIM >= 2 && kpos[2], kp3 = SP != 0 && DIM >= 2 && kpos[3];
     const bool kp4 = SP != 0 && DIM == 3 && kpos[4], kp5 = SP != 0 && DIM == 3 && kpos[5];
     set_publish_plane(z);
-    PlaneIter it(tid, nt, qpr);
-    while (it.y < rows) {
+    // pipelined form (hist given): exactly one quad per thread, the threads
+    // beyond the plane's quads repeating the last one (the same values to
+    // the same addresses), so that the body runs once with no branch
+    // around its stores and the compiler can leave them in flight past the
+    // next plane's wait for its loads
+    const bool one = hist != nullptr;
+    const int quads = qpr * rows;
+    PlaneIter it(one && tid >= quads ? quads - 1 : tid, nt, qpr);
+    bool more = one || it.y < rows;
+    while (more) {
       int qxs[QB], ys[QB];
       Q pa[QB], pb[QB];
 #pragma unroll
@@ -706,6 +714,7 @@ struct Sweep {
         ys[j] = it.y;
         it.next();
       }
+      more = !one && it.y < rows;
       if (hist != nullptr) {
         // one quad per thread: the only live one is j = 0
         pa[0] = hist[0];
@@ -722,7 +731,7 @@ struct Sweep {
 #pragma unroll
       for (int j = 0; j < QB; ++j) {
         const int y = ys[j];
-        if (y >= rows) break;
+        if (one ? j > 0 : y >= rows) break;
         const int ype = y + yl0;   // row within the PE
         const int qx = qxs[j], x = 4 * qx;
         const int ly = DIM >= 2 ? y + SD : 0;
@@ -868,8 +877,6 @@ struct Sweep {
           }
           un.v[e] = r;
         }
-        st4<Real>(uout + g, un);
-        if (KIND == kVAb2 || KIND == kVAb3) st4<Real>(fout + g, fq);
         if (!sync) {
           // the new edge values of this quad into the strips they lie in
           if (qx == 0)
@@ -900,6 +907,11 @@ struct Sweep {
             }
           }
         }
+        // the bulk stores last: in the pipelined form they are the newest
+        // memory operations of the plane, which the next plane's wait for
+        // its loads may leave in flight
+        st4<Real>(uout + g, un);
+        if (KIND == kVAb2 || KIND == kVAb3) st4<Real>(fout + g, fq);
       }
     }
   }
