@@ -168,8 +168,11 @@ at_status at_workspace_size(const at_problem* prob, const at_delay* delay, size_
  * zero, or a host table). Derives the central-difference taps and the level
  * weights c_m(k) of the AT combination (Sec. 3.4 Example 3, eq. cd4-at).
  * Validates: ndim 1..3; divisibility; PE edge >= 2s on used axes; order in
- * {2,4,6}; 1 <= L <= 8; 1 <= T <= 4; host delays < L (AT_EINVAL);
- * AT_ENOMEM when ws_bytes is too small. The library keeps `ws_dev` and the
+ * {2,4,6}; 1 <= L <= 8; 1 <= T <= 4; host delays < L; a PE tile whose
+ * sweep workgroup needs more than the 160 KB of LDS of a compute unit (the
+ * generic 3-D sweep splits large cross-sections into y-halves where it may
+ * split a PE, which lowers the need) (AT_EINVAL); AT_ENOMEM when ws_bytes
+ * is too small. The library keeps `ws_dev` and the
  * stream; the caller keeps ownership of both and of every host array. */
 at_status at_create(const at_problem* prob, const at_delay* delay, void* ws_dev,
                     size_t ws_bytes, void* hip_stream, at_ctx** out);
