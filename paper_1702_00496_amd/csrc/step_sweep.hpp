@@ -1018,8 +1018,6 @@ __device__ inline void nonuniform_face(const StepParams& p, int pid, int f, int6
   }
 }
 
-// VEC: the vector layout and path, specialised on the integrator stage KIND
-// and the equation EQ (the scalar path reads both at run time).
 // The face stencil of face f (the space-expanded single-level taps of
 // Sec. 3.4 and Tables atschemes-left/right, mirrored for a high face, or the
 // non-uniform taps nu of Example 1) minus the CD2 taps it replaces, by
@@ -1056,6 +1054,8 @@ constexpr bool pipe_form() {
   return SP == 0 && (sizeof(Real) == 4 || S < 3);
 }
 
+// VEC: the vector layout and path, specialised on the integrator stage KIND
+// and the equation EQ (the scalar path reads both at run time).
 // PIPE (3-D vector path only): the pipelined sweep, at most kMaxVec3Threads
 // threads, so that it may hold 168 VGPRs per lane.
 template <typename Real, int DIM, int S, int SP, bool VEC = false, int KIND = 0, int EQ = 0, bool PIPE = false>
