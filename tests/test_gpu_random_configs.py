@@ -87,7 +87,7 @@ def draw_deep(seed):
     return case, rng.choice(("f64", "f32"))
 
 
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(32))
 def test_random_deep_generic_configuration_matches_the_oracle(seed):
     case, precision = draw_deep(3000 + seed)
     print(f"[random] deep seed {seed}: {case} {precision}", flush=True)
@@ -117,7 +117,7 @@ def draw_wide(seed):
     return case, precision
 
 
-@pytest.mark.parametrize("seed", range(48))
+@pytest.mark.parametrize("seed", range(96))
 def test_random_wide_generic_configuration_matches_the_oracle(seed):
     case, precision = draw_wide(7000 + seed)
     print(f"[random] wide seed {seed}: {case} {precision}", flush=True)
