@@ -273,18 +273,22 @@ __global__ __launch_bounds__(kB * kB / V) void at_step3d_fast_kernel(StepParams 
   // x items (side and four consecutive values of the producer strip [z][y][d],
   // i.e. rows and depths (e / S, e % S); the synchronous arm reads rows
   // yq..yq+3 at one depth of the neighbour's field instead) and y items (side,
-  // depth d, columns xq..xq+3; strip [z][d][x]). Each wave owns a contiguous
-  // share of the items in its low lanes; other lanes alias item 0 (their reads
-  // hit the same lines and are discarded).
+  // depth d, columns xq..xq+3; strip [z][d][x]). FP32: the items fill the
+  // first threads (one wave for s <= 2), so that the other waves skip the
+  // FP64 combination (256^3 AT 69.4 -> 68.6 us); FP64: each wave owns a
+  // contiguous share of the items in its low lanes (the first form measured
+  // 130.3 -> 132.2 us there). Other threads alias item 0 (their reads hit the
+  // same lines and are discarded).
   constexpr int QPR = kB / 4;
   constexpr int NHX = 2 * S * QPR;
   constexpr int NH = 2 * NHX;
+  constexpr bool kFirst = sizeof(Real) == 4;
   constexpr int NW = NT / 64;
   constexpr int NHW = NH / NW;
-  static_assert(NH % NW == 0 && NHW <= 64, "halo items per wave");
+  static_assert(kFirst ? NH <= NT : (NH % NW == 0 && NHW <= 64), "halo items per wave");
   const int lane = tid & 63;
-  const bool is_h = lane < NHW;
-  const int hid = is_h ? (tid >> 6) * NHW + lane : 0;
+  const bool is_h = kFirst ? tid < NH : lane < NHW;
+  const int hid = is_h ? (kFirst ? tid : (tid >> 6) * NHW + lane) : 0;
   Src hs;
   int hp[4];                        // LDS positions of the 4 values
   int estride;                      // element stride of the synchronous arm's reads
